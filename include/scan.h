@@ -1,0 +1,216 @@
+/*
+ * scan.h -- C ABI of the fused columnar scan for AMD Instinct MI355X (gfx950).
+ *
+ * The operation (the paper, "Problem and Model" and "Method"): read a
+ * bit-packed integer column, decode every value, test a range predicate and
+ * aggregate COUNT and SUM in one pass, optionally skipping 1024-value blocks
+ * whose min/max zone map misses the predicate.  Results are exact integers:
+ *     count = #{ i < n : lo <= v_i < hi }
+ *     sum   = (sum of those v_i) mod 2^64, as two's-complement int64
+ *     blocks_read = blocks whose payload the scan had to decode: all blocks
+ *                   with zone maps off, #{k : not(max_k < lo or min_k >= hi)}
+ *                   with zone maps on; 0 when lo >= hi.
+ * Every strategy (decoder layout, branch-free or compacting predicate, zone
+ * maps on or off, batched or single) gives bit-identical count and sum.
+ *
+ * Conventions.
+ *  - No C++ types, no exceptions cross this boundary.  Every call returns a
+ *    scan_status; the message of the last failure on a context is kept for
+ *    scan_last_error().
+ *  - "device" pointers are HIP device allocations (e.g. a torch CUDA tensor's
+ *    data_ptr()); the caller owns them and keeps them alive until the call (or,
+ *    for *_async and replayed batches, the stream) is done.  "host" pointers
+ *    are ordinary CPU memory.
+ *  - A context is bound to one device and one HIP stream and is NOT thread
+ *    safe: use one context per host thread.  All GPU work of a context is
+ *    enqueued on its stream.
+ *
+ * Column format (the paper fixes 1024-value blocks, a row-major and a
+ * lane-transposed packing, byte-aligned widths that coincide with plain
+ * arrays, frame-of-reference bit-unpacking and per-block zone maps; the bit
+ * order and the delta/dictionary variants are this library's reading):
+ *  - L = 1024 values per block, nb = ceil(n / L) blocks; block k holds
+ *    32*b u32 words (b*128 bytes) starting at word 32*b*k of the payload.
+ *  - SCAN_LAYOUT_RM: value j of a block occupies block bits [j*b, j*b + b);
+ *    block bit t is bit (t mod 32) of block word (t div 32) (LSB first).
+ *  - SCAN_LAYOUT_LI: value j goes to lane j mod 32, slot j div 32; lane bit t
+ *    is bit (t mod 32) of block word 32*(t div 32) + lane, so slot s of every
+ *    lane shares one word index and shift.
+ *  - Tail slots (j >= n - k*L in the last block) are zero and never counted.
+ *  - SCAN_ENC_FOR: v = block_ref[k] + code as u32 (block_ref NULL: all 0).
+ *  - SCAN_ENC_DELTA_FOR: v = block_base[k] + d_0 + ... + d_j (int64), d_0 = 0.
+ *  - SCAN_ENC_DICT: v = dict[code], dict strictly increasing int64,
+ *    dict_len <= min(2^b, 4096).
+ *  - Zone maps: per block, min and max over the block's valid slots of the
+ *    decoded values (u32 for FOR, int64 for DELTA_FOR) or of the codes (u32,
+ *    DICT).
+ */
+#ifndef SCAN_H
+#define SCAN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SCAN_BLOCK_VALUES 1024u
+#define SCAN_MAX_DICT 4096u
+
+typedef struct scan_ctx scan_ctx;
+
+typedef enum {
+  SCAN_OK = 0,
+  SCAN_EINVAL = -1,       /* bad argument; nothing was enqueued */
+  SCAN_ENOMEM = -2,       /* a device or host allocation failed */
+  SCAN_EDEVICE = -3,      /* a HIP call failed; the context may be unusable */
+  SCAN_EUNSUPPORTED = -4, /* strategy not valid for this column (layout, width, missing zone maps) */
+  SCAN_EBUSY = -5         /* resource temporarily exhausted (serving admission) */
+} scan_status;
+
+typedef enum { SCAN_ENC_FOR = 0, SCAN_ENC_DELTA_FOR = 1, SCAN_ENC_DICT = 2 } scan_encoding;
+typedef enum { SCAN_LAYOUT_RM = 0, SCAN_LAYOUT_LI = 1 } scan_layout;
+
+/* Half-open predicate [lo, hi) on decoded values; lo >= hi selects nothing.
+ * Equality v == x is [x, x+1); v < c on unsigned data is [0, c). */
+typedef struct {
+  int64_t lo, hi;
+} scan_predicate;
+
+enum { SCAN_AGG_COUNT = 1u, SCAN_AGG_SUM = 2u };
+
+/* Strategy = decoder | (predicate mode << 2) | (zone maps << 3).
+ *  decoder SCAN_DEC_RM_LDS:    row-major; a wavefront stages each block in LDS
+ *                              and extracts values with funnel shifts;
+ *  decoder SCAN_DEC_RM_DIRECT: row-major; each lane loads its own 32-value slice
+ *                              (b words) into registers, constant shifts;
+ *  decoder SCAN_DEC_LI:        lane-interleaved layout, register decode;
+ *  decoder SCAN_DEC_BYTES:     b in {8,16,32}, FOR, row-major read as a plain array.
+ *  mode SCAN_PRED_BF:  branch-free: every value is tested and added under a mask;
+ *  mode SCAN_PRED_SV:  wavefront selection-vector compaction (ballot + mbcnt)
+ *                      into LDS, aggregated over the compacted list.
+ * SCAN_STRAT_AUTO lets the library choose (learned selector if loaded, else a
+ * fixed heuristic). */
+enum {
+  SCAN_DEC_RM_LDS = 0,
+  SCAN_DEC_RM_DIRECT = 1,
+  SCAN_DEC_LI = 2,
+  SCAN_DEC_BYTES = 3,
+  SCAN_PRED_BF = 0,
+  SCAN_PRED_SV = 1,
+  SCAN_STRAT_AUTO = -1
+};
+#define SCAN_STRATEGY(dec, sv, zm) ((int32_t)((dec) | ((sv) << 2) | ((zm) << 3)))
+
+typedef struct {
+  const uint32_t* payload;    /* device: nb*32*b words, 16-byte aligned */
+  const uint32_t* block_ref;  /* device: FOR references (nb u32) or NULL for all-zero */
+  const int64_t* block_base;  /* device: DELTA_FOR bases (nb int64) */
+  const int64_t* dict;        /* device: DICT entries */
+  uint32_t dict_len;
+  uint32_t layout;            /* scan_layout */
+  const void* zone_min;       /* device: nb entries (u32, or int64 for DELTA_FOR); NULL = none */
+  const void* zone_max;
+  uint64_t n;                 /* values in the column */
+} scan_column;
+
+typedef struct {
+  uint64_t count;
+  int64_t sum;
+  uint64_t blocks_read;
+  uint64_t blocks_total;
+  int32_t strategy_used;
+  int32_t status;             /* scan_status of this item (batch and serving results) */
+} scan_result;
+
+typedef struct {
+  scan_column col;
+  int32_t enc;                /* scan_encoding */
+  uint32_t b;                 /* bits per code, 1..32 */
+  scan_predicate pred;
+  uint32_t agg;               /* SCAN_AGG_* bits; COUNT is always produced */
+  int32_t strategy;           /* SCAN_STRATEGY(...) or SCAN_STRAT_AUTO */
+} scan_item;
+
+/* Launch tuning of one (encoding, width, strategy): work-group size (64, 128,
+ * 192 or 256), work-groups per compute unit (0 = as many as fit), and the
+ * minimum number of blocks each wavefront takes (bounds the grid of small
+ * columns).  Zero fields mean "library default". */
+typedef struct {
+  int32_t wg_size;
+  int32_t wgs_per_cu;
+  int32_t min_blocks_per_wave;
+  int32_t reserved;
+} scan_tune;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device` enqueuing on `hip_stream`
+ * (a hipStream_t, or NULL for the null stream).  Allocates the context's
+ * device scratch (partials, counters, result slots). */
+scan_status scan_create(scan_ctx** out, int device, void* hip_stream);
+/* Change the stream later calls enqueue on. */
+scan_status scan_set_stream(scan_ctx* ctx, void* hip_stream);
+/* Waits for the context's stream, then frees everything the context owns. */
+void scan_destroy(scan_ctx* ctx);
+/* Message of the last failed call on ctx ("" if none).  Valid until the next call. */
+const char* scan_last_error(const scan_ctx* ctx);
+/* Number of compute units of the context's device. */
+int scan_device_cus(const scan_ctx* ctx);
+
+/* ------------------------------------------------------------------ scans */
+
+/* Scan one column and wait for the result (written to *out, host memory).
+ * Errors: b outside 1..32, NULL payload, misaligned payload, missing
+ * references/bases/dictionary for the encoding, dict_len > min(2^b, 4096)
+ * -> SCAN_EINVAL; strategy not valid for the column -> SCAN_EUNSUPPORTED.
+ * n == 0 or lo >= hi -> SCAN_OK with zero count and sum. */
+scan_status scan_run(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b,
+                     const scan_predicate* pred, uint32_t agg, int32_t strategy, scan_result* out);
+
+/* Enqueue one scan on the context stream; the result lands in *out_dev
+ * (device memory, one scan_result) when the stream reaches it.  No host sync;
+ * scan_sync() waits.  SCAN_STRAT_AUTO resolves to the heuristic here (no sync). */
+scan_status scan_run_async(scan_ctx* ctx, const scan_item* item, scan_result* out_dev);
+scan_status scan_sync(scan_ctx* ctx);
+
+/* Set / read the launch tuning used for (enc, b, strategy). */
+scan_status scan_set_tune(scan_ctx* ctx, int32_t enc, uint32_t b, int32_t strategy, const scan_tune* t);
+scan_status scan_get_tune(scan_ctx* ctx, int32_t enc, uint32_t b, int32_t strategy, scan_tune* t);
+
+/* -------------------------------------------------------------- encoders */
+/* Host-side encoders (host pointers).  Payload buffers must hold
+ * scan_payload_words(n, b) u32; zone-map and reference/base buffers nb entries.
+ * They are written from the format text above, independently of any checker. */
+uint64_t scan_payload_words(uint64_t n, uint32_t b);
+/* FOR: ref_policy 0 = all references 0, 1 = per-block minimum (block_ref must
+ * then be non-NULL).  Fails with SCAN_EINVAL if a value does not fit b bits
+ * above its reference.  zone_min/zone_max may be NULL. */
+scan_status scan_encode_for(const uint32_t* values, uint64_t n, uint32_t b, uint32_t layout,
+                            int32_t ref_policy, uint32_t* payload, uint32_t* block_ref,
+                            uint32_t* zone_min, uint32_t* zone_max);
+/* DELTA_FOR: values non-decreasing; every difference must fit b bits. */
+scan_status scan_encode_delta(const int64_t* values, uint64_t n, uint32_t b, uint32_t* payload,
+                              int64_t* block_base, int64_t* zone_min, int64_t* zone_max);
+/* DICT: codes (indices into a dictionary of dict_len entries) packed row-major. */
+scan_status scan_encode_dict(const uint32_t* codes, uint64_t n, uint32_t b, uint32_t dict_len,
+                             uint32_t* payload, uint32_t* zone_min, uint32_t* zone_max);
+
+/* ----------------------------------------------------- bandwidth probes */
+/* Streaming read of `bytes` (multiple of 16) from `buf` (device) with 16-byte
+ * loads; `wgs` work-groups of `wg_size` threads (0 = defaults); `unroll`
+ * independent loads in flight per thread (1, 2, 4 or 8).  Writes a checksum
+ * into sink[0] (device u64) so the reads cannot be elided.  Enqueue only. */
+scan_status scan_beta_read(scan_ctx* ctx, const void* buf, uint64_t bytes, int32_t wgs,
+                           int32_t wg_size, int32_t unroll, uint64_t* sink);
+/* STREAM triad a[i] = b[i] + s*c[i] over n floats (device). Enqueue only. */
+scan_status scan_beta_triad(scan_ctx* ctx, float* a, const float* b, const float* c, float s,
+                            uint64_t n);
+/* Overwrite `bytes` of device scratch so that later reads miss the caches. Enqueue only. */
+scan_status scan_cache_flush(scan_ctx* ctx, void* buf, uint64_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCAN_H */

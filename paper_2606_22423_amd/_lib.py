@@ -1,0 +1,134 @@
+"""ctypes declarations of the C ABI in include/scan.h (argument marshalling only).
+
+The shared library is built in-tree by ``build.py`` into ``libscan.so``.
+Loading fails loudly when it is missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libscan.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "scan.h")
+
+# status codes
+SCAN_OK, SCAN_EINVAL, SCAN_ENOMEM, SCAN_EDEVICE, SCAN_EUNSUPPORTED, SCAN_EBUSY = 0, -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "SCAN_OK", -1: "SCAN_EINVAL", -2: "SCAN_ENOMEM", -3: "SCAN_EDEVICE",
+                -4: "SCAN_EUNSUPPORTED", -5: "SCAN_EBUSY"}
+ENC_FOR, ENC_DELTA, ENC_DICT = 0, 1, 2
+LAYOUT_RM, LAYOUT_LI = 0, 1
+DEC_RM_LDS, DEC_RM_DIRECT, DEC_LI, DEC_BYTES = 0, 1, 2, 3
+PRED_BF, PRED_SV = 0, 1
+STRAT_AUTO = -1
+AGG_COUNT, AGG_SUM = 1, 2
+
+
+def strategy(dec: int, sv: int = 0, zm: int = 0) -> int:
+    return dec | (sv << 2) | (zm << 3)
+
+
+def strategy_name(s: int) -> str:
+    if s < 0:
+        return "auto"
+    dec = ("rm_lds", "rm_direct", "li", "bytes")[s & 3]
+    return "%s/%s/%s" % (dec, "sv" if (s >> 2) & 1 else "bf", "zm" if (s >> 3) & 1 else "nozm")
+
+
+class ScanColumn(ctypes.Structure):
+    _fields_ = [("payload", ctypes.c_void_p), ("block_ref", ctypes.c_void_p),
+                ("block_base", ctypes.c_void_p), ("dict", ctypes.c_void_p),
+                ("dict_len", ctypes.c_uint32), ("layout", ctypes.c_uint32),
+                ("zone_min", ctypes.c_void_p), ("zone_max", ctypes.c_void_p),
+                ("n", ctypes.c_uint64)]
+
+
+class ScanPredicate(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_int64), ("hi", ctypes.c_int64)]
+
+
+class ScanResult(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_uint64), ("sum", ctypes.c_int64),
+                ("blocks_read", ctypes.c_uint64), ("blocks_total", ctypes.c_uint64),
+                ("strategy_used", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"count": int(self.count), "sum": int(self.sum), "blocks_read": int(self.blocks_read),
+                "blocks_total": int(self.blocks_total), "strategy_used": int(self.strategy_used),
+                "status": int(self.status)}
+
+
+class ScanItem(ctypes.Structure):
+    _fields_ = [("col", ScanColumn), ("enc", ctypes.c_int32), ("b", ctypes.c_uint32),
+                ("pred", ScanPredicate), ("agg", ctypes.c_uint32), ("strategy", ctypes.c_int32)]
+
+
+class ScanTune(ctypes.Structure):
+    _fields_ = [("wg_size", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
+                ("min_blocks_per_wave", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_vp, _u64, _u32, _i32, _i64, _f32 = (ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32,
+                                     ctypes.c_int64, ctypes.c_float)
+_P = ctypes.POINTER
+
+SIGNATURES = {
+    "scan_create": (_i32, [_P(_vp), ctypes.c_int, _vp]),
+    "scan_set_stream": (_i32, [_vp, _vp]),
+    "scan_destroy": (None, [_vp]),
+    "scan_last_error": (ctypes.c_char_p, [_vp]),
+    "scan_device_cus": (ctypes.c_int, [_vp]),
+    "scan_run": (_i32, [_vp, _P(ScanColumn), _i32, _u32, _P(ScanPredicate), _u32, _i32, _P(ScanResult)]),
+    "scan_run_async": (_i32, [_vp, _P(ScanItem), _vp]),
+    "scan_sync": (_i32, [_vp]),
+    "scan_set_tune": (_i32, [_vp, _i32, _u32, _i32, _P(ScanTune)]),
+    "scan_get_tune": (_i32, [_vp, _i32, _u32, _i32, _P(ScanTune)]),
+    "scan_payload_words": (_u64, [_u64, _u32]),
+    "scan_encode_for": (_i32, [_vp, _u64, _u32, _u32, _i32, _vp, _vp, _vp, _vp]),
+    "scan_encode_delta": (_i32, [_vp, _u64, _u32, _vp, _vp, _vp, _vp]),
+    "scan_encode_dict": (_i32, [_vp, _u64, _u32, _u32, _vp, _vp, _vp]),
+    "scan_beta_read": (_i32, [_vp, _vp, _u64, _i32, _i32, _i32, _vp]),
+    "scan_beta_triad": (_i32, [_vp, _vp, _vp, _vp, _f32, _u64]),
+    "scan_cache_flush": (_i32, [_vp, _vp, _u64]),
+}
+
+_lib = None
+
+
+class ScanError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+def header_functions():
+    """Every function the public header declares (name list)."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(scan_[a-z0-9_]+)\s*\(", text)) - {"scan_status"})
+
+
+def load():
+    """Load libscan.so (built by build.py).  Raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libscan.so is not built: run `python paper_2606_22423_amd/build.py` "
+                               "(or __graft_entry__.build()); there is no fallback path")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def register(name, restype, argtypes):
+    """Declare an additional entry point (used by the batch/selector/serving modules)."""
+    SIGNATURES[name] = (restype, argtypes)
+    if _lib is not None:
+        f = getattr(_lib, name)
+        f.restype = restype
+        f.argtypes = argtypes

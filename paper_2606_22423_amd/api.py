@@ -1,0 +1,226 @@
+"""Python face of the C ABI: device-resident columns and a scan context.
+
+Thin wrappers only: arguments are marshalled to the C library, which does all
+encoding, decoding, filtering and aggregation.  PyTorch provides device memory
+(tensors) and the HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import _lib
+from ._lib import (ENC_DELTA, ENC_DICT, ENC_FOR, LAYOUT_LI, LAYOUT_RM, STRAT_AUTO, ScanColumn, ScanError,
+                   ScanItem, ScanPredicate, ScanResult, ScanTune)
+
+L = 1024
+
+
+def nblocks(n: int) -> int:
+    return (n + L - 1) // L
+
+
+def _ptr(a) -> int | None:
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise ScanError(rc, what)
+
+
+# --------------------------------------------------------------- host encoders
+def host_encode_for(values, b: int, layout: int = LAYOUT_RM, ref_policy: int = 0):
+    """(payload, refs or None, zmin, zmax) as numpy arrays, by the library's host encoder."""
+    lib = _lib.load()
+    v = np.ascontiguousarray(values, dtype=np.uint32)
+    n = len(v)
+    payload = np.empty(int(lib.scan_payload_words(n, b)), dtype=np.uint32)
+    refs = np.empty(nblocks(n), dtype=np.uint32) if ref_policy == 1 else None
+    zmin = np.empty(nblocks(n), dtype=np.uint32)
+    zmax = np.empty(nblocks(n), dtype=np.uint32)
+    rc = lib.scan_encode_for(_ptr(v), n, b, layout, ref_policy, _ptr(payload), _ptr(refs), _ptr(zmin), _ptr(zmax))
+    _check(rc, "scan_encode_for rejected the values (width %d, policy %d)" % (b, ref_policy))
+    return payload, refs, zmin, zmax
+
+
+def host_encode_delta(values, b: int):
+    lib = _lib.load()
+    v = np.ascontiguousarray(values, dtype=np.int64)
+    n = len(v)
+    payload = np.empty(int(lib.scan_payload_words(n, b)), dtype=np.uint32)
+    bases = np.empty(nblocks(n), dtype=np.int64)
+    zmin = np.empty(nblocks(n), dtype=np.int64)
+    zmax = np.empty(nblocks(n), dtype=np.int64)
+    rc = lib.scan_encode_delta(_ptr(v), n, b, _ptr(payload), _ptr(bases), _ptr(zmin), _ptr(zmax))
+    _check(rc, "scan_encode_delta rejected the values (width %d)" % b)
+    return payload, bases, zmin, zmax
+
+
+def host_encode_dict(codes, b: int, dict_len: int):
+    lib = _lib.load()
+    c = np.ascontiguousarray(codes, dtype=np.uint32)
+    n = len(c)
+    payload = np.empty(int(lib.scan_payload_words(n, b)), dtype=np.uint32)
+    zmin = np.empty(nblocks(n), dtype=np.uint32)
+    zmax = np.empty(nblocks(n), dtype=np.uint32)
+    rc = lib.scan_encode_dict(_ptr(c), n, b, dict_len, _ptr(payload), _ptr(zmin), _ptr(zmax))
+    _check(rc, "scan_encode_dict rejected the codes (width %d, %d entries)" % (b, dict_len))
+    return payload, zmin, zmax
+
+
+# --------------------------------------------------------------- device columns
+@dataclass
+class Column:
+    """A column resident in device memory.  Tensors own the memory."""
+    enc: int
+    b: int
+    n: int
+    layout: int
+    payload: object
+    refs: object = None
+    bases: object = None
+    dct: object = None
+    zmin: object = None
+    zmax: object = None
+    _keep: list = field(default_factory=list)
+
+    def struct(self, zone_maps: bool = True) -> ScanColumn:
+        c = ScanColumn()
+        c.payload = _ptr(self.payload)
+        c.block_ref = _ptr(self.refs)
+        c.block_base = _ptr(self.bases)
+        c.dict = _ptr(self.dct)
+        c.dict_len = 0 if self.dct is None else int(self.dct.numel())
+        c.layout = self.layout
+        c.zone_min = _ptr(self.zmin) if zone_maps else None
+        c.zone_max = _ptr(self.zmax) if zone_maps else None
+        c.n = self.n
+        return c
+
+    @property
+    def payload_bytes(self) -> int:
+        return int(self.payload.numel()) * 4
+
+    def item(self, lo: int, hi: int, strategy: int = STRAT_AUTO, zone_maps: bool = True) -> ScanItem:
+        it = ScanItem()
+        it.col = self.struct(zone_maps)
+        it.enc = self.enc
+        it.b = self.b
+        it.pred = ScanPredicate(int(lo), int(hi))
+        it.agg = 3
+        it.strategy = strategy
+        return it
+
+
+def _to_dev(a, device):
+    import torch
+    if a is None:
+        return None
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device)
+
+
+def encode_for(values, b: int, layout: int = LAYOUT_RM, ref_policy: int = 0, device="cuda") -> Column:
+    payload, refs, zmin, zmax = host_encode_for(values, b, layout, ref_policy)
+    return Column(ENC_FOR, b, len(values), layout, _to_dev(payload, device), refs=_to_dev(refs, device),
+                  zmin=_to_dev(zmin, device), zmax=_to_dev(zmax, device))
+
+
+def encode_delta(values, b: int, device="cuda") -> Column:
+    payload, bases, zmin, zmax = host_encode_delta(values, b)
+    return Column(ENC_DELTA, b, len(values), LAYOUT_RM, _to_dev(payload, device), bases=_to_dev(bases, device),
+                  zmin=_to_dev(zmin, device), zmax=_to_dev(zmax, device))
+
+
+def encode_dict(codes, b: int, dct, device="cuda") -> Column:
+    dct = np.ascontiguousarray(dct, dtype=np.int64)
+    payload, zmin, zmax = host_encode_dict(codes, b, len(dct))
+    return Column(ENC_DICT, b, len(codes), LAYOUT_RM, _to_dev(payload, device), dct=_to_dev(dct, device),
+                  zmin=_to_dev(zmin, device), zmax=_to_dev(zmax, device))
+
+
+# --------------------------------------------------------------- context
+class Context:
+    """One scan_ctx bound to a device and to torch's current stream on it."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.lib = _lib.load()
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = ctypes.c_void_p()
+        rc = self.lib.scan_create(ctypes.byref(h), device, ctypes.c_void_p(self.stream.cuda_stream))
+        _check(rc, "scan_create(device=%d)" % device)
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.scan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def error(self) -> str:
+        return self.lib.scan_last_error(self.h).decode()
+
+    def check(self, rc: int, what: str):
+        if rc != 0:
+            raise ScanError(rc, "%s: %s" % (what, self.error()))
+
+    @property
+    def cus(self) -> int:
+        return int(self.lib.scan_device_cus(self.h))
+
+    def run(self, col: Column, lo: int, hi: int, strategy: int = STRAT_AUTO, zone_maps: bool = True) -> dict:
+        c = col.struct(zone_maps)
+        r = ScanResult()
+        pred = ScanPredicate(int(lo), int(hi))
+        rc = self.lib.scan_run(self.h, ctypes.byref(c), col.enc, col.b, ctypes.byref(pred), 3, strategy,
+                               ctypes.byref(r))
+        self.check(rc, "scan_run")
+        return r.as_dict()
+
+    def run_async(self, col: Column, lo: int, hi: int, strategy: int, out_dev, zone_maps: bool = True):
+        """Enqueue; the 40-byte result lands in out_dev (a device tensor of >= 40 bytes)."""
+        it = col.item(lo, hi, strategy, zone_maps)
+        rc = self.lib.scan_run_async(self.h, ctypes.byref(it), ctypes.c_void_p(_ptr(out_dev)))
+        self.check(rc, "scan_run_async")
+
+    def sync(self):
+        self.check(self.lib.scan_sync(self.h), "scan_sync")
+
+    def set_tune(self, enc: int, b: int, strategy: int, wg_size=0, wgs_per_cu=0, min_blocks_per_wave=0):
+        t = ScanTune(wg_size, wgs_per_cu, min_blocks_per_wave, 0)
+        self.check(self.lib.scan_set_tune(self.h, enc, b, strategy, ctypes.byref(t)), "scan_set_tune")
+
+    def get_tune(self, enc: int, b: int, strategy: int) -> tuple:
+        t = ScanTune()
+        self.check(self.lib.scan_get_tune(self.h, enc, b, strategy, ctypes.byref(t)), "scan_get_tune")
+        return (t.wg_size, t.wgs_per_cu, t.min_blocks_per_wave)
+
+    def beta_read(self, buf, nbytes: int, sink, wgs=0, wg_size=0, unroll=0):
+        self.check(self.lib.scan_beta_read(self.h, _ptr(buf), nbytes, wgs, wg_size, unroll, _ptr(sink)),
+                   "scan_beta_read")
+
+    def beta_triad(self, a, b, c, s: float):
+        self.check(self.lib.scan_beta_triad(self.h, _ptr(a), _ptr(b), _ptr(c), s, a.numel()), "scan_beta_triad")
+
+    def cache_flush(self, buf, nbytes: int):
+        self.check(self.lib.scan_cache_flush(self.h, _ptr(buf), nbytes), "scan_cache_flush")
+
+
+def result_from_tensor(t) -> dict:
+    """Decode a 40-byte scan_result held in a (host) tensor/array."""
+    raw = t.cpu().numpy().tobytes() if hasattr(t, "cpu") else bytes(t)
+    r = ScanResult.from_buffer_copy(raw[:ctypes.sizeof(ScanResult)])
+    return r.as_dict()

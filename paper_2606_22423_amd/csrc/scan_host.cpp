@@ -1,0 +1,425 @@
+// Host runtime of the C ABI: context, argument validation, strategy
+// resolution, launch geometry and the single-column scan entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+
+#include "../../include/scan.h"
+#include "launch_tables.h"
+#include "scan_internal.h"
+
+using namespace scan_dev;
+
+namespace scan_dev {
+hipError_t launch_beta_read(const void* buf, uint64_t bytes, uint32_t grid, uint32_t block, int unroll,
+                            uint64_t* sink, hipStream_t st);
+hipError_t launch_beta_triad(float* a, const float* b, const float* c, float s, uint64_t n, uint32_t grid,
+                             hipStream_t st);
+hipError_t launch_cache_flush(void* buf, uint64_t bytes, uint32_t grid, uint32_t salt, hipStream_t st);
+}  // namespace scan_dev
+
+scan_status fail(scan_ctx* ctx, scan_status st, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return st;
+}
+
+scan_status hip_fail(scan_ctx* ctx, hipError_t e, const char* what) {
+  return fail(ctx, SCAN_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+namespace {
+
+LaunchFn code_fn(int enc, int dec, int mode, int pf, uint32_t b) {
+  const bool a = b <= 16;
+  switch (dec) {
+    case DEC_RM_LDS: return a ? code_fn_rm_lds_a(enc, mode, pf, b) : code_fn_rm_lds_b(enc, mode, pf, b);
+    case DEC_RM_DIRECT: return a ? code_fn_rm_direct_a(enc, mode, pf, b) : code_fn_rm_direct_b(enc, mode, pf, b);
+    case DEC_LI: return a ? code_fn_li_a(enc, mode, pf, b) : code_fn_li_b(enc, mode, pf, b);
+    case DEC_BYTES: return code_fn_bytes(enc, mode, pf, b);
+  }
+  return nullptr;
+}
+
+LaunchFn delta_fn(int dec, int mode, uint32_t b) {
+  const bool a = b <= 16;
+  switch (dec) {
+    case DEC_RM_LDS: return a ? delta_fn_rm_lds_a(mode, b) : delta_fn_rm_lds_b(mode, b);
+    case DEC_RM_DIRECT: return a ? delta_fn_rm_direct_a(mode, b) : delta_fn_rm_direct_b(mode, b);
+  }
+  return nullptr;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ validation
+
+scan_status validate_column(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b) {
+  if (!col) return fail(ctx, SCAN_EINVAL, "column is NULL");
+  if (b < 1 || b > 32) return fail(ctx, SCAN_EINVAL, "bit width %u outside 1..32", b);
+  if (enc < SCAN_ENC_FOR || enc > SCAN_ENC_DICT) return fail(ctx, SCAN_EINVAL, "unknown encoding %d", enc);
+  if (col->layout > SCAN_LAYOUT_LI) return fail(ctx, SCAN_EINVAL, "unknown layout %u", col->layout);
+  if (col->n == 0) return SCAN_OK;
+  if (!col->payload) return fail(ctx, SCAN_EINVAL, "payload is NULL");
+  if (reinterpret_cast<uintptr_t>(col->payload) % 16u)
+    return fail(ctx, SCAN_EINVAL, "payload must be 16-byte aligned");
+  if (enc == SCAN_ENC_DELTA_FOR && !col->block_base) return fail(ctx, SCAN_EINVAL, "delta column without bases");
+  if (enc == SCAN_ENC_DICT) {
+    if (!col->dict || col->dict_len == 0) return fail(ctx, SCAN_EINVAL, "dictionary column without entries");
+    const uint64_t cap = std::min<uint64_t>(SCAN_MAX_DICT, b >= 13 ? SCAN_MAX_DICT : (1ull << b));
+    if (col->dict_len > cap) return fail(ctx, SCAN_EINVAL, "dict_len %u exceeds min(2^b, 4096)", col->dict_len);
+  }
+  if (enc != SCAN_ENC_FOR && col->layout != SCAN_LAYOUT_RM)
+    return fail(ctx, SCAN_EINVAL, "delta and dictionary columns are row-major");
+  if ((col->zone_min == nullptr) != (col->zone_max == nullptr))
+    return fail(ctx, SCAN_EINVAL, "zone_min and zone_max must both be set or both NULL");
+  return SCAN_OK;
+}
+
+int32_t heuristic_strategy(const scan_column* col, int32_t enc, uint32_t b) {
+  const int zm = col->zone_min ? 1 : 0;
+  if (enc == SCAN_ENC_FOR && col->layout == SCAN_LAYOUT_LI) return SCAN_STRATEGY(SCAN_DEC_LI, SCAN_PRED_BF, zm);
+  (void)b;
+  return SCAN_STRATEGY(SCAN_DEC_RM_DIRECT, SCAN_PRED_BF, zm);
+}
+
+scan_status check_strategy(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b, int32_t s) {
+  if (s < 0 || s > 15) return fail(ctx, SCAN_EINVAL, "strategy %d out of range", s);
+  const int dec = s & 3, zm = (s >> 3) & 1;
+  if (zm && !col->zone_min) return fail(ctx, SCAN_EUNSUPPORTED, "zone-map strategy on a column without zone maps");
+  if (dec == SCAN_DEC_LI) {
+    if (enc != SCAN_ENC_FOR || col->layout != SCAN_LAYOUT_LI)
+      return fail(ctx, SCAN_EUNSUPPORTED, "lane-interleaved decoder needs a FOR column in the LI layout");
+  } else {
+    if (col->layout != SCAN_LAYOUT_RM) return fail(ctx, SCAN_EUNSUPPORTED, "decoder %d needs the row-major layout", dec);
+    if (dec == SCAN_DEC_BYTES && (enc != SCAN_ENC_FOR || (b != 8 && b != 16 && b != 32)))
+      return fail(ctx, SCAN_EUNSUPPORTED, "byte-aligned decoder needs a FOR column with b in {8,16,32}");
+  }
+  return SCAN_OK;
+}
+
+// ------------------------------------------------------------ tuning
+
+scan_tune default_tune(int32_t enc, uint32_t b, int32_t s) {
+  (void)enc;
+  (void)b;
+  scan_tune t;
+  (void)s;
+  t.wg_size = 256;
+  t.wgs_per_cu = 0;           // 0: as many as fit (occupancy)
+  t.min_blocks_per_wave = 8;  // small columns launch fewer work-groups
+  t.reserved = 0;
+  return t;
+}
+
+scan_tune effective_tune(scan_ctx* ctx, int32_t enc, uint32_t b, int32_t s) {
+  scan_tune t = default_tune(enc, b, s);
+  auto it = ctx->tunes.find(std::make_tuple(enc, b, s));
+  if (it != ctx->tunes.end()) {
+    if (it->second.wg_size) t.wg_size = it->second.wg_size;
+    if (it->second.wgs_per_cu) t.wgs_per_cu = it->second.wgs_per_cu;
+    if (it->second.min_blocks_per_wave) t.min_blocks_per_wave = it->second.min_blocks_per_wave;
+  }
+  return t;
+}
+
+// ------------------------------------------------------------ launch
+
+// Resident work-groups per compute unit of one kernel instance (cached).
+scan_status occupancy(scan_ctx* ctx, LaunchFn fn, uint32_t block, int* occ) {
+  auto key = std::make_pair(reinterpret_cast<const void*>(fn), block);
+  auto it = ctx->occupancy.find(key);
+  if (it != ctx->occupancy.end()) {
+    *occ = it->second;
+    return SCAN_OK;
+  }
+  Params dummy;
+  std::memset(&dummy, 0, sizeof dummy);
+  hipError_t e = fn(dummy, 0, block, ctx->stream, occ);
+  if (e != hipSuccess) return hip_fail(ctx, e, "occupancy query");
+  if (*occ < 1) *occ = 1;
+  ctx->occupancy[key] = *occ;
+  return SCAN_OK;
+}
+
+// Fills p and the launch geometry for one (column, strategy); returns the
+// launcher or nullptr with ctx->err set.
+scan_status prepare_scan(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b, const scan_predicate* pred,
+                         int32_t s, Result* out_dev, Params& p, LaunchFn& fn, uint32_t& grid, uint32_t& block,
+                         bool& trivially_empty) {
+  const int dec = s & 3, mode = (s >> 2) & 1, zm = (s >> 3) & 1;
+  std::memset(&p, 0, sizeof p);
+  p.payload = col->payload;
+  p.refs = col->block_ref;
+  p.bases = col->block_base;
+  p.dict = col->dict;
+  p.dict_len = col->dict_len;
+  p.zmin = col->zone_min;
+  p.zmax = col->zone_max;
+  p.n = col->n;
+  p.nb = (col->n + SCAN_BLOCK_VALUES - 1) / SCAN_BLOCK_VALUES;
+  p.lo = pred->lo;
+  p.hi = pred->hi;
+  p.use_zm = (uint32_t)zm;
+  p.tail = (uint32_t)(col->n - (p.nb ? (p.nb - 1) : 0) * SCAN_BLOCK_VALUES);
+  p.strategy = s;
+  p.partials = ctx->partials;
+  p.ticket = ctx->ticket;
+  p.out = out_dev;
+  trivially_empty = (col->n == 0 || pred->lo >= pred->hi);
+  int pf = PF_RANGE;
+  if (enc == SCAN_ENC_FOR) {
+    // Clamp the predicate to the u32 value domain of FOR columns.
+    const int64_t lo = std::max<int64_t>(pred->lo, 0);
+    const int64_t hi = std::min<int64_t>(pred->hi, (int64_t)1 << 32);
+    if (lo >= hi) trivially_empty = true;
+    else {
+      p.lo32 = (uint32_t)lo;
+      p.hi32m1 = (uint32_t)(hi - 1);
+      pf = col->block_ref ? PF_REFS : (p.lo32 == 0 ? PF_LO0 : PF_RANGE);
+    }
+  }
+  if (trivially_empty) return SCAN_OK;
+  fn = enc == SCAN_ENC_DELTA_FOR ? delta_fn(dec, mode, b) : code_fn(enc, dec, mode, pf, b);
+  if (!fn) return fail(ctx, SCAN_EUNSUPPORTED, "no kernel for enc %d b %u strategy %d", enc, b, s);
+  const scan_tune t = effective_tune(ctx, enc, b, s);
+  block = (uint32_t)t.wg_size;
+  if (block < 64 || block > 256 || block % 64) return fail(ctx, SCAN_EINVAL, "wg_size %u invalid (64..256)", block);
+  int occ = 0;
+  scan_status st = occupancy(ctx, fn, block, &occ);
+  if (st != SCAN_OK) return st;
+  const uint64_t per_cu = t.wgs_per_cu > 0 ? std::min<uint64_t>((uint64_t)t.wgs_per_cu, (uint64_t)occ) : (uint64_t)occ;
+  const uint64_t waves = block / 64u;
+  const uint64_t minb = (uint64_t)std::max(1, t.min_blocks_per_wave);
+  const uint64_t need = (p.nb + minb * waves - 1) / (minb * waves);
+  const uint64_t cap = std::min<uint64_t>((uint64_t)ctx->cus * std::max<uint64_t>(1, per_cu), ctx->max_grid);
+  grid = (uint32_t)std::max<uint64_t>(1, std::min(need, cap));
+  return SCAN_OK;
+}
+
+scan_status enqueue_scan(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b, const scan_predicate* pred,
+                         int32_t strategy, Result* out_dev, Result* host_empty_out) {
+  Params p;
+  LaunchFn fn = nullptr;
+  uint32_t grid = 0, block = 0;
+  bool empty = false;
+  scan_status st = prepare_scan(ctx, col, enc, b, pred, strategy, out_dev, p, fn, grid, block, empty);
+  if (st != SCAN_OK) return st;
+  if (empty) {
+    Result r{};
+    r.blocks_total = p.nb;
+    r.blocks_read = (pred->lo < pred->hi && !((strategy >> 3) & 1)) ? p.nb : 0;
+    r.strategy_used = strategy;
+    if (host_empty_out) {
+      *host_empty_out = r;
+      return SCAN_OK;
+    }
+    hipError_t e = hipMemcpyAsync(out_dev, &r, sizeof r, hipMemcpyHostToDevice, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpyAsync");
+    e = hipStreamSynchronize(ctx->stream);  // r lives on this host stack frame
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+    return SCAN_OK;
+  }
+  hipError_t e = fn(p, grid, block, ctx->stream, nullptr);
+  if (e != hipSuccess) return hip_fail(ctx, e, "scan kernel launch");
+  return SCAN_OK;
+}
+
+scan_status resolve_strategy(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b,
+                             const scan_predicate* pred, int32_t strategy, bool allow_sync, int32_t* out) {
+  if (strategy == SCAN_STRAT_AUTO) {
+    if (allow_sync && ctx->selector_ready) {
+      scan_status st = selector_pick(ctx, col, enc, b, pred, out);
+      if (st == SCAN_OK) return SCAN_OK;
+    }
+    *out = heuristic_strategy(col, enc, b);
+    return SCAN_OK;
+  }
+  *out = strategy;
+  return SCAN_OK;
+}
+
+// ------------------------------------------------------------ C ABI
+
+extern "C" {
+
+scan_status scan_create(scan_ctx** out, int device, void* hip_stream) {
+  if (!out) return SCAN_EINVAL;
+  *out = nullptr;
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) return SCAN_EDEVICE;
+  scan_ctx* ctx = new scan_ctx();
+  ctx->device = device;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) {
+    delete ctx;
+    return SCAN_EDEVICE;
+  }
+  ctx->cus = prop.multiProcessorCount;
+  ctx->max_grid = 16384;
+  if (hipMalloc(&ctx->partials, sizeof(Partial) * ctx->max_grid) != hipSuccess ||
+      hipMalloc(&ctx->ticket, 256) != hipSuccess || hipMalloc(&ctx->out_dev, sizeof(Result) * 2) != hipSuccess ||
+      hipHostMalloc(&ctx->out_host, sizeof(Result) * 2, hipHostMallocDefault) != hipSuccess) {
+    scan_destroy(ctx);
+    return SCAN_ENOMEM;
+  }
+  if (hipMemset(ctx->ticket, 0, 256) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    scan_destroy(ctx);
+    return SCAN_EDEVICE;
+  }
+  *out = ctx;
+  return SCAN_OK;
+}
+
+scan_status scan_set_stream(scan_ctx* ctx, void* hip_stream) {
+  if (!ctx) return SCAN_EINVAL;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return SCAN_OK;
+}
+
+void scan_destroy(scan_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  destroy_batches(ctx);
+  destroy_selector(ctx);
+  if (ctx->partials) (void)hipFree(ctx->partials);
+  if (ctx->ticket) (void)hipFree(ctx->ticket);
+  if (ctx->out_dev) (void)hipFree(ctx->out_dev);
+  if (ctx->out_host) (void)hipHostFree(ctx->out_host);
+  delete ctx;
+}
+
+const char* scan_last_error(const scan_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int scan_device_cus(const scan_ctx* ctx) { return ctx ? ctx->cus : 0; }
+
+scan_status scan_run(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b, const scan_predicate* pred,
+                     uint32_t agg, int32_t strategy, scan_result* out) {
+  if (!ctx) return SCAN_EINVAL;
+  if (!pred || !out) return fail(ctx, SCAN_EINVAL, "predicate and result must not be NULL");
+  (void)agg;
+  scan_status st = validate_column(ctx, col, enc, b);
+  if (st != SCAN_OK) return st;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  int32_t s = 0;
+  st = resolve_strategy(ctx, col, enc, b, pred, strategy, true, &s);
+  if (st != SCAN_OK) return st;
+  st = check_strategy(ctx, col, enc, b, s);
+  if (st != SCAN_OK) return st;
+  Result host_r{};
+  bool host_done = false;
+  {
+    Params p;
+    LaunchFn fn = nullptr;
+    uint32_t grid = 0, block = 0;
+    bool empty = false;
+    st = prepare_scan(ctx, col, enc, b, pred, s, ctx->out_dev, p, fn, grid, block, empty);
+    if (st != SCAN_OK) return st;
+    if (empty) {
+      host_r.blocks_total = p.nb;
+      host_r.blocks_read = (pred->lo < pred->hi && !((s >> 3) & 1)) ? p.nb : 0;
+      host_r.strategy_used = s;
+      host_done = true;
+    } else {
+      e = fn(p, grid, block, ctx->stream, nullptr);
+      if (e != hipSuccess) return hip_fail(ctx, e, "scan kernel launch");
+    }
+  }
+  if (!host_done) {
+    e = hipMemcpyAsync(ctx->out_host, ctx->out_dev, sizeof(Result), hipMemcpyDeviceToHost, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpyAsync");
+    e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+    host_r = *ctx->out_host;
+  }
+  static_assert(sizeof(Result) == sizeof(scan_result), "result layout");
+  std::memcpy(out, &host_r, sizeof host_r);
+  return SCAN_OK;
+}
+
+scan_status scan_run_async(scan_ctx* ctx, const scan_item* item, scan_result* out_dev) {
+  if (!ctx) return SCAN_EINVAL;
+  if (!item || !out_dev) return fail(ctx, SCAN_EINVAL, "item and out_dev must not be NULL");
+  scan_status st = validate_column(ctx, &item->col, item->enc, item->b);
+  if (st != SCAN_OK) return st;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  int32_t s = 0;
+  st = resolve_strategy(ctx, &item->col, item->enc, item->b, &item->pred, item->strategy, false, &s);
+  if (st != SCAN_OK) return st;
+  st = check_strategy(ctx, &item->col, item->enc, item->b, s);
+  if (st != SCAN_OK) return st;
+  return enqueue_scan(ctx, &item->col, item->enc, item->b, &item->pred, s, reinterpret_cast<Result*>(out_dev),
+                      nullptr);
+}
+
+scan_status scan_sync(scan_ctx* ctx) {
+  if (!ctx) return SCAN_EINVAL;
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  return e == hipSuccess ? SCAN_OK : hip_fail(ctx, e, "hipStreamSynchronize");
+}
+
+scan_status scan_set_tune(scan_ctx* ctx, int32_t enc, uint32_t b, int32_t strategy, const scan_tune* t) {
+  if (!ctx) return SCAN_EINVAL;
+  if (!t) return fail(ctx, SCAN_EINVAL, "tune is NULL");
+  if (t->wg_size && (t->wg_size < 64 || t->wg_size > 1024 || t->wg_size % 64))
+    return fail(ctx, SCAN_EINVAL, "wg_size must be a multiple of 64 in 64..1024");
+  if (t->wgs_per_cu < 0 || t->wgs_per_cu > 64) return fail(ctx, SCAN_EINVAL, "wgs_per_cu must be in 0..64");
+  if (t->wg_size > 256) return fail(ctx, SCAN_EINVAL, "wg_size above 256 is not supported");
+  if (t->min_blocks_per_wave < 0 || t->min_blocks_per_wave > 1 << 20)
+    return fail(ctx, SCAN_EINVAL, "min_blocks_per_wave must be in 0..2^20");
+  ctx->tunes[std::make_tuple(enc, b, strategy)] = *t;
+  return SCAN_OK;
+}
+
+scan_status scan_get_tune(scan_ctx* ctx, int32_t enc, uint32_t b, int32_t strategy, scan_tune* t) {
+  if (!ctx) return SCAN_EINVAL;
+  if (!t) return fail(ctx, SCAN_EINVAL, "tune is NULL");
+  *t = effective_tune(ctx, enc, b, strategy);
+  return SCAN_OK;
+}
+
+scan_status scan_beta_read(scan_ctx* ctx, const void* buf, uint64_t bytes, int32_t wgs, int32_t wg_size,
+                           int32_t unroll, uint64_t* sink) {
+  if (!ctx) return SCAN_EINVAL;
+  if (!buf || !sink || bytes % 16u) return fail(ctx, SCAN_EINVAL, "beta_read needs a buffer, a sink and bytes % 16 == 0");
+  if (wg_size == 0) wg_size = 256;
+  if (wgs == 0) wgs = ctx->cus * 8;
+  if (unroll == 0) unroll = 4;
+  if (wg_size < 64 || wg_size > 1024 || wg_size % 64 || wgs < 1)
+    return fail(ctx, SCAN_EINVAL, "bad beta_read geometry");
+  hipError_t e = launch_beta_read(buf, bytes, (uint32_t)wgs, (uint32_t)wg_size, unroll, sink, ctx->stream);
+  return e == hipSuccess ? SCAN_OK : hip_fail(ctx, e, "beta_read launch");
+}
+
+scan_status scan_beta_triad(scan_ctx* ctx, float* a, const float* b, const float* c, float s, uint64_t n) {
+  if (!ctx) return SCAN_EINVAL;
+  if (!a || !b || !c || n % 4u) return fail(ctx, SCAN_EINVAL, "triad needs three buffers and n % 4 == 0");
+  hipError_t e = launch_beta_triad(a, b, c, s, n, (uint32_t)ctx->cus * 8u, ctx->stream);
+  return e == hipSuccess ? SCAN_OK : hip_fail(ctx, e, "triad launch");
+}
+
+scan_status scan_cache_flush(scan_ctx* ctx, void* buf, uint64_t bytes) {
+  if (!ctx) return SCAN_EINVAL;
+  if (!buf || bytes % 16u) return fail(ctx, SCAN_EINVAL, "flush needs a buffer and bytes % 16 == 0");
+  hipError_t e = launch_cache_flush(buf, bytes, (uint32_t)ctx->cus * 8u, ++ctx->flush_salt, ctx->stream);
+  return e == hipSuccess ? SCAN_OK : hip_fail(ctx, e, "flush launch");
+}
+
+}  // extern "C"

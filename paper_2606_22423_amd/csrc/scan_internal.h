@@ -1,0 +1,48 @@
+// Host-side internals shared by the runtime's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <tuple>
+
+#include "../../include/scan.h"
+#include "device_common.h"
+
+struct SelectorState;
+struct BatchPlan;
+
+struct scan_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int cus = 0;
+  uint32_t max_grid = 0;
+  scan_dev::Partial* partials = nullptr;  // per-work-group partial results (device)
+  uint32_t* ticket = nullptr;             // last-work-group counter (device, zero between launches)
+  scan_dev::Result* out_dev = nullptr;    // result slot of synchronous scans (device)
+  scan_dev::Result* out_host = nullptr;   // pinned staging for it
+  uint32_t flush_salt = 0;
+  std::string err;
+  std::map<std::tuple<int32_t, uint32_t, int32_t>, scan_tune> tunes;
+  std::map<std::pair<const void*, uint32_t>, int> occupancy;
+  bool selector_ready = false;
+  SelectorState* selector = nullptr;
+  std::map<uint64_t, BatchPlan*> batches;
+  uint64_t next_batch = 1;
+};
+
+scan_status fail(scan_ctx* ctx, scan_status st, const char* fmt, ...);
+scan_status hip_fail(scan_ctx* ctx, hipError_t e, const char* what);
+scan_status validate_column(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b);
+scan_status check_strategy(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b, int32_t s);
+int32_t heuristic_strategy(const scan_column* col, int32_t enc, uint32_t b);
+scan_tune effective_tune(scan_ctx* ctx, int32_t enc, uint32_t b, int32_t s);
+
+// Learned selector (selector.cpp).
+scan_status selector_pick(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b,
+                          const scan_predicate* pred, int32_t* out);
+void destroy_selector(scan_ctx* ctx);
+
+// Batched scans (batch.cpp).
+void destroy_batches(scan_ctx* ctx);

@@ -1,0 +1,956 @@
+// Fused decode + predicate + aggregate kernels (gfx950, wave64).
+//
+// One launch scans one column.  The grid is persistent (sized to the resident
+// capacity of the device) and every wavefront owns one contiguous range of
+// 1024-value blocks, so the static split is balanced to one block.  A
+// wavefront walks its range in windows of 64 blocks: one ballot over the
+// window's zone maps gives the survivors (all blocks with zone maps off),
+// which are compacted into a per-wavefront LDS list (mbcnt positions).
+//
+// Survivors are decoded in steps of about 4 KiB of payload per wavefront, and
+// the next step's words are loaded into registers while the current step is
+// decoded (software pipelining), so every wavefront keeps a load in flight:
+//  * RM-direct / lane-interleaved: two blocks per wavefront pass, one per
+//    half-wavefront; lane l holds 32 codes in B registers and extracts them
+//    with compile-time shifts;
+//  * RM-LDS: the wavefront stages whole blocks in LDS with coalesced loads and
+//    lane l extracts values j = l + 64 t with a funnel shift;
+//  * byte-aligned (B = 8, 16, 32): plain u8/u16/u32 vector loads.
+// Per value: extract, one unsigned compare in code space
+// ((c - lo_c) <= w - 1; just c <= w - 1 when lo_c = 0), ballot of the compare
+// (the compare's lane mask), scalar popcount for COUNT, and the selected value
+// added under the mask (branch-free) or compacted into an LDS selection-vector
+// ring that is drained 64 entries at a time (compaction).
+// The partial last block of a column is excluded from the pipelined loop and
+// decoded once, with a per-value validity test, by the wavefront that owns it.
+#pragma once
+
+#include <type_traits>
+
+#include "device_common.h"
+
+namespace scan_dev {
+
+// Predicate forms of the FOR/DICT kernels.
+enum PredForm {
+  PF_REFS = 0,   // FOR with per-block references: code range per block
+  PF_RANGE = 1,  // one code range for the whole column: (c - lo) <= w - 1
+  PF_LO0 = 2     // one code range starting at 0: c <= w - 1
+};
+
+template <int B>
+struct Geo {
+  static constexpr int kPairs = B >= 16 ? 1 : 16 / B;       // block pairs per step (half-wavefront decoders)
+  static constexpr int kLdsBlocks = B >= 32 ? 1 : 32 / B;   // blocks staged per step (RM-LDS)
+  static constexpr int kStageWords = 32 * B + 4;            // one staged block plus an over-read pad
+  static constexpr int kStageLoads = (32 * B + 63) / 64;    // words per lane to stage one block
+  static constexpr int kByteBlocks = B >= 32 ? 1 : 32 / B;  // blocks per step (byte-aligned, B = 8/16/32)
+};
+
+// Empty register constraint: pins `x` to VGPRs at this point so the compiler
+// cannot defer and re-associate the per-value adds (which would keep every
+// value's compare mask alive and spill them).  Emits no instruction.
+template <typename T>
+__device__ __forceinline__ void pin(T& x) {
+  if constexpr (sizeof(T) == 4) {
+    asm volatile("" : "+v"(x));
+  } else {
+    uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    asm volatile("" : "+v"(lo), "+v"(hi));
+    x = ((T)hi << 32) | lo;
+  }
+}
+
+// ------------------------------------------------------------------ loads
+
+template <int B>
+__device__ __forceinline__ void load_slice(const uint32_t* __restrict__ src, uint32_t (&w)[B]) {
+  if constexpr (B % 4 == 0) {
+#pragma unroll
+    for (int i = 0; i < B / 4; ++i) {
+      uint4 v = reinterpret_cast<const uint4*>(src)[i];
+      w[4 * i] = v.x;
+      w[4 * i + 1] = v.y;
+      w[4 * i + 2] = v.z;
+      w[4 * i + 3] = v.w;
+    }
+  } else if constexpr (B % 2 == 0) {
+#pragma unroll
+    for (int i = 0; i < B / 2; ++i) {
+      uint2 v = reinterpret_cast<const uint2*>(src)[i];
+      w[2 * i] = v.x;
+      w[2 * i + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < B; ++i) w[i] = src[i];
+  }
+}
+
+// Code t of a run of codes held in registers: bits [t*B, t*B + B).  Every
+// shift is a compile-time constant (one v_bfe_u32, or alignbit + and).
+template <int B, int N>
+__device__ __forceinline__ uint32_t run_code(const uint32_t (&y)[N], int t) {
+  const int bit = t * B;
+  const int wi = bit >> 5, sh = bit & 31;
+  if (B == 32) return y[t];
+  if (sh + B <= 32) return (y[wi] >> sh) & width_mask<B>();
+  return funnel(y[wi + 1], y[wi], sh) & width_mask<B>();
+}
+
+// ------------------------------------------------------ per-wave state
+
+template <typename EntryT>
+struct WaveState {
+  uint64_t count = 0;   // uniform
+  uint64_t blocks = 0;  // uniform
+  uint64_t refsum = 0;  // uniform: sum over blocks of (matches in block) * (reference or base)
+  uint64_t lsum = 0;    // per lane
+  uint32_t head = 0, tail = 0;  // selection-vector ring counters (uniform)
+  EntryT* ring = nullptr;
+};
+
+// Value of a selected code: FOR adds the code (references are added through
+// counts); DICT adds the dictionary entry staged in LDS (index clamped).
+template <int ENC>
+__device__ __forceinline__ uint64_t code_value(uint32_t c, const int64_t* dict_lds, uint32_t dict_last) {
+  if constexpr (ENC == ENC_DICT) return (uint64_t)dict_lds[c < dict_last ? c : dict_last];
+  else return (uint64_t)c;
+}
+
+// Selection-vector push: compact the selected lanes' entries into the ring at
+// mbcnt positions; when 64 or more are pending, every lane consumes one.
+template <int ENC, typename EntryT>
+__device__ __forceinline__ void sv_push(WaveState<EntryT>& s, EntryT e, bool pass, uint64_t m, uint32_t lane,
+                                        const int64_t* dict_lds, uint32_t dict_last) {
+  if (m) {
+    const uint32_t pos = mbcnt(m);
+    if (pass) s.ring[(s.head + pos) & (kRingEntries - 1)] = e;
+    s.head += (uint32_t)__builtin_popcountll(m);
+    if (s.head - s.tail >= 64u) {
+      __builtin_amdgcn_wave_barrier();
+      const EntryT x = s.ring[(s.tail + lane) & (kRingEntries - 1)];
+      if constexpr (ENC == ENC_DICT) s.lsum += code_value<ENC>((uint32_t)x, dict_lds, dict_last);
+      else s.lsum += (uint64_t)x;
+      s.tail += 64u;
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+}
+
+template <int ENC, typename EntryT>
+__device__ __forceinline__ void sv_drain_rest(WaveState<EntryT>& s, uint32_t lane, const int64_t* dict_lds,
+                                              uint32_t dict_last) {
+  const uint32_t rem = s.head - s.tail;
+  __builtin_amdgcn_wave_barrier();
+  if (lane < rem) {
+    const EntryT x = s.ring[(s.tail + lane) & (kRingEntries - 1)];
+    if constexpr (ENC == ENC_DICT) s.lsum += code_value<ENC>((uint32_t)x, dict_lds, dict_last);
+    else s.lsum += (uint64_t)x;
+  }
+  s.tail = s.head;
+}
+
+// Per-lane partial sum of one decode pass: u32 is exact for FOR codes of
+// B <= 26 bits (a lane adds at most 64 of them before folding).
+template <int B, int ENC>
+using PartT = typename std::conditional<(ENC == ENC_FOR && B <= 26), uint32_t, uint64_t>::type;
+
+// Code-space predicate of one block.
+struct CodeRange {
+  uint32_t loc, wm1;
+  bool nonempty;
+};
+
+template <int B, int ENC, int PF>
+__device__ __forceinline__ CodeRange block_range(const Params& p, uint32_t ref, uint32_t clo, uint32_t chi) {
+  CodeRange r;
+  if constexpr (ENC == ENC_DICT) {
+    r.nonempty = clo < chi;
+    r.loc = clo;
+    r.wm1 = chi - clo - 1u;
+  } else {
+    r.nonempty = for_code_range<B>(PF == PF_REFS ? ref : 0u, p.lo32, p.hi32m1, r.loc, r.wm1);
+  }
+  return r;
+}
+
+// ------------------------------------------------------ block windows
+
+// Survivors among blocks k0 .. k0+cnt-1 (cnt <= 64) of a FOR/DICT column,
+// without block `excl` (the partial last block, decoded separately).
+template <int ENC>
+__device__ __forceinline__ uint64_t window_live(const Params& p, uint64_t k0, uint32_t cnt, uint32_t clo, uint32_t chi,
+                                                uint64_t excl) {
+  const uint32_t lane = lane_id();
+  bool keep = lane < cnt && (k0 + lane) != excl;
+  if (p.use_zm && keep) {
+    const uint32_t mn = static_cast<const uint32_t*>(p.zmin)[k0 + lane];
+    const uint32_t mx = static_cast<const uint32_t*>(p.zmax)[k0 + lane];
+    if constexpr (ENC == ENC_DICT) keep = !(mx < clo || mn >= chi);
+    else keep = !(mx < p.lo32 || mn > p.hi32m1);
+  }
+  return ballot(keep);
+}
+
+__device__ __forceinline__ uint64_t window_live_i64(const Params& p, uint64_t k0, uint32_t cnt, uint64_t excl) {
+  const uint32_t lane = lane_id();
+  bool keep = lane < cnt && (k0 + lane) != excl;
+  if (p.use_zm && keep) {
+    const int64_t mn = static_cast<const int64_t*>(p.zmin)[k0 + lane];
+    const int64_t mx = static_cast<const int64_t*>(p.zmax)[k0 + lane];
+    keep = !(mx < p.lo || mn >= p.hi);
+  }
+  return ballot(keep);
+}
+
+// Zone-map test of one block (uniform), for the separately decoded last block.
+template <int ENC>
+__device__ __forceinline__ bool block_survives(const Params& p, uint64_t k, uint32_t clo, uint32_t chi) {
+  if (!p.use_zm) return true;
+  if constexpr (ENC == ENC_DELTA) {
+    const int64_t mn = static_cast<const int64_t*>(p.zmin)[k], mx = static_cast<const int64_t*>(p.zmax)[k];
+    return !(mx < p.lo || mn >= p.hi);
+  } else {
+    const uint32_t mn = static_cast<const uint32_t*>(p.zmin)[k], mx = static_cast<const uint32_t*>(p.zmax)[k];
+    if constexpr (ENC == ENC_DICT) return !(mx < clo || mn >= chi);
+    else return !(mx < p.lo32 || mn > p.hi32m1);
+  }
+}
+
+// The wavefront's contiguous share [a, e) of the column's blocks.
+__device__ __forceinline__ void wave_range(uint64_t nb, uint64_t gw, uint64_t tw, uint64_t& a, uint64_t& e) {
+  a = nb * gw / tw;
+  e = nb * (gw + 1) / tw;
+}
+
+// Walks the wavefront's range window by window and hands out the surviving
+// blocks in steps of up to NPER per half-wavefront (lanes 0-31 take list
+// entries pos, pos+2, ...; lanes 32-63 take pos+1, pos+3, ...).
+template <int NPER, typename LiveFn>
+struct PairCursor {
+  uint64_t next_k, end_k, k0;
+  uint32_t nsurv, pos;
+  uint32_t* list;  // per-wavefront LDS, 64 entries
+  uint64_t safe;   // a block this lane was last handed (valid once a fetch succeeded)
+
+  __device__ __forceinline__ bool fetch(uint64_t (&kb)[NPER], uint32_t& actbits, uint64_t& blocks, LiveFn& live_fn,
+                                        uint32_t lane) {
+    while (pos >= nsurv) {
+      if (next_k >= end_k) {
+        // Exhausted: hand out the last valid block again so the caller's
+        // unconditional prefetch stays in bounds (its result is not decoded).
+#pragma unroll
+        for (int q = 0; q < NPER; ++q) kb[q] = safe;
+        actbits = 0;
+        return false;
+      }
+      const uint64_t left = end_k - next_k;
+      const uint32_t cnt = left < 64 ? (uint32_t)left : 64u;
+      k0 = next_k;
+      next_k += cnt;
+      const uint64_t live = live_fn(k0, cnt);
+      blocks += (uint64_t)__builtin_popcountll(live);
+      __builtin_amdgcn_wave_barrier();
+      if ((live >> lane) & 1ull) list[mbcnt(live)] = lane;
+      __builtin_amdgcn_wave_barrier();
+      nsurv = (uint32_t)__builtin_popcountll(live);
+      pos = 0;
+    }
+    const uint32_t h = lane >> 5;
+    actbits = 0;
+#pragma unroll
+    for (int q = 0; q < NPER; ++q) {
+      const uint32_t idx = pos + 2u * q + h;
+      const bool a = idx < nsurv;
+      kb[q] = k0 + list[a ? idx : pos];
+      actbits |= (a ? 1u : 0u) << q;
+    }
+    pos += 2u * NPER;
+    safe = kb[0];
+    return true;
+  }
+};
+
+// Same walk for decoders that take one block per wavefront pass: a step is a
+// uniform mask of up to NB window bits.
+template <int NB, typename LiveFn>
+struct BlockCursor {
+  uint64_t next_k, end_k, k0, live;
+
+  __device__ __forceinline__ bool fetch(uint64_t& sk0, uint64_t& smask, uint64_t& blocks, LiveFn& live_fn) {
+    while (live == 0) {
+      if (next_k >= end_k) return false;
+      const uint64_t left = end_k - next_k;
+      const uint32_t cnt = left < 64 ? (uint32_t)left : 64u;
+      k0 = next_k;
+      next_k += cnt;
+      live = live_fn(k0, cnt);
+      blocks += (uint64_t)__builtin_popcountll(live);
+    }
+    uint64_t m = 0, l = live;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const uint64_t bit = l & (~l + 1ull);
+      m |= bit;
+      l ^= bit;
+    }
+    live = l;
+    sk0 = k0;
+    smask = m;
+    return true;
+  }
+};
+
+// -------------------------------------------- half-wavefront pair decoding
+
+// Decode the 32 codes each lane holds for one block (lanes 0-31: one block,
+// lanes 32-63: another).  `act`: this lane's block is real and may match.
+template <int B, int DEC, int MODE, int ENC, int PF, bool TAIL>
+__device__ __forceinline__ void decode_pair(const Params& p, WaveState<uint32_t>& s, uint32_t lane,
+                                            const uint32_t (&w)[B], uint64_t kb, bool act, const int64_t* dict_lds,
+                                            uint32_t dict_last, uint32_t clo, uint32_t chi) {
+  const uint32_t l = lane & 31u;
+  uint32_t ref = 0;
+  if constexpr (PF == PF_REFS) ref = p.refs[kb];
+  const CodeRange cr = block_range<B, ENC, PF>(p, ref, clo, chi);
+  act = act && cr.nonempty;
+  const uint64_t act_m = ballot(act);
+  if (act_m == 0) return;
+  const uint32_t limit = (TAIL && kb == p.nb - 1) ? p.tail : kBlockValues;
+  uint32_t cA = 0, cB = 0, call = 0;
+  PartT<B, ENC> part = 0;
+#pragma unroll
+  for (int t = 0; t < 32; ++t) {
+    const uint32_t c = run_code<B, B>(w, t);
+    const bool hit = (PF == PF_LO0) ? (c <= cr.wm1) : ((c - cr.loc) <= cr.wm1);
+    uint64_t m = ballot(hit) & act_m;
+    bool valid = true;
+    if (TAIL) {
+      const uint32_t j = (DEC == DEC_RM_DIRECT) ? (32u * l + t) : (32u * t + l);
+      valid = j < limit;
+      m &= ballot(valid);
+    }
+    if constexpr (PF == PF_REFS) {
+      cA += (uint32_t)__builtin_popcount((uint32_t)m);
+      cB += (uint32_t)__builtin_popcount((uint32_t)(m >> 32));
+    } else {
+      call += (uint32_t)__builtin_popcountll(m);
+    }
+    if constexpr (MODE == MODE_BF) {
+      const uint64_t v = code_value<ENC>(c, dict_lds, dict_last);
+      part += (hit && (!TAIL || valid)) ? (PartT<B, ENC>)v : (PartT<B, ENC>)0;
+      pin(part);
+    } else {
+      sv_push<ENC, uint32_t>(s, c, hit && act && valid, m, lane, dict_lds, dict_last);
+    }
+  }
+  if constexpr (PF == PF_REFS) {
+    s.count += (uint64_t)cA + cB;
+    s.refsum += (uint64_t)cA * readlane(ref, 0) + (uint64_t)cB * readlane(ref, 32);
+  } else {
+    s.count += call;
+  }
+  if constexpr (MODE == MODE_BF) s.lsum += act ? (uint64_t)part : 0ull;
+}
+
+template <int B, int DEC>
+__device__ __forceinline__ void load_pair_words(const Params& p, uint64_t kb, uint32_t l, uint32_t (&w)[B]) {
+  const uint32_t* __restrict__ blk = p.payload + kb * (32u * B);
+  if constexpr (DEC == DEC_RM_DIRECT) {
+    load_slice<B>(blk + l * B, w);
+  } else {
+#pragma unroll
+    for (int r = 0; r < B; ++r) w[r] = blk[32 * r + l];
+  }
+}
+
+template <int B, int DEC, int MODE, int ENC, int PF>
+__device__ __forceinline__ void run_pairs(const Params& p, WaveState<uint32_t>& s, uint32_t lane, uint32_t* list,
+                                          uint64_t ka, uint64_t ke, uint64_t excl, const int64_t* dict_lds,
+                                          uint32_t dict_last, uint32_t clo, uint32_t chi) {
+  constexpr int P = Geo<B>::kPairs;
+  const uint32_t l = lane & 31u;
+  auto live_fn = [&](uint64_t k0, uint32_t cnt) { return window_live<ENC>(p, k0, cnt, clo, chi, excl); };
+  PairCursor<P, decltype(live_fn)> cur{ka, ke, 0, 0, 0, list, ka};
+  // Two register buffers used alternately: the next step's loads are always
+  // issued (a harmless reload of a valid block when there is no next step)
+  // before the current step is decoded, so exactly one step is in flight.
+  uint64_t k0b[P], k1b[P];
+  uint32_t a0 = 0, a1 = 0;
+  uint32_t w0[P][B], w1[P][B];
+  auto load = [&](const uint64_t (&kb)[P], uint32_t (&w)[P][B]) {
+#pragma unroll
+    for (int q = 0; q < P; ++q) load_pair_words<B, DEC>(p, kb[q], l, w[q]);
+  };
+  auto decode = [&](const uint32_t (&w)[P][B], const uint64_t (&kb)[P], uint32_t ab) {
+#pragma unroll
+    for (int q = 0; q < P; ++q)
+      decode_pair<B, DEC, MODE, ENC, PF, false>(p, s, lane, w[q], kb[q], (ab >> q) & 1u, dict_lds, dict_last, clo,
+                                                chi);
+  };
+  if (!cur.fetch(k0b, a0, s.blocks, live_fn, lane)) return;
+  load(k0b, w0);
+  while (true) {
+    const bool more1 = cur.fetch(k1b, a1, s.blocks, live_fn, lane);
+    load(k1b, w1);
+    decode(w0, k0b, a0);
+    if (!more1) break;
+    const bool more0 = cur.fetch(k0b, a0, s.blocks, live_fn, lane);
+    load(k0b, w0);
+    decode(w1, k1b, a1);
+    if (!more0) break;
+  }
+}
+
+// ---------------------------------------------- wavefront block decoding
+
+// RM-LDS: decode one staged block; lane l takes values j = l + 64 t (t < 16),
+// which share the shift (l*B mod 32) and sit 2*B*t words apart.
+template <int B, int MODE, int ENC, int PF, bool TAIL>
+__device__ __forceinline__ void decode_staged(const Params& p, WaveState<uint32_t>& s, uint32_t lane,
+                                              const uint32_t* st, uint64_t k, const int64_t* dict_lds,
+                                              uint32_t dict_last, uint32_t clo, uint32_t chi) {
+  uint32_t ref = 0;
+  if constexpr (PF == PF_REFS) ref = p.refs[k];
+  const CodeRange cr = block_range<B, ENC, PF>(p, ref, clo, chi);
+  if (!cr.nonempty) return;
+  const uint32_t limit = TAIL ? p.tail : kBlockValues;
+  const uint32_t bit0 = lane * B;
+  const uint32_t* sp = st + (bit0 >> 5);
+  const uint32_t sh = bit0 & 31u;
+  uint32_t cnt = 0;
+  PartT<B, ENC> part = 0;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    uint32_t c;
+    if (B == 32) c = sp[64 * t];
+    else c = funnel(sp[2 * B * t + 1], sp[2 * B * t], sh) & width_mask<B>();
+    const bool hit = (PF == PF_LO0) ? (c <= cr.wm1) : ((c - cr.loc) <= cr.wm1);
+    uint64_t m = ballot(hit);
+    bool valid = true;
+    if (TAIL) {
+      valid = lane + 64u * t < limit;
+      m &= ballot(valid);
+    }
+    cnt += (uint32_t)__builtin_popcountll(m);
+    if constexpr (MODE == MODE_BF) {
+      const uint64_t v = code_value<ENC>(c, dict_lds, dict_last);
+      part += (hit && valid) ? (PartT<B, ENC>)v : (PartT<B, ENC>)0;
+      pin(part);
+    } else {
+      sv_push<ENC, uint32_t>(s, c, hit && valid, m, lane, dict_lds, dict_last);
+    }
+  }
+  s.count += cnt;
+  s.refsum += (uint64_t)cnt * ref;
+  s.lsum += (uint64_t)part;
+}
+
+// Byte-aligned: one 16-byte load per lane per KiB of the block.
+template <int B, int MODE, int ENC, int PF, bool TAIL>
+__device__ __forceinline__ void decode_bytes(const Params& p, WaveState<uint32_t>& s, uint32_t lane,
+                                             const uint4 (&x)[B / 8], uint64_t k) {
+  uint32_t ref = 0;
+  if constexpr (PF == PF_REFS) ref = p.refs[k];
+  const CodeRange cr = block_range<B, ENC, PF>(p, ref, 0, 0);
+  if (!cr.nonempty) return;
+  const uint32_t limit = TAIL ? p.tail : kBlockValues;
+  uint32_t cnt = 0;
+  PartT<B, ENC> part = 0;
+  constexpr int V = 128 / B;  // values per 16-byte load
+#pragma unroll
+  for (int q = 0; q < B / 8; ++q) {
+    const uint32_t xs[4] = {x[q].x, x[q].y, x[q].z, x[q].w};
+    const uint32_t idx0 = q * (8192 / B) + lane * V;
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      uint32_t c;
+      if (B == 8) c = (xs[e >> 2] >> (8 * (e & 3))) & 0xFFu;
+      else if (B == 16) c = (xs[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+      else c = xs[e];
+      const bool hit = (PF == PF_LO0) ? (c <= cr.wm1) : ((c - cr.loc) <= cr.wm1);
+      uint64_t m = ballot(hit);
+      bool valid = true;
+      if (TAIL) {
+        valid = idx0 + e < limit;
+        m &= ballot(valid);
+      }
+      cnt += (uint32_t)__builtin_popcountll(m);
+      if constexpr (MODE == MODE_BF) {
+        part += (hit && valid) ? (PartT<B, ENC>)c : (PartT<B, ENC>)0;
+        pin(part);
+      } else {
+        sv_push<ENC, uint32_t>(s, c, hit && valid, m, lane, nullptr, 0);
+      }
+    }
+  }
+  s.count += cnt;
+  s.refsum += (uint64_t)cnt * ref;
+  s.lsum += (uint64_t)part;
+}
+
+// Coalesced staging loads of one block into registers (lane takes words
+// lane + 64 i), and their store into the block's LDS slot.
+template <int B>
+__device__ __forceinline__ void stage_load(const uint32_t* __restrict__ blk, uint32_t lane,
+                                           uint32_t (&r)[Geo<B>::kStageLoads]) {
+#pragma unroll
+  for (int i = 0; i < Geo<B>::kStageLoads; ++i) {
+    const uint32_t w = lane + 64u * i;
+    r[i] = ((32 * B) % 64 == 0 || w < 32u * B) ? blk[w] : 0u;
+  }
+}
+
+template <int B>
+__device__ __forceinline__ void stage_store(uint32_t* st, uint32_t lane, const uint32_t (&r)[Geo<B>::kStageLoads]) {
+#pragma unroll
+  for (int i = 0; i < Geo<B>::kStageLoads; ++i) {
+    const uint32_t w = lane + 64u * i;
+    if ((32 * B) % 64 == 0 || w < 32u * B) st[w] = r[i];
+  }
+}
+
+// The j-th block of a step: the j-th set bit of the step mask, or (past the
+// last one) the step's first block, so that every step issues the same loads.
+__device__ __forceinline__ uint64_t step_block(uint64_t k0, uint64_t mask, int j) {
+  uint64_t m = mask;
+  for (int i = 0; i < j && (m & (m - 1ull)); ++i) m &= m - 1ull;
+  return k0 + (uint64_t)__builtin_ctzll(m);
+}
+
+template <int B, int MODE, int ENC, int PF>
+__device__ __forceinline__ void run_staged(const Params& p, WaveState<uint32_t>& s, uint32_t lane, uint32_t* st,
+                                           uint64_t ka, uint64_t ke, uint64_t excl, const int64_t* dict_lds,
+                                           uint32_t dict_last, uint32_t clo, uint32_t chi) {
+  constexpr int NB = Geo<B>::kLdsBlocks, NL = Geo<B>::kStageLoads, SW = Geo<B>::kStageWords;
+  auto live_fn = [&](uint64_t k0, uint32_t cnt) { return window_live<ENC>(p, k0, cnt, clo, chi, excl); };
+  BlockCursor<NB, decltype(live_fn)> cur{ka, ke, 0, 0};
+  uint64_t k0 = 0, m0 = 0, k1 = 0, m1 = 0;
+  uint32_t r0[NB][NL], r1[NB][NL];
+  auto load = [&](uint64_t base, uint64_t mask, uint32_t (&dst)[NB][NL]) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) stage_load<B>(p.payload + step_block(base, mask, j) * (32u * B), lane, dst[j]);
+  };
+  auto decode = [&](uint64_t base, uint64_t mask, const uint32_t (&src)[NB][NL]) {
+    const int n = __builtin_popcountll(mask);
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+      if (j < n) stage_store<B>(st + j * SW, lane, src[j]);
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      if (mask) {
+        const uint64_t k = base + (uint64_t)__builtin_ctzll(mask);
+        mask &= mask - 1ull;
+        decode_staged<B, MODE, ENC, PF, false>(p, s, lane, st + j * SW, k, dict_lds, dict_last, clo, chi);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  };
+  if (!cur.fetch(k0, m0, s.blocks, live_fn)) return;
+  load(k0, m0, r0);
+  while (true) {
+    const bool more1 = cur.fetch(k1, m1, s.blocks, live_fn);
+    if (!more1) { k1 = k0; m1 = m0; }
+    load(k1, m1, r1);
+    decode(k0, m0, r0);
+    if (!more1) break;
+    const bool more0 = cur.fetch(k0, m0, s.blocks, live_fn);
+    if (!more0) { k0 = k1; m0 = m1; }
+    load(k0, m0, r0);
+    decode(k1, m1, r1);
+    if (!more0) break;
+  }
+}
+
+template <int B, int MODE, int ENC, int PF>
+__device__ __forceinline__ void run_bytes(const Params& p, WaveState<uint32_t>& s, uint32_t lane, uint64_t ka,
+                                          uint64_t ke, uint64_t excl) {
+  constexpr int NB = Geo<B>::kByteBlocks, Q = B / 8;
+  auto live_fn = [&](uint64_t k0, uint32_t cnt) { return window_live<ENC>(p, k0, cnt, 0, 0, excl); };
+  BlockCursor<NB, decltype(live_fn)> cur{ka, ke, 0, 0};
+  uint64_t k0 = 0, m0 = 0, k1 = 0, m1 = 0;
+  uint4 x0[NB][Q], x1[NB][Q];
+  auto load = [&](uint64_t base, uint64_t mask, uint4 (&dst)[NB][Q]) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const uint4* blk = reinterpret_cast<const uint4*>(p.payload + step_block(base, mask, j) * (32u * B));
+#pragma unroll
+      for (int q = 0; q < Q; ++q) dst[j][q] = blk[64 * q + lane];
+    }
+  };
+  auto decode = [&](uint64_t base, uint64_t mask, const uint4 (&src)[NB][Q]) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      if (mask) {
+        const uint64_t k = base + (uint64_t)__builtin_ctzll(mask);
+        mask &= mask - 1ull;
+        decode_bytes<B, MODE, ENC, PF, false>(p, s, lane, src[j], k);
+      }
+    }
+  };
+  if (!cur.fetch(k0, m0, s.blocks, live_fn)) return;
+  load(k0, m0, x0);
+  while (true) {
+    const bool more1 = cur.fetch(k1, m1, s.blocks, live_fn);
+    if (!more1) { k1 = k0; m1 = m0; }
+    load(k1, m1, x1);
+    decode(k0, m0, x0);
+    if (!more1) break;
+    const bool more0 = cur.fetch(k0, m0, s.blocks, live_fn);
+    if (!more0) { k0 = k1; m0 = m1; }
+    load(k0, m0, x0);
+    decode(k1, m1, x1);
+    if (!more0) break;
+  }
+}
+
+// ------------------------------------------------------------ FOR / DICT
+
+__device__ __forceinline__ uint32_t lower_bound_lds(const int64_t* d, uint32_t m, int64_t x) {
+  uint32_t a = 0, e = m;
+  while (a < e) {
+    const uint32_t mid = (a + e) >> 1;
+    if (d[mid] < x) a = mid + 1u;
+    else e = mid;
+  }
+  return a;
+}
+
+constexpr uint32_t kListWords = 64;  // per-wavefront survivor list
+
+template <int B, int DEC, int MODE>
+__host__ __device__ constexpr uint32_t wave_lds_words() {
+  return kListWords + (DEC == DEC_RM_LDS ? Geo<B>::kLdsBlocks * Geo<B>::kStageWords : 0u) +
+         (MODE == MODE_SV ? kRingEntries : 0u);
+}
+
+// Dynamic LDS bytes of code_scan for a work-group of `waves` wavefronts.
+template <int B, int DEC, int MODE, int ENC>
+__host__ __device__ constexpr uint32_t code_scan_lds(uint32_t waves) {
+  return (ENC == ENC_DICT ? kMaxDict * 8u : 0u) + waves * wave_lds_words<B, DEC, MODE>() * 4u;
+}
+
+template <int B, int DEC, int MODE, int ENC, int PF>
+__global__ __launch_bounds__(256) void code_scan(const Params p) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int64_t* dict_lds = reinterpret_cast<int64_t*>(smem);
+  uint32_t* wave_area = reinterpret_cast<uint32_t*>(smem + (ENC == ENC_DICT ? kMaxDict * 8u : 0u)) +
+                        wave * wave_lds_words<B, DEC, MODE>();
+  uint32_t* list = wave_area;
+  uint32_t* st = wave_area + kListWords;  // 16-byte aligned: the list is 256 bytes
+  WaveState<uint32_t> s;
+  s.ring = st + (DEC == DEC_RM_LDS ? Geo<B>::kLdsBlocks * Geo<B>::kStageWords : 0u);
+
+  uint32_t clo = 0, chi = 0, dict_last = 0;
+  if constexpr (ENC == ENC_DICT) {
+    for (uint32_t i = threadIdx.x; i < p.dict_len; i += blockDim.x) dict_lds[i] = p.dict[i];
+    __syncthreads();
+    clo = lower_bound_lds(dict_lds, p.dict_len, p.lo);
+    chi = lower_bound_lds(dict_lds, p.dict_len, p.hi);
+    dict_last = p.dict_len - 1u;
+  }
+  uint64_t ka, ke;
+  wave_range(p.nb, (uint64_t)blockIdx.x * nw + wave, (uint64_t)gridDim.x * nw, ka, ke);
+  const uint64_t last = p.nb - 1;
+  const bool tail_partial = p.tail != kBlockValues;
+  const uint64_t excl = tail_partial ? last : ~0ull;
+  if constexpr (DEC == DEC_RM_DIRECT || DEC == DEC_LI) {
+    run_pairs<B, DEC, MODE, ENC, PF>(p, s, lane, list, ka, ke, excl, dict_lds, dict_last, clo, chi);
+  } else if constexpr (DEC == DEC_RM_LDS) {
+    run_staged<B, MODE, ENC, PF>(p, s, lane, st, ka, ke, excl, dict_lds, dict_last, clo, chi);
+  } else {
+    run_bytes<B, MODE, ENC, PF>(p, s, lane, ka, ke, excl);
+  }
+  // The partial last block: its owner decodes it with per-value validity.
+  if (tail_partial && ka <= last && last < ke && block_survives<ENC>(p, last, clo, chi)) {
+    s.blocks += 1;
+    if constexpr (DEC == DEC_RM_DIRECT || DEC == DEC_LI) {
+      uint32_t w[B];
+      load_pair_words<B, DEC>(p, last, lane & 31u, w);
+      decode_pair<B, DEC, MODE, ENC, PF, true>(p, s, lane, w, last, lane < 32u, dict_lds, dict_last, clo, chi);
+    } else if constexpr (DEC == DEC_RM_LDS) {
+      uint32_t r[Geo<B>::kStageLoads];
+      stage_load<B>(p.payload + last * (32u * B), lane, r);
+      stage_store<B>(st, lane, r);
+      __builtin_amdgcn_wave_barrier();
+      decode_staged<B, MODE, ENC, PF, true>(p, s, lane, st, last, dict_lds, dict_last, clo, chi);
+    } else {
+      uint4 x[B / 8];
+      const uint4* blk = reinterpret_cast<const uint4*>(p.payload + last * (32u * B));
+#pragma unroll
+      for (int q = 0; q < B / 8; ++q) x[q] = blk[64 * q + lane];
+      decode_bytes<B, MODE, ENC, PF, true>(p, s, lane, x, last);
+    }
+  }
+  if constexpr (MODE == MODE_SV) sv_drain_rest<ENC, uint32_t>(s, lane, dict_lds, dict_last);
+  finish_scan(p, s.count, s.lsum + (lane == 0 ? s.refsum : 0ull), s.blocks);
+}
+
+// ------------------------------------------------------------- delta scan
+
+// Block-relative value rel = v - base_k < 1024 * 2^B: u32 for B <= 22.
+template <int B>
+using RelT = typename std::conditional<(B <= 22), uint32_t, uint64_t>::type;
+
+template <int B>
+struct RelRange {
+  RelT<B> loc, wm1;
+  bool nonempty;
+};
+
+// [lo, hi) on values -> [loc, loc + wm1] on rel = v - base (exact for any int64 inputs).
+template <int B>
+__device__ __forceinline__ RelRange<B> rel_range(int64_t base, int64_t lo, int64_t hi) {
+  constexpr uint64_t kCap = (B <= 22) ? (1ull << 32) : (1ull << 43);
+  uint64_t dlo = lo > base ? (uint64_t)lo - (uint64_t)base : 0ull;
+  uint64_t dhi = hi > base ? (uint64_t)hi - (uint64_t)base : 0ull;
+  if (dlo > kCap) dlo = kCap;
+  if (dhi > kCap) dhi = kCap;
+  RelRange<B> r;
+  r.nonempty = dlo < dhi;
+  r.loc = (RelT<B>)dlo;
+  r.wm1 = (RelT<B>)(dhi - dlo - 1ull);
+  return r;
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl_up_t(T x, int d, int width) {
+  if constexpr (sizeof(T) == 4) {
+    return (T)__shfl_up((uint32_t)x, d, width);
+  } else {
+    const uint32_t lo = __shfl_up((uint32_t)x, d, width), hi = __shfl_up((uint32_t)(x >> 32), d, width);
+    return ((T)hi << 32) | lo;
+  }
+}
+
+// Inclusive scan of x over segments of WIDTH lanes.
+template <typename T, int WIDTH>
+__device__ __forceinline__ T seg_inclusive_scan(T x, uint32_t lane) {
+#pragma unroll
+  for (int d = 1; d < WIDTH; d <<= 1) {
+    const T y = shfl_up_t<T>(x, d, WIDTH);
+    if ((lane & (WIDTH - 1)) >= (uint32_t)d) x += y;
+  }
+  return x;
+}
+
+// Delta, half-wavefront per block: lane l holds deltas 32 l .. 32 l + 31,
+// forms its local inclusive prefix, the half-wavefront scans the slice totals,
+// rel = exclusive + local prefix.
+template <int B, int MODE, bool TAIL>
+__device__ __forceinline__ void decode_delta_pair(const Params& p, WaveState<RelT<B>>& s, uint32_t lane,
+                                                  const uint32_t (&w)[B], uint64_t kb, bool act) {
+  using R = RelT<B>;
+  const uint32_t l = lane & 31u;
+  const int64_t base = p.bases[kb];
+  const RelRange<B> rr = rel_range<B>(base, p.lo, p.hi);
+  act = act && rr.nonempty;
+  const uint64_t act_m = ballot(act);
+  if (act_m == 0) return;
+  const uint32_t limit = (TAIL && kb == p.nb - 1) ? p.tail : kBlockValues;
+  R pre[32];
+  R run = 0;
+#pragma unroll
+  for (int t = 0; t < 32; ++t) {
+    run += (R)run_code<B, B>(w, t);
+    pre[t] = run;
+  }
+  const R excl = seg_inclusive_scan<R, 32>(run, lane) - run;
+  uint32_t cA = 0, cB = 0;
+  using PT = typename std::conditional<(B <= 16), uint32_t, uint64_t>::type;
+  PT part = 0;
+#pragma unroll
+  for (int t = 0; t < 32; ++t) {
+    const R rel = excl + pre[t];
+    const bool hit = (R)(rel - rr.loc) <= rr.wm1;
+    uint64_t m = ballot(hit) & act_m;
+    bool valid = true;
+    if (TAIL) {
+      valid = 32u * l + t < limit;
+      m &= ballot(valid);
+    }
+    cA += (uint32_t)__builtin_popcount((uint32_t)m);
+    cB += (uint32_t)__builtin_popcount((uint32_t)(m >> 32));
+    if constexpr (MODE == MODE_BF) {
+      part += (hit && valid) ? (PT)rel : (PT)0;
+      pin(part);
+    } else {
+      sv_push<ENC_DELTA, R>(s, rel, hit && act && valid, m, lane, nullptr, 0);
+    }
+  }
+  s.count += (uint64_t)cA + cB;
+  s.refsum += (uint64_t)cA * readlane64((uint64_t)base, 0) + (uint64_t)cB * readlane64((uint64_t)base, 32);
+  if constexpr (MODE == MODE_BF) s.lsum += act ? (uint64_t)part : 0ull;
+}
+
+// Delta, wavefront per staged block: lane l takes the contiguous run
+// 16 l .. 16 l + 15, realigns its words with one funnel shift so every code
+// sits at a compile-time offset, and the wavefront scans the run totals.
+template <int B, int MODE, bool TAIL>
+__device__ __forceinline__ void decode_delta_staged(const Params& p, WaveState<RelT<B>>& s, uint32_t lane,
+                                                    const uint32_t* st, uint64_t k) {
+  using R = RelT<B>;
+  const int64_t base = p.bases[k];
+  const RelRange<B> rr = rel_range<B>(base, p.lo, p.hi);
+  if (!rr.nonempty) return;
+  constexpr int NY = (16 * B + 31) / 32;
+  const uint32_t bit0 = 16u * lane * B;
+  const uint32_t* sp = st + (bit0 >> 5);
+  const uint32_t sh = bit0 & 31u;
+  uint32_t y[NY + 1];
+#pragma unroll
+  for (int i = 0; i < NY; ++i) y[i] = funnel(sp[i + 1], sp[i], sh);
+  y[NY] = 0;
+  const uint32_t limit = TAIL ? p.tail : kBlockValues;
+  R pre[16];
+  R run = 0;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    run += (R)run_code<B, NY + 1>(y, t);
+    pre[t] = run;
+  }
+  const R excl = seg_inclusive_scan<R, 64>(run, lane) - run;
+  uint32_t cnt = 0;
+  using PT = typename std::conditional<(B <= 16), uint32_t, uint64_t>::type;
+  PT part = 0;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const R rel = excl + pre[t];
+    const bool hit = (R)(rel - rr.loc) <= rr.wm1;
+    uint64_t m = ballot(hit);
+    bool valid = true;
+    if (TAIL) {
+      valid = 16u * lane + t < limit;
+      m &= ballot(valid);
+    }
+    cnt += (uint32_t)__builtin_popcountll(m);
+    if constexpr (MODE == MODE_BF) {
+      part += (hit && valid) ? (PT)rel : (PT)0;
+      pin(part);
+    } else {
+      sv_push<ENC_DELTA, R>(s, rel, hit && valid, m, lane, nullptr, 0);
+    }
+  }
+  s.count += cnt;
+  s.refsum += (uint64_t)cnt * (uint64_t)base;
+  s.lsum += (uint64_t)part;
+}
+
+template <int B, int DEC, int MODE>
+__host__ __device__ constexpr uint32_t delta_wave_words() {
+  return kListWords + (DEC == DEC_RM_LDS ? Geo<B>::kLdsBlocks * Geo<B>::kStageWords : 0u) +
+         (MODE == MODE_SV ? kRingEntries * (uint32_t)sizeof(RelT<B>) / 4u : 0u);
+}
+
+template <int B, int DEC, int MODE>
+__host__ __device__ constexpr uint32_t delta_scan_lds(uint32_t waves) {
+  return waves * delta_wave_words<B, DEC, MODE>() * 4u;
+}
+
+template <int B, int DEC, int MODE>
+__global__ __launch_bounds__(256) void delta_scan(const Params p) {
+  using R = RelT<B>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  uint32_t* wave_area = reinterpret_cast<uint32_t*>(smem) + wave * delta_wave_words<B, DEC, MODE>();
+  uint32_t* list = wave_area;
+  uint32_t* st = wave_area + kListWords;
+  WaveState<R> s;
+  s.ring = reinterpret_cast<R*>(st + (DEC == DEC_RM_LDS ? Geo<B>::kLdsBlocks * Geo<B>::kStageWords : 0u));
+  uint64_t ka, ke;
+  wave_range(p.nb, (uint64_t)blockIdx.x * nw + wave, (uint64_t)gridDim.x * nw, ka, ke);
+  const uint64_t last = p.nb - 1;
+  const bool tail_partial = p.tail != kBlockValues;
+  const uint64_t excl = tail_partial ? last : ~0ull;
+  auto live_fn = [&](uint64_t k0, uint32_t cnt) { return window_live_i64(p, k0, cnt, excl); };
+  if constexpr (DEC == DEC_RM_DIRECT) {
+    constexpr int P = Geo<B>::kPairs;
+    const uint32_t l = lane & 31u;
+    PairCursor<P, decltype(live_fn)> cur{ka, ke, 0, 0, 0, list, ka};
+    uint64_t k0b[P], k1b[P];
+    uint32_t a0 = 0, a1 = 0;
+    uint32_t w0[P][B], w1[P][B];
+    auto load = [&](const uint64_t (&kb)[P], uint32_t (&w)[P][B]) {
+#pragma unroll
+      for (int q = 0; q < P; ++q) load_pair_words<B, DEC_RM_DIRECT>(p, kb[q], l, w[q]);
+    };
+    auto decode = [&](const uint32_t (&w)[P][B], const uint64_t (&kb)[P], uint32_t ab) {
+#pragma unroll
+      for (int q = 0; q < P; ++q) decode_delta_pair<B, MODE, false>(p, s, lane, w[q], kb[q], (ab >> q) & 1u);
+    };
+    if (cur.fetch(k0b, a0, s.blocks, live_fn, lane)) {
+      load(k0b, w0);
+      while (true) {
+        const bool more1 = cur.fetch(k1b, a1, s.blocks, live_fn, lane);
+        load(k1b, w1);
+        decode(w0, k0b, a0);
+        if (!more1) break;
+        const bool more0 = cur.fetch(k0b, a0, s.blocks, live_fn, lane);
+        load(k0b, w0);
+        decode(w1, k1b, a1);
+        if (!more0) break;
+      }
+    }
+  } else {
+    constexpr int NB = Geo<B>::kLdsBlocks, NL = Geo<B>::kStageLoads, SW = Geo<B>::kStageWords;
+    BlockCursor<NB, decltype(live_fn)> cur{ka, ke, 0, 0};
+    uint64_t k0 = 0, m0 = 0, k1 = 0, m1 = 0;
+    uint32_t r0[NB][NL], r1[NB][NL];
+    auto load = [&](uint64_t base, uint64_t mask, uint32_t (&dst)[NB][NL]) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) stage_load<B>(p.payload + step_block(base, mask, j) * (32u * B), lane, dst[j]);
+    };
+    auto decode = [&](uint64_t base, uint64_t mask, const uint32_t (&src)[NB][NL]) {
+      const int n = __builtin_popcountll(mask);
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        if (j < n) stage_store<B>(st + j * SW, lane, src[j]);
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if (mask) {
+          const uint64_t k = base + (uint64_t)__builtin_ctzll(mask);
+          mask &= mask - 1ull;
+          decode_delta_staged<B, MODE, false>(p, s, lane, st + j * SW, k);
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+    };
+    if (cur.fetch(k0, m0, s.blocks, live_fn)) {
+      load(k0, m0, r0);
+      while (true) {
+        const bool more1 = cur.fetch(k1, m1, s.blocks, live_fn);
+        if (!more1) { k1 = k0; m1 = m0; }
+        load(k1, m1, r1);
+        decode(k0, m0, r0);
+        if (!more1) break;
+        const bool more0 = cur.fetch(k0, m0, s.blocks, live_fn);
+        if (!more0) { k0 = k1; m0 = m1; }
+        load(k0, m0, r0);
+        decode(k1, m1, r1);
+        if (!more0) break;
+      }
+    }
+  }
+  if (tail_partial && ka <= last && last < ke && block_survives<ENC_DELTA>(p, last, 0, 0)) {
+    s.blocks += 1;
+    if constexpr (DEC == DEC_RM_DIRECT) {
+      uint32_t w[B];
+      load_pair_words<B, DEC_RM_DIRECT>(p, last, lane & 31u, w);
+      decode_delta_pair<B, MODE, true>(p, s, lane, w, last, lane < 32u);
+    } else {
+      uint32_t r[Geo<B>::kStageLoads];
+      stage_load<B>(p.payload + last * (32u * B), lane, r);
+      stage_store<B>(st, lane, r);
+      __builtin_amdgcn_wave_barrier();
+      decode_delta_staged<B, MODE, true>(p, s, lane, st, last);
+    }
+  }
+  if constexpr (MODE == MODE_SV) sv_drain_rest<ENC_DELTA, R>(s, lane, nullptr, 0);
+  finish_scan(p, s.count, s.lsum + (lane == 0 ? s.refsum : 0ull), s.blocks);
+}
+
+}  // namespace scan_dev

@@ -1,0 +1,235 @@
+"""GPU parity: every scan strategy, bit-exact against the CPU oracle.
+
+Inputs come from the shared seeded generators; the GPU reads the library
+encoder's bytes, the oracle packs the same raw values itself.  Tolerance is
+zero: count, sum and blocks_read are integers.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2606_22423_amd import _lib, api  # noqa: E402
+from paper_2606_22423_amd._lib import (DEC_BYTES, DEC_LI, DEC_RM_DIRECT, DEC_RM_LDS, ENC_DELTA,  # noqa: E402
+                                       ENC_DICT, ENC_FOR, LAYOUT_LI, LAYOUT_RM, strategy)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rm_strategies(b, enc=ENC_FOR):
+    decs = [DEC_RM_LDS, DEC_RM_DIRECT]
+    if enc == ENC_FOR and b in (8, 16, 32):
+        decs.append(DEC_BYTES)
+    return [strategy(d, sv, zm) for d in decs for sv in (0, 1) for zm in (0, 1)]
+
+
+LI_STRATS = [strategy(DEC_LI, sv, zm) for sv in (0, 1) for zm in (0, 1)]
+
+
+def check(got, want, zm, what, want_off=None):
+    """want: the oracle with zone maps on.  With zone maps off every block of a
+    non-empty predicate is read, so blocks_read is the block count (0 if lo >= hi)."""
+    assert (got["count"], got["sum"]) == (want.count, want.sum), (what, got, want)
+    if zm:
+        assert got["blocks_read"] == want.blocks_read, (what, got, want)
+    elif want_off is not None:
+        assert got["blocks_read"] == want_off.blocks_read, (what, got, want_off)
+    assert got["blocks_total"] == want.blocks_total
+
+
+def preds_for(b, v, rng):
+    top = 1 << b
+    x = int(v[len(v) // 2])
+    out = [(0, top), (0, max(1, top // 10)), (x, x + 1), (top // 3, top // 3 + max(1, top // 7)),
+           (-5, 3), (top - 1, top + 100), (5, 5), (9, 2)]
+    lo, hi = sorted(int(t) for t in rng.integers(0, top + 1, size=2))
+    out.append((lo, hi + 1))
+    return out
+
+
+def test_config1_every_strategy(ctx):
+    v, lo, hi = synth.config1()
+    want = oracle.scan_for(oracle.pack_rm(v, 8), len(v), 8, lo, hi, zone_maps=True)
+    want_off = oracle.scan_for(oracle.pack_rm(v, 8), len(v), 8, lo, hi, zone_maps=False)
+    assert want.count > 100_000
+    col = api.encode_for(v, 8)
+    for s in rm_strategies(8):
+        say("config1 strategy", _lib.strategy_name(s))
+        got = ctx.run(col, lo, hi, s)
+        check(got, want, (s >> 3) & 1, s, want_off)
+        assert got["strategy_used"] == s
+    coli = api.encode_for(v, 8, layout=LAYOUT_LI)
+    for s in LI_STRATS:
+        got = ctx.run(coli, lo, hi, s)
+        check(got, want, (s >> 3) & 1, s, want_off)
+
+
+@pytest.mark.parametrize("b", range(1, 33))
+def test_for_every_width_and_strategy(ctx, b):
+    rng = np.random.default_rng(1000 + b)
+    for n in (1, 1023, 1025, 5 * 1024 + 77):
+        v = synth.width_values(synth.pcg32(77, b * 100 + n % 97, n), b)
+        v[:2] = [0, (1 << b) - 1] if n >= 2 else v[:2]
+        w_rm, w_li = oracle.pack_rm(v, b), oracle.pack_li(v, b)
+        col = api.encode_for(v, b)
+        coli = api.encode_for(v, b, layout=LAYOUT_LI)
+        for lo, hi in preds_for(b, v, rng):
+            want = oracle.scan_for(w_rm, n, b, lo, hi, zone_maps=True)
+            want_off = oracle.scan_for(w_rm, n, b, lo, hi, zone_maps=False)
+            want_li = oracle.scan_for(w_li, n, b, lo, hi, layout=1, zone_maps=True)
+            assert (want.count, want.sum, want.blocks_read) == (want_li.count, want_li.sum, want_li.blocks_read)
+            for s in rm_strategies(b):
+                got = ctx.run(col, lo, hi, s)
+                check(got, want, (s >> 3) & 1, (b, n, lo, hi, _lib.strategy_name(s)), want_off)
+            for s in LI_STRATS:
+                got = ctx.run(coli, lo, hi, s)
+                check(got, want, (s >> 3) & 1, (b, n, lo, hi, _lib.strategy_name(s)))
+
+
+@pytest.mark.parametrize("b", [1, 5, 12, 20, 31])
+def test_for_block_references(ctx, b):
+    n = 6 * 1024 + 13
+    top = (1 << 32) - (1 << b)  # block bases keep every value inside u32
+    base = (np.repeat(np.arange(7, dtype=np.uint64) * top // 7, 1024)[:n]).astype(np.uint64)
+    v = (base + synth.width_values(synth.pcg32(5, b, n), b).astype(np.uint64)).astype(np.uint32)
+    refs, codes = oracle.for_encode(v, b, policy=1)
+    w = oracle.pack_rm(codes, b)
+    col = api.encode_for(v, b, ref_policy=1)
+    rng = np.random.default_rng(b)
+    for lo, hi in [(0, 1 << 32), (int(v[3000]), int(v[3000]) + 1), (1_000_000_000, 2_500_000_000),
+                   (int(v.min()), int(v.min()) + (1 << b) // 2)] + \
+            [tuple(sorted(int(t) for t in rng.integers(0, 1 << 32, size=2))) for _ in range(3)]:
+        want = oracle.scan_for(w, n, b, lo, hi, refs=refs, zone_maps=True)
+        want_off = oracle.scan_for(w, n, b, lo, hi, refs=refs, zone_maps=False)
+        for s in rm_strategies(b):
+            check(ctx.run(col, lo, hi, s), want, (s >> 3) & 1, (b, lo, hi, s), want_off)
+
+
+@pytest.mark.parametrize("b", [1, 2, 7, 13, 16, 17, 22, 23, 28, 32])
+def test_delta_every_strategy(ctx, b):
+    for n in (1, 1024, 4 * 1024 + 333):
+        d = synth.width_values(synth.pcg32(31, b, n), b).astype(np.int64)
+        d[0] = int(synth.pcg32(32, b, 1)[0])
+        v = np.cumsum(d)
+        bases, codes = oracle.delta_encode(v, b)
+        w = oracle.pack_rm(codes, b)
+        col = api.encode_delta(v, b)
+        rng = np.random.default_rng(b * 7 + n)
+        preds = [(int(v[0]), int(v[-1]) + 1), (int(v[n // 2]), int(v[n // 2]) + 1), (-(1 << 62), 1 << 62),
+                 (int(v[-1]) + 1, int(v[-1]) + 5), (5, 5)]
+        for _ in range(3):
+            p, q = sorted(int(t) for t in rng.integers(0, n, size=2))
+            preds.append((int(v[p]), int(v[q]) + 1))
+        for lo, hi in preds:
+            want = oracle.scan_delta(w, bases, n, b, lo, hi, zone_maps=True)
+            want_off = oracle.scan_delta(w, bases, n, b, lo, hi, zone_maps=False)
+            for s in rm_strategies(b, ENC_DELTA):
+                check(ctx.run(col, lo, hi, s), want, (s >> 3) & 1, (b, n, lo, hi, _lib.strategy_name(s)), want_off)
+
+
+@pytest.mark.parametrize("b", [1, 3, 8, 12, 13, 20, 24, 32])
+def test_dict_every_strategy(ctx, b):
+    m = min(1 << b, 4096)
+    dct = synth.dict_entries(m, 9, b, 38)
+    for n in (1, 1025, 5 * 1024 + 3):
+        codes = synth.bounded(8, b, n, m)
+        w = oracle.pack_rm(codes, b)
+        col = api.encode_dict(codes, b, dct)
+        rng = np.random.default_rng(b + n)
+        preds = [(int(dct[0]), int(dct[-1]) + 1), (int(dct[m // 2]), int(dct[m // 2]) + 1),
+                 (int(dct[0]) - 10, int(dct[0])), (-(1 << 62), 1 << 62)]
+        if m > 2:
+            preds.append((int(dct[1]) + 1, int(dct[2])))  # no entry inside: empty code range
+        for _ in range(3):
+            i, j = sorted(int(t) for t in rng.integers(0, m, size=2))
+            preds.append((int(dct[i]), int(dct[j]) + 1))
+        for lo, hi in preds:
+            want = oracle.scan_dict(w, dct, n, b, lo, hi, zone_maps=True)
+            want_off = oracle.scan_dict(w, dct, n, b, lo, hi, zone_maps=False)
+            for s in rm_strategies(b, ENC_DICT):
+                check(ctx.run(col, lo, hi, s), want, (s >> 3) & 1, (b, n, lo, hi, _lib.strategy_name(s)), want_off)
+
+
+def test_sorted_column_zone_maps_read_exact_blocks(ctx):
+    n, nd = 1 << 22, 1 << 8  # 2^14 copies per value: 16 whole blocks each
+    v = synth.config3_column(n, nd, 0).numpy().astype(np.uint32)
+    col = api.encode_for(v, 16)
+    for lo, hi in ((0, 1), (17, 40), (0, 256), (255, 256)):
+        for s in (strategy(DEC_RM_DIRECT, 0, 1), strategy(DEC_RM_LDS, 1, 1), strategy(DEC_BYTES, 0, 1)):
+            got = ctx.run(col, lo, hi, s)
+            assert got["count"] == (hi - lo) << 14
+            assert got["sum"] == (1 << 14) * (hi - lo) * (lo + hi - 1) // 2
+            assert got["blocks_read"] == 16 * (hi - lo)
+
+
+def test_edge_cases_and_errors(ctx):
+    v = synth.width_values(synth.pcg32(1, 1, 5000), 7)
+    col = api.encode_for(v, 7)
+    nb = oracle.nblocks(5000)
+    r = ctx.run(col, 9, 3, strategy(DEC_RM_DIRECT, 0, 1))
+    assert (r["count"], r["sum"], r["blocks_read"]) == (0, 0, 0)
+    r = ctx.run(col, 1 << 40, 1 << 41, strategy(DEC_RM_DIRECT, 0, 0))
+    assert (r["count"], r["sum"], r["blocks_read"], r["blocks_total"]) == (0, 0, nb, nb)
+    r = ctx.run(col, 1 << 40, 1 << 41, strategy(DEC_RM_DIRECT, 0, 1))
+    assert (r["count"], r["sum"], r["blocks_read"]) == (0, 0, 0)
+    empty = api.Column(ENC_FOR, 7, 0, LAYOUT_RM, col.payload)
+    r = ctx.run(empty, 0, 100, strategy(DEC_RM_DIRECT, 0, 0))
+    assert (r["count"], r["sum"], r["blocks_total"]) == (0, 0, 0)
+    with pytest.raises(_lib.ScanError) as e:
+        ctx.run(col, 0, 10, strategy(DEC_LI, 0, 0))
+    assert e.value.status == _lib.SCAN_EUNSUPPORTED
+    with pytest.raises(_lib.ScanError) as e:
+        ctx.run(col, 0, 10, strategy(DEC_BYTES, 0, 0))
+    assert e.value.status == _lib.SCAN_EUNSUPPORTED
+    bad = api.Column(ENC_FOR, 7, 5000, LAYOUT_RM, col.payload[1:])  # 4-byte offset: misaligned
+    with pytest.raises(_lib.ScanError) as e:
+        ctx.run(bad, 0, 10, strategy(DEC_RM_DIRECT, 0, 0))
+    assert e.value.status == _lib.SCAN_EINVAL
+    with pytest.raises(_lib.ScanError):
+        ctx.run(col, 0, 10, 99)
+    dcol = api.encode_dict(np.zeros(10, dtype=np.uint32), 2, np.arange(4, dtype=np.int64))
+    dcol.dct = torch.arange(5, dtype=torch.int64, device="cuda")  # 5 entries > 2^2
+    with pytest.raises(_lib.ScanError) as e:
+        ctx.run(dcol, 0, 3, strategy(DEC_RM_DIRECT, 0, 0))
+    assert e.value.status == _lib.SCAN_EINVAL
+
+
+def test_async_results_and_repeat_launches(ctx):
+    v = synth.width_values(synth.pcg32(3, 3, 100_000), 11)
+    col = api.encode_for(v, 11)
+    preds = [(0, 100), (50, 1500), (0, 2048), (1000, 1001)]
+    out = torch.zeros((len(preds) * 3, 5), dtype=torch.int64, device="cuda")
+    k = 0
+    for lo, hi in preds:
+        for s in (strategy(DEC_RM_LDS, 0, 0), strategy(DEC_RM_DIRECT, 1, 1), strategy(DEC_RM_DIRECT, 0, 1)):
+            ctx.run_async(col, lo, hi, s, out[k])
+            k += 1
+    ctx.sync()
+    host = out.cpu()
+    k = 0
+    w = oracle.pack_rm(v, 11)
+    for lo, hi in preds:
+        want = oracle.scan_for(w, len(v), 11, lo, hi, zone_maps=True)
+        for s in range(3):
+            r = api.result_from_tensor(host[k])
+            assert (r["count"], r["sum"]) == (want.count, want.sum)
+            k += 1
