@@ -1,0 +1,66 @@
+"""Pins of the law and its fit: synthetic recovery, the paper's Table 1
+consistency, and the large-T_dec (FastLanes) limit the paper quotes."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2606_22423_amd import lawfit
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def table1():
+    rows = []
+    for line in open(os.path.join(GOLDEN, "table1_fits.txt")):
+        if line.strip() and not line.startswith("#"):
+            m, s, t, b, e = line.split()
+            rows.append((m, s, float(t), float(b), float(e)))
+    return rows
+
+
+@pytest.mark.parametrize("t_dec,beta", [(3.91e9, 14.3e9), (8.0e12, 6.9e12), (2.5e11, 7.1e12), (9.04e9, 70e9)])
+def test_fit_recovers_synthetic_law(t_dec, beta):
+    bs = np.arange(1, 33)
+    fs = lawfit.law(t_dec, bs, beta)
+    fit = lawfit.fit_tdec(bs, fs, beta)
+    if np.all(fs >= 1.0):
+        pytest.skip("every point on the plateau: T_dec is unidentifiable")
+    assert abs(fit.t_dec / t_dec - 1) < 1e-6
+    assert abs(fit.b_star / lawfit.ridge(t_dec, beta) - 1) < 1e-6
+    assert fit.median_err < 1e-9
+    if fit.compute_bound_points:
+        assert abs(fit.t_dec_ls / t_dec - 1) < 1e-9
+
+
+def test_fit_with_noise_and_plateau():
+    rng = np.random.default_rng(3)
+    beta, t = 7.0e12, 9.0e12
+    bs = np.arange(1, 33)
+    fs = lawfit.law(t, bs, beta) * (1 + 0.01 * rng.standard_normal(32))
+    fit = lawfit.fit_tdec(bs, fs, beta)
+    assert abs(fit.t_dec / t - 1) < 0.03 and fit.median_err < 0.02
+
+
+def test_table1_is_consistent_with_the_stated_bandwidths():
+    for machine, strategy, t_dec, b_star, _ in table1():
+        beta = b_star * t_dec / 8.0  # GB/s
+        if machine == "x86":
+            assert 14.0 <= beta <= 16.0, (strategy, beta)
+        else:
+            assert 69.5 <= beta <= 70.5, (strategy, beta)
+        assert abs(lawfit.ridge(t_dec * 1e9, beta * 1e9) - b_star) < 1e-9
+
+
+def test_large_tdec_limit_reproduces_decode_is_free_at_three_bits():
+    """T_dec = 140 Gval/s against 52 GB/s: f(3) = 1 and the ridge is 2.97 bits."""
+    t, beta = 140e9, 52e9
+    assert lawfit.law(t, 3, beta) == 1.0
+    assert abs(lawfit.ridge(t, beta) - 8 * 52 / 140) < 1e-12
+    assert lawfit.law(t, 2, beta) < 1.0
+
+
+def test_bandwidth_fraction_and_quantization():
+    assert lawfit.bandwidth_fraction(2**28, 8, 2**28 / 7e12, 7e12) == pytest.approx(1.0)
+    assert lawfit.sigma_achieved(1, 1) == 0.5
+    assert lawfit.is_quantized(1e-4, 1, 1) and not lawfit.is_quantized(0.1, 6554, 16)
