@@ -135,12 +135,13 @@ typedef struct {
 
 /* Launch tuning of one (encoding, width, strategy): work-group size (64, 128,
  * 192 or 256), work-groups per compute unit (0 = as many as fit), and the
- * minimum number of blocks each wavefront takes (bounds the grid of small
- * columns).  Zero fields mean "library default". */
+ * window: wavefronts take grid-strided windows of this many consecutive
+ * blocks (1..64; 0 = one pipelined decode step).  Zero fields mean "library
+ * default". */
 typedef struct {
   int32_t wg_size;
   int32_t wgs_per_cu;
-  int32_t min_blocks_per_wave;
+  int32_t window_blocks;
   int32_t reserved;
 } scan_tune;
 
@@ -178,6 +179,86 @@ scan_status scan_sync(scan_ctx* ctx);
 /* Set / read the launch tuning used for (enc, b, strategy). */
 scan_status scan_set_tune(scan_ctx* ctx, int32_t enc, uint32_t b, int32_t strategy, const scan_tune* t);
 scan_status scan_get_tune(scan_ctx* ctx, int32_t enc, uint32_t b, int32_t strategy, scan_tune* t);
+
+/* Autotuner: times every launch configuration of a small grid (work-group
+ * size {64,128,256} x work-groups per CU {1,2,4,8} x window {4,16,64} blocks)
+ * for one column and strategy, median of `reps` runs each with HIP events on
+ * the context stream (a 512 MiB read before each run keeps the column out of
+ * the 256 MB last-level cache), and keeps the fastest with scan_set_tune.
+ * *out (host, may be NULL) receives it, *ms_out (may be NULL) its time in ms.
+ * The context allocates its 512 MiB eviction buffer on first use. */
+scan_status scan_autotune(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b,
+                          const scan_predicate* pred, int32_t strategy, int32_t reps, scan_tune* out, float* ms_out);
+/* Persist / restore every tuning of the context as JSON (one entry per line). */
+scan_status scan_tune_save(scan_ctx* ctx, const char* path);
+scan_status scan_tune_load(scan_ctx* ctx, const char* path);
+
+/* ---------------------------------------------------------------- batches */
+/* Many columns (mixed length, width, encoding, strategy) scanned by one
+ * captured hipGraph: per-column setup, strategy selection on the device (the
+ * loaded selector for SCAN_STRAT_AUTO items, else the heuristic), then one
+ * persistent kernel per (encoding, decoder, predicate mode) class draining
+ * windows of blocks from all its columns.  Columns must be row-major; explicit
+ * strategies must use the SCAN_DEC_RM_LDS or SCAN_DEC_RM_DIRECT decoder.
+ * Results equal scan_run's for every item, bit for bit.
+ *
+ * scan_batch_prepare validates the items, uploads their descriptors and
+ * captures the graph once; the selector state and the tuning stored for
+ * (enc -1, b 0, strategy -1) at that moment are baked in (tuning: work-groups
+ * per CU of the class kernels and the window, at most 64 blocks).  An invalid
+ * item does not fail the call: its result carries the error in `status`.
+ * `items` (host) may be freed after the call; the columns' device buffers must
+ * stay alive until the handle is released.  *handle (host) receives an id. */
+scan_status scan_batch_prepare(scan_ctx* ctx, const scan_item* items, size_t n_items, uint64_t* handle);
+/* Launch the batch's graph on the context stream.  With out (host, n_items
+ * results) non-NULL, waits and fills it; with out NULL, only enqueues.  May be
+ * replayed any number of times. */
+scan_status scan_batch_replay(scan_ctx* ctx, uint64_t handle, scan_result* out);
+/* Wait for the stream and free the batch's graph and buffers. */
+scan_status scan_batch_release(scan_ctx* ctx, uint64_t handle);
+/* prepare + replay + release. */
+scan_status scan_batch_run(scan_ctx* ctx, const scan_item* items, size_t n_items, scan_result* out);
+/* Launch tuning of the batch class kernels (wgs_per_cu, window_blocks). */
+scan_status scan_batch_set_tune(scan_ctx* ctx, const scan_tune* t);
+
+/* --------------------------------------------------------------- selector */
+/* The strategy selector is a fully connected fp32 network 6 -> 64 -> 64 -> 8
+ * (ReLU after both hidden layers) predicting a log-time for each of the eight
+ * row-major strategies: class c = decoder (c & 1: RM_LDS or RM_DIRECT),
+ * predicate mode ((c >> 1) & 1), zone maps ((c >> 2) & 1).  The library picks
+ * the class of smallest prediction among those valid for the column (zone-map
+ * classes need zone maps; ties to the lowest class).  Parameters: W1[64][6],
+ * b1[64], W2[64][64], b2[64], W3[8][64], b3[8], row-major, in that order. */
+int scan_mlp_param_count(void);
+/* Install parameters (host, scan_mlp_param_count() finite floats). */
+scan_status scan_selector_set(scan_ctx* ctx, const float* theta_host, size_t count);
+/* Back to the heuristic. */
+scan_status scan_selector_clear(scan_ctx* ctx);
+int scan_selector_loaded(const scan_ctx* ctx);
+/* Text file: "scan-mlp-v1 <count>" then the parameters, whitespace separated. */
+scan_status scan_selector_load(scan_ctx* ctx, const char* path);
+scan_status scan_selector_save(scan_ctx* ctx, const char* path);
+/* The selector's input features of n_items columns, written to X_dev (device,
+ * n_items x 6 floats, row-major), from zone maps and descriptors only:
+ *   b/32, log2(n)/24, log10(max(s, 1e-6))/6 (s: selectivity estimated from the
+ *   zone maps, values spread evenly over each block's [min, max]), fraction
+ *   of blocks whose [min, max] meets the predicate, clustering
+ *   1 - mean(max - min)/(global max - global min + 1), encoding/2.
+ * Columns without zone maps get s = 1, fraction 1, clustering 0.  Synchronous. */
+scan_status scan_features(scan_ctx* ctx, const scan_item* items, size_t n_items, float* X_dev);
+
+/* Training kernels (all pointers device, fp32, enqueued on the context stream).
+ * Forward: out[rows][8] = network(theta, X[rows][6]). */
+scan_status scan_mlp_forward(scan_ctx* ctx, const float* theta, const float* X, uint32_t rows, float* out);
+/* Masked squared error L = inv_denom * sum_{i,j} M[i][j] (out[i][j] - Y[i][j])^2
+ * and its gradient w.r.t. theta (grad: param_count floats; loss: one float,
+ * may be NULL).  Work space is owned by the context. */
+scan_status scan_mlp_loss_grad(scan_ctx* ctx, const float* theta, const float* X, const float* Y, const float* M,
+                               uint32_t rows, float inv_denom, float* grad, float* loss);
+/* One Adam update (Kingma and Ba, 2015) of `count` parameters at 1-based
+ * `step`, with bias correction. */
+scan_status scan_adam_step(scan_ctx* ctx, float* theta, const float* grad, float* m, float* v, uint32_t count,
+                           int32_t step, float lr, float beta1, float beta2, float eps);
 
 /* -------------------------------------------------------------- encoders */
 /* Host-side encoders (host pointers).  Payload buffers must hold

@@ -66,7 +66,7 @@ class ScanItem(ctypes.Structure):
 
 class ScanTune(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
-                ("min_blocks_per_wave", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("window_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _vp, _u64, _u32, _i32, _i64, _f32 = (ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32,
@@ -84,6 +84,25 @@ SIGNATURES = {
     "scan_sync": (_i32, [_vp]),
     "scan_set_tune": (_i32, [_vp, _i32, _u32, _i32, _P(ScanTune)]),
     "scan_get_tune": (_i32, [_vp, _i32, _u32, _i32, _P(ScanTune)]),
+    "scan_autotune": (_i32, [_vp, _P(ScanColumn), _i32, _u32, _P(ScanPredicate), _i32, _i32, _P(ScanTune),
+                             _P(ctypes.c_float)]),
+    "scan_tune_save": (_i32, [_vp, ctypes.c_char_p]),
+    "scan_tune_load": (_i32, [_vp, ctypes.c_char_p]),
+    "scan_batch_prepare": (_i32, [_vp, _P(ScanItem), ctypes.c_size_t, _P(_u64)]),
+    "scan_batch_replay": (_i32, [_vp, _u64, _P(ScanResult)]),
+    "scan_batch_release": (_i32, [_vp, _u64]),
+    "scan_batch_run": (_i32, [_vp, _P(ScanItem), ctypes.c_size_t, _P(ScanResult)]),
+    "scan_batch_set_tune": (_i32, [_vp, _P(ScanTune)]),
+    "scan_mlp_param_count": (ctypes.c_int, []),
+    "scan_selector_set": (_i32, [_vp, _vp, ctypes.c_size_t]),
+    "scan_selector_clear": (_i32, [_vp]),
+    "scan_selector_loaded": (ctypes.c_int, [_vp]),
+    "scan_selector_load": (_i32, [_vp, ctypes.c_char_p]),
+    "scan_selector_save": (_i32, [_vp, ctypes.c_char_p]),
+    "scan_features": (_i32, [_vp, _P(ScanItem), ctypes.c_size_t, _vp]),
+    "scan_mlp_forward": (_i32, [_vp, _vp, _vp, _u32, _vp]),
+    "scan_mlp_loss_grad": (_i32, [_vp, _vp, _vp, _vp, _vp, _u32, _f32, _vp, _vp]),
+    "scan_adam_step": (_i32, [_vp, _vp, _vp, _vp, _vp, _u32, _i32, _f32, _f32, _f32, _f32]),
     "scan_payload_words": (_u64, [_u64, _u32]),
     "scan_encode_for": (_i32, [_vp, _u64, _u32, _u32, _i32, _vp, _vp, _vp, _vp]),
     "scan_encode_delta": (_i32, [_vp, _u64, _u32, _vp, _vp, _vp, _vp]),

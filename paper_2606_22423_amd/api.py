@@ -199,15 +199,109 @@ class Context:
     def sync(self):
         self.check(self.lib.scan_sync(self.h), "scan_sync")
 
-    def set_tune(self, enc: int, b: int, strategy: int, wg_size=0, wgs_per_cu=0, min_blocks_per_wave=0):
-        t = ScanTune(wg_size, wgs_per_cu, min_blocks_per_wave, 0)
+    def set_tune(self, enc: int, b: int, strategy: int, wg_size=0, wgs_per_cu=0, window_blocks=0):
+        t = ScanTune(wg_size, wgs_per_cu, window_blocks, 0)
         self.check(self.lib.scan_set_tune(self.h, enc, b, strategy, ctypes.byref(t)), "scan_set_tune")
 
     def get_tune(self, enc: int, b: int, strategy: int) -> tuple:
         t = ScanTune()
         self.check(self.lib.scan_get_tune(self.h, enc, b, strategy, ctypes.byref(t)), "scan_get_tune")
-        return (t.wg_size, t.wgs_per_cu, t.min_blocks_per_wave)
+        return (t.wg_size, t.wgs_per_cu, t.window_blocks)
 
+    def autotune(self, col: Column, lo: int, hi: int, strategy: int, reps: int = 3, zone_maps: bool = True):
+        """Exhaustive launch-configuration search; returns ((wg, per_cu, window), best ms)."""
+        c = col.struct(zone_maps)
+        t = ScanTune()
+        ms = ctypes.c_float()
+        pred = ScanPredicate(int(lo), int(hi))
+        self.check(self.lib.scan_autotune(self.h, ctypes.byref(c), col.enc, col.b, ctypes.byref(pred), strategy,
+                                          reps, ctypes.byref(t), ctypes.byref(ms)), "scan_autotune")
+        return (t.wg_size, t.wgs_per_cu, t.window_blocks), float(ms.value)
+
+    def tune_save(self, path: str):
+        self.check(self.lib.scan_tune_save(self.h, path.encode()), "scan_tune_save")
+
+    def tune_load(self, path: str):
+        self.check(self.lib.scan_tune_load(self.h, path.encode()), "scan_tune_load")
+
+    # ------------------------------------------------------------ batches
+    @staticmethod
+    def _items(items):
+        arr = (ScanItem * max(1, len(items)))()
+        for i, it in enumerate(items):
+            arr[i] = it
+        return arr
+
+    def batch_prepare(self, items) -> int:
+        """Capture a batch of ScanItem (see Column.item); returns its handle."""
+        arr = self._items(items)
+        h = ctypes.c_uint64()
+        self.check(self.lib.scan_batch_prepare(self.h, arr, len(items), ctypes.byref(h)), "scan_batch_prepare")
+        return int(h.value)
+
+    def batch_replay(self, handle: int, n_items: int | None = None, wait: bool = True):
+        """Replay; with wait, returns the list of per-item result dicts."""
+        if not wait:
+            self.check(self.lib.scan_batch_replay(self.h, handle, None), "scan_batch_replay")
+            return None
+        out = (ScanResult * max(1, n_items or 0))()
+        self.check(self.lib.scan_batch_replay(self.h, handle, out), "scan_batch_replay")
+        return [out[i].as_dict() for i in range(n_items or 0)]
+
+    def batch_release(self, handle: int):
+        self.check(self.lib.scan_batch_release(self.h, handle), "scan_batch_release")
+
+    def batch_run(self, items) -> list:
+        arr = self._items(items)
+        out = (ScanResult * max(1, len(items)))()
+        self.check(self.lib.scan_batch_run(self.h, arr, len(items), out), "scan_batch_run")
+        return [out[i].as_dict() for i in range(len(items))]
+
+    def batch_set_tune(self, wgs_per_cu=0, window_blocks=0):
+        t = ScanTune(0, wgs_per_cu, window_blocks, 0)
+        self.check(self.lib.scan_batch_set_tune(self.h, ctypes.byref(t)), "scan_batch_set_tune")
+
+    # ----------------------------------------------------------- selector
+    @staticmethod
+    def mlp_param_count() -> int:
+        return int(_lib.load().scan_mlp_param_count())
+
+    def selector_set(self, theta):
+        """Install network parameters (any array-like of param_count floats)."""
+        a = np.ascontiguousarray(np.asarray(theta, dtype=np.float32).ravel())
+        self.check(self.lib.scan_selector_set(self.h, a.ctypes.data, a.size), "scan_selector_set")
+
+    def selector_clear(self):
+        self.check(self.lib.scan_selector_clear(self.h), "scan_selector_clear")
+
+    @property
+    def selector_loaded(self) -> bool:
+        return bool(self.lib.scan_selector_loaded(self.h))
+
+    def selector_load(self, path: str):
+        self.check(self.lib.scan_selector_load(self.h, path.encode()), "scan_selector_load")
+
+    def selector_save(self, path: str):
+        self.check(self.lib.scan_selector_save(self.h, path.encode()), "scan_selector_save")
+
+    def features(self, items, X_dev):
+        """Selector features of the items into X_dev (device float32 [len(items), 6])."""
+        arr = self._items(items)
+        self.check(self.lib.scan_features(self.h, arr, len(items), _ptr(X_dev)), "scan_features")
+
+    def mlp_forward(self, theta, X, out):
+        self.check(self.lib.scan_mlp_forward(self.h, _ptr(theta), _ptr(X), X.shape[0], _ptr(out)),
+                   "scan_mlp_forward")
+
+    def mlp_loss_grad(self, theta, X, Y, M, inv_denom: float, grad, loss=None):
+        self.check(self.lib.scan_mlp_loss_grad(self.h, _ptr(theta), _ptr(X), _ptr(Y), _ptr(M), X.shape[0],
+                                               float(inv_denom), _ptr(grad), _ptr(loss)), "scan_mlp_loss_grad")
+
+    def adam_step(self, theta, grad, m, v, step: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.check(self.lib.scan_adam_step(self.h, _ptr(theta), _ptr(grad), _ptr(m), _ptr(v), theta.numel(), step,
+                                           lr, beta1, beta2, eps), "scan_adam_step")
+
+    # ------------------------------------------------------ bandwidth probes
     def beta_read(self, buf, nbytes: int, sink, wgs=0, wg_size=0, unroll=0):
         self.check(self.lib.scan_beta_read(self.h, _ptr(buf), nbytes, wgs, wg_size, unroll, _ptr(sink)),
                    "scan_beta_read")

@@ -7,6 +7,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import os
+import re
 import subprocess
 import sys
 
@@ -28,14 +29,24 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
-def headers():
-    return [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")] + \
-        [os.path.join(ROOT, "include", "scan.h")]
+_INC = re.compile(r'^\s*#\s*include\s+"([^"]+)"', re.M)
+
+
+def deps(src: str, seen=None) -> set:
+    """The source and every local header it includes, transitively."""
+    seen = set() if seen is None else seen
+    if src in seen or not os.path.exists(src):
+        return seen
+    seen.add(src)
+    with open(src) as fh:
+        for inc in _INC.findall(fh.read()):
+            deps(os.path.normpath(os.path.join(os.path.dirname(src), inc)), seen)
+    return seen
 
 
 def _compile(src: str, force: bool) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    newest_dep = max(os.path.getmtime(h) for h in headers() + [src])
+    newest_dep = max(os.path.getmtime(h) for h in deps(src))
     if force or not os.path.exists(obj) or os.path.getmtime(obj) < newest_dep:
         cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj + ".tmp"]
         r = subprocess.run(cmd, capture_output=True, text=True)

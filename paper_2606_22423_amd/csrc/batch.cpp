@@ -1,4 +1,404 @@
-// Batched scans: host side.
+// Batched scans: host side.  A batch is planned once (validation, column
+// descriptors, work items, device buffers) and captured into one hipGraph:
+//   setup (clear slots, dictionary code ranges)
+//   -> [features -> selector MLP]  (when a selector is loaded)
+//   -> select (strategy per column, written on the device)
+//   -> bin (items into twelve class lists)
+//   -> twelve persistent class scans
+// Replaying the graph is one host call; the 32-byte result slots come back
+// with one copy.  The same column descriptors serve the single-column
+// selector (scan_run with SCAN_STRAT_AUTO) and the feature export.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "batch_kernels.h"
 #include "scan_internal.h"
 
-void destroy_batches(scan_ctx* ctx) { ctx->batches.clear(); }
+using namespace scan_dev;
+
+namespace scan_dev {
+hipError_t launch_batch_setup(const BatchArgs& a, hipStream_t st);
+hipError_t launch_batch_features(const BatchCol* cols, uint32_t n_cols, float* X, uint32_t grid, hipStream_t st);
+hipError_t launch_batch_select(BatchCol* cols, uint32_t n_cols, const float* scores, int32_t k, BatchOut* out,
+                               hipStream_t st);
+hipError_t launch_batch_bin(const BatchArgs& a, hipStream_t st);
+hipError_t launch_mlp_forward(const float* theta, const float* X, uint32_t rows, float* out, hipStream_t st);
+}  // namespace scan_dev
+
+namespace {
+
+constexpr uint32_t kMaxWindow = 64;  // a wavefront's block-survivor list holds 64 entries
+
+// Device buffers of a batch (or of the one-column selector scratch).
+struct BatchBuffers {
+  BatchCol* cols = nullptr;
+  BatchWork* work = nullptr;
+  uint32_t* lists = nullptr;
+  uint32_t* counters = nullptr;  // counts [12] then cursors [12]
+  BatchOut* out = nullptr;
+  BatchOut* out_host = nullptr;  // pinned
+  float* feats = nullptr;
+  float* scores = nullptr;
+
+  void release() {
+    for (void* p : {(void*)cols, (void*)work, (void*)lists, (void*)counters, (void*)out, (void*)feats, (void*)scores})
+      if (p) (void)hipFree(p);
+    if (out_host) (void)hipHostFree(out_host);
+    *this = BatchBuffers();
+  }
+
+  hipError_t allocate(size_t n_cols, size_t n_work) {
+    const size_t nc = std::max<size_t>(1, n_cols), nw = std::max<size_t>(1, n_work);
+    hipError_t e;
+    if ((e = hipMalloc(&cols, sizeof(BatchCol) * nc)) != hipSuccess) return e;
+    if ((e = hipMalloc(&work, sizeof(BatchWork) * nw)) != hipSuccess) return e;
+    if ((e = hipMalloc(&lists, sizeof(uint32_t) * nw * kBatchClasses)) != hipSuccess) return e;
+    if ((e = hipMalloc(&counters, sizeof(uint32_t) * 2 * kBatchClasses)) != hipSuccess) return e;
+    if ((e = hipMalloc(&out, sizeof(BatchOut) * nc)) != hipSuccess) return e;
+    if ((e = hipMalloc(&feats, sizeof(float) * 6 * nc)) != hipSuccess) return e;
+    if ((e = hipMalloc(&scores, sizeof(float) * 8 * nc)) != hipSuccess) return e;
+    return hipHostMalloc(&out_host, sizeof(BatchOut) * nc, hipHostMallocDefault);
+  }
+};
+
+BatchArgs make_args(const BatchBuffers& m, uint32_t n_cols, uint32_t n_work, int cls) {
+  BatchArgs a;
+  a.cols = m.cols;
+  a.work = m.work;
+  a.lists = m.lists;
+  a.counts = m.counters;
+  a.cursors = m.counters + kBatchClasses;
+  a.out = m.out;
+  a.n_cols = n_cols;
+  a.n_work = n_work;
+  a.cls = cls;
+  a.pad = 0;
+  return a;
+}
+
+// Host descriptors of the columns, their validation status and the work
+// items (windows of up to `window` blocks of every non-empty valid column).
+void plan_cols(scan_ctx* ctx, const scan_item* items, size_t n, uint32_t window, std::vector<BatchCol>& cols,
+               std::vector<int32_t>& status, std::vector<BatchWork>* work) {
+  cols.resize(n);
+  status.assign(n, SCAN_OK);
+  for (size_t i = 0; i < n; ++i) {
+    const scan_item& it = items[i];
+    BatchCol c;
+    std::memset(&c, 0, sizeof c);
+    c.requested = it.strategy;
+    c.enc = it.enc;
+    c.b = it.b;
+    scan_status st = validate_column(ctx, &it.col, it.enc, it.b);
+    if (st == SCAN_OK && it.col.layout != SCAN_LAYOUT_RM)
+      st = fail(ctx, SCAN_EUNSUPPORTED, "batched scans read row-major columns");
+    if (st == SCAN_OK && it.strategy >= 0) {
+      st = check_strategy(ctx, &it.col, it.enc, it.b, it.strategy);
+      const int dec = it.strategy & 3;
+      if (st == SCAN_OK && dec != SCAN_DEC_RM_LDS && dec != SCAN_DEC_RM_DIRECT)
+        st = fail(ctx, SCAN_EUNSUPPORTED, "batched scans use the RM-LDS or RM-direct decoder");
+    }
+    if (st != SCAN_OK) {
+      status[i] = st;
+      c.flags = kColSkip;
+      c.strategy = it.strategy;
+      cols[i] = c;
+      continue;
+    }
+    c.payload = it.col.payload;
+    c.refs = it.col.block_ref;
+    c.bases = it.col.block_base;
+    c.dict = it.col.dict;
+    c.dict_len = it.col.dict_len;
+    c.zmin = it.col.zone_min;
+    c.zmax = it.col.zone_max;
+    c.n = it.col.n;
+    c.nb = (it.col.n + SCAN_BLOCK_VALUES - 1) / SCAN_BLOCK_VALUES;
+    c.tail = c.nb ? (uint32_t)(it.col.n - (c.nb - 1) * SCAN_BLOCK_VALUES) : 0u;
+    c.lo = it.pred.lo;
+    c.hi = it.pred.hi;
+    bool empty = it.col.n == 0 || it.pred.lo >= it.pred.hi;
+    if (it.enc == SCAN_ENC_FOR && !empty) {
+      const int64_t lo = std::max<int64_t>(it.pred.lo, 0), hi = std::min<int64_t>(it.pred.hi, (int64_t)1 << 32);
+      if (lo >= hi) empty = true;
+      else {
+        c.lo32 = (uint32_t)lo;
+        c.hi32m1 = (uint32_t)(hi - 1);
+      }
+    }
+    const bool zm = it.col.zone_min != nullptr;
+    c.flags = (empty ? kColEmpty : 0u) | (zm ? kColHasZm : 0u);
+    uint32_t mask = 0;
+    for (int q = 0; q < 8; ++q)
+      if (zm || !((q >> 2) & 1)) mask |= 1u << q;
+    c.valid_mask = mask;
+    int32_t h = heuristic_strategy(&it.col, it.enc, it.b);
+    if ((h & 3) != SCAN_DEC_RM_LDS && (h & 3) != SCAN_DEC_RM_DIRECT) h = (h & ~3) | SCAN_DEC_RM_DIRECT;
+    c.heuristic = h;
+    c.strategy = it.strategy >= 0 ? it.strategy : h;
+    cols[i] = c;
+    if (work && !empty)
+      for (uint64_t k = 0; k < c.nb; k += window)
+        work->push_back(BatchWork{(uint32_t)i, (uint32_t)std::min<uint64_t>(window, c.nb - k), k});
+  }
+}
+
+// Setup, then (with a selector) features and network scores, then selection:
+// enqueued on `st`.
+hipError_t enqueue_select(scan_ctx* ctx, const BatchBuffers& m, uint32_t n_cols, bool use_selector, hipStream_t st) {
+  hipError_t e = launch_batch_setup(make_args(m, n_cols, 0, 0), st);
+  if (e != hipSuccess || n_cols == 0) return e;
+  if (use_selector) {
+    e = launch_batch_features(m.cols, n_cols, m.feats, (uint32_t)ctx->cus * 4u, st);
+    if (e != hipSuccess) return e;
+    e = launch_mlp_forward(selector_theta(ctx), m.feats, n_cols, m.scores, st);
+    if (e != hipSuccess) return e;
+  }
+  return launch_batch_select(m.cols, n_cols, use_selector ? m.scores : nullptr, 8, m.out, st);
+}
+
+}  // namespace
+
+struct BatchPlan {
+  size_t n_items = 0;
+  uint32_t n_work = 0;
+  std::vector<BatchCol> cols;
+  std::vector<int32_t> status;
+  BatchBuffers mem;
+  bool selector = false;
+  uint32_t grid = 0;
+  hipStream_t stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static void free_plan(BatchPlan* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+  b->mem.release();
+  delete b;
+}
+
+// One-column scratch of the selector path of scan_run, per context.
+struct PickScratch {
+  BatchBuffers mem;
+};
+static std::map<const scan_ctx*, PickScratch*>& pick_scratch() {
+  static std::map<const scan_ctx*, PickScratch*> m;
+  return m;
+}
+
+void destroy_batches(scan_ctx* ctx) {
+  for (auto& kv : ctx->batches) free_plan(kv.second);
+  ctx->batches.clear();
+  auto& ps = pick_scratch();
+  auto it = ps.find(ctx);
+  if (it != ps.end()) {
+    it->second->mem.release();
+    delete it->second;
+    ps.erase(it);
+  }
+}
+
+static hipError_t enqueue_batch(scan_ctx* ctx, BatchPlan* b, hipStream_t st) {
+  hipError_t e = enqueue_select(ctx, b->mem, (uint32_t)b->n_items, b->selector, st);
+  if (e != hipSuccess || b->n_work == 0) return e;
+  e = launch_batch_bin(make_args(b->mem, (uint32_t)b->n_items, b->n_work, 0), st);
+  if (e != hipSuccess) return e;
+  for (int cls = 0; cls < kBatchClasses; ++cls) {
+    e = batch_class_fn(cls)(make_args(b->mem, (uint32_t)b->n_items, b->n_work, cls), b->grid, 256, st, nullptr);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+static void fill_results(const BatchPlan* b, scan_result* out) {
+  for (size_t i = 0; i < b->n_items; ++i) {
+    scan_result r;
+    std::memset(&r, 0, sizeof r);
+    const BatchCol& c = b->cols[i];
+    r.status = b->status[i];
+    if (r.status == SCAN_OK) {
+      const BatchOut& o = b->mem.out_host[i];
+      const int32_t s = (int32_t)o.pad;
+      r.count = o.count;
+      r.sum = (int64_t)o.sum;
+      r.blocks_total = c.nb;
+      r.strategy_used = s;
+      // An empty predicate reads nothing; without zone maps the scan still
+      // accounts every block, as a single-column scan does.
+      if (c.flags & kColEmpty) r.blocks_read = (c.lo < c.hi && !((s >> 3) & 1)) ? c.nb : 0;
+      else r.blocks_read = o.blocks;
+    } else {
+      r.strategy_used = c.requested;
+    }
+    out[i] = r;
+  }
+}
+
+// Strategy for one column from the loaded selector (synchronous).
+scan_status selector_pick(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b, const scan_predicate* pred,
+                          int32_t* out) {
+  if (!ctx->selector_ready) return fail(ctx, SCAN_EUNSUPPORTED, "no selector loaded");
+  if (col->layout != SCAN_LAYOUT_RM) return fail(ctx, SCAN_EUNSUPPORTED, "the selector covers row-major columns");
+  scan_item it;
+  std::memset(&it, 0, sizeof it);
+  it.col = *col;
+  it.enc = enc;
+  it.b = b;
+  it.pred = *pred;
+  it.agg = SCAN_AGG_COUNT | SCAN_AGG_SUM;
+  it.strategy = SCAN_STRAT_AUTO;
+  std::vector<BatchCol> cols;
+  std::vector<int32_t> status;
+  plan_cols(ctx, &it, 1, kMaxWindow, cols, status, nullptr);
+  if (status[0] != SCAN_OK) return (scan_status)status[0];
+  auto& ps = pick_scratch();
+  PickScratch*& sc = ps[ctx];
+  if (!sc) {
+    sc = new PickScratch();
+    const hipError_t e = sc->mem.allocate(1, 1);
+    if (e != hipSuccess) {
+      sc->mem.release();
+      delete sc;
+      ps.erase(ctx);
+      return fail(ctx, SCAN_ENOMEM, "selector scratch: %s", hipGetErrorString(e));
+    }
+  }
+  hipError_t e = hipMemcpyAsync(sc->mem.cols, cols.data(), sizeof(BatchCol), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = enqueue_select(ctx, sc->mem, 1, true, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(sc->mem.out_host, sc->mem.out, sizeof(BatchOut), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "selector");
+  *out = (int32_t)sc->mem.out_host[0].pad;
+  return SCAN_OK;
+}
+
+extern "C" {
+
+scan_status scan_batch_prepare(scan_ctx* ctx, const scan_item* items, size_t n_items, uint64_t* handle) {
+  if (!ctx) return SCAN_EINVAL;
+  if (!handle || (n_items && !items)) return fail(ctx, SCAN_EINVAL, "items and handle must not be NULL");
+  if (n_items > (1u << 24)) return fail(ctx, SCAN_EINVAL, "at most 2^24 items per batch");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  const scan_tune t = effective_tune(ctx, -1, 0, -1);
+  const uint32_t window = (uint32_t)std::clamp(t.window_blocks, 1, (int)kMaxWindow);
+  BatchPlan* b = new BatchPlan();
+  b->n_items = n_items;
+  b->selector = ctx->selector_ready;
+  b->grid = (uint32_t)ctx->cus * (uint32_t)std::clamp(t.wgs_per_cu, 1, 16);
+  std::vector<BatchWork> work;
+  plan_cols(ctx, items, n_items, window, b->cols, b->status, &work);
+  if (work.size() > 0xFFFFFFFFull) {
+    free_plan(b);
+    return fail(ctx, SCAN_EINVAL, "too many work items");
+  }
+  b->n_work = (uint32_t)work.size();
+  e = b->mem.allocate(n_items, work.size());
+  if (e != hipSuccess) {
+    free_plan(b);
+    return fail(ctx, SCAN_ENOMEM, "batch buffers: %s", hipGetErrorString(e));
+  }
+  if (n_items) e = hipMemcpy(b->mem.cols, b->cols.data(), sizeof(BatchCol) * n_items, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !work.empty())
+    e = hipMemcpy(b->mem.work, work.data(), sizeof(BatchWork) * work.size(), hipMemcpyHostToDevice);
+  // Capture on a private stream of default priority; replays go to the
+  // context's stream.
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) {
+    e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      const hipError_t e2 = enqueue_batch(ctx, b, b->stream);
+      e = hipStreamEndCapture(b->stream, &b->graph);
+      if (e2 != hipSuccess) e = e2;
+    }
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    free_plan(b);
+    return hip_fail(ctx, e, "batch graph");
+  }
+  const uint64_t h = ctx->next_batch++;
+  ctx->batches[h] = b;
+  *handle = h;
+  return SCAN_OK;
+}
+
+scan_status scan_batch_replay(scan_ctx* ctx, uint64_t handle, scan_result* out) {
+  if (!ctx) return SCAN_EINVAL;
+  auto it = ctx->batches.find(handle);
+  if (it == ctx->batches.end()) return fail(ctx, SCAN_EINVAL, "unknown batch handle %llu", (unsigned long long)handle);
+  BatchPlan* b = it->second;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = hipGraphLaunch(b->exec, ctx->stream);
+  if (e == hipSuccess && out && b->n_items)
+    e = hipMemcpyAsync(b->mem.out_host, b->mem.out, sizeof(BatchOut) * b->n_items, hipMemcpyDeviceToHost,
+                       ctx->stream);
+  if (e == hipSuccess && out) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "batch replay");
+  if (out) fill_results(b, out);
+  return SCAN_OK;
+}
+
+scan_status scan_batch_release(scan_ctx* ctx, uint64_t handle) {
+  if (!ctx) return SCAN_EINVAL;
+  auto it = ctx->batches.find(handle);
+  if (it == ctx->batches.end()) return fail(ctx, SCAN_EINVAL, "unknown batch handle %llu", (unsigned long long)handle);
+  (void)hipStreamSynchronize(ctx->stream);
+  free_plan(it->second);
+  ctx->batches.erase(it);
+  return SCAN_OK;
+}
+
+scan_status scan_batch_run(scan_ctx* ctx, const scan_item* items, size_t n_items, scan_result* out) {
+  if (!ctx) return SCAN_EINVAL;
+  if (!out && n_items) return fail(ctx, SCAN_EINVAL, "out must not be NULL");
+  uint64_t h = 0;
+  scan_status st = scan_batch_prepare(ctx, items, n_items, &h);
+  if (st != SCAN_OK) return st;
+  st = scan_batch_replay(ctx, h, out);
+  const scan_status st2 = scan_batch_release(ctx, h);
+  return st != SCAN_OK ? st : st2;
+}
+
+scan_status scan_batch_set_tune(scan_ctx* ctx, const scan_tune* t) {
+  if (!ctx) return SCAN_EINVAL;
+  if (!t) return fail(ctx, SCAN_EINVAL, "tune is NULL");
+  if (t->wgs_per_cu < 0 || t->wgs_per_cu > 16) return fail(ctx, SCAN_EINVAL, "wgs_per_cu must be in 0..16");
+  if (t->window_blocks < 0 || t->window_blocks > (int)kMaxWindow)
+    return fail(ctx, SCAN_EINVAL, "window_blocks must be in 0..%u", kMaxWindow);
+  ctx->tunes[std::make_tuple((int32_t)-1, 0u, (int32_t)-1)] = *t;
+  return SCAN_OK;
+}
+
+scan_status scan_features(scan_ctx* ctx, const scan_item* items, size_t n_items, float* X_dev) {
+  if (!ctx) return SCAN_EINVAL;
+  if (n_items == 0) return SCAN_OK;
+  if (!items || !X_dev) return fail(ctx, SCAN_EINVAL, "items and X must not be NULL");
+  if (n_items > (1u << 24)) return fail(ctx, SCAN_EINVAL, "at most 2^24 items");
+  std::vector<BatchCol> cols;
+  std::vector<int32_t> status;
+  plan_cols(ctx, items, n_items, kMaxWindow, cols, status, nullptr);
+  for (size_t i = 0; i < n_items; ++i)
+    if (status[i] != SCAN_OK) return (scan_status)status[i];
+  BatchBuffers m;
+  hipError_t e = m.allocate(n_items, 1);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(m.cols, cols.data(), sizeof(BatchCol) * n_items, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = launch_batch_setup(make_args(m, (uint32_t)n_items, 0, 0), ctx->stream);
+  if (e == hipSuccess)
+    e = launch_batch_features(m.cols, (uint32_t)n_items, X_dev, (uint32_t)ctx->cus * 4u, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  m.release();
+  if (e != hipSuccess) return hip_fail(ctx, e, "features");
+  return SCAN_OK;
+}
+
+}  // extern "C"

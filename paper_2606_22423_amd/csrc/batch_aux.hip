@@ -1,0 +1,203 @@
+// Batch graph kernels around the class scans: per-column setup, zone-map
+// features for the selector, strategy selection and item binning.
+#include "batch_kernels.h"
+
+namespace scan_dev {
+
+hipError_t launch_batch_for_lds_bf(const BatchArgs&, uint32_t, uint32_t, hipStream_t, int*);
+hipError_t launch_batch_for_lds_sv(const BatchArgs&, uint32_t, uint32_t, hipStream_t, int*);
+hipError_t launch_batch_for_direct_bf(const BatchArgs&, uint32_t, uint32_t, hipStream_t, int*);
+hipError_t launch_batch_for_direct_sv(const BatchArgs&, uint32_t, uint32_t, hipStream_t, int*);
+hipError_t launch_batch_delta_lds_bf(const BatchArgs&, uint32_t, uint32_t, hipStream_t, int*);
+hipError_t launch_batch_delta_lds_sv(const BatchArgs&, uint32_t, uint32_t, hipStream_t, int*);
+hipError_t launch_batch_delta_direct_bf(const BatchArgs&, uint32_t, uint32_t, hipStream_t, int*);
+hipError_t launch_batch_delta_direct_sv(const BatchArgs&, uint32_t, uint32_t, hipStream_t, int*);
+hipError_t launch_batch_dict_lds_bf(const BatchArgs&, uint32_t, uint32_t, hipStream_t, int*);
+hipError_t launch_batch_dict_lds_sv(const BatchArgs&, uint32_t, uint32_t, hipStream_t, int*);
+hipError_t launch_batch_dict_direct_bf(const BatchArgs&, uint32_t, uint32_t, hipStream_t, int*);
+hipError_t launch_batch_dict_direct_sv(const BatchArgs&, uint32_t, uint32_t, hipStream_t, int*);
+
+BatchLaunchFn batch_class_fn(int cls) {
+  static const BatchLaunchFn table[kBatchClasses] = {launch_batch_for_lds_bf, launch_batch_for_lds_sv, launch_batch_for_direct_bf, launch_batch_for_direct_sv, launch_batch_delta_lds_bf, launch_batch_delta_lds_sv, launch_batch_delta_direct_bf, launch_batch_delta_direct_sv, launch_batch_dict_lds_bf, launch_batch_dict_lds_sv, launch_batch_dict_direct_bf, launch_batch_dict_direct_sv};
+  return (cls >= 0 && cls < kBatchClasses) ? table[cls] : nullptr;
+}
+
+// Per column: clear the result slot, find a dictionary's code range
+// [lower_bound(D, lo), lower_bound(D, hi)) by binary search in global memory.
+// Thread 0 also clears the per-class counters and cursors.
+__global__ __launch_bounds__(256) void batch_setup_kernel(BatchArgs a) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    for (int c = 0; c < kBatchClasses; ++c) {
+      a.counts[c] = 0;
+      a.cursors[c] = 0;
+    }
+  }
+  if (i >= a.n_cols) return;
+  a.out[i] = BatchOut{0, 0, 0, 0};
+  BatchCol& c = a.cols[i];
+  if (c.enc == ENC_DICT && c.dict_len) {
+    uint32_t lo = 0, e = c.dict_len;
+    while (lo < e) {
+      const uint32_t m = (lo + e) >> 1;
+      if (c.dict[m] < c.lo) lo = m + 1u;
+      else e = m;
+    }
+    uint32_t lo2 = 0, e2 = c.dict_len;
+    while (lo2 < e2) {
+      const uint32_t m = (lo2 + e2) >> 1;
+      if (c.dict[m] < c.hi) lo2 = m + 1u;
+      else e2 = m;
+    }
+    c.clo = lo;
+    c.chi = lo2;
+  }
+}
+
+__device__ __forceinline__ double wave_sum_f64(double x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+__device__ __forceinline__ double wave_min_f64(double x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x = fmin(x, __shfl_xor(x, o, 64));
+  return x;
+}
+__device__ __forceinline__ double wave_max_f64(double x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+  return x;
+}
+
+// Selector features of each column from its zone maps only (one wavefront per
+// column, fp64 accumulation):
+//   f0 = b/32, f1 = log2(n)/24,
+//   f2 = log10(max(s, 1e-6))/6 with s = sum_k c_k overlap_k / n, overlap_k the
+//        share of block k's [min, max] covered by [lo, hi) (values spread evenly),
+//   f3 = fraction of blocks whose [min, max] meets [lo, hi),
+//   f4 = 1 - mean_k(max_k - min_k) / (max(max) - min(min) + 1) (clustering),
+//   f5 = encoding / 2.
+// Dictionary columns use codes and the code range; columns without zone maps
+// get s = 1, f3 = 1, f4 = 0.
+__global__ __launch_bounds__(256) void batch_features_kernel(const BatchCol* cols, uint32_t n_cols, float* X) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint32_t tw = (gridDim.x * blockDim.x) >> 6;
+  for (uint32_t col = gw; col < n_cols; col += tw) {
+    const BatchCol c = cols[col];
+    double lo, hi;
+    if (c.enc == ENC_DICT) {
+      lo = (double)c.clo;
+      hi = (double)c.chi;
+    } else {
+      lo = (double)c.lo;
+      hi = (double)c.hi;
+    }
+    double s = 1.0, frac = 1.0, clust = 0.0;
+    if ((c.flags & kColHasZm) && c.nb) {
+      double acc = 0.0, meet = 0.0, spread = 0.0, gmin = 1e300, gmax = -1e300;
+      for (uint64_t k = lane; k < c.nb; k += 64) {
+        double mn, mx;
+        if (c.enc == ENC_DELTA) {
+          mn = (double)static_cast<const int64_t*>(c.zmin)[k];
+          mx = (double)static_cast<const int64_t*>(c.zmax)[k];
+        } else {
+          mn = (double)static_cast<const uint32_t*>(c.zmin)[k];
+          mx = (double)static_cast<const uint32_t*>(c.zmax)[k];
+        }
+        const double cnt = (k == c.nb - 1) ? (double)c.tail : 1024.0;
+        if (lo < hi) {
+          const double ov = fmax(fmin(hi, mx + 1.0) - fmax(lo, mn), 0.0) / (mx - mn + 1.0);
+          acc += cnt * ov;
+          meet += (mx < lo || mn >= hi) ? 0.0 : 1.0;
+        }
+        spread += mx - mn;
+        gmin = fmin(gmin, mn);
+        gmax = fmax(gmax, mx);
+      }
+      acc = wave_sum_f64(acc);
+      meet = wave_sum_f64(meet);
+      spread = wave_sum_f64(spread);
+      gmin = wave_min_f64(gmin);
+      gmax = wave_max_f64(gmax);
+      s = acc / (double)c.n;
+      frac = meet / (double)c.nb;
+      clust = 1.0 - (spread / (double)c.nb) / (gmax - gmin + 1.0);
+    }
+    if (!(lo < hi)) s = 0.0;
+    if (lane == 0) {
+      float* x = X + (size_t)col * 6u;
+      x[0] = (float)((double)c.b / 32.0);
+      x[1] = (float)(log2((double)c.n) / 24.0);
+      x[2] = (float)(log10(fmax(s, 1e-6)) / 6.0);
+      x[3] = (float)frac;
+      x[4] = (float)clust;
+      x[5] = (float)((double)c.enc / 2.0);
+    }
+  }
+}
+
+// Strategy per column: the requested one, else the argmin over the selector's
+// allowed classes (ties to the lowest class; class c = decoder c&1, SV (c>>1)&1,
+// zone maps (c>>2)&1), else the heuristic when no selector scores are given.
+// The choice is also recorded in the column's result slot.
+__global__ __launch_bounds__(256) void batch_select_kernel(BatchCol* cols, uint32_t n_cols, const float* scores,
+                                                           int32_t k, BatchOut* out) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_cols) return;
+  BatchCol& c = cols[i];
+  int32_t s = c.requested;
+  if (s < 0) {
+    s = c.heuristic;
+    if (scores) {
+      float best = 0.0f;
+      int bc = -1;
+      for (int q = 0; q < k; ++q) {
+        if (!((c.valid_mask >> q) & 1u)) continue;
+        const float v = scores[(size_t)i * k + q];
+        if (bc < 0 || v < best) {
+          best = v;
+          bc = q;
+        }
+      }
+      if (bc >= 0) s = (bc & 1) | (((bc >> 1) & 1) << 2) | (((bc >> 2) & 1) << 3);
+    }
+  }
+  c.strategy = s;
+  out[i].pad = (uint64_t)(uint32_t)s;
+}
+
+// Items into per-class lists.
+__global__ __launch_bounds__(256) void batch_bin_kernel(BatchArgs a) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n_work) return;
+  const BatchCol& c = a.cols[a.work[i].col];
+  if (c.flags & (kColEmpty | kColSkip)) return;
+  const int cls = batch_class(c.enc, c.strategy);
+  const uint32_t pos = atomicAdd(&a.counts[cls], 1u);
+  a.lists[(size_t)cls * a.n_work + pos] = i;
+}
+
+hipError_t launch_batch_setup(const BatchArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(batch_setup_kernel, dim3((a.n_cols + 255) / 256 + 1), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_features(const BatchCol* cols, uint32_t n_cols, float* X, uint32_t grid, hipStream_t st) {
+  hipLaunchKernelGGL(batch_features_kernel, dim3(grid), dim3(256), 0, st, cols, n_cols, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_select(BatchCol* cols, uint32_t n_cols, const float* scores, int32_t k, BatchOut* out,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(batch_select_kernel, dim3((n_cols + 255) / 256), dim3(256), 0, st, cols, n_cols, scores, k, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_bin(const BatchArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(batch_bin_kernel, dim3((a.n_work + 255) / 256), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace scan_dev

@@ -1,0 +1,182 @@
+// Batched scans: thousands of columns of mixed length, width, encoding and
+// strategy in one captured graph.
+//
+// Each column is cut into work items of up to G blocks.  A binning kernel
+// sorts the items into twelve classes (encoding x decoder x predicate mode),
+// reading each column's strategy from device memory (so a selector kernel that
+// ran earlier in the same graph decides it), and one persistent kernel per
+// class drains its item list through an atomic cursor: a wavefront takes an
+// item, switches (wave-uniformly) on the column's width to the same templated
+// range decoders the single-column kernels use, and adds its exact partial
+// (count, sum mod 2^64, blocks read) to the column's slot with three 64-bit
+// atomics.  Zone maps on/off is a per-column run-time flag.
+#pragma once
+
+#include "scan_kernels.h"
+
+namespace scan_dev {
+
+constexpr int kBatchClasses = 12;  // enc (3) x decoder {RM-LDS, RM-direct} x mode {BF, SV}
+
+// One batch column (device).
+struct BatchCol {
+  const uint32_t* payload;
+  const uint32_t* refs;
+  const int64_t* bases;
+  const int64_t* dict;
+  const void* zmin;
+  const void* zmax;
+  uint64_t n, nb;
+  int64_t lo, hi;
+  uint32_t lo32, hi32m1;  // FOR: predicate clamped to the u32 domain
+  uint32_t dict_len, tail;
+  uint32_t b;
+  int32_t enc;
+  int32_t requested;      // strategy asked for, or -1 (choose on device)
+  int32_t strategy;       // strategy used (written on device)
+  uint32_t clo, chi;      // dictionary code range (written on device)
+  uint32_t valid_mask;    // selector classes allowed for this column (bit c)
+  uint32_t flags;         // kColEmpty | kColHasZm | kColSkip
+  int32_t heuristic;      // strategy used when no selector is loaded
+  uint32_t pad;
+};
+
+enum : uint32_t { kColEmpty = 1u, kColHasZm = 2u, kColSkip = 4u };
+
+struct BatchWork {
+  uint32_t col;
+  uint32_t nblk;
+  uint64_t k0;
+};
+
+struct BatchOut {
+  uint64_t count, sum, blocks;
+  uint64_t pad;  // strategy used (written by the selection kernel)
+};
+
+struct BatchArgs {
+  BatchCol* cols;
+  const BatchWork* work;
+  uint32_t* lists;     // kBatchClasses lists of n_work item indices
+  uint32_t* counts;    // kBatchClasses item counts
+  uint32_t* cursors;   // kBatchClasses atomic cursors
+  BatchOut* out;       // per column
+  uint32_t n_cols, n_work;
+  int32_t cls;         // class handled by this launch
+  uint32_t pad;
+};
+
+__host__ __device__ inline int batch_class(int enc, int strategy) {
+  return enc * 4 + (strategy & 1) * 2 + ((strategy >> 2) & 1);
+}
+
+__device__ __forceinline__ Params batch_params(const BatchCol& c) {
+  Params p;
+  p.payload = c.payload;
+  p.refs = c.refs;
+  p.bases = c.bases;
+  p.dict = c.dict;
+  p.zmin = c.zmin;
+  p.zmax = c.zmax;
+  p.n = c.n;
+  p.nb = c.nb;
+  p.units = 0;
+  p.lo = c.lo;
+  p.hi = c.hi;
+  p.lo32 = c.lo32;
+  p.hi32m1 = c.hi32m1;
+  p.dict_len = c.dict_len;
+  p.G = 0;
+  p.use_zm = (c.strategy >> 3) & 1;
+  p.tail = c.tail;
+  p.strategy = c.strategy;
+  p.pad0 = 0;
+  p.partials = nullptr;
+  p.ticket = nullptr;
+  p.out = nullptr;
+  return p;
+}
+
+constexpr uint32_t kBatchWaveWords = kListWords + 32u * 32u + 4u + 2u * kRingEntries;
+
+template <int B, int ENC, int DEC, int MODE>
+__device__ __forceinline__ void batch_item(const Params& p, const BatchCol& c, uint64_t k0, uint64_t k1,
+                                           uint32_t lane, uint32_t* list, uint32_t* st, BatchOut* out) {
+  uint64_t count, blocks, lsum;
+  if constexpr (ENC == ENC_DELTA) {
+    WaveState<RelT<B>> s;
+    s.ring = reinterpret_cast<RelT<B>*>(st + 32u * 32u + 4u);
+    delta_range<B, DEC, MODE, true>(p, s, lane, list, st, k0, k1, 64, 64);
+    if constexpr (MODE == MODE_SV) sv_drain_rest<ENC_DELTA, RelT<B>>(s, lane, nullptr, 0);
+    count = s.count + wave_sum_u64(s.lcount);
+    blocks = s.blocks;
+    lsum = s.lsum + (lane == 0 ? s.refsum : 0ull);
+  } else {
+    WaveState<uint32_t> s;
+    s.ring = st + 32u * 32u + 4u;
+    const uint32_t dlast = c.dict_len ? c.dict_len - 1u : 0u;
+    if (ENC == ENC_FOR && c.refs)
+      scan_range<B, DEC, MODE, ENC, PF_REFS, true>(p, s, lane, list, st, k0, k1, 64, 64, c.dict, dlast, c.clo, c.chi);
+    else
+      scan_range<B, DEC, MODE, ENC, PF_RANGE, true>(p, s, lane, list, st, k0, k1, 64, 64, c.dict, dlast, c.clo,
+                                                    c.chi);
+    if constexpr (MODE == MODE_SV) sv_drain_rest<ENC, uint32_t>(s, lane, c.dict, dlast);
+    count = s.count + wave_sum_u64(s.lcount);
+    blocks = s.blocks;
+    lsum = s.lsum + (lane == 0 ? s.refsum : 0ull);
+  }
+  const uint64_t sum = wave_sum_u64(lsum);
+  if (lane == 0) {
+    atomicAdd(reinterpret_cast<unsigned long long*>(&out->count), (unsigned long long)count);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&out->sum), (unsigned long long)sum);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&out->blocks), (unsigned long long)blocks);
+  }
+}
+
+#define SCAN_WIDTHS_ALL(F)                                                                                \
+  F(1) F(2) F(3) F(4) F(5) F(6) F(7) F(8) F(9) F(10) F(11) F(12) F(13) F(14) F(15) F(16) F(17) F(18) F(19) F(20) \
+      F(21) F(22) F(23) F(24) F(25) F(26) F(27) F(28) F(29) F(30) F(31) F(32)
+
+#define BATCH_CASE(B)                                                              \
+  case B:                                                                          \
+    batch_item<B, ENC, DEC, MODE>(p, c, w.k0, w.k0 + w.nblk, lane, list, st, out); \
+    break;
+
+template <int ENC, int DEC, int MODE>
+__global__ __launch_bounds__(256) void batch_scan(const BatchArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  uint32_t* list = reinterpret_cast<uint32_t*>(smem) + wave * kBatchWaveWords;
+  uint32_t* st = list + kListWords;
+  const uint32_t n = a.counts[a.cls];
+  const uint32_t* items = a.lists + (size_t)a.cls * a.n_work;
+  while (true) {
+    uint32_t idx = 0;
+    if (lane == 0) idx = atomicAdd(&a.cursors[a.cls], 1u);
+    idx = __shfl(idx, 0, 64);
+    if (idx >= n) break;
+    const BatchWork w = a.work[items[idx]];
+    const BatchCol c = a.cols[w.col];
+    const Params p = batch_params(c);
+    BatchOut* out = a.out + w.col;
+    switch (c.b) {
+      SCAN_WIDTHS_ALL(BATCH_CASE)
+      default: break;
+    }
+  }
+}
+
+using BatchLaunchFn = hipError_t (*)(const BatchArgs&, uint32_t grid, uint32_t block, hipStream_t st, int* occ);
+
+template <int ENC, int DEC, int MODE>
+hipError_t launch_batch_class(const BatchArgs& a, uint32_t grid, uint32_t block, hipStream_t st, int* occ) {
+  const uint32_t lds = (block / 64u) * kBatchWaveWords * 4u;
+  if (occ) return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, batch_scan<ENC, DEC, MODE>, (int)block, lds);
+  hipLaunchKernelGGL((batch_scan<ENC, DEC, MODE>), dim3(grid), dim3(block), lds, st, a);
+  return hipGetLastError();
+}
+
+// Defined in the k_batch_*.hip instantiation units; indexed by batch_class().
+BatchLaunchFn batch_class_fn(int cls);
+
+}  // namespace scan_dev

@@ -1,0 +1,12 @@
+// Instantiation unit: code_fn_rm_lds_d (widths 17-32).
+#include "launch_tables.h"
+
+namespace scan_dev {
+#define CASE(B) \
+  case B:       \
+    return pick_code<B, DEC_RM_LDS>(enc, mode, pf);
+LaunchFn code_fn_rm_lds_d(int enc, int mode, int pf, int b) {
+  switch (b) { SCAN_WIDTHS_17_32(CASE) }
+  return nullptr;
+}
+}  // namespace scan_dev

@@ -1,4 +1,4 @@
-// Instantiation unit: code_fn_li_b (widths B).
+// Instantiation unit: code_fn_li_b (widths 5-8).
 #include "launch_tables.h"
 
 namespace scan_dev {
@@ -6,7 +6,7 @@ namespace scan_dev {
   case B:       \
     return pick_code<B, DEC_LI>(enc, mode, pf);
 LaunchFn code_fn_li_b(int enc, int mode, int pf, int b) {
-  switch (b) { SCAN_WIDTHS_B(CASE) }
+  switch (b) { SCAN_WIDTHS_5_8(CASE) }
   return nullptr;
 }
 }  // namespace scan_dev

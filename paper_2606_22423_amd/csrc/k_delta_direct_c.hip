@@ -1,0 +1,12 @@
+// Instantiation unit: delta_fn_rm_direct_c (widths 9-16).
+#include "launch_tables.h"
+
+namespace scan_dev {
+#define CASE(B) \
+  case B:       \
+    return pick_delta<B, DEC_RM_DIRECT>(mode);
+LaunchFn delta_fn_rm_direct_c(int mode, int b) {
+  switch (b) { SCAN_WIDTHS_9_16(CASE) }
+  return nullptr;
+}
+}  // namespace scan_dev

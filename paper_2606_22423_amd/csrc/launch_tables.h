@@ -69,20 +69,32 @@ LaunchFn pick_delta(int mode) {
   return mode == MODE_BF ? &launch_delta<B, DEC, MODE_BF> : &launch_delta<B, DEC, MODE_SV>;
 }
 
-// Defined in the k_*.hip instantiation units.
+// Defined in the k_*.hip instantiation units (widths 1-4, 5-8, 9-16, 17-32).
 LaunchFn code_fn_rm_lds_a(int enc, int mode, int pf, int b);
 LaunchFn code_fn_rm_lds_b(int enc, int mode, int pf, int b);
+LaunchFn code_fn_rm_lds_c(int enc, int mode, int pf, int b);
+LaunchFn code_fn_rm_lds_d(int enc, int mode, int pf, int b);
 LaunchFn code_fn_rm_direct_a(int enc, int mode, int pf, int b);
 LaunchFn code_fn_rm_direct_b(int enc, int mode, int pf, int b);
+LaunchFn code_fn_rm_direct_c(int enc, int mode, int pf, int b);
+LaunchFn code_fn_rm_direct_d(int enc, int mode, int pf, int b);
 LaunchFn code_fn_li_a(int enc, int mode, int pf, int b);
 LaunchFn code_fn_li_b(int enc, int mode, int pf, int b);
+LaunchFn code_fn_li_c(int enc, int mode, int pf, int b);
+LaunchFn code_fn_li_d(int enc, int mode, int pf, int b);
 LaunchFn code_fn_bytes(int enc, int mode, int pf, int b);
 LaunchFn delta_fn_rm_lds_a(int mode, int b);
 LaunchFn delta_fn_rm_lds_b(int mode, int b);
+LaunchFn delta_fn_rm_lds_c(int mode, int b);
+LaunchFn delta_fn_rm_lds_d(int mode, int b);
 LaunchFn delta_fn_rm_direct_a(int mode, int b);
 LaunchFn delta_fn_rm_direct_b(int mode, int b);
+LaunchFn delta_fn_rm_direct_c(int mode, int b);
+LaunchFn delta_fn_rm_direct_d(int mode, int b);
 
 }  // namespace scan_dev
 
-#define SCAN_WIDTHS_A(F) F(1) F(2) F(3) F(4) F(5) F(6) F(7) F(8) F(9) F(10) F(11) F(12) F(13) F(14) F(15) F(16)
-#define SCAN_WIDTHS_B(F) F(17) F(18) F(19) F(20) F(21) F(22) F(23) F(24) F(25) F(26) F(27) F(28) F(29) F(30) F(31) F(32)
+#define SCAN_WIDTHS_1_4(F) F(1) F(2) F(3) F(4)
+#define SCAN_WIDTHS_5_8(F) F(5) F(6) F(7) F(8)
+#define SCAN_WIDTHS_9_16(F) F(9) F(10) F(11) F(12) F(13) F(14) F(15) F(16)
+#define SCAN_WIDTHS_17_32(F) F(17) F(18) F(19) F(20) F(21) F(22) F(23) F(24) F(25) F(26) F(27) F(28) F(29) F(30) F(31) F(32)

@@ -42,22 +42,34 @@ scan_status hip_fail(scan_ctx* ctx, hipError_t e, const char* what) {
 
 namespace {
 
+// Width group of the instantiation units: 1-4, 5-8, 9-16, 17-32.
+int width_group(uint32_t b) { return b <= 4 ? 0 : b <= 8 ? 1 : b <= 16 ? 2 : 3; }
+
 LaunchFn code_fn(int enc, int dec, int mode, int pf, uint32_t b) {
-  const bool a = b <= 16;
+  static LaunchFn (*const lds[4])(int, int, int, int) = {code_fn_rm_lds_a, code_fn_rm_lds_b, code_fn_rm_lds_c,
+                                                         code_fn_rm_lds_d};
+  static LaunchFn (*const direct[4])(int, int, int, int) = {code_fn_rm_direct_a, code_fn_rm_direct_b,
+                                                            code_fn_rm_direct_c, code_fn_rm_direct_d};
+  static LaunchFn (*const li[4])(int, int, int, int) = {code_fn_li_a, code_fn_li_b, code_fn_li_c, code_fn_li_d};
+  const int g = width_group(b);
   switch (dec) {
-    case DEC_RM_LDS: return a ? code_fn_rm_lds_a(enc, mode, pf, b) : code_fn_rm_lds_b(enc, mode, pf, b);
-    case DEC_RM_DIRECT: return a ? code_fn_rm_direct_a(enc, mode, pf, b) : code_fn_rm_direct_b(enc, mode, pf, b);
-    case DEC_LI: return a ? code_fn_li_a(enc, mode, pf, b) : code_fn_li_b(enc, mode, pf, b);
-    case DEC_BYTES: return code_fn_bytes(enc, mode, pf, b);
+    case DEC_RM_LDS: return lds[g](enc, mode, pf, (int)b);
+    case DEC_RM_DIRECT: return direct[g](enc, mode, pf, (int)b);
+    case DEC_LI: return li[g](enc, mode, pf, (int)b);
+    case DEC_BYTES: return code_fn_bytes(enc, mode, pf, (int)b);
   }
   return nullptr;
 }
 
 LaunchFn delta_fn(int dec, int mode, uint32_t b) {
-  const bool a = b <= 16;
+  static LaunchFn (*const lds[4])(int, int) = {delta_fn_rm_lds_a, delta_fn_rm_lds_b, delta_fn_rm_lds_c,
+                                               delta_fn_rm_lds_d};
+  static LaunchFn (*const direct[4])(int, int) = {delta_fn_rm_direct_a, delta_fn_rm_direct_b, delta_fn_rm_direct_c,
+                                                  delta_fn_rm_direct_d};
+  const int g = width_group(b);
   switch (dec) {
-    case DEC_RM_LDS: return a ? delta_fn_rm_lds_a(mode, b) : delta_fn_rm_lds_b(mode, b);
-    case DEC_RM_DIRECT: return a ? delta_fn_rm_direct_a(mode, b) : delta_fn_rm_direct_b(mode, b);
+    case DEC_RM_LDS: return lds[g](mode, (int)b);
+    case DEC_RM_DIRECT: return direct[g](mode, (int)b);
   }
   return nullptr;
 }
@@ -118,8 +130,10 @@ scan_tune default_tune(int32_t enc, uint32_t b, int32_t s) {
   scan_tune t;
   (void)s;
   t.wg_size = 256;
-  t.wgs_per_cu = 0;           // 0: as many as fit (occupancy)
-  t.min_blocks_per_wave = 8;  // small columns launch fewer work-groups
+  // Measured on MI355X: few resident wavefronts, each streaming 16-block
+  // windows, beat full occupancy (fewer concurrent streams into HBM).
+  t.wgs_per_cu = 2;
+  t.window_blocks = 16;
   t.reserved = 0;
   return t;
 }
@@ -130,12 +144,19 @@ scan_tune effective_tune(scan_ctx* ctx, int32_t enc, uint32_t b, int32_t s) {
   if (it != ctx->tunes.end()) {
     if (it->second.wg_size) t.wg_size = it->second.wg_size;
     if (it->second.wgs_per_cu) t.wgs_per_cu = it->second.wgs_per_cu;
-    if (it->second.min_blocks_per_wave) t.min_blocks_per_wave = it->second.min_blocks_per_wave;
+    if (it->second.window_blocks) t.window_blocks = it->second.window_blocks;
   }
   return t;
 }
 
 // ------------------------------------------------------------ launch
+
+// Blocks one wavefront decodes per pipelined step (the kernels' Geo<B>).
+uint32_t step_blocks(int dec, uint32_t b) {
+  if (dec == DEC_RM_LDS) return b >= 32 ? 1u : std::min(8u, 32u / b);
+  if (dec == DEC_BYTES) return b >= 32 ? 1u : 32u / b;
+  return 2u * (b >= 16 ? 1u : std::min(4u, 16u / b));
+}
 
 // Resident work-groups per compute unit of one kernel instance (cached).
 scan_status occupancy(scan_ctx* ctx, LaunchFn fn, uint32_t block, int* occ) {
@@ -202,8 +223,11 @@ scan_status prepare_scan(scan_ctx* ctx, const scan_column* col, int32_t enc, uin
   if (st != SCAN_OK) return st;
   const uint64_t per_cu = t.wgs_per_cu > 0 ? std::min<uint64_t>((uint64_t)t.wgs_per_cu, (uint64_t)occ) : (uint64_t)occ;
   const uint64_t waves = block / 64u;
-  const uint64_t minb = (uint64_t)std::max(1, t.min_blocks_per_wave);
-  const uint64_t need = (p.nb + minb * waves - 1) / (minb * waves);
+  const uint32_t win = t.window_blocks > 0 ? (uint32_t)t.window_blocks : step_blocks(dec, b);
+  (void)step_blocks;
+  p.G = std::min<uint32_t>(win, 64u);
+  p.units = (p.nb + p.G - 1) / p.G;
+  const uint64_t need = (p.units + waves - 1) / waves;
   const uint64_t cap = std::min<uint64_t>((uint64_t)ctx->cus * std::max<uint64_t>(1, per_cu), ctx->max_grid);
   grid = (uint32_t)std::max<uint64_t>(1, std::min(need, cap));
   return SCAN_OK;
@@ -301,6 +325,7 @@ void scan_destroy(scan_ctx* ctx) {
   if (ctx->ticket) (void)hipFree(ctx->ticket);
   if (ctx->out_dev) (void)hipFree(ctx->out_dev);
   if (ctx->out_host) (void)hipHostFree(ctx->out_host);
+  if (ctx->evict_buf) (void)hipFree(ctx->evict_buf);
   delete ctx;
 }
 
@@ -382,8 +407,7 @@ scan_status scan_set_tune(scan_ctx* ctx, int32_t enc, uint32_t b, int32_t strate
     return fail(ctx, SCAN_EINVAL, "wg_size must be a multiple of 64 in 64..1024");
   if (t->wgs_per_cu < 0 || t->wgs_per_cu > 64) return fail(ctx, SCAN_EINVAL, "wgs_per_cu must be in 0..64");
   if (t->wg_size > 256) return fail(ctx, SCAN_EINVAL, "wg_size above 256 is not supported");
-  if (t->min_blocks_per_wave < 0 || t->min_blocks_per_wave > 1 << 20)
-    return fail(ctx, SCAN_EINVAL, "min_blocks_per_wave must be in 0..2^20");
+  if (t->window_blocks < 0 || t->window_blocks > 64) return fail(ctx, SCAN_EINVAL, "window_blocks must be in 0..64");
   ctx->tunes[std::make_tuple(enc, b, strategy)] = *t;
   return SCAN_OK;
 }
@@ -393,6 +417,112 @@ scan_status scan_get_tune(scan_ctx* ctx, int32_t enc, uint32_t b, int32_t strate
   if (!t) return fail(ctx, SCAN_EINVAL, "tune is NULL");
   *t = effective_tune(ctx, enc, b, strategy);
   return SCAN_OK;
+}
+
+scan_status scan_autotune(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b,
+                          const scan_predicate* pred, int32_t strategy, int32_t reps, scan_tune* out, float* ms_out) {
+  if (!ctx) return SCAN_EINVAL;
+  if (!pred) return fail(ctx, SCAN_EINVAL, "predicate is NULL");
+  scan_status st = validate_column(ctx, col, enc, b);
+  if (st != SCAN_OK) return st;
+  st = check_strategy(ctx, col, enc, b, strategy);
+  if (st != SCAN_OK) return st;
+  if (reps < 1) reps = 3;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  // A read of twice the 256 MB last-level cache between timed runs keeps the
+  // column cold, as it is when a scan streams it once.
+  constexpr uint64_t kEvict = 512ull << 20;
+  if (!ctx->evict_buf) {
+    e = hipMalloc(&ctx->evict_buf, kEvict);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(evict)");
+    e = hipMemsetAsync(ctx->evict_buf, 1, kEvict, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemsetAsync(evict)");
+  }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(ctx, SCAN_EDEVICE, "events");
+  const scan_tune saved = effective_tune(ctx, enc, b, strategy);
+  const bool had = ctx->tunes.count(std::make_tuple(enc, b, strategy)) > 0;
+  static const int kWg[] = {64, 128, 256};
+  static const int kPerCu[] = {1, 2, 4, 8};
+  static const int kWin[] = {4, 16, 64};
+  float best_ms = 1e30f;
+  scan_tune best = saved;
+  for (int wg : kWg)
+    for (int pc : kPerCu)
+      for (int win : kWin) {
+        scan_tune t{wg, pc, win, 0};
+        ctx->tunes[std::make_tuple(enc, b, strategy)] = t;
+        float ts[16];
+        const int r = std::min(reps, 16);
+        for (int i = 0; i < r; ++i) {
+          (void)scan_dev::launch_beta_read(ctx->evict_buf, kEvict, (uint32_t)ctx->cus * 8u, 1024u, 1,
+                                           reinterpret_cast<uint64_t*>(ctx->ticket) + 8, ctx->stream);
+          hipEventRecord(e0, ctx->stream);
+          st = enqueue_scan(ctx, col, enc, b, pred, strategy, ctx->out_dev, nullptr);
+          hipEventRecord(e1, ctx->stream);
+          if (st != SCAN_OK) break;
+          hipEventSynchronize(e1);
+          hipEventElapsedTime(&ts[i], e0, e1);
+        }
+        if (st != SCAN_OK) break;
+        std::sort(ts, ts + r);
+        if (ts[r / 2] < best_ms) {
+          best_ms = ts[r / 2];
+          best = t;
+        }
+      }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != SCAN_OK) {
+    if (had) ctx->tunes[std::make_tuple(enc, b, strategy)] = saved;
+    else ctx->tunes.erase(std::make_tuple(enc, b, strategy));
+    return st;
+  }
+  ctx->tunes[std::make_tuple(enc, b, strategy)] = best;
+  if (out) *out = best;
+  if (ms_out) *ms_out = best_ms;
+  return SCAN_OK;
+}
+
+scan_status scan_tune_save(scan_ctx* ctx, const char* path) {
+  if (!ctx) return SCAN_EINVAL;
+  if (!path) return fail(ctx, SCAN_EINVAL, "path is NULL");
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(ctx, SCAN_EINVAL, "cannot write %s", path);
+  std::fprintf(f, "{\"format\": \"scan-autotune-1\", \"entries\": [\n");
+  size_t i = 0;
+  for (const auto& kv : ctx->tunes) {
+    std::fprintf(f, "  {\"enc\": %d, \"b\": %u, \"strategy\": %d, \"wg_size\": %d, \"wgs_per_cu\": %d, "
+                    "\"window_blocks\": %d}%s\n",
+                 std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), kv.second.wg_size,
+                 kv.second.wgs_per_cu, kv.second.window_blocks, ++i < ctx->tunes.size() ? "," : "");
+  }
+  std::fprintf(f, "]}\n");
+  std::fclose(f);
+  return SCAN_OK;
+}
+
+scan_status scan_tune_load(scan_ctx* ctx, const char* path) {
+  if (!ctx) return SCAN_EINVAL;
+  if (!path) return fail(ctx, SCAN_EINVAL, "path is NULL");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(ctx, SCAN_EINVAL, "cannot read %s", path);
+  char line[512];
+  int loaded = 0;
+  while (std::fgets(line, sizeof line, f)) {
+    int enc, strat, wg, pc, win;
+    unsigned b;
+    if (std::sscanf(line,
+                    " {\"enc\": %d, \"b\": %u, \"strategy\": %d, \"wg_size\": %d, \"wgs_per_cu\": %d, "
+                    "\"window_blocks\": %d}",
+                    &enc, &b, &strat, &wg, &pc, &win) == 6) {
+      scan_tune t{wg, pc, win, 0};
+      if (scan_set_tune(ctx, enc, b, strat, &t) == SCAN_OK) ++loaded;
+    }
+  }
+  std::fclose(f);
+  return loaded >= 0 ? SCAN_OK : SCAN_EINVAL;
 }
 
 scan_status scan_beta_read(scan_ctx* ctx, const void* buf, uint64_t bytes, int32_t wgs, int32_t wg_size,

@@ -23,6 +23,7 @@ struct scan_ctx {
   scan_dev::Result* out_dev = nullptr;    // result slot of synchronous scans (device)
   scan_dev::Result* out_host = nullptr;   // pinned staging for it
   uint32_t flush_salt = 0;
+  void* evict_buf = nullptr;              // autotuner's cache-evicting read buffer
   std::string err;
   std::map<std::tuple<int32_t, uint32_t, int32_t>, scan_tune> tunes;
   std::map<std::pair<const void*, uint32_t>, int> occupancy;
@@ -38,10 +39,17 @@ scan_status validate_column(scan_ctx* ctx, const scan_column* col, int32_t enc, 
 scan_status check_strategy(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b, int32_t s);
 int32_t heuristic_strategy(const scan_column* col, int32_t enc, uint32_t b);
 scan_tune effective_tune(scan_ctx* ctx, int32_t enc, uint32_t b, int32_t s);
+scan_status enqueue_scan(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b, const scan_predicate* pred,
+                         int32_t strategy, scan_dev::Result* out_dev, scan_dev::Result* host_empty_out);
+namespace scan_dev {
+hipError_t launch_beta_read(const void* buf, uint64_t bytes, uint32_t grid, uint32_t block, int unroll,
+                            uint64_t* sink, hipStream_t st);
+}
 
-// Learned selector (selector.cpp).
+// Learned selector (selector.cpp; the one-column pick lives in batch.cpp).
 scan_status selector_pick(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b,
                           const scan_predicate* pred, int32_t* out);
+const float* selector_theta(scan_ctx* ctx);
 void destroy_selector(scan_ctx* ctx);
 
 // Batched scans (batch.cpp).

@@ -40,8 +40,11 @@ enum PredForm {
 
 template <int B>
 struct Geo {
-  static constexpr int kPairs = B >= 16 ? 1 : 16 / B;       // block pairs per step (half-wavefront decoders)
-  static constexpr int kLdsBlocks = B >= 32 ? 1 : 32 / B;   // blocks staged per step (RM-LDS)
+  // block pairs per step (half-wavefront decoders): about 4 KiB per wavefront,
+  // at most 4 pairs (below b = 4 the decode is compute-bound anyway)
+  static constexpr int kPairs = B >= 16 ? 1 : (16 / B > 4 ? 4 : 16 / B);
+  // blocks staged per step (RM-LDS), at most 8
+  static constexpr int kLdsBlocks = B >= 32 ? 1 : (32 / B > 8 ? 8 : 32 / B);
   static constexpr int kStageWords = 32 * B + 4;            // one staged block plus an over-read pad
   static constexpr int kStageLoads = (32 * B + 63) / 64;    // words per lane to stage one block
   static constexpr int kByteBlocks = B >= 32 ? 1 : 32 / B;  // blocks per step (byte-aligned, B = 8/16/32)
@@ -49,7 +52,8 @@ struct Geo {
 
 // Empty register constraint: pins `x` to VGPRs at this point so the compiler
 // cannot defer and re-associate the per-value adds (which would keep every
-// value's compare mask alive and spill them).  Emits no instruction.
+// value's compare mask alive and spill them).  Emits no instruction; applied
+// every fourth value, so the scheduler still interleaves four values.
 template <typename T>
 __device__ __forceinline__ void pin(T& x) {
   if constexpr (sizeof(T) == 4) {
@@ -106,6 +110,7 @@ struct WaveState {
   uint64_t blocks = 0;  // uniform
   uint64_t refsum = 0;  // uniform: sum over blocks of (matches in block) * (reference or base)
   uint64_t lsum = 0;    // per lane
+  uint64_t lcount = 0;  // per lane (branch-free mode counts per lane, no ballot)
   uint32_t head = 0, tail = 0;  // selection-vector ring counters (uniform)
   EntryT* ring = nullptr;
 };
@@ -218,21 +223,24 @@ __device__ __forceinline__ bool block_survives(const Params& p, uint64_t k, uint
   }
 }
 
-// The wavefront's contiguous share [a, e) of the column's blocks.
-__device__ __forceinline__ void wave_range(uint64_t nb, uint64_t gw, uint64_t tw, uint64_t& a, uint64_t& e) {
-  a = nb * gw / tw;
-  e = nb * (gw + 1) / tw;
+// Whether block k lies in one of the windows [a + j*stride, a + j*stride + win)
+// that end before e.
+__device__ __forceinline__ bool owns_block(uint64_t k, uint64_t a, uint64_t e, uint64_t stride, uint32_t win) {
+  return k >= a && k < e && ((k - a) % stride) < win;
 }
 
-// Walks the wavefront's range window by window and hands out the surviving
-// blocks in steps of up to NPER per half-wavefront (lanes 0-31 take list
-// entries pos, pos+2, ...; lanes 32-63 take pos+1, pos+3, ...).
+// Walks the wavefront's windows (win blocks each, `stride` blocks apart, up to
+// end_k) and hands out the surviving blocks in steps of up to NPER per
+// half-wavefront (lanes 0-31 take list entries pos, pos+2, ...; lanes 32-63
+// take pos+1, pos+3, ...).
 template <int NPER, typename LiveFn>
 struct PairCursor {
   uint64_t next_k, end_k, k0;
   uint32_t nsurv, pos;
-  uint32_t* list;  // per-wavefront LDS, 64 entries
-  uint64_t safe;   // a block this lane was last handed (valid once a fetch succeeded)
+  uint32_t* list;   // per-wavefront LDS, 64 entries
+  uint64_t safe;    // a block this lane was last handed (valid once a fetch succeeded)
+  uint64_t stride;  // distance between this wavefront's windows
+  uint32_t win;     // blocks per window (1..64)
 
   __device__ __forceinline__ bool fetch(uint64_t (&kb)[NPER], uint32_t& actbits, uint64_t& blocks, LiveFn& live_fn,
                                         uint32_t lane) {
@@ -246,9 +254,9 @@ struct PairCursor {
         return false;
       }
       const uint64_t left = end_k - next_k;
-      const uint32_t cnt = left < 64 ? (uint32_t)left : 64u;
+      const uint32_t cnt = left < win ? (uint32_t)left : win;
       k0 = next_k;
-      next_k += cnt;
+      next_k += stride;
       const uint64_t live = live_fn(k0, cnt);
       blocks += (uint64_t)__builtin_popcountll(live);
       __builtin_amdgcn_wave_barrier();
@@ -277,14 +285,16 @@ struct PairCursor {
 template <int NB, typename LiveFn>
 struct BlockCursor {
   uint64_t next_k, end_k, k0, live;
+  uint64_t stride;  // distance between this wavefront's windows
+  uint32_t win;     // blocks per window (1..64)
 
   __device__ __forceinline__ bool fetch(uint64_t& sk0, uint64_t& smask, uint64_t& blocks, LiveFn& live_fn) {
     while (live == 0) {
       if (next_k >= end_k) return false;
       const uint64_t left = end_k - next_k;
-      const uint32_t cnt = left < 64 ? (uint32_t)left : 64u;
+      const uint32_t cnt = left < win ? (uint32_t)left : win;
       k0 = next_k;
-      next_k += cnt;
+      next_k += stride;
       live = live_fn(k0, cnt);
       blocks += (uint64_t)__builtin_popcountll(live);
     }
@@ -318,40 +328,57 @@ __device__ __forceinline__ void decode_pair(const Params& p, WaveState<uint32_t>
   const uint64_t act_m = ballot(act);
   if (act_m == 0) return;
   const uint32_t limit = (TAIL && kb == p.nb - 1) ? p.tail : kBlockValues;
-  uint32_t cA = 0, cB = 0, call = 0;
   PartT<B, ENC> part = 0;
+  if constexpr (MODE == MODE_BF) {
+    // Branch-free: per-lane count and masked add; the compare's mask stays in
+    // VCC and feeds a select and a carry-add (no ballot, no scalar work).
+    uint32_t lc = 0;
 #pragma unroll
-  for (int t = 0; t < 32; ++t) {
-    const uint32_t c = run_code<B, B>(w, t);
-    const bool hit = (PF == PF_LO0) ? (c <= cr.wm1) : ((c - cr.loc) <= cr.wm1);
-    uint64_t m = ballot(hit) & act_m;
-    bool valid = true;
-    if (TAIL) {
-      const uint32_t j = (DEC == DEC_RM_DIRECT) ? (32u * l + t) : (32u * t + l);
-      valid = j < limit;
-      m &= ballot(valid);
-    }
-    if constexpr (PF == PF_REFS) {
-      cA += (uint32_t)__builtin_popcount((uint32_t)m);
-      cB += (uint32_t)__builtin_popcount((uint32_t)(m >> 32));
-    } else {
-      call += (uint32_t)__builtin_popcountll(m);
-    }
-    if constexpr (MODE == MODE_BF) {
+    for (int t = 0; t < 32; ++t) {
+      const uint32_t c = run_code<B, B>(w, t);
+      bool ok = (PF == PF_LO0) ? (c <= cr.wm1) : ((c - cr.loc) <= cr.wm1);
+      if (TAIL) ok = ok && (((DEC == DEC_RM_DIRECT) ? (32u * l + t) : (32u * t + l)) < limit);
+      lc += ok ? 1u : 0u;
       const uint64_t v = code_value<ENC>(c, dict_lds, dict_last);
-      part += (hit && (!TAIL || valid)) ? (PartT<B, ENC>)v : (PartT<B, ENC>)0;
-      pin(part);
-    } else {
+      part += ok ? (PartT<B, ENC>)v : (PartT<B, ENC>)0;
+      if ((t & 3) == 3) {
+        pin(part);
+        pin(lc);
+      }
+    }
+    if (act) {
+      s.lcount += lc;
+      s.lsum += (uint64_t)part;
+      if constexpr (PF == PF_REFS) s.lsum += (uint64_t)lc * ref;
+    }
+  } else {
+    uint32_t cA = 0, cB = 0, call = 0;
+#pragma unroll
+    for (int t = 0; t < 32; ++t) {
+      const uint32_t c = run_code<B, B>(w, t);
+      const bool hit = (PF == PF_LO0) ? (c <= cr.wm1) : ((c - cr.loc) <= cr.wm1);
+      uint64_t m = ballot(hit) & act_m;
+      bool valid = true;
+      if (TAIL) {
+        const uint32_t j = (DEC == DEC_RM_DIRECT) ? (32u * l + t) : (32u * t + l);
+        valid = j < limit;
+        m &= ballot(valid);
+      }
+      if constexpr (PF == PF_REFS) {
+        cA += (uint32_t)__builtin_popcount((uint32_t)m);
+        cB += (uint32_t)__builtin_popcount((uint32_t)(m >> 32));
+      } else {
+        call += (uint32_t)__builtin_popcountll(m);
+      }
       sv_push<ENC, uint32_t>(s, c, hit && act && valid, m, lane, dict_lds, dict_last);
     }
+    if constexpr (PF == PF_REFS) {
+      s.count += (uint64_t)cA + cB;
+      s.refsum += (uint64_t)cA * readlane(ref, 0) + (uint64_t)cB * readlane(ref, 32);
+    } else {
+      s.count += call;
+    }
   }
-  if constexpr (PF == PF_REFS) {
-    s.count += (uint64_t)cA + cB;
-    s.refsum += (uint64_t)cA * readlane(ref, 0) + (uint64_t)cB * readlane(ref, 32);
-  } else {
-    s.count += call;
-  }
-  if constexpr (MODE == MODE_BF) s.lsum += act ? (uint64_t)part : 0ull;
 }
 
 template <int B, int DEC>
@@ -365,14 +392,13 @@ __device__ __forceinline__ void load_pair_words(const Params& p, uint64_t kb, ui
   }
 }
 
-template <int B, int DEC, int MODE, int ENC, int PF>
+template <int B, int DEC, int MODE, int ENC, int PF, int P>
 __device__ __forceinline__ void run_pairs(const Params& p, WaveState<uint32_t>& s, uint32_t lane, uint32_t* list,
-                                          uint64_t ka, uint64_t ke, uint64_t excl, const int64_t* dict_lds,
-                                          uint32_t dict_last, uint32_t clo, uint32_t chi) {
-  constexpr int P = Geo<B>::kPairs;
+                                          uint64_t ka, uint64_t ke, uint64_t stride, uint32_t win, uint64_t excl,
+                                          const int64_t* dict_lds, uint32_t dict_last, uint32_t clo, uint32_t chi) {
   const uint32_t l = lane & 31u;
   auto live_fn = [&](uint64_t k0, uint32_t cnt) { return window_live<ENC>(p, k0, cnt, clo, chi, excl); };
-  PairCursor<P, decltype(live_fn)> cur{ka, ke, 0, 0, 0, list, ka};
+  PairCursor<P, decltype(live_fn)> cur{ka, ke, 0, 0, 0, list, ka, stride, win};
   // Two register buffers used alternately: the next step's loads are always
   // issued (a harmless reload of a valid block when there is no next step)
   // before the current step is decoded, so exactly one step is in flight.
@@ -427,24 +453,30 @@ __device__ __forceinline__ void decode_staged(const Params& p, WaveState<uint32_
     if (B == 32) c = sp[64 * t];
     else c = funnel(sp[2 * B * t + 1], sp[2 * B * t], sh) & width_mask<B>();
     const bool hit = (PF == PF_LO0) ? (c <= cr.wm1) : ((c - cr.loc) <= cr.wm1);
-    uint64_t m = ballot(hit);
-    bool valid = true;
-    if (TAIL) {
-      valid = lane + 64u * t < limit;
-      m &= ballot(valid);
-    }
-    cnt += (uint32_t)__builtin_popcountll(m);
+    const bool valid = !TAIL || (lane + 64u * t < limit);
     if constexpr (MODE == MODE_BF) {
+      const bool ok = hit && valid;
+      cnt += ok ? 1u : 0u;
       const uint64_t v = code_value<ENC>(c, dict_lds, dict_last);
-      part += (hit && valid) ? (PartT<B, ENC>)v : (PartT<B, ENC>)0;
-      pin(part);
+      part += ok ? (PartT<B, ENC>)v : (PartT<B, ENC>)0;
+      if ((t & 3) == 3) {
+        pin(part);
+        pin(cnt);
+      }
     } else {
+      uint64_t m = ballot(hit);
+      if (TAIL) m &= ballot(valid);
+      cnt += (uint32_t)__builtin_popcountll(m);
       sv_push<ENC, uint32_t>(s, c, hit && valid, m, lane, dict_lds, dict_last);
     }
   }
-  s.count += cnt;
-  s.refsum += (uint64_t)cnt * ref;
-  s.lsum += (uint64_t)part;
+  if constexpr (MODE == MODE_BF) {
+    s.lcount += cnt;  // per lane
+    s.lsum += (uint64_t)part + (uint64_t)cnt * ref;
+  } else {
+    s.count += cnt;   // uniform
+    s.refsum += (uint64_t)cnt * ref;
+  }
 }
 
 // Byte-aligned: one 16-byte load per lane per KiB of the block.
@@ -470,24 +502,30 @@ __device__ __forceinline__ void decode_bytes(const Params& p, WaveState<uint32_t
       else if (B == 16) c = (xs[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
       else c = xs[e];
       const bool hit = (PF == PF_LO0) ? (c <= cr.wm1) : ((c - cr.loc) <= cr.wm1);
-      uint64_t m = ballot(hit);
-      bool valid = true;
-      if (TAIL) {
-        valid = idx0 + e < limit;
-        m &= ballot(valid);
-      }
-      cnt += (uint32_t)__builtin_popcountll(m);
+      const bool valid = !TAIL || (idx0 + e < limit);
       if constexpr (MODE == MODE_BF) {
-        part += (hit && valid) ? (PartT<B, ENC>)c : (PartT<B, ENC>)0;
-        pin(part);
+        const bool ok = hit && valid;
+        cnt += ok ? 1u : 0u;
+        part += ok ? (PartT<B, ENC>)c : (PartT<B, ENC>)0;
+        if ((e & 3) == 3) {
+          pin(part);
+          pin(cnt);
+        }
       } else {
+        uint64_t m = ballot(hit);
+        if (TAIL) m &= ballot(valid);
+        cnt += (uint32_t)__builtin_popcountll(m);
         sv_push<ENC, uint32_t>(s, c, hit && valid, m, lane, nullptr, 0);
       }
     }
   }
-  s.count += cnt;
-  s.refsum += (uint64_t)cnt * ref;
-  s.lsum += (uint64_t)part;
+  if constexpr (MODE == MODE_BF) {
+    s.lcount += cnt;
+    s.lsum += (uint64_t)part + (uint64_t)cnt * ref;
+  } else {
+    s.count += cnt;
+    s.refsum += (uint64_t)cnt * ref;
+  }
 }
 
 // Coalesced staging loads of one block into registers (lane takes words
@@ -519,13 +557,13 @@ __device__ __forceinline__ uint64_t step_block(uint64_t k0, uint64_t mask, int j
   return k0 + (uint64_t)__builtin_ctzll(m);
 }
 
-template <int B, int MODE, int ENC, int PF>
+template <int B, int MODE, int ENC, int PF, int NB>
 __device__ __forceinline__ void run_staged(const Params& p, WaveState<uint32_t>& s, uint32_t lane, uint32_t* st,
-                                           uint64_t ka, uint64_t ke, uint64_t excl, const int64_t* dict_lds,
-                                           uint32_t dict_last, uint32_t clo, uint32_t chi) {
-  constexpr int NB = Geo<B>::kLdsBlocks, NL = Geo<B>::kStageLoads, SW = Geo<B>::kStageWords;
+                                           uint64_t ka, uint64_t ke, uint64_t stride, uint32_t win, uint64_t excl,
+                                           const int64_t* dict_lds, uint32_t dict_last, uint32_t clo, uint32_t chi) {
+  constexpr int NL = Geo<B>::kStageLoads, SW = Geo<B>::kStageWords;
   auto live_fn = [&](uint64_t k0, uint32_t cnt) { return window_live<ENC>(p, k0, cnt, clo, chi, excl); };
-  BlockCursor<NB, decltype(live_fn)> cur{ka, ke, 0, 0};
+  BlockCursor<NB, decltype(live_fn)> cur{ka, ke, 0, 0, stride, win};
   uint64_t k0 = 0, m0 = 0, k1 = 0, m1 = 0;
   uint32_t r0[NB][NL], r1[NB][NL];
   auto load = [&](uint64_t base, uint64_t mask, uint32_t (&dst)[NB][NL]) {
@@ -564,12 +602,12 @@ __device__ __forceinline__ void run_staged(const Params& p, WaveState<uint32_t>&
   }
 }
 
-template <int B, int MODE, int ENC, int PF>
+template <int B, int MODE, int ENC, int PF, int NB>
 __device__ __forceinline__ void run_bytes(const Params& p, WaveState<uint32_t>& s, uint32_t lane, uint64_t ka,
-                                          uint64_t ke, uint64_t excl) {
-  constexpr int NB = Geo<B>::kByteBlocks, Q = B / 8;
+                                          uint64_t ke, uint64_t stride, uint32_t win, uint64_t excl) {
+  constexpr int Q = B / 8;
   auto live_fn = [&](uint64_t k0, uint32_t cnt) { return window_live<ENC>(p, k0, cnt, 0, 0, excl); };
-  BlockCursor<NB, decltype(live_fn)> cur{ka, ke, 0, 0};
+  BlockCursor<NB, decltype(live_fn)> cur{ka, ke, 0, 0, stride, win};
   uint64_t k0 = 0, m0 = 0, k1 = 0, m1 = 0;
   uint4 x0[NB][Q], x1[NB][Q];
   auto load = [&](uint64_t base, uint64_t mask, uint4 (&dst)[NB][Q]) {
@@ -632,6 +670,51 @@ __host__ __device__ constexpr uint32_t code_scan_lds(uint32_t waves) {
   return (ENC == ENC_DICT ? kMaxDict * 8u : 0u) + waves * wave_lds_words<B, DEC, MODE>() * 4u;
 }
 
+// Scan blocks [ka, ke) of a FOR/DICT column into the wavefront state.  SMALL
+// selects one block pair (or one staged block) per pipelined step instead of
+// ~4 KiB steps (the batched kernels use it to bound code size).  The partial
+// last block, when it lies in the range, is decoded here with per-value
+// validity after the pipelined loop.
+template <int B, int DEC, int MODE, int ENC, int PF, bool SMALL>
+__device__ __forceinline__ void scan_range(const Params& p, WaveState<uint32_t>& s, uint32_t lane, uint32_t* list,
+                                           uint32_t* st, uint64_t ka, uint64_t ke, uint64_t stride, uint32_t win,
+                                           const int64_t* dict_lds, uint32_t dict_last, uint32_t clo, uint32_t chi) {
+  const uint64_t last = p.nb - 1;
+  const bool tail_partial = p.tail != kBlockValues;
+  const uint64_t excl = tail_partial ? last : ~0ull;
+  if constexpr (DEC == DEC_RM_DIRECT || DEC == DEC_LI) {
+    run_pairs<B, DEC, MODE, ENC, PF, SMALL ? 1 : Geo<B>::kPairs>(p, s, lane, list, ka, ke, stride, win, excl, dict_lds,
+                                                                 dict_last, clo, chi);
+  } else if constexpr (DEC == DEC_RM_LDS) {
+    run_staged<B, MODE, ENC, PF, SMALL ? 1 : Geo<B>::kLdsBlocks>(p, s, lane, st, ka, ke, stride, win, excl, dict_lds,
+                                                                 dict_last, clo, chi);
+  } else {
+    run_bytes<B, MODE, ENC, PF, SMALL ? 1 : Geo<B>::kByteBlocks>(p, s, lane, ka, ke, stride, win, excl);
+  }
+  if (tail_partial && owns_block(last, ka, ke, stride, win) && block_survives<ENC>(p, last, clo, chi)) {
+    s.blocks += 1;
+    if constexpr (DEC == DEC_RM_DIRECT || DEC == DEC_LI) {
+      uint32_t w[B];
+      load_pair_words<B, DEC>(p, last, lane & 31u, w);
+      decode_pair<B, DEC, MODE, ENC, PF, true>(p, s, lane, w, last, lane < 32u, dict_lds, dict_last, clo, chi);
+    } else if constexpr (DEC == DEC_RM_LDS) {
+      uint32_t r[Geo<B>::kStageLoads];
+      stage_load<B>(p.payload + last * (32u * B), lane, r);
+      __builtin_amdgcn_wave_barrier();
+      stage_store<B>(st, lane, r);
+      __builtin_amdgcn_wave_barrier();
+      decode_staged<B, MODE, ENC, PF, true>(p, s, lane, st, last, dict_lds, dict_last, clo, chi);
+      __builtin_amdgcn_wave_barrier();
+    } else {
+      uint4 x[B / 8];
+      const uint4* blk = reinterpret_cast<const uint4*>(p.payload + last * (32u * B));
+#pragma unroll
+      for (int q = 0; q < B / 8; ++q) x[q] = blk[64 * q + lane];
+      decode_bytes<B, MODE, ENC, PF, true>(p, s, lane, x, last);
+    }
+  }
+}
+
 template <int B, int DEC, int MODE, int ENC, int PF>
 __global__ __launch_bounds__(256) void code_scan(const Params p) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -652,41 +735,13 @@ __global__ __launch_bounds__(256) void code_scan(const Params p) {
     chi = lower_bound_lds(dict_lds, p.dict_len, p.hi);
     dict_last = p.dict_len - 1u;
   }
-  uint64_t ka, ke;
-  wave_range(p.nb, (uint64_t)blockIdx.x * nw + wave, (uint64_t)gridDim.x * nw, ka, ke);
-  const uint64_t last = p.nb - 1;
-  const bool tail_partial = p.tail != kBlockValues;
-  const uint64_t excl = tail_partial ? last : ~0ull;
-  if constexpr (DEC == DEC_RM_DIRECT || DEC == DEC_LI) {
-    run_pairs<B, DEC, MODE, ENC, PF>(p, s, lane, list, ka, ke, excl, dict_lds, dict_last, clo, chi);
-  } else if constexpr (DEC == DEC_RM_LDS) {
-    run_staged<B, MODE, ENC, PF>(p, s, lane, st, ka, ke, excl, dict_lds, dict_last, clo, chi);
-  } else {
-    run_bytes<B, MODE, ENC, PF>(p, s, lane, ka, ke, excl);
-  }
-  // The partial last block: its owner decodes it with per-value validity.
-  if (tail_partial && ka <= last && last < ke && block_survives<ENC>(p, last, clo, chi)) {
-    s.blocks += 1;
-    if constexpr (DEC == DEC_RM_DIRECT || DEC == DEC_LI) {
-      uint32_t w[B];
-      load_pair_words<B, DEC>(p, last, lane & 31u, w);
-      decode_pair<B, DEC, MODE, ENC, PF, true>(p, s, lane, w, last, lane < 32u, dict_lds, dict_last, clo, chi);
-    } else if constexpr (DEC == DEC_RM_LDS) {
-      uint32_t r[Geo<B>::kStageLoads];
-      stage_load<B>(p.payload + last * (32u * B), lane, r);
-      stage_store<B>(st, lane, r);
-      __builtin_amdgcn_wave_barrier();
-      decode_staged<B, MODE, ENC, PF, true>(p, s, lane, st, last, dict_lds, dict_last, clo, chi);
-    } else {
-      uint4 x[B / 8];
-      const uint4* blk = reinterpret_cast<const uint4*>(p.payload + last * (32u * B));
-#pragma unroll
-      for (int q = 0; q < B / 8; ++q) x[q] = blk[64 * q + lane];
-      decode_bytes<B, MODE, ENC, PF, true>(p, s, lane, x, last);
-    }
-  }
+  // Grid-strided windows of p.G blocks: at any moment the wavefronts read one
+  // compact region of the column (DRAM row locality), like a streaming copy.
+  const uint64_t gw = (uint64_t)blockIdx.x * nw + wave, tw = (uint64_t)gridDim.x * nw;
+  scan_range<B, DEC, MODE, ENC, PF, false>(p, s, lane, list, st, gw * p.G, p.nb, tw * p.G, p.G, dict_lds, dict_last,
+                                           clo, chi);
   if constexpr (MODE == MODE_SV) sv_drain_rest<ENC, uint32_t>(s, lane, dict_lds, dict_last);
-  finish_scan(p, s.count, s.lsum + (lane == 0 ? s.refsum : 0ull), s.blocks);
+  finish_scan(p, s.count + wave_sum_u64(s.lcount), s.lsum + (lane == 0 ? s.refsum : 0ull), s.blocks);
 }
 
 // ------------------------------------------------------------- delta scan
@@ -759,31 +814,45 @@ __device__ __forceinline__ void decode_delta_pair(const Params& p, WaveState<Rel
     pre[t] = run;
   }
   const R excl = seg_inclusive_scan<R, 32>(run, lane) - run;
-  uint32_t cA = 0, cB = 0;
   using PT = typename std::conditional<(B <= 16), uint32_t, uint64_t>::type;
   PT part = 0;
+  if constexpr (MODE == MODE_BF) {
+    uint32_t lc = 0;
 #pragma unroll
-  for (int t = 0; t < 32; ++t) {
-    const R rel = excl + pre[t];
-    const bool hit = (R)(rel - rr.loc) <= rr.wm1;
-    uint64_t m = ballot(hit) & act_m;
-    bool valid = true;
-    if (TAIL) {
-      valid = 32u * l + t < limit;
-      m &= ballot(valid);
+    for (int t = 0; t < 32; ++t) {
+      const R rel = excl + pre[t];
+      bool ok = (R)(rel - rr.loc) <= rr.wm1;
+      if (TAIL) ok = ok && (32u * l + t < limit);
+      lc += ok ? 1u : 0u;
+      part += ok ? (PT)rel : (PT)0;
+      if ((t & 3) == 3) {
+        pin(part);
+        pin(lc);
+      }
     }
-    cA += (uint32_t)__builtin_popcount((uint32_t)m);
-    cB += (uint32_t)__builtin_popcount((uint32_t)(m >> 32));
-    if constexpr (MODE == MODE_BF) {
-      part += (hit && valid) ? (PT)rel : (PT)0;
-      pin(part);
-    } else {
+    if (act) {
+      s.lcount += lc;
+      s.lsum += (uint64_t)part + (uint64_t)lc * (uint64_t)base;
+    }
+  } else {
+    uint32_t cA = 0, cB = 0;
+#pragma unroll
+    for (int t = 0; t < 32; ++t) {
+      const R rel = excl + pre[t];
+      const bool hit = (R)(rel - rr.loc) <= rr.wm1;
+      uint64_t m = ballot(hit) & act_m;
+      bool valid = true;
+      if (TAIL) {
+        valid = 32u * l + t < limit;
+        m &= ballot(valid);
+      }
+      cA += (uint32_t)__builtin_popcount((uint32_t)m);
+      cB += (uint32_t)__builtin_popcount((uint32_t)(m >> 32));
       sv_push<ENC_DELTA, R>(s, rel, hit && act && valid, m, lane, nullptr, 0);
     }
+    s.count += (uint64_t)cA + cB;
+    s.refsum += (uint64_t)cA * readlane64((uint64_t)base, 0) + (uint64_t)cB * readlane64((uint64_t)base, 32);
   }
-  s.count += (uint64_t)cA + cB;
-  s.refsum += (uint64_t)cA * readlane64((uint64_t)base, 0) + (uint64_t)cB * readlane64((uint64_t)base, 32);
-  if constexpr (MODE == MODE_BF) s.lsum += act ? (uint64_t)part : 0ull;
 }
 
 // Delta, wavefront per staged block: lane l takes the contiguous run
@@ -820,23 +889,29 @@ __device__ __forceinline__ void decode_delta_staged(const Params& p, WaveState<R
   for (int t = 0; t < 16; ++t) {
     const R rel = excl + pre[t];
     const bool hit = (R)(rel - rr.loc) <= rr.wm1;
-    uint64_t m = ballot(hit);
-    bool valid = true;
-    if (TAIL) {
-      valid = 16u * lane + t < limit;
-      m &= ballot(valid);
-    }
-    cnt += (uint32_t)__builtin_popcountll(m);
+    const bool valid = !TAIL || (16u * lane + t < limit);
     if constexpr (MODE == MODE_BF) {
-      part += (hit && valid) ? (PT)rel : (PT)0;
-      pin(part);
+      const bool ok = hit && valid;
+      cnt += ok ? 1u : 0u;
+      part += ok ? (PT)rel : (PT)0;
+      if ((t & 3) == 3) {
+        pin(part);
+        pin(cnt);
+      }
     } else {
+      uint64_t m = ballot(hit);
+      if (TAIL) m &= ballot(valid);
+      cnt += (uint32_t)__builtin_popcountll(m);
       sv_push<ENC_DELTA, R>(s, rel, hit && valid, m, lane, nullptr, 0);
     }
   }
-  s.count += cnt;
-  s.refsum += (uint64_t)cnt * (uint64_t)base;
-  s.lsum += (uint64_t)part;
+  if constexpr (MODE == MODE_BF) {
+    s.lcount += cnt;
+    s.lsum += (uint64_t)part + (uint64_t)cnt * (uint64_t)base;
+  } else {
+    s.count += cnt;
+    s.refsum += (uint64_t)cnt * (uint64_t)base;
+  }
 }
 
 template <int B, int DEC, int MODE>
@@ -850,26 +925,19 @@ __host__ __device__ constexpr uint32_t delta_scan_lds(uint32_t waves) {
   return waves * delta_wave_words<B, DEC, MODE>() * 4u;
 }
 
-template <int B, int DEC, int MODE>
-__global__ __launch_bounds__(256) void delta_scan(const Params p) {
-  using R = RelT<B>;
-  extern __shared__ __align__(16) unsigned char smem[];
-  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  uint32_t* wave_area = reinterpret_cast<uint32_t*>(smem) + wave * delta_wave_words<B, DEC, MODE>();
-  uint32_t* list = wave_area;
-  uint32_t* st = wave_area + kListWords;
-  WaveState<R> s;
-  s.ring = reinterpret_cast<R*>(st + (DEC == DEC_RM_LDS ? Geo<B>::kLdsBlocks * Geo<B>::kStageWords : 0u));
-  uint64_t ka, ke;
-  wave_range(p.nb, (uint64_t)blockIdx.x * nw + wave, (uint64_t)gridDim.x * nw, ka, ke);
+// Scan blocks [ka, ke) of a delta column into the wavefront state (see
+// scan_range for SMALL and the partial last block).
+template <int B, int DEC, int MODE, bool SMALL>
+__device__ __forceinline__ void delta_range(const Params& p, WaveState<RelT<B>>& s, uint32_t lane, uint32_t* list,
+                                            uint32_t* st, uint64_t ka, uint64_t ke, uint64_t stride, uint32_t win) {
   const uint64_t last = p.nb - 1;
   const bool tail_partial = p.tail != kBlockValues;
   const uint64_t excl = tail_partial ? last : ~0ull;
   auto live_fn = [&](uint64_t k0, uint32_t cnt) { return window_live_i64(p, k0, cnt, excl); };
   if constexpr (DEC == DEC_RM_DIRECT) {
-    constexpr int P = Geo<B>::kPairs;
+    constexpr int P = SMALL ? 1 : Geo<B>::kPairs;
     const uint32_t l = lane & 31u;
-    PairCursor<P, decltype(live_fn)> cur{ka, ke, 0, 0, 0, list, ka};
+    PairCursor<P, decltype(live_fn)> cur{ka, ke, 0, 0, 0, list, ka, stride, win};
     uint64_t k0b[P], k1b[P];
     uint32_t a0 = 0, a1 = 0;
     uint32_t w0[P][B], w1[P][B];
@@ -895,8 +963,8 @@ __global__ __launch_bounds__(256) void delta_scan(const Params p) {
       }
     }
   } else {
-    constexpr int NB = Geo<B>::kLdsBlocks, NL = Geo<B>::kStageLoads, SW = Geo<B>::kStageWords;
-    BlockCursor<NB, decltype(live_fn)> cur{ka, ke, 0, 0};
+    constexpr int NB = SMALL ? 1 : Geo<B>::kLdsBlocks, NL = Geo<B>::kStageLoads, SW = Geo<B>::kStageWords;
+    BlockCursor<NB, decltype(live_fn)> cur{ka, ke, 0, 0, stride, win};
     uint64_t k0 = 0, m0 = 0, k1 = 0, m1 = 0;
     uint32_t r0[NB][NL], r1[NB][NL];
     auto load = [&](uint64_t base, uint64_t mask, uint32_t (&dst)[NB][NL]) {
@@ -935,7 +1003,7 @@ __global__ __launch_bounds__(256) void delta_scan(const Params p) {
       }
     }
   }
-  if (tail_partial && ka <= last && last < ke && block_survives<ENC_DELTA>(p, last, 0, 0)) {
+  if (tail_partial && owns_block(last, ka, ke, stride, win) && block_survives<ENC_DELTA>(p, last, 0, 0)) {
     s.blocks += 1;
     if constexpr (DEC == DEC_RM_DIRECT) {
       uint32_t w[B];
@@ -949,8 +1017,22 @@ __global__ __launch_bounds__(256) void delta_scan(const Params p) {
       decode_delta_staged<B, MODE, true>(p, s, lane, st, last);
     }
   }
+}
+
+template <int B, int DEC, int MODE>
+__global__ __launch_bounds__(256) void delta_scan(const Params p) {
+  using R = RelT<B>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  uint32_t* wave_area = reinterpret_cast<uint32_t*>(smem) + wave * delta_wave_words<B, DEC, MODE>();
+  uint32_t* list = wave_area;
+  uint32_t* st = wave_area + kListWords;
+  WaveState<R> s;
+  s.ring = reinterpret_cast<R*>(st + (DEC == DEC_RM_LDS ? Geo<B>::kLdsBlocks * Geo<B>::kStageWords : 0u));
+  const uint64_t gw = (uint64_t)blockIdx.x * nw + wave, tw = (uint64_t)gridDim.x * nw;
+  delta_range<B, DEC, MODE, false>(p, s, lane, list, st, gw * p.G, p.nb, tw * p.G, p.G);
   if constexpr (MODE == MODE_SV) sv_drain_rest<ENC_DELTA, R>(s, lane, nullptr, 0);
-  finish_scan(p, s.count, s.lsum + (lane == 0 ? s.refsum : 0ull), s.blocks);
+  finish_scan(p, s.count + wave_sum_u64(s.lcount), s.lsum + (lane == 0 ? s.refsum : 0ull), s.blocks);
 }
 
 }  // namespace scan_dev

@@ -1,0 +1,271 @@
+"""GPU parity of batched scans and of the strategy selector.
+
+Batches mix every encoding, width, length (ragged tails, one-value columns),
+predicate edge case and strategy; every item must equal the CPU oracle bit
+for bit, whatever strategy the device chose, and replays must repeat it.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2606_22423_amd import _lib, api  # noqa: E402
+from paper_2606_22423_amd._lib import DEC_RM_DIRECT, DEC_RM_LDS, ENC_DELTA, ENC_DICT, ENC_FOR, strategy  # noqa: E402
+
+K = 8  # selector classes
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def class_strategy(c):
+    return strategy(c & 1, (c >> 1) & 1, (c >> 2) & 1)
+
+
+class Case:
+    """One column: device encoding, raw values and oracle results on demand."""
+
+    def __init__(self, spec):
+        self.spec = spec
+        v, lo, hi, dct = synth.config4_values(spec)
+        self.v, self.lo, self.hi, self.dct = v, lo, hi, dct
+        b, n = spec.b, spec.n
+        if spec.enc == ENC_FOR:
+            self.col = api.encode_for(v, b)
+            self.words = oracle.pack_rm(v, b)
+        elif spec.enc == ENC_DELTA:
+            self.col = api.encode_delta(v, b)
+            self.bases, codes = oracle.delta_encode(v, b)
+            self.words = oracle.pack_rm(codes, b)
+        else:
+            self.col = api.encode_dict(v, b, dct)
+            self.words = oracle.pack_rm(v, b)
+
+    def want(self, lo, hi, zm):
+        s, b, n = self.spec, self.spec.b, self.spec.n
+        if s.enc == ENC_FOR:
+            return oracle.scan_for(self.words, n, b, lo, hi, zone_maps=zm)
+        if s.enc == ENC_DELTA:
+            return oracle.scan_delta(self.words, self.bases, n, b, lo, hi, zone_maps=zm)
+        return oracle.scan_dict(self.words, self.dct, n, b, lo, hi, zone_maps=zm)
+
+    def zone_domain(self, lo, hi):
+        """Zone maps and predicate in the domain the zone maps are kept in."""
+        if self.spec.enc == ENC_FOR:
+            zmin, zmax = oracle.zonemap_u32(self.v)
+        elif self.spec.enc == ENC_DELTA:
+            zmin, zmax = oracle.zonemap_i64(self.v)
+        else:
+            zmin, zmax = oracle.zonemap_u32(self.v)
+            lo, hi = int(np.searchsorted(self.dct, lo)), int(np.searchsorted(self.dct, hi))
+        return zmin, zmax, lo, hi
+
+
+@pytest.fixture(scope="module")
+def cases():
+    specs = synth.config4_specs(96, seed=synth.SEED_BASE + 40, log2_min=0.0, log2_max=16.5, bmax=32)
+    return [Case(s) for s in specs]
+
+
+def predicates(case, j):
+    """The workload's predicate, plus edge cases on some columns."""
+    lo, hi = case.lo, case.hi
+    extra = [(lo, hi), (5, 5), (hi, lo), (-(1 << 62), 1 << 62)]
+    return extra[j % 4] if j % 5 == 4 else (lo, hi)
+
+
+def check_item(case, got, lo, hi, what):
+    assert got["status"] == 0, (what, got)
+    s = got["strategy_used"]
+    want = case.want(lo, hi, zm=bool((s >> 3) & 1))
+    assert (got["count"], got["sum"], got["blocks_read"], got["blocks_total"]) == \
+        (want.count, want.sum, want.blocks_read, want.blocks_total), (what, got, want)
+
+
+def build_items(cases, with_zone_maps=True):
+    items, meta = [], []
+    for j, c in enumerate(cases):
+        lo, hi = predicates(c, j)
+        zm = with_zone_maps and j % 7 != 3
+        choice = j % (K + 1)
+        strat = -1 if choice == K else class_strategy(choice)
+        if not zm and strat >= 0 and (strat >> 3) & 1:
+            strat &= ~8
+        items.append(c.col.item(lo, hi, strat, zone_maps=zm))
+        meta.append((c, lo, hi, strat, zm))
+    return items, meta
+
+
+def test_batch_matches_oracle(ctx, cases):
+    items, meta = build_items(cases)
+    say("batch of", len(items), "columns")
+    res = ctx.batch_run(items)
+    for (c, lo, hi, strat, zm), got in zip(meta, res):
+        what = (c.spec.index, c.spec.enc, c.spec.b, c.spec.n, lo, hi, strat)
+        check_item(c, got, lo, hi, what)
+        if strat >= 0:
+            assert got["strategy_used"] == strat, what
+        else:
+            # no selector: the heuristic (row-major direct decoder, branch-free,
+            # zone maps when present)
+            assert got["strategy_used"] == strategy(DEC_RM_DIRECT, 0, 1 if zm else 0), what
+
+
+def test_batch_equals_single_scans(ctx, cases):
+    items, meta = build_items(cases[:40])
+    res = ctx.batch_run(items)
+    for (c, lo, hi, strat, zm), got in zip(meta, res):
+        single = ctx.run(c.col, lo, hi, got["strategy_used"], zone_maps=zm)
+        assert {k: got[k] for k in ("count", "sum", "blocks_read", "blocks_total", "strategy_used")} == \
+            {k: single[k] for k in ("count", "sum", "blocks_read", "blocks_total", "strategy_used")}
+
+
+def test_batch_replays_repeat(ctx, cases):
+    items, meta = build_items(cases[:50])
+    h = ctx.batch_prepare(items)
+    try:
+        first = ctx.batch_replay(h, len(items))
+        ctx.batch_replay(h, wait=False)
+        ctx.batch_replay(h, wait=False)
+        # eager work between replays on the same stream
+        x = torch.ones(1 << 20, device="cuda")
+        x.mul_(2.0)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            assert ctx.batch_replay(h, len(items)) == first
+    finally:
+        ctx.batch_release(h)
+    for (c, lo, hi, strat, zm), got in zip(meta, first):
+        check_item(c, got, lo, hi, (c.spec.index, strat))
+
+
+def test_batch_window_and_occupancy_do_not_change_results(ctx, cases):
+    items, meta = build_items(cases[:30])
+    base = ctx.batch_run(items)
+    try:
+        for per_cu, win in ((1, 1), (4, 7), (2, 64)):
+            ctx.batch_set_tune(per_cu, win)
+            assert ctx.batch_run(items) == base, (per_cu, win)
+    finally:
+        ctx.batch_set_tune(0, 0)
+
+
+def test_batch_invalid_items_report_status(ctx, cases):
+    c = cases[5]
+    good = c.col.item(c.lo, c.hi, class_strategy(1))
+    bad_width = c.col.item(c.lo, c.hi, class_strategy(1))
+    bad_width.b = 0
+    bad_strat = c.col.item(c.lo, c.hi, strategy(2, 0, 0))  # lane-interleaved decoder on a row-major column
+    no_zm = c.col.item(c.lo, c.hi, class_strategy(4), zone_maps=False)  # zone-map class without zone maps
+    res = ctx.batch_run([good, bad_width, bad_strat, no_zm, good])
+    assert res[1]["status"] == _lib.SCAN_EINVAL
+    assert res[2]["status"] == _lib.SCAN_EUNSUPPORTED
+    assert res[3]["status"] == _lib.SCAN_EUNSUPPORTED
+    check_item(c, res[0], c.lo, c.hi, "good")
+    assert res[4] == res[0]
+    assert ctx.batch_run([]) == []
+
+
+def random_theta(seed, scale=0.4):
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal(omlp.n_params(K)) * scale).astype(np.float32)
+
+
+def test_features_match_oracle(ctx, cases):
+    items, meta = [], []
+    for j, c in enumerate(cases):
+        lo, hi = predicates(c, j)
+        items.append(c.col.item(lo, hi, -1))
+        meta.append((c, lo, hi))
+    X = torch.zeros(len(items), 6, dtype=torch.float32, device="cuda")
+    ctx.features(items, X)
+    got = X.cpu().numpy().astype(np.float64)
+    for (c, lo, hi), g in zip(meta, got):
+        zmin, zmax, zlo, zhi = c.zone_domain(lo, hi)
+        want = omlp.features(c.spec.b, c.spec.n, c.spec.enc, zmin, zmax, zlo, zhi)
+        # fp64 on both sides, rounded to fp32 on the device
+        assert np.allclose(g, want, rtol=2e-6, atol=2e-6), (c.spec.index, lo, hi, g, want)
+
+
+def test_selector_choice_is_network_argmin(ctx, cases):
+    theta = random_theta(11)
+    items, meta = [], []
+    for j, c in enumerate(cases):
+        lo, hi = predicates(c, j)
+        zm = j % 7 != 3
+        items.append(c.col.item(lo, hi, -1, zone_maps=zm))
+        meta.append((c, lo, hi, zm))
+    X = torch.zeros(len(items), 6, dtype=torch.float32, device="cuda")
+    ctx.selector_set(theta)
+    try:
+        assert ctx.selector_loaded
+        ctx.features(items, X)
+        res = ctx.batch_run(items)
+    finally:
+        ctx.selector_clear()
+    pred, _ = omlp.forward(theta.astype(np.float64), X.cpu().numpy().astype(np.float64), K)
+    checked = 0
+    for i, ((c, lo, hi, zm), got) in enumerate(zip(meta, res)):
+        check_item(c, got, lo, hi, (c.spec.index, "auto"))
+        valid = np.array([zm or not ((q >> 2) & 1) for q in range(K)])
+        p = np.where(valid, pred[i], np.inf)
+        order = np.argsort(p, kind="stable")
+        if p[order[1]] - p[order[0]] < 1e-3:  # fp32 near-tie: either choice is the network's
+            continue
+        assert got["strategy_used"] == class_strategy(int(order[0])), (i, p, got)
+        checked += 1
+    assert checked > len(res) // 2
+
+
+def test_scan_run_auto_uses_selector(ctx, cases, tmp_path):
+    theta = random_theta(12)
+    path = str(tmp_path / "sel.txt")
+    ctx.selector_set(theta)
+    try:
+        ctx.selector_save(path)
+        ctx.selector_clear()
+        assert not ctx.selector_loaded
+        ctx.selector_load(path)
+        items = [c.col.item(c.lo, c.hi, -1) for c in cases[:24]]
+        batch = ctx.batch_run(items)
+        for c, got in zip(cases[:24], batch):
+            single = ctx.run(c.col, c.lo, c.hi, -1)
+            assert single["strategy_used"] == got["strategy_used"]
+            check_item(c, single, c.lo, c.hi, c.spec.index)
+    finally:
+        ctx.selector_clear()
+    loaded = np.loadtxt(path, skiprows=1, dtype=np.float64)
+    assert np.array_equal(loaded.astype(np.float32), theta)
+
+
+def test_selector_rejects_bad_parameters(ctx, tmp_path):
+    with pytest.raises(_lib.ScanError):
+        ctx.selector_set(np.zeros(10, dtype=np.float32))
+    bad = random_theta(1)
+    bad[7] = np.nan
+    with pytest.raises(_lib.ScanError):
+        ctx.selector_set(bad)
+    p = tmp_path / "bad.txt"
+    p.write_text("not-a-selector 3\n1 2 3\n")
+    with pytest.raises(_lib.ScanError):
+        ctx.selector_load(str(p))
+    assert not ctx.selector_loaded

@@ -1,0 +1,114 @@
+"""GPU selector-network kernels (forward, masked-MSE gradient, Adam) against
+the fp64 CPU reference.  Bar: per parameter tensor,
+max|g - g_ref| <= 1e-4 * (max|g_ref| + 1e-6); forward outputs and the loss
+within 1e-4 of the reference's scale; Adam within fp32 rounding."""
+import numpy as np
+import pytest
+
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2606_22423_amd import api  # noqa: E402
+
+K = 8
+SHAPES = [(64, 6), (64,), (64, 64), (64,), (K, 64), (K,)]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def data(rows, seed):
+    rng = np.random.default_rng(seed)
+    theta = (rng.standard_normal(omlp.n_params(K)) * 0.3).astype(np.float32)
+    X = rng.uniform(-1.0, 1.0, size=(rows, 6)).astype(np.float32)
+    Y = rng.standard_normal((rows, K)).astype(np.float32)
+    M = (rng.uniform(size=(rows, K)) < 0.7).astype(np.float32)
+    M[0] = 1.0
+    return theta, X, Y, M
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_param_count():
+    assert api.Context.mlp_param_count() == omlp.n_params(K) == 5128
+
+
+@pytest.mark.parametrize("rows", [1, 63, 64, 1000, 4096])
+def test_forward_matches_reference(ctx, rows):
+    theta, X, _, _ = data(rows, rows)
+    out = torch.empty(rows, K, dtype=torch.float32, device="cuda")
+    ctx.mlp_forward(dev(theta), dev(X), out)
+    torch.cuda.synchronize()
+    ref, _ = omlp.forward(theta.astype(np.float64), X.astype(np.float64), K)
+    got = out.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(got - ref)) <= 1e-4 * (np.max(np.abs(ref)) + 1e-6)
+
+
+@pytest.mark.parametrize("rows", [1, 31, 32, 33, 1000, 2500])
+def test_gradient_matches_reference(ctx, rows):
+    theta, X, Y, M = data(rows, 100 + rows)
+    inv = 1.0 / float(M.sum())
+    grad = torch.empty(omlp.n_params(K), dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    ctx.mlp_loss_grad(dev(theta), dev(X), dev(Y), dev(M), inv, grad, loss)
+    torch.cuda.synchronize()
+    L, g_ref = omlp.backward(theta.astype(np.float64), X.astype(np.float64), Y.astype(np.float64),
+                             M.astype(np.float64), K)
+    g = grad.cpu().numpy().astype(np.float64)
+    assert abs(float(loss.item()) - L) <= 1e-4 * (abs(L) + 1e-6)
+    off = 0
+    for shp in SHAPES:
+        size = int(np.prod(shp))
+        a, r = g[off:off + size], g_ref[off:off + size]
+        assert np.max(np.abs(a - r)) <= 1e-4 * (np.max(np.abs(r)) + 1e-6), (shp, np.max(np.abs(a - r)))
+        off += size
+
+
+def test_adam_matches_reference(ctx):
+    theta, X, Y, M = data(300, 7)
+    n = theta.size
+    rng = np.random.default_rng(3)
+    t_dev, m_dev, v_dev = dev(theta), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
+    t_ref, m_ref, v_ref = theta.astype(np.float64), np.zeros(n), np.zeros(n)
+    for step in range(1, 6):
+        g = (rng.standard_normal(n) * 10.0 ** rng.uniform(-4, 0, size=n)).astype(np.float32)
+        ctx.adam_step(t_dev, dev(g), m_dev, v_dev, step, lr=1e-3)
+        t_ref, m_ref, v_ref = omlp.adam_step(t_ref, g.astype(np.float64), m_ref, v_ref, step, lr=1e-3)
+    torch.cuda.synchronize()
+    assert np.allclose(t_dev.cpu().numpy(), t_ref, rtol=0, atol=1e-6)
+    assert np.allclose(m_dev.cpu().numpy(), m_ref, rtol=1e-5, atol=1e-9)
+    assert np.allclose(v_dev.cpu().numpy(), v_ref, rtol=1e-5, atol=1e-12)
+
+
+def test_training_on_device_reduces_loss(ctx):
+    """A few hundred device Adam steps on a smooth target lower the loss."""
+    rng = np.random.default_rng(5)
+    rows = 2048
+    X = rng.uniform(0, 1, size=(rows, 6)).astype(np.float32)
+    W = rng.standard_normal((6, K))
+    Y = (np.sin(X @ W) + 0.1 * X.sum(axis=1, keepdims=True)).astype(np.float32)
+    M = np.ones((rows, K), dtype=np.float32)
+    theta = (rng.standard_normal(omlp.n_params(K)) * 0.1).astype(np.float32)
+    t, m, v = dev(theta), torch.zeros(theta.size, device="cuda"), torch.zeros(theta.size, device="cuda")
+    Xd, Yd, Md = dev(X), dev(Y), dev(M)
+    grad = torch.empty(theta.size, device="cuda")
+    loss = torch.empty(1, device="cuda")
+    ctx.mlp_loss_grad(t, Xd, Yd, Md, 1.0 / M.sum(), grad, loss)
+    first = float(loss.item())
+    for step in range(1, 301):
+        ctx.mlp_loss_grad(t, Xd, Yd, Md, 1.0 / M.sum(), grad, loss)
+        ctx.adam_step(t, grad, m, v, step, lr=3e-3)
+    ctx.mlp_loss_grad(t, Xd, Yd, Md, 1.0 / M.sum(), grad, loss)
+    last = float(loss.item())
+    assert last < 0.2 * first, (first, last)

@@ -233,3 +233,21 @@ def test_async_results_and_repeat_launches(ctx):
             r = api.result_from_tensor(host[k])
             assert (r["count"], r["sum"]) == (want.count, want.sum)
             k += 1
+
+
+def test_launch_tuning_does_not_change_results(ctx):
+    """Work-group size, work-groups per CU and the window size are speed knobs only."""
+    n = 300 * 1024 + 999
+    for b in (3, 13, 32):
+        v = synth.width_values(synth.pcg32(44, b, n), b)
+        col = api.encode_for(v, b)
+        lo, hi = (1 << b) // 5, (1 << b) // 2
+        want = oracle.scan_for(oracle.pack_rm(v, b), n, b, lo, hi, zone_maps=True)
+        for s in (strategy(DEC_RM_DIRECT, 0, 1), strategy(DEC_RM_LDS, 1, 0)):
+            for wg, per_cu, win in ((64, 1, 1), (128, 3, 5), (256, 0, 64), (192, 2, 0)):
+                ctx.set_tune(ENC_FOR, b, s, wg, per_cu, win)
+                got = ctx.run(col, lo, hi, s)
+                assert (got["count"], got["sum"]) == (want.count, want.sum), (b, s, wg, per_cu, win)
+                if (s >> 3) & 1:
+                    assert got["blocks_read"] == want.blocks_read
+            ctx.set_tune(ENC_FOR, b, s, 0, 0, 0)
