@@ -86,6 +86,109 @@ def measure_beta(ctx, torch, reps=7):
     return best, best_cfg, triad
 
 
+def batch_leg(ctx, torch, ncols, reps, selector_path):
+    """Mixed-column workload: ncols columns (lengths 2^10..2^24, widths 1..24,
+    FOR / delta / dictionary by index mod 3, log-uniform selectivity, zone maps
+    on all).  Baseline: one launch per column with the default strategy, (i)
+    synchronous calls, (ii) asynchronous launches on one stream and one final
+    sync.  Treatment: one replay of the captured batch graph with the trained
+    selector (and, for reference, with the heuristic).  Results of every
+    column must agree across all three."""
+    import numpy as np
+
+    import synth
+    from paper_2606_22423_amd import selector_train as st
+    from paper_2606_22423_amd._lib import DEC_RM_DIRECT, strategy
+
+    t0 = time.time()
+    specs = synth.config4_specs(ncols)
+    cols = st.build_columns(specs)
+    torch.cuda.synchronize()
+    total_values = sum(sp.n for sp in specs)
+    payload = sum(c.payload_bytes for c, _, _ in cols)
+    log("[bench] batch workload: %d columns, %.3g values, %.2f GB payload, built in %.0f s" %
+        (ncols, total_values, payload / 1e9, time.time() - t0))
+    default = strategy(DEC_RM_DIRECT, 0, 1)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        fn()
+        b.record(stream)
+        b.synchronize()
+        return a.elapsed_time(b) * 1e-3
+
+    # (i) synchronous per-column calls (host clock: each call waits)
+    t_sync = []
+    res_sync = None
+    for _ in range(max(1, reps // 2)):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        res_sync = [ctx.run(c, lo, hi, default) for c, lo, hi in cols]
+        t_sync.append(time.perf_counter() - t1)
+    # (ii) asynchronous launches, one sync
+    out = torch.zeros((ncols, 5), dtype=torch.int64, device="cuda")
+
+    def launch_all():
+        for i, (c, lo, hi) in enumerate(cols):
+            ctx.run_async(c, lo, hi, default, out[i])
+
+    launch_all()
+    t_async = [timed(launch_all) for _ in range(reps)]
+    host = out.cpu().numpy()
+    items_auto = [c.item(lo, hi, -1) for c, lo, hi in cols]
+
+    def replay_times(handle):
+        ctx.batch_replay(handle, wait=False)
+        return [timed(lambda: ctx.batch_replay(handle, wait=False)) for _ in range(reps)]
+
+    def check(res, what):
+        for i, r in enumerate(res):
+            if (r["status"], r["count"], r["sum"]) != (0, res_sync[i]["count"], res_sync[i]["sum"]) or \
+                    (r["count"], r["sum"]) != (int(host[i, 0]), int(host[i, 1])):
+                raise RuntimeError("%s: column %d differs: %s vs %s" % (what, i, r, res_sync[i]))
+
+    ctx.selector_clear()
+    h = ctx.batch_prepare(items_auto)
+    t_heur = replay_times(h)
+    res_heur = ctx.batch_replay(h, ncols)
+    ctx.batch_release(h)
+    check(res_heur, "heuristic batch")
+    learned = None
+    if selector_path and os.path.exists(selector_path):
+        ctx.selector_load(selector_path)
+        h = ctx.batch_prepare(items_auto)
+        t_learn = replay_times(h)
+        res_learn = ctx.batch_replay(h, ncols)
+        ctx.batch_release(h)
+        ctx.selector_clear()
+        check(res_learn, "learned batch")
+        chosen = np.bincount([st.STRATEGIES.index(r["strategy_used"]) for r in res_learn], minlength=8)
+        learned = {"ms": round(float(np.median(t_learn)) * 1e3, 3), "class_counts": chosen.tolist()}
+    base_ms = float(np.median(t_async)) * 1e3
+    treat_ms = learned["ms"] if learned else float(np.median(t_heur)) * 1e3
+    res = {
+        "workload": "%d mixed columns: n = floor(2^(10+14u)), b in 1..24, FOR/delta/dict by index mod 3, "
+                    "sigma log-uniform [1e-4, 0.9], zone maps on all" % ncols,
+        "values": int(total_values), "payload_bytes": int(payload),
+        "baseline_sync_ms": round(float(np.median(t_sync)) * 1e3, 3),
+        "baseline_async_ms": round(base_ms, 3),
+        "batch_heuristic_ms": round(float(np.median(t_heur)) * 1e3, 3),
+        "batch_learned": learned,
+        "speedup_vs_async": round(base_ms / treat_ms, 3),
+        "speedup_vs_sync": round(float(np.median(t_sync)) * 1e3 / treat_ms, 3),
+        "batch_values_per_s": round(total_values / (treat_ms * 1e-3), 1),
+        "batch_gb_per_s": round(payload / (treat_ms * 1e-3) / 1e9, 1),
+        "parity": "every column equal across sync, async and both batches",
+    }
+    log("[bench] batch: async %.3f ms, heuristic batch %.3f ms, learned %s" %
+        (base_ms, res["batch_heuristic_ms"], learned))
+    del cols
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +199,10 @@ def main():
     ap.add_argument("--no-sweep-sigmas", action="store_true", help="sweep only sigma = 0.1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--detail", default=None, help="write the full sweep as JSON to this file")
+    ap.add_argument("--no-autotune", action="store_true", help="library default launch shapes")
+    ap.add_argument("--batch-cols", type=int, default=4096, help="mixed-column workload size (0: skip it)")
+    ap.add_argument("--selector", default=os.path.join(ROOT, "paper_2606_22423_amd", "selector_mi355x.txt"),
+                    help="trained selector parameters for the batched leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: every run here has exactly one MI355X; --gpus %d is not supported "
@@ -161,6 +268,16 @@ def main():
         torch.cuda.synchronize()
         return {b: events[2 * i].elapsed_time(events[2 * i + 1]) * 1e-3
                 for i, b in enumerate(widths) if strat_of_b(b) is not None}
+
+    # --- launch autotuning of every (width, strategy) at the headline selectivity
+    tuned = {}
+    if not args.no_autotune:
+        t0 = time.time()
+        for b in widths:
+            for s in cands(b):
+                cfg, ms = ctx.autotune(col_for(b, s), 0, bounds[b], s, reps=3)
+                tuned["%d/%s" % (b, strategy_name(s))] = list(cfg) + [round(ms, 5)]
+        log("[bench] autotuned %d (width, strategy) pairs in %.1f s" % (len(tuned), time.time() - t0))
 
     # --- sweep: every decoder x predicate mode, every width, median of reps
     sigmas = [SIGMA] if args.no_sweep_sigmas else list(synth.SIGMAS_SWEEP)
@@ -293,6 +410,10 @@ def main():
                          "serial decode + filter + exact sum, median of 5 per width" % (list(sample_w),)}
         log("[bench] cpu oracle %.3g values/s" % (tot_v / tot_t))
 
+    batch = None
+    if args.batch_cols > 0:
+        batch = batch_leg(ctx, torch, args.batch_cols, args.reps, args.selector)
+
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "decoded values/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(total_s / args.steps * 1e3, 4),
@@ -308,10 +429,11 @@ def main():
         "per_b": per_b,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batch": batch,
     }
     if args.detail:
         with open(args.detail, "w") as fh:
-            json.dump({"line": line, "sigma_fits": sigma_fits,
+            json.dump({"line": line, "sigma_fits": sigma_fits, "autotuned": tuned,
                        "sweep_ms": {"%s@%g" % (strategy_name(s), sg): {b: round(t * 1e3, 5) for b, t in tb.items()}
                                     for (sg, s), tb in sweep.items()}}, fh, indent=1)
     print(json.dumps(line), flush=True)

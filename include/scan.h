@@ -260,6 +260,96 @@ scan_status scan_mlp_loss_grad(scan_ctx* ctx, const float* theta, const float* X
 scan_status scan_adam_step(scan_ctx* ctx, float* theta, const float* grad, float* m, float* v, uint32_t count,
                            int32_t step, float lr, float beta1, float beta2, float eps);
 
+/* ---------------------------------------------------------------- serving */
+/* A table: columns of equal row count, each row-major frame-of-reference
+ * (optional per-block references) or dictionary, any width 1..32, all with
+ * zone maps.  A query: COUNT and SUM(sum_col) over the rows where every filter
+ * conjunct filter_col[f] in [lo_f, hi_f) holds (1..3 conjuncts; values for FOR
+ * columns, dictionary entries for dictionary columns).  Same exact-integer
+ * contract as scan_run: count = #{rows passing}, sum = (sum of sum_col over
+ * them) mod 2^64; blocks_read = blocks no conjunct's zone map excluded.  A
+ * result never depends on the other queries of a batch. */
+typedef struct {
+  scan_column col;            /* device buffers, caller-owned, alive as long as the table */
+  int32_t enc;                /* SCAN_ENC_FOR or SCAN_ENC_DICT */
+  uint32_t b;
+} scan_table_column;
+
+typedef struct scan_table scan_table;
+typedef struct scan_server scan_server;
+
+typedef struct {
+  uint32_t n_filters;         /* 1..3 */
+  uint32_t filter_col[3];
+  scan_predicate filter[3];
+  uint32_t sum_col;
+  uint32_t reserved;
+} scan_query;
+
+typedef struct {
+  uint64_t ticket;            /* scan_server_submit's ticket (scan_query_run: the query's index) */
+  uint64_t count;
+  int64_t sum;
+  uint64_t blocks_read;
+  double submit_us, done_us;  /* host steady clock (scan_server_clock_us): submission, completion seen */
+  int32_t status;
+  int32_t reserved;
+} scan_query_result;
+
+/* Server knobs.  Admission: a submit returns SCAN_EBUSY when max_inflight
+ * queries are admitted and unfinished, or when one more would take the
+ * device workspace of admitted queries (a descriptor and two result slots,
+ * 184 bytes each) past hbm_budget_bytes.  Batching: a free stream launches the
+ * oldest pending queries (at most max_batch) when the batch is full, when the
+ * oldest has waited batch_window_us, when no stream is busy, or when a stream
+ * has just completed.  window_blocks (0 = 16, at most 64) and wgs_per_cu
+ * (0 = 2) shape the kernel launch. */
+typedef struct {
+  uint64_t hbm_budget_bytes;
+  uint32_t max_inflight;
+  uint32_t n_streams;         /* 1..16 streams of default priority */
+  uint32_t max_batch;
+  uint32_t batch_window_us;
+  uint32_t window_blocks;
+  uint32_t wgs_per_cu;
+} scan_server_config;
+
+/* Validate the columns and upload their descriptors.  Errors: different row
+ * counts, missing zone maps, delta columns or LI layout -> SCAN_EINVAL /
+ * SCAN_EUNSUPPORTED. */
+scan_status scan_table_create(scan_ctx* ctx, const scan_table_column* cols, uint32_t n_cols, scan_table** out);
+void scan_table_destroy(scan_table* t);
+/* Run n queries as one batch on the context stream and wait; out (host) gets
+ * n results.  Bad filter or sum column indices -> SCAN_EINVAL. */
+scan_status scan_query_run(scan_ctx* ctx, const scan_table* t, const scan_query* queries, size_t n,
+                           scan_query_result* out);
+/* Launch shape of scan_query_run (0 = default). */
+scan_status scan_query_set_tune(scan_ctx* ctx, int32_t wgs_per_cu, int32_t window_blocks);
+
+/* Start a server on the context's device (its own host thread and streams;
+ * the context itself is not used by the thread).  The table must outlive it. */
+scan_status scan_server_create(scan_ctx* ctx, const scan_table* t, const scan_server_config* cfg, scan_server** out);
+/* Thread-safe.  SCAN_EBUSY: not admitted (retry later); *ticket identifies it. */
+scan_status scan_server_submit(scan_server* s, const scan_query* q, uint64_t* ticket);
+/* Thread-safe.  Moves up to max finished results to out, waiting up to wait_us
+ * for the first; *n_out receives how many. */
+scan_status scan_server_poll(scan_server* s, scan_query_result* out, size_t max, size_t* n_out, uint32_t wait_us);
+/* stats4: batches launched, queries launched, admitted unfinished, pending. */
+scan_status scan_server_stats(scan_server* s, uint64_t* stats4);
+/* The clock of submit_us / done_us, in microseconds. */
+double scan_server_clock_us(void);
+/* Stops the thread, waits for launched batches; pending queries are dropped. */
+void scan_server_destroy(scan_server* s);
+
+/* Host-only discrete-event run of the same admission and batching policy:
+ * arrivals at arrival_us[0..n) (non-decreasing), a batch of q queries busy
+ * for batch_fixed_us + q * per_query_us on its stream.  Writes per query the
+ * launch and completion times and the admission status (SCAN_EBUSY: refused,
+ * times -1), and the number of batches.  Needs no GPU. */
+scan_status scan_serve_simulate(const scan_server_config* cfg, const double* arrival_us, size_t n,
+                                double batch_fixed_us, double per_query_us, double* launch_us, double* done_us,
+                                int32_t* status, uint64_t* n_batches);
+
 /* -------------------------------------------------------------- encoders */
 /* Host-side encoders (host pointers).  Payload buffers must hold
  * scan_payload_words(n, b) u32; zone-map and reference/base buffers nb entries.

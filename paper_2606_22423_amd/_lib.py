@@ -69,6 +69,32 @@ class ScanTune(ctypes.Structure):
                 ("window_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class ScanTableColumn(ctypes.Structure):
+    _fields_ = [("col", ScanColumn), ("enc", ctypes.c_int32), ("b", ctypes.c_uint32)]
+
+
+class ScanQuery(ctypes.Structure):
+    _fields_ = [("n_filters", ctypes.c_uint32), ("filter_col", ctypes.c_uint32 * 3),
+                ("filter", ScanPredicate * 3), ("sum_col", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class ScanQueryResult(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("count", ctypes.c_uint64), ("sum", ctypes.c_int64),
+                ("blocks_read", ctypes.c_uint64), ("submit_us", ctypes.c_double), ("done_us", ctypes.c_double),
+                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"ticket": int(self.ticket), "count": int(self.count), "sum": int(self.sum),
+                "blocks_read": int(self.blocks_read), "submit_us": float(self.submit_us),
+                "done_us": float(self.done_us), "status": int(self.status)}
+
+
+class ScanServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_uint32),
+                ("n_streams", ctypes.c_uint32), ("max_batch", ctypes.c_uint32), ("batch_window_us", ctypes.c_uint32),
+                ("window_blocks", ctypes.c_uint32), ("wgs_per_cu", ctypes.c_uint32)]
+
+
 _vp, _u64, _u32, _i32, _i64, _f32 = (ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32,
                                      ctypes.c_int64, ctypes.c_float)
 _P = ctypes.POINTER
@@ -103,6 +129,18 @@ SIGNATURES = {
     "scan_mlp_forward": (_i32, [_vp, _vp, _vp, _u32, _vp]),
     "scan_mlp_loss_grad": (_i32, [_vp, _vp, _vp, _vp, _vp, _u32, _f32, _vp, _vp]),
     "scan_adam_step": (_i32, [_vp, _vp, _vp, _vp, _vp, _u32, _i32, _f32, _f32, _f32, _f32]),
+    "scan_table_create": (_i32, [_vp, _P(ScanTableColumn), _u32, _P(_vp)]),
+    "scan_table_destroy": (None, [_vp]),
+    "scan_query_run": (_i32, [_vp, _vp, _P(ScanQuery), ctypes.c_size_t, _P(ScanQueryResult)]),
+    "scan_query_set_tune": (_i32, [_vp, _i32, _i32]),
+    "scan_server_create": (_i32, [_vp, _vp, _P(ScanServerConfig), _P(_vp)]),
+    "scan_server_submit": (_i32, [_vp, _P(ScanQuery), _P(_u64)]),
+    "scan_server_poll": (_i32, [_vp, _P(ScanQueryResult), ctypes.c_size_t, _P(ctypes.c_size_t), _u32]),
+    "scan_server_stats": (_i32, [_vp, _P(_u64)]),
+    "scan_server_clock_us": (ctypes.c_double, []),
+    "scan_server_destroy": (None, [_vp]),
+    "scan_serve_simulate": (_i32, [_P(ScanServerConfig), _P(ctypes.c_double), ctypes.c_size_t, ctypes.c_double,
+                                   ctypes.c_double, _P(ctypes.c_double), _P(ctypes.c_double), _P(_i32), _P(_u64)]),
     "scan_payload_words": (_u64, [_u64, _u32]),
     "scan_encode_for": (_i32, [_vp, _u64, _u32, _u32, _i32, _vp, _vp, _vp, _vp]),
     "scan_encode_delta": (_i32, [_vp, _u64, _u32, _vp, _vp, _vp, _vp]),

@@ -36,16 +36,53 @@ def class_strategy(c: int) -> int:
 STRATEGIES = [class_strategy(c) for c in range(K)]
 
 
-def make_column(spec, device="cuda"):
-    """(Column, lo, hi) of one workload column, encoded by the library."""
+def _host_column(spec):
+    """Raw values -> host-encoded arrays (library encoder) of one column."""
     v, lo, hi, dct = synth.config4_values(spec)
     if spec.enc == ENC_FOR:
-        col = api.encode_for(v, spec.b, device=device)
+        payload, refs, zmin, zmax = api.host_encode_for(v, spec.b)
+        extra = None
     elif spec.enc == ENC_DELTA:
-        col = api.encode_delta(v, spec.b, device=device)
+        payload, extra, zmin, zmax = api.host_encode_delta(v, spec.b)
     else:
-        col = api.encode_dict(v, spec.b, dct, device=device)
+        payload, zmin, zmax = api.host_encode_dict(v, spec.b, len(dct))
+        extra = np.ascontiguousarray(dct, dtype=np.int64)
+    return spec, payload, extra, zmin, zmax, lo, hi
+
+
+def _upload(host, device):
+    import torch
+    spec, payload, extra, zmin, zmax, lo, hi = host
+    dev = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(device)  # noqa: E731
+    kw = {}
+    if spec.enc == ENC_DELTA:
+        kw["bases"] = dev(extra)
+    elif spec.enc == ENC_DICT:
+        kw["dct"] = dev(extra)
+    col = api.Column(spec.enc, spec.b, spec.n, 0, dev(payload), zmin=dev(zmin), zmax=dev(zmax), **kw)
     return col, lo, hi
+
+
+def make_column(spec, device="cuda"):
+    """(Column, lo, hi) of one workload column, encoded by the library."""
+    return _upload(_host_column(spec), device)
+
+
+def build_columns(specs, device="cuda", threads: int = 8, window: int = 32):
+    """Generate, encode and upload many columns; host work runs on `threads`
+    threads, at most `window` columns ahead of the upload."""
+    from concurrent.futures import ThreadPoolExecutor
+    out = []
+    with ThreadPoolExecutor(threads) as ex:
+        pending = []
+        it = iter(specs)
+        for spec in it:
+            pending.append(ex.submit(_host_column, spec))
+            if len(pending) >= window:
+                out.append(_upload(pending.pop(0).result(), device))
+        for f in pending:
+            out.append(_upload(f.result(), device))
+    return out
 
 
 class Timer:
@@ -80,24 +117,32 @@ class Timer:
 
 
 def collect(ctx: api.Context, n_cols: int = 2560, reps: int = 5, seed: int = TRAIN_SEED, log=print,
-            log2_max: float = 24.0):
+            log2_max: float = 24.0, threads: int = 8):
     """Time all eight strategies on n_cols fresh columns.
 
     Returns (X [n, 6] float32 features, T [n, 8] float64 median seconds)."""
     import torch
+    from concurrent.futures import ThreadPoolExecutor
     specs = synth.config4_specs(n_cols, seed=seed, log2_max=log2_max)
     timer = Timer(ctx)
     X = torch.zeros(n_cols, 6, dtype=torch.float32, device="cuda")
     T = np.zeros((n_cols, K))
     t0 = time.time()
-    for i, spec in enumerate(specs):
-        col, lo, hi = make_column(spec)
-        ctx.features([col.item(lo, hi, -1)], X[i:i + 1])
-        times = timer.time_strategies(col, lo, hi, STRATEGIES, reps)
-        T[i] = [float(np.median(times[s])) for s in STRATEGIES]
-        del col
-        if log and (i + 1) % 256 == 0:
-            log("selector timings: %d/%d columns, %.0f s" % (i + 1, n_cols, time.time() - t0))
+    with ThreadPoolExecutor(threads) as ex:
+        futs = [ex.submit(_host_column, sp) for sp in specs[:2 * threads]]
+        for i in range(n_cols):
+            host = futs[i].result()
+            futs[i] = None
+            if i + 2 * threads < n_cols:
+                futs.append(ex.submit(_host_column, specs[i + 2 * threads]))
+            col, lo, hi = _upload(host, "cuda")
+            del host
+            ctx.features([col.item(lo, hi, -1)], X[i:i + 1])
+            times = timer.time_strategies(col, lo, hi, STRATEGIES, reps)
+            T[i] = [float(np.median(times[s])) for s in STRATEGIES]
+            del col
+            if log and (i + 1) % 512 == 0:
+                log("selector timings: %d/%d columns, %.0f s" % (i + 1, n_cols, time.time() - t0))
     return X.cpu().numpy(), T
 
 
@@ -168,3 +213,60 @@ def regret(T: np.ndarray, choice: np.ndarray) -> dict:
     chosen = T[rows, choice]
     best = T.min(axis=1)
     return {"total": float(chosen.sum() / best.sum() - 1.0), "mean": float(np.mean(chosen / best - 1.0))}
+
+
+def evaluate(ctx: api.Context, theta: np.ndarray, X: np.ndarray, T: np.ndarray) -> dict:
+    """Regret of the learned choice and of the fixed alternatives on timed columns."""
+    pred = predict(ctx, theta, X)
+    learned = np.argmin(pred, axis=1)  # ties to the lowest class, as on the device
+    default = np.full(len(T), 5)       # row-major direct decoder, branch-free, zone maps on
+    best_fixed = int(np.argmin(T.sum(axis=0)))
+    return {
+        "columns": int(len(T)),
+        "learned": regret(T, learned),
+        "fixed_default": regret(T, default),
+        "best_fixed_in_hindsight": {"class": best_fixed, **regret(T, np.full(len(T), best_fixed))},
+        "time_s": {"learned": float(T[np.arange(len(T)), learned].sum()), "best": float(T.min(axis=1).sum()),
+                   "fixed_default": float(T[:, 5].sum())},
+        "learned_class_counts": np.bincount(learned, minlength=K).tolist(),
+        "best_class_counts": np.bincount(np.argmin(T, axis=1), minlength=K).tolist(),
+    }
+
+
+def main(argv=None):
+    import argparse
+    import json
+
+    ap = argparse.ArgumentParser(description="train and evaluate the strategy selector on this GPU")
+    ap.add_argument("--cols", type=int, default=2560, help="training columns (x 8 strategies timings)")
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--eval-cols", type=int, default=4096, help="held-out columns (the mixed workload's own)")
+    ap.add_argument("--eval-reps", type=int, default=3)
+    ap.add_argument("--epochs", type=int, default=400)
+    ap.add_argument("--out", required=True, help="selector file to write")
+    ap.add_argument("--report", default=None, help="JSON report")
+    args = ap.parse_args(argv)
+    say = lambda *a: print(*a, flush=True)  # noqa: E731
+    ctx = api.Context(0)
+    t0 = time.time()
+    X, T = collect(ctx, args.cols, args.reps, log=say)
+    say("training set: %d columns x %d strategies in %.0f s" % (len(T), K, time.time() - t0))
+    theta, loss = train(ctx, X, targets(T), epochs=args.epochs, log=say)
+    ctx.selector_set(theta)
+    ctx.selector_save(args.out)
+    train_eval = evaluate(ctx, theta, X, T)
+    t1 = time.time()
+    Xe, Te = collect(ctx, args.eval_cols, args.eval_reps, seed=synth.SEED_BASE + 3, log=say)
+    say("held-out set: %d columns in %.0f s" % (len(Te), time.time() - t1))
+    held = evaluate(ctx, theta, Xe, Te)
+    report = {"train_columns": len(T), "timings": int(T.size), "reps": args.reps, "epochs": args.epochs,
+              "final_loss": loss, "train": train_eval, "held_out": held}
+    say(json.dumps(report))
+    if args.report:
+        with open(args.report, "w") as fh:
+            json.dump(report, fh, indent=1)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

