@@ -26,6 +26,8 @@ hipError_t launch_batch_select(BatchCol* cols, uint32_t n_cols, const float* sco
                                hipStream_t st);
 hipError_t launch_batch_bin(const BatchArgs& a, hipStream_t st);
 hipError_t launch_mlp_forward(const float* theta, const float* X, uint32_t rows, float* out, hipStream_t st);
+hipError_t preload_batch_aux();
+hipError_t preload_mlp();
 }  // namespace scan_dev
 
 namespace {
@@ -205,6 +207,23 @@ void destroy_batches(scan_ctx* ctx) {
   }
 }
 
+// Every kernel a batch graph contains is loaded and launched once (with no
+// work) outside stream capture, before the first capture on the context:
+// with deferred code-object loading, a kernel's first launch loads its
+// module (device allocations and copies), which must not happen while a
+// stream is being captured.
+static hipError_t preload_graph_kernels(scan_ctx* ctx, const BatchBuffers& m) {
+  if (ctx->batch_kernels_loaded) return hipSuccess;
+  hipError_t e = preload_batch_aux();
+  if (e == hipSuccess) e = preload_mlp();
+  if (e == hipSuccess) e = launch_batch_setup(make_args(m, 0, 0, 0), ctx->stream);  // zeroes the class counters
+  for (int cls = 0; cls < kBatchClasses && e == hipSuccess; ++cls)
+    e = batch_class_fn(cls)(make_args(m, 0, 0, cls), 1, 256, ctx->stream, nullptr);  // no items: exits at once
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess) ctx->batch_kernels_loaded = true;
+  return e;
+}
+
 static hipError_t enqueue_batch(scan_ctx* ctx, BatchPlan* b, hipStream_t st) {
   hipError_t e = enqueue_select(ctx, b->mem, (uint32_t)b->n_items, b->selector, st);
   if (e != hipSuccess || b->n_work == 0) return e;
@@ -282,8 +301,16 @@ scan_status selector_pick(scan_ctx* ctx, const scan_column* col, int32_t enc, ui
 
 extern "C" {
 
+// The captured class-kernel graph is switched off: its first runs on MI355X
+// did not complete (the host waited in this call until the test's time limit)
+// and the cause has not been found.  The code stays for the investigation.
+constexpr bool kGraphBatchEnabled = false;
+
 scan_status scan_batch_prepare(scan_ctx* ctx, const scan_item* items, size_t n_items, uint64_t* handle) {
   if (!ctx) return SCAN_EINVAL;
+  if (!kGraphBatchEnabled)
+    return fail(ctx, SCAN_EUNSUPPORTED,
+                "captured batch graphs are disabled (runs did not complete; cause under investigation)");
   if (!handle || (n_items && !items)) return fail(ctx, SCAN_EINVAL, "items and handle must not be NULL");
   if (n_items > (1u << 24)) return fail(ctx, SCAN_EINVAL, "at most 2^24 items per batch");
   hipError_t e = hipSetDevice(ctx->device);
@@ -309,6 +336,7 @@ scan_status scan_batch_prepare(scan_ctx* ctx, const scan_item* items, size_t n_i
   if (n_items) e = hipMemcpy(b->mem.cols, b->cols.data(), sizeof(BatchCol) * n_items, hipMemcpyHostToDevice);
   if (e == hipSuccess && !work.empty())
     e = hipMemcpy(b->mem.work, work.data(), sizeof(BatchWork) * work.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = preload_graph_kernels(ctx, b->mem);
   // Capture on a private stream of default priority; replays go to the
   // context's stream.
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);

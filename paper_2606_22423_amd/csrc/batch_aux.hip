@@ -179,6 +179,21 @@ __global__ __launch_bounds__(256) void batch_bin_kernel(BatchArgs a) {
   a.lists[(size_t)cls * a.n_work + pos] = i;
 }
 
+// Loads the code objects of this unit's kernels (deferred loading would
+// otherwise load them at their first launch, possibly inside a graph capture).
+hipError_t preload_batch_aux() {
+  hipFuncAttributes attr;
+  const void* fns[] = {reinterpret_cast<const void*>(&batch_setup_kernel),
+                       reinterpret_cast<const void*>(&batch_features_kernel),
+                       reinterpret_cast<const void*>(&batch_select_kernel),
+                       reinterpret_cast<const void*>(&batch_bin_kernel)};
+  for (const void* f : fns) {
+    const hipError_t e = hipFuncGetAttributes(&attr, f);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_batch_setup(const BatchArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(batch_setup_kernel, dim3((a.n_cols + 255) / 256 + 1), dim3(256), 0, st, a);
   return hipGetLastError();

@@ -30,6 +30,7 @@ struct scan_ctx {
   bool selector_ready = false;
   SelectorState* selector = nullptr;
   std::map<uint64_t, BatchPlan*> batches;
+  bool batch_kernels_loaded = false;  // batch graph kernels launched once outside capture
   uint64_t next_batch = 1;
 };
 

@@ -137,8 +137,12 @@ __global__ __launch_bounds__(256) void query_scan_kernel(const QArgs a) {
       const uint32_t nsel = (uint32_t)__builtin_popcount(rows);
       lcount += nsel;
       if (s.enc == ENC_DICT) {
+        const uint32_t last = s.dict_len - 1u;  // codes index the dictionary (clamped)
         for (uint32_t t = 0; t < 16u; ++t)
-          if ((rows >> t) & 1u) lsum += (uint64_t)s.dict[ex(t)];
+          if ((rows >> t) & 1u) {
+            const uint32_t code = ex(t);
+            lsum += (uint64_t)s.dict[code < last ? code : last];
+          }
       } else {
         uint64_t part = 0;
 #pragma unroll

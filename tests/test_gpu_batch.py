@@ -24,6 +24,11 @@ from paper_2606_22423_amd._lib import DEC_RM_DIRECT, DEC_RM_LDS, ENC_DELTA, ENC_
 
 K = 8  # selector classes
 
+# The captured batch graph did not complete on MI355X (the host waited in
+# scan_batch_run until the time limit, twice) and the library now refuses it
+# with SCAN_EUNSUPPORTED until the cause is found.  These tests stay, skipped.
+GRAPH_OFF = pytest.mark.skip(reason="captured batch graph disabled: its GPU runs did not complete, cause not found")
+
 
 def say(*a):
     print(*a, flush=True)
@@ -115,6 +120,7 @@ def build_items(cases, with_zone_maps=True):
     return items, meta
 
 
+@GRAPH_OFF
 def test_batch_matches_oracle(ctx, cases):
     items, meta = build_items(cases)
     say("batch of", len(items), "columns")
@@ -130,6 +136,7 @@ def test_batch_matches_oracle(ctx, cases):
             assert got["strategy_used"] == strategy(DEC_RM_DIRECT, 0, 1 if zm else 0), what
 
 
+@GRAPH_OFF
 def test_batch_equals_single_scans(ctx, cases):
     items, meta = build_items(cases[:40])
     res = ctx.batch_run(items)
@@ -139,6 +146,7 @@ def test_batch_equals_single_scans(ctx, cases):
             {k: single[k] for k in ("count", "sum", "blocks_read", "blocks_total", "strategy_used")}
 
 
+@GRAPH_OFF
 def test_batch_replays_repeat(ctx, cases):
     items, meta = build_items(cases[:50])
     h = ctx.batch_prepare(items)
@@ -158,6 +166,7 @@ def test_batch_replays_repeat(ctx, cases):
         check_item(c, got, lo, hi, (c.spec.index, strat))
 
 
+@GRAPH_OFF
 def test_batch_window_and_occupancy_do_not_change_results(ctx, cases):
     items, meta = build_items(cases[:30])
     base = ctx.batch_run(items)
@@ -169,6 +178,7 @@ def test_batch_window_and_occupancy_do_not_change_results(ctx, cases):
         ctx.batch_set_tune(0, 0)
 
 
+@GRAPH_OFF
 def test_batch_invalid_items_report_status(ctx, cases):
     c = cases[5]
     good = c.col.item(c.lo, c.hi, class_strategy(1))
@@ -206,7 +216,16 @@ def test_features_match_oracle(ctx, cases):
         assert np.allclose(g, want, rtol=2e-6, atol=2e-6), (c.spec.index, lo, hi, g, want)
 
 
+def test_batch_graph_is_refused(ctx, cases):
+    c = cases[0]
+    with pytest.raises(_lib.ScanError) as e:
+        ctx.batch_run([c.col.item(c.lo, c.hi, -1)])
+    assert e.value.status == _lib.SCAN_EUNSUPPORTED
+
+
 def test_selector_choice_is_network_argmin(ctx, cases):
+    """scan_run with SCAN_STRAT_AUTO takes the network's argmin over the
+    classes valid for the column, and the result stays exact."""
     theta = random_theta(11)
     items, meta = [], []
     for j, c in enumerate(cases):
@@ -219,7 +238,7 @@ def test_selector_choice_is_network_argmin(ctx, cases):
     try:
         assert ctx.selector_loaded
         ctx.features(items, X)
-        res = ctx.batch_run(items)
+        res = [ctx.run(c.col, lo, hi, -1, zone_maps=zm) for c, lo, hi, zm in meta]
     finally:
         ctx.selector_clear()
     pred, _ = omlp.forward(theta.astype(np.float64), X.cpu().numpy().astype(np.float64), K)
@@ -236,21 +255,22 @@ def test_selector_choice_is_network_argmin(ctx, cases):
     assert checked > len(res) // 2
 
 
-def test_scan_run_auto_uses_selector(ctx, cases, tmp_path):
+def test_selector_file_round_trip(ctx, cases, tmp_path):
     theta = random_theta(12)
     path = str(tmp_path / "sel.txt")
     ctx.selector_set(theta)
     try:
+        first = [ctx.run(c.col, c.lo, c.hi, -1)["strategy_used"] for c in cases[:24]]
         ctx.selector_save(path)
         ctx.selector_clear()
         assert not ctx.selector_loaded
+        assert [ctx.run(c.col, c.lo, c.hi, -1)["strategy_used"] for c in cases[:24]] == \
+            [strategy(DEC_RM_DIRECT, 0, 1)] * 24  # heuristic without a selector
         ctx.selector_load(path)
-        items = [c.col.item(c.lo, c.hi, -1) for c in cases[:24]]
-        batch = ctx.batch_run(items)
-        for c, got in zip(cases[:24], batch):
-            single = ctx.run(c.col, c.lo, c.hi, -1)
-            assert single["strategy_used"] == got["strategy_used"]
-            check_item(c, single, c.lo, c.hi, c.spec.index)
+        for c, s in zip(cases[:24], first):
+            got = ctx.run(c.col, c.lo, c.hi, -1)
+            assert got["strategy_used"] == s
+            check_item(c, got, c.lo, c.hi, c.spec.index)
     finally:
         ctx.selector_clear()
     loaded = np.loadtxt(path, skiprows=1, dtype=np.float64)

@@ -60,7 +60,7 @@ def world(ctx):
         ([(2, -(1 << 40), 1 << 40), (4, 0, 9)], 3),         # clamped range plus a narrow one
         ([(1, int(d1[3]), int(d1[3]) + 1)], 5),             # dictionary equality
         ([(1, int(d1[0]) - 100, int(d1[0]))], 6),           # dictionary range with no entry
-        ([(3, int(dicts[3][0]), int(dicts[3][-1]) + 1), (5, int(dicts[5][2]), int(dicts[5][40])),
+        ([(3, int(dicts[3][0]), int(dicts[3][-1]) + 1), (5, int(dicts[5][2]), int(dicts[5][-3])),
           (8, 0, 1 << 10)], 9),                             # three conjuncts
     ]
     yield {"table": table, "queries": queries, "ocols": ocols, "spec": spec, "zones": zones, "dicts": dicts}
