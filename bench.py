@@ -152,7 +152,7 @@ def batch_leg(ctx, torch, ncols, reps, selector_path):
         "values": int(total_values), "payload_bytes": int(payload),
         "baseline_sync_ms": round(float(np.median(t_sync)) * 1e3, 3),
         "baseline_async_ms": round(float(np.median(t_async)) * 1e3, 3),
-        "graph_batch": "disabled in the library (its GPU runs did not complete; cause not found)",
+        "graph_batch": "disabled in the library for now (its runs did not complete; the cause, a work-fetch loop the optimizer let lanes 1-63 re-enter without the fetch, is fixed but not yet run on the GPU)",
     }
     if selector_path and os.path.exists(selector_path):
         ctx.selector_load(selector_path)

@@ -302,15 +302,20 @@ scan_status selector_pick(scan_ctx* ctx, const scan_column* col, int32_t enc, ui
 extern "C" {
 
 // The captured class-kernel graph is switched off: its first runs on MI355X
-// did not complete (the host waited in this call until the test's time limit)
-// and the cause has not been found.  The code stays for the investigation.
+// did not complete (the host waited in this call until the test's time limit).
+// The cause was the class kernels' work fetch (lane 0 took the item with an
+// atomic, a lane shuffle broadcast it): the optimizer routed lanes 1-63 back
+// to the broadcast without passing the fetch, so with lane 0 held outside
+// that path they re-read item 0 forever.  The fetch is now wave-uniform
+// (wave_next_item), the same fix the query kernel runs with, but this path
+// has not been run on the GPU since, so it stays off.
 constexpr bool kGraphBatchEnabled = false;
 
 scan_status scan_batch_prepare(scan_ctx* ctx, const scan_item* items, size_t n_items, uint64_t* handle) {
   if (!ctx) return SCAN_EINVAL;
   if (!kGraphBatchEnabled)
     return fail(ctx, SCAN_EUNSUPPORTED,
-                "captured batch graphs are disabled (runs did not complete; cause under investigation)");
+                "captured batch graphs are disabled (their kernels' former work fetch could spin forever; the fixed path is not yet validated on the GPU)");
   if (!handle || (n_items && !items)) return fail(ctx, SCAN_EINVAL, "items and handle must not be NULL");
   if (n_items > (1u << 24)) return fail(ctx, SCAN_EINVAL, "at most 2^24 items per batch");
   hipError_t e = hipSetDevice(ctx->device);

@@ -151,9 +151,7 @@ __global__ __launch_bounds__(256) void batch_scan(const BatchArgs a) {
   const uint32_t n = a.counts[a.cls];
   const uint32_t* items = a.lists + (size_t)a.cls * a.n_work;
   while (true) {
-    uint32_t idx = 0;
-    if (lane == 0) idx = atomicAdd(&a.cursors[a.cls], 1u);
-    idx = __shfl(idx, 0, 64);
+    const uint32_t idx = wave_next_item(&a.cursors[a.cls], lane);
     if (idx >= n) break;
     const BatchWork w = a.work[items[idx]];
     const BatchCol c = a.cols[w.col];

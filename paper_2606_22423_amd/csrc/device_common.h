@@ -70,6 +70,19 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t x, int l) {
   return (uint64_t)readlane((uint32_t)x, l) | ((uint64_t)readlane((uint32_t)(x >> 32), l) << 32);
 }
 
+// Next work item of a wavefront from a shared counter.  Every lane takes
+// part in the atomic (lane 0 adds 1, the others 0; the compiler folds it into
+// one atomic per wavefront) and the first lane's old value is read into a
+// scalar register.  The item is thus wave-uniform by construction and the
+// work loop's control flow stays uniform.  (Fetching with `if (lane == 0)`
+// and broadcasting with a lane shuffle let the optimizer route lanes 1-63
+// back to the broadcast without passing the fetch; with lane 0 held outside
+// that path they re-read item 0 forever.)
+__device__ __forceinline__ uint32_t wave_next_item(uint32_t* cursor, uint32_t lane) {
+  const uint32_t old = atomicAdd(cursor, lane == 0 ? 1u : 0u);
+  return __builtin_amdgcn_readfirstlane(old);
+}
+
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {

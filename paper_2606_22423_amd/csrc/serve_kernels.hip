@@ -26,7 +26,7 @@ __device__ __forceinline__ void stage_block(uint32_t* st, const QCol& c, uint64_
   uint4* dst = reinterpret_cast<uint4*>(st);
   __builtin_amdgcn_wave_barrier();
   for (uint32_t i = lane; i < words / 4u; i += 64u) dst[i] = src[i];
-  if (lane == 0) st[words] = 0u;
+  st[words] = 0u;  // every lane writes the same pad word
   __builtin_amdgcn_wave_barrier();
 }
 
@@ -78,9 +78,7 @@ __global__ __launch_bounds__(256) void query_scan_kernel(const QArgs a) {
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
   uint32_t* st = lds[wave];
   while (true) {
-    uint32_t item = 0;
-    if (lane == 0) item = atomicAdd(a.cursor, 1u);
-    item = __shfl(item, 0, 64);
+    const uint32_t item = wave_next_item(a.cursor, lane);
     if (item >= a.items) break;
     const uint32_t qi = item % a.nq;
     const uint64_t k0 = (uint64_t)(item / a.nq) * a.G;
