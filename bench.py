@@ -31,6 +31,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "decoded values/s and HBM fraction f=GB/s/β per b; batched+learned vs plain"
 HBM_PEAK_GBPS = 8000.0
+BETA_BYTES = 4 << 30      # beta: streaming read of this many bytes (>> the 256 MB last-level cache)
+TRIAD_FLOATS = 1 << 28    # STREAM triad length
 SIGMA = 0.1
 
 
@@ -49,7 +51,7 @@ def kernel_source_hash() -> str:
 def measure_beta(ctx, torch, reps=7):
     """Sequential-read maximum over a 4 GiB buffer (>> the 256 MB last-level cache)."""
     import numpy as np
-    nbytes = 4 << 30
+    nbytes = BETA_BYTES
     buf = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda")
     buf.fill_(7)
     sink = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -69,7 +71,7 @@ def measure_beta(ctx, torch, reps=7):
                 if gbs > best:
                     best, best_cfg = gbs, {"wg": wg, "wgs_per_cu": mult, "unroll": unroll}
     # STREAM triad for context
-    n = 1 << 28
+    n = TRIAD_FLOATS
     a, b, c = (torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(3))
     b.fill_(1.0)
     c.fill_(2.0)
@@ -174,6 +176,71 @@ def batch_leg(ctx, torch, ncols, reps, selector_path):
     log("[bench] batch: %s" % {k: v for k, v in res.items() if k.endswith("_ms") or k.startswith("speedup")})
     del cols
     return res
+
+
+def zonemap_leg(ctx, torch, n_log2, beta_gbs, reps=5):
+    """Zone-map workload: N = 2^n_log2 values at b = 16, the sorted base
+    v_r = r >> (n_log2 - 16) displaced by a noisy sort of s ranks (s = 0, 2^4,
+    2^10, 2^16) or randomly permuted; predicate [lo, lo + w), w = round(sigma
+    2^16).  Zone maps on vs off (row-major direct decoder, branch-free), cold
+    cache, median of reps.  COUNT and SUM must be identical across every
+    clustering level and both zone-map settings; on the sorted column they and
+    blocks_read must equal their closed forms."""
+    import numpy as np
+
+    import synth
+    from paper_2606_22423_amd import api
+    from paper_2606_22423_amd._lib import DEC_RM_DIRECT, strategy
+
+    n = 1 << n_log2
+    nb = n // 1024
+    per = n >> 16  # copies of each value
+    sigmas = (1e-4, 1e-3, 1e-2, 0.1, 0.3, 0.5)
+    preds = [synth.config3_predicate(sg) for sg in sigmas]
+    evict = torch.empty(128 << 20, dtype=torch.int32, device="cuda")
+    out = torch.zeros(8, dtype=torch.int64, device="cuda")
+    rows, want = [], {}
+    t0 = time.time()
+    for lvl in (0, 16, 1024, 65536, "random"):
+        vals = synth.config3_column(n, s=lvl, device="cuda")
+        col = api.encode_for(vals.cpu().numpy().view(np.uint32), 16)
+        del vals
+        for sg, (lo, hi) in zip(sigmas, preds):
+            for zm in (1, 0):
+                s = strategy(DEC_RM_DIRECT, 0, zm)
+                r = ctx.run(col, lo, hi, s)
+                key = (lo, hi)
+                if key not in want:
+                    want[key] = (r["count"], r["sum"])
+                if (r["count"], r["sum"]) != want[key]:
+                    raise RuntimeError("zone-map workload: results differ across levels (%s, %s)" % (lvl, key))
+                if lvl == 0 and zm:
+                    closed = ((hi - lo) * per, per * (hi - lo) * (lo + hi - 1) // 2)
+                    # each value fills per / 1024 whole blocks when per >= 1024
+                    if (r["count"], r["sum"]) != closed or (per >= 1024 and r["blocks_read"] != (hi - lo) * per // 1024):
+                        raise RuntimeError("sorted column differs from its closed form: %s vs %s" % (r, closed))
+                ts = []
+                for _ in range(reps):
+                    ctx.cache_flush(evict, evict.numel() * 4)
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    ctx.run_async(col, lo, hi, s, out)
+                    e1.record()
+                    e1.synchronize()
+                    ts.append(e0.elapsed_time(e1) * 1e-3)
+                t = float(np.median(ts))
+                read_bytes = r["blocks_read"] * 2048 + (8 * nb if zm else 0)
+                rows.append({"s": lvl, "sigma": sg, "zone_maps": bool(zm), "ms": round(t * 1e3, 4),
+                             "blocks_read_frac": round(r["blocks_read"] / nb, 6),
+                             "logical_gvalues_per_s": round(n / t / 1e9, 1),
+                             "decoded_gvalues_per_s": round(r["blocks_read"] * 1024 / t / 1e9, 1),
+                             "f_on_bytes_read": round(read_bytes / t / 1e9 / beta_gbs, 4)})
+        del col
+        log("[bench] zone maps: level %s done" % lvl)
+    log("[bench] zone-map workload in %.0f s" % (time.time() - t0))
+    return {"workload": "N=2^%d values at b=16, sorted base displaced by s in {0,2^4,2^10,2^16} ranks or random, "
+                        "[lo, lo+round(sigma 2^16)), zone maps on vs off, cold cache, median of %d" % (n_log2, reps),
+            "identical_across_levels_and_zone_maps": True, "sorted_closed_forms": True, "points": rows}
 
 
 def serve_leg(ctx, torch, rows_log2, nq, lambdas=(0.25, 0.5, 0.8, 0.95), warm=500):
@@ -285,6 +352,7 @@ def main():
     ap.add_argument("--detail", default=None, help="write the full sweep as JSON to this file")
     ap.add_argument("--no-autotune", action="store_true", help="library default launch shapes")
     ap.add_argument("--batch-cols", type=int, default=4096, help="mixed-column workload size (0: skip it)")
+    ap.add_argument("--zonemap-log2", type=int, default=30, help="zone-map workload rows (0: skip the leg)")
     ap.add_argument("--serve-rows-log2", type=int, default=28, help="serving table rows (0: skip the serving leg)")
     ap.add_argument("--serve-queries", type=int, default=10000, help="measured queries per arrival rate")
     ap.add_argument("--selector", default=os.path.join(ROOT, "paper_2606_22423_amd", "selector_mi355x.txt"),
@@ -500,6 +568,10 @@ def main():
     if args.batch_cols > 0:
         batch = batch_leg(ctx, torch, args.batch_cols, args.reps, args.selector)
 
+    zonemap = None
+    if args.zonemap_log2 > 0:
+        zonemap = zonemap_leg(ctx, torch, args.zonemap_log2, beta_gbs)
+
     serving = None
     if args.serve_rows_log2 > 0:
         serving = serve_leg(ctx, torch, args.serve_rows_log2, args.serve_queries)
@@ -512,6 +584,7 @@ def main():
                                "v < round(0.1*2^b), COUNT+SUM, per-width autotuned strategy, zone maps off"
                                % args.n_log2, "values_per_step": N * len(widths)},
         "beta_GBps": round(beta_gbs, 1), "beta_config": beta_cfg, "triad_GBps": round(triad_gbs, 1),
+        "beta_buffer_bytes": BETA_BYTES, "triad_floats": TRIAD_FLOATS,
         "law_fit_best": {"T_dec_gvalues_per_s": round(ft_best.t_dec / 1e9, 1), "b_star": round(ft_best.b_star, 2),
                          "median_abs_err": round(ft_best.median_err, 4),
                          "min_f_at_or_above_ridge": round(min(over_ridge), 4) if over_ridge else None},
@@ -520,6 +593,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batch": batch,
+        "zonemap": zonemap,
         "serving": serving,
     }
     if args.detail:

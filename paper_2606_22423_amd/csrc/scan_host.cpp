@@ -126,14 +126,31 @@ scan_status check_strategy(scan_ctx* ctx, const scan_column* col, int32_t enc, u
 
 scan_tune default_tune(int32_t enc, uint32_t b, int32_t s) {
   (void)enc;
-  (void)b;
   scan_tune t;
-  (void)s;
+  // From the autotuner on MI355X (2^28-value columns, cold): few resident
+  // wavefronts, each streaming its own windows, beat full occupancy (fewer
+  // concurrent streams into HBM); narrow widths are compute-bound and want
+  // more wavefronts and longer windows.
   t.wg_size = 256;
-  // Measured on MI355X: few resident wavefronts, each streaming 16-block
-  // windows, beat full occupancy (fewer concurrent streams into HBM).
-  t.wgs_per_cu = 2;
-  t.window_blocks = 16;
+  if (b <= 2) {
+    t.wgs_per_cu = 4;
+    t.window_blocks = 64;
+  } else if (b <= 4) {
+    t.wgs_per_cu = 2;
+    t.window_blocks = 16;
+  } else if (b <= 12) {
+    t.wgs_per_cu = 1;
+    t.window_blocks = 64;
+  } else if (b <= 16) {
+    t.wgs_per_cu = 1;
+    t.window_blocks = 16;
+  } else {
+    t.wgs_per_cu = 1;
+    t.window_blocks = 4;
+  }
+  // With zone maps every window costs one dependent zone-map load and ballot
+  // per wavefront: 64-block windows test 64 blocks per step.
+  if (s >= 0 && ((s >> 3) & 1)) t.window_blocks = 64;
   t.reserved = 0;
   return t;
 }

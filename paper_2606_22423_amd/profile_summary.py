@@ -1,7 +1,7 @@
 """Summarise rocprofv3 CSV output of profile_run.py into a short text report
 and the HBM-traffic table bench.py reads.
 
-    python -m paper_2606_22423_amd.profile_summary --stats DIR/x_kernel_stats.csv \\
+    python -m paper_2606_22423_amd.profile_summary --trace DIR/x_kernel_trace.csv \\
         --fetch DIR2/x_counter_collection.csv --write DIR3/x_counter_collection.csv \\
         --run-json profile_run.json --command "..." --out summary.txt --traffic-json hbm_traffic.json
 
@@ -41,61 +41,108 @@ def short_name(name: str) -> str:
     return m.group(1) if m else name[:80]
 
 
-def read_counters(path, counter):
-    """kernel short name -> list of per-dispatch values (KiB)."""
-    out = defaultdict(list)
+def read_counters(path, counter, last):
+    """(kernel short name -> values of its last `last` dispatches (KiB),
+    calibration values: the dispatches before the first scan)."""
+    rows = []
     with open(path) as fh:
         for row in csv.DictReader(fh):
             if row["Counter_Name"] == counter:
-                out[short_name(row["Kernel_Name"])].append(float(row["Counter_Value"]))
-    return out
+                rows.append((int(row["Dispatch_Id"]), short_name(row["Kernel_Name"]), float(row["Counter_Value"])))
+    rows.sort()
+    first_scan = min([d for d, k, _ in rows if k.startswith("code_scan")] or [0])
+    per = defaultdict(list)
+    cal = defaultdict(list)
+    for d, k, v in rows:
+        per[k].append(v)
+        if d < first_scan:
+            cal[k].append(v)
+    return {k: v[-last:] for k, v in per.items()}, cal
+
+
+def read_trace(path, last):
+    """kernel short name -> durations (ns) of its last `last` dispatches."""
+    rows = []
+    with open(path) as fh:
+        for row in csv.DictReader(fh):
+            rows.append((int(row["Dispatch_Id"]), short_name(row["Kernel_Name"]),
+                         int(row["End_Timestamp"]) - int(row["Start_Timestamp"])))
+    rows.sort()
+    per = defaultdict(list)
+    for _, k, t in rows:
+        per[k].append(t)
+    return {k: v[-last:] for k, v in per.items()}
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--stats", required=True)
+    ap.add_argument("--trace", required=True, help="kernel_trace.csv of the --kernel-trace run")
+    ap.add_argument("--last", type=int, default=5, help="timed launches per kernel (after autotuning)")
     ap.add_argument("--fetch")
     ap.add_argument("--write")
-    ap.add_argument("--run-json", required=True, help="stdout of profile_run.py")
+    ap.add_argument("--run-json", help="stdout of profile_run.py")
+    ap.add_argument("--bench-json", help="stdout of a bench.py run (its dominant kernel and timed launches)")
     ap.add_argument("--command", required=True, help="the commands that produced the CSVs")
     ap.add_argument("--out", required=True)
     ap.add_argument("--traffic-json")
     args = ap.parse_args(argv)
 
-    with open(args.run_json) as fh:
-        run = json.loads([ln for ln in fh if ln.startswith("{")][-1])
-    stats = {}
-    with open(args.stats) as fh:
-        for row in csv.DictReader(fh):
-            stats[short_name(row["Name"])] = (int(row["Calls"]), float(row["AverageNs"]), float(row["MinNs"]),
-                                              float(row["MaxNs"]))
+    if args.bench_json:
+        with open(args.bench_json) as fh:
+            line = json.loads([ln for ln in fh if ln.startswith("{")][-1])
+        rf = line["roofline"]
+        m = re.match(r"code_scan<B=(\d+),([a-z_]+)/([a-z]+)/nozm>", rf["kernel"])
+        run = {"n": line["config"]["values_per_step"] // 32,
+               "pairs": [{"b": int(m.group(1)), "strategy": "%s/%s" % (m.group(2), m.group(3)), "tune": None,
+                          "algorithmic_bytes": rf["algorithmic_bytes_per_launch"]}],
+               "cal_read_bytes": line["beta_buffer_bytes"], "cal_triad_floats": line["triad_floats"],
+               "bench_avg_launch_ms": rf["avg_launch_ms"]}
+        args.last = line["steps"]
+    else:
+        with open(args.run_json) as fh:
+            run = json.loads([ln for ln in fh if ln.startswith("{")][-1])
+    trace = read_trace(args.trace, args.last)
     lines = ["# rocprofv3 summary: scan kernels on one MI355X", "", "Commands (repository root):", ""]
     lines += ["    " + c for c in args.command.split(" ;; ")]
-    lines += ["", "Workload: FOR columns of 2^%d uniform values, predicate v < round(0.1 * 2^b), zone maps off, "
-              "cold cache per launch; pairs autotuned as in bench.py." % (run["n"].bit_length() - 1), "",
-              "| kernel | calls | avg us | min us | max us | algorithmic GB/s (avg) |", "|---|---|---|---|---|---|"]
-    algo = {}
+    if args.bench_json:
+        lines += ["", "Workload: the bench's timed region (32 FOR columns of 2^%d uniform values, one per width, "
+                  "v < round(0.1 * 2^b), zone maps off, each column read once per step).  The rows are the dominant "
+                  "kernel's last %d dispatches, i.e. the timed steps; bench.py measured %.4f ms per launch with HIP "
+                  "events in the same run." % (run["n"].bit_length() - 1, args.last, run["bench_avg_launch_ms"]), ""]
+    else:
+        lines += ["", "Workload: FOR columns of 2^%d uniform values, predicate v < round(0.1 * 2^b), zone maps off, "
+                  "cold cache per launch (512 MiB overwrite between launches); each (width, strategy) pair autotuned "
+                  "as in bench.py, then launched %d times; the rows below are those %d launches (kernel trace)."
+                  % (run["n"].bit_length() - 1, args.last, args.last), ""]
+    lines += [
+              "| kernel | launch shape (threads, WGs/CU, window) | avg us | min us | max us | algorithmic bytes | "
+              "algorithmic GB/s (avg) | fraction of 8 TB/s |", "|---|---|---|---|---|---|---|---|"]
+    algo, shape = {}, {}
     for p in run["pairs"]:
         key = "code_scan<B=%d,%s/nozm>" % (p["b"], p["strategy"])
         algo[key] = p["algorithmic_bytes"]
-    for k, (calls, avg, mn, mx) in sorted(stats.items(), key=lambda kv: -kv[1][0] * kv[1][1]):
-        if not (k.startswith("code_scan") or k.startswith("beta")):
+        shape[key] = p.get("tune")
+    for k in sorted(algo, key=lambda k: -algo[k]):
+        ts = trace.get(k, [])
+        if not ts:
             continue
-        gbs = "%.0f" % (algo[k] / avg) if k in algo else ""
-        lines.append("| `%s` | %d | %.1f | %.1f | %.1f | %s |" % (k, calls, avg / 1e3, mn / 1e3, mx / 1e3, gbs))
+        avg = sum(ts) / len(ts)
+        lines.append("| `%s` | %s | %.1f | %.1f | %.1f | %d | %.0f | %.3f |" % (
+            k, shape[k], avg / 1e3, min(ts) / 1e3, max(ts) / 1e3, algo[k], algo[k] / avg, algo[k] / avg / 8000.0))
     traffic = {}
     if args.fetch and args.write:
-        fetch = read_counters(args.fetch, "FETCH_SIZE")
-        write = read_counters(args.write, "WRITE_SIZE")
+        fetch, fcal = read_counters(args.fetch, "FETCH_SIZE", args.last)
+        write, wcal = read_counters(args.write, "WRITE_SIZE", args.last)
         cal_r = run["cal_read_bytes"]
         cal_w = run["cal_triad_floats"] * 4
-        f_cal = sorted(fetch.get("beta_read_kernel<1>", []) + fetch.get("beta_read_kernel<2>", []))
-        w_cal = sorted(write.get("beta_triad_kernel", []))
+        f_cal = sorted(v for k, vs in fcal.items() if k.startswith("beta_read") for v in vs)
+        w_cal = sorted(wcal.get("beta_triad_kernel", []))
         sf = f_cal[len(f_cal) // 2] * 1024 / cal_r if f_cal else None
         sw = w_cal[len(w_cal) // 2] * 1024 / cal_w if w_cal else None
         lines += ["", "HBM traffic from FETCH_SIZE / WRITE_SIZE (KiB per dispatch), each scaled by the counter's",
-                  "reading for a kernel of known traffic: FETCH factor %.4f (1 GiB streaming read), "
-                  "WRITE factor %.4f (triad, 4 B written per float)." % (sf or 0, sw or 0), "",
+                  "reading for a kernel of known traffic dispatched before any scan: FETCH factor %.4f "
+                  "(streaming read of %d bytes), WRITE factor %.4f (triad, 4 B written per float)."
+                  % (sf or 0, cal_r, sw or 0), "",
                   "| kernel | FETCH KiB (median) | WRITE KiB (median) | scaled bytes per launch | algorithmic bytes | ratio |",
                   "|---|---|---|---|---|---|"]
         for k in sorted(algo):
