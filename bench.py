@@ -238,7 +238,14 @@ def zonemap_leg(ctx, torch, n_log2, beta_gbs, reps=5):
         del col
         log("[bench] zone maps: level %s done" % lvl)
     log("[bench] zone-map workload in %.0f s" % (time.time() - t0))
-    return {"workload": "N=2^%d values at b=16, sorted base displaced by s in {0,2^4,2^10,2^16} ranks or random, "
+    # bytes-read model: with zone maps on, the read fraction is sigma plus a
+    # clustering term c_s (the share of blocks whose value range straddles a
+    # predicate edge grows with the displacement s); c_s = median(frac - sigma)
+    model = {}
+    for lvl in (0, 16, 1024, 65536, "random"):
+        d = [r["blocks_read_frac"] - r["sigma"] for r in rows if r["s"] == lvl and r["zone_maps"]]
+        model[str(lvl)] = round(float(np.median(d)), 6)
+    return {"read_fraction_minus_sigma": model,"workload": "N=2^%d values at b=16, sorted base displaced by s in {0,2^4,2^10,2^16} ranks or random, "
                         "[lo, lo+round(sigma 2^16)), zone maps on vs off, cold cache, median of %d" % (n_log2, reps),
             "identical_across_levels_and_zone_maps": True, "sorted_closed_forms": True, "points": rows}
 
@@ -521,6 +528,22 @@ def main():
                 sigma_fits["%s@%g" % (strategy_name(s), sg)] = {"T_dec_gvalues_per_s": round(ft.t_dec / 1e9, 1),
                                                                "b_star": round(ft.b_star, 2)}
 
+    # --- branch-free vs compaction crossover per width (needs the sigma sweep)
+    crossover = None
+    if len(sigmas) > 2:
+        crossover = {}
+        for dec in (DEC_RM_DIRECT, DEC_RM_LDS):
+            bf, sv = strategy(dec, 0, 0), strategy(dec, 1, 0)
+            rows = []
+            for b in widths:
+                tb = [sweep[(sg, bf)][b] for sg in sigmas]
+                ts = [sweep[(sg, sv)][b] for sg in sigmas]
+                c = lawfit.fit_crossover(sigmas, tb, ts)
+                rows.append({"b": b, "sigma_star": None if c.sigma_star != c.sigma_star else round(c.sigma_star, 4),
+                             "faster_below": c.faster_below, "bf_us": [round(c.a_bf * 1e6, 2), round(c.b_bf * 1e6, 2)],
+                             "sv_us": [round(c.a_sv * 1e6, 2), round(c.b_sv * 1e6, 2)]})
+            crossover[strategy_name(bf).split("/")[0]] = rows
+
     # --- roofline of the dominant kernel (largest share of the step)
     dom_b = max(widths, key=lambda b: float(np.median(per_kernel[b])))
     dom_t = float(np.mean(per_kernel[dom_b]))
@@ -589,6 +612,7 @@ def main():
                          "median_abs_err": round(ft_best.median_err, 4),
                          "min_f_at_or_above_ridge": round(min(over_ridge), 4) if over_ridge else None},
         "law_fit_per_strategy": fits,
+        "crossover_bf_sv": crossover,
         "per_b": per_b,
         "roofline": roofline,
         "cpu_baseline": cpu,

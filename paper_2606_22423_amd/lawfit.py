@@ -94,3 +94,47 @@ def sigma_achieved(c: int, b: int) -> float:
 def is_quantized(sigma_target: float, c: int, b: int) -> bool:
     """Flag widths where v < c cannot get within half a decade of the target selectivity."""
     return abs(math.log10(sigma_achieved(c, b) / sigma_target)) > 0.3
+
+
+# ------------------------------------------------- branch-free vs compaction
+@dataclass
+class Crossover:
+    a_bf: float           # seconds: branch-free cost model a + b * sigma
+    b_bf: float
+    a_sv: float           # selection-vector (compaction) cost model
+    b_sv: float
+    sigma_star: float     # where the two models meet (nan if they do not cross in (0, 1))
+    faster_below: str     # mode that wins for sigma below sigma_star ("bf" or "sv"; the winner everywhere if no cross)
+
+
+def _linear(x, y):
+    """Least-squares line y = a + b x."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    b, a = np.polyfit(x, y, 1)
+    return float(a), float(b)
+
+
+def fit_crossover(sigmas, t_bf, t_sv) -> Crossover:
+    """The GPU analogue of the paper's branchy / branch-free crossover.
+
+    On a CPU the branchy filter pays A + B sigma (1 - sigma) for
+    mispredictions ("Results: the two crossovers").  A wavefront has no
+    branch predictor: the branch-free mode tests and masks every value, so its
+    time is flat in sigma, while compaction writes each selected value to LDS
+    and reads it back, so its time grows linearly with the selected count.
+    Both are fitted as a + b sigma by least squares; sigma* solves
+    a_bf + b_bf s = a_sv + b_sv s."""
+    s = np.asarray(sigmas, dtype=np.float64)
+    if len(s) < 2 or len(s) != len(t_bf) or len(s) != len(t_sv):
+        raise ValueError("need at least two matching (sigma, t_bf, t_sv) points")
+    a1, b1 = _linear(s, t_bf)
+    a2, b2 = _linear(s, t_sv)
+    star = float("nan")
+    if b1 != b2:
+        x = (a2 - a1) / (b1 - b2)
+        if 0.0 < x < 1.0:
+            star = float(x)
+    low = 1e-6 if star != star else star * 0.5
+    faster = "bf" if a1 + b1 * low <= a2 + b2 * low else "sv"
+    return Crossover(a1, b1, a2, b2, star, faster)

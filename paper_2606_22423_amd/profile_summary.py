@@ -85,6 +85,7 @@ def main(argv=None):
     ap.add_argument("--command", required=True, help="the commands that produced the CSVs")
     ap.add_argument("--out", required=True)
     ap.add_argument("--traffic-json")
+    ap.add_argument("--sq", help="counter_collection.csv of an SQ_* pass")
     args = ap.parse_args(argv)
 
     if args.bench_json:
@@ -96,7 +97,8 @@ def main(argv=None):
                "pairs": [{"b": int(m.group(1)), "strategy": "%s/%s" % (m.group(2), m.group(3)), "tune": None,
                           "algorithmic_bytes": rf["algorithmic_bytes_per_launch"]}],
                "cal_read_bytes": line["beta_buffer_bytes"], "cal_triad_floats": line["triad_floats"],
-               "bench_avg_launch_ms": rf["avg_launch_ms"]}
+               "bench_avg_launch_ms": rf["avg_launch_ms"],
+               "timed_kernels": ["code_scan<B=%d,%s>" % (r["b"], r["strategy"]) for r in line["per_b"]]}
         args.last = line["steps"]
     else:
         with open(args.run_json) as fh:
@@ -145,7 +147,15 @@ def main(argv=None):
                   % (sf or 0, cal_r, sw or 0), "",
                   "| kernel | FETCH KiB (median) | WRITE KiB (median) | scaled bytes per launch | algorithmic bytes | ratio |",
                   "|---|---|---|---|---|---|"]
-        for k in sorted(algo):
+        keys = sorted(algo)
+        if args.bench_json:
+            # every per-width scan kernel of the bench: algorithmic bytes n * b / 8
+            for k in run["timed_kernels"]:
+                if k in fetch and k in write and k not in algo:
+                    algo[k] = run["n"] * int(re.match(r"code_scan<B=(\d+),", k).group(1)) // 8
+                    keys.append(k)
+            keys.sort(key=lambda k: -algo[k])
+        for k in keys:
             fv, wv = sorted(fetch.get(k, [])), sorted(write.get(k, []))
             if not fv or not wv or not sf or not sw:
                 continue
@@ -153,6 +163,27 @@ def main(argv=None):
             tb = fm * 1024 / sf + wm * 1024 / sw
             traffic[k] = {"bytes_per_launch": int(tb), "fetch_kib": fm, "write_kib": wm}
             lines.append("| `%s` | %.0f | %.1f | %.0f | %d | %.3f |" % (k, fm, wm, tb, algo[k], tb / algo[k]))
+    if args.sq:
+        names = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM", "SQ_ACTIVE_INST_VALU",
+                 "SQ_WAVE_CYCLES")
+        sq = {nm: read_counters(args.sq, nm, args.last)[0] for nm in names}
+        lines += ["", "SQ counters (medians of the same launches; instructions are per wavefront, shown per value",
+                  "as count x 64 / values): VALU, SALU, LDS and vector-memory instructions per value, and the",
+                  "share of wavefront cycles with a VALU instruction issued.", "",
+                  "| kernel | waves | VALU / value | SALU / value | LDS / value | VMEM / value | VALU-active cycles |",
+                  "|---|---|---|---|---|---|---|"]
+        for k in sorted(algo, key=lambda k: -algo[k]):
+            vals = {}
+            for nm in names:
+                v = sorted(sq[nm].get(k, []))
+                vals[nm] = v[len(v) // 2] if v else None
+            if vals["SQ_INSTS_VALU"] is None:
+                continue
+            nv = run["n"]
+            lines.append("| `%s` | %d | %.2f | %.2f | %.3f | %.3f | %.3f |" % (
+                k, vals["SQ_WAVES"], vals["SQ_INSTS_VALU"] * 64 / nv, vals["SQ_INSTS_SALU"] * 64 / nv,
+                vals["SQ_INSTS_LDS"] * 64 / nv, vals["SQ_INSTS_VMEM"] * 64 / nv,
+                vals["SQ_ACTIVE_INST_VALU"] / vals["SQ_WAVE_CYCLES"] if vals["SQ_WAVE_CYCLES"] else 0.0))
     with open(args.out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     if args.traffic_json and traffic:

@@ -64,3 +64,24 @@ def test_bandwidth_fraction_and_quantization():
     assert lawfit.bandwidth_fraction(2**28, 8, 2**28 / 7e12, 7e12) == pytest.approx(1.0)
     assert lawfit.sigma_achieved(1, 1) == 0.5
     assert lawfit.is_quantized(1e-4, 1, 1) and not lawfit.is_quantized(0.1, 6554, 16)
+
+
+def test_crossover_recovers_synthetic_lines():
+    s = np.array([1e-4, 1e-3, 1e-2, 0.1, 0.3, 0.5, 0.7, 0.9, 0.99])
+    # compaction cheaper at low selectivity, branch-free flat
+    t_bf = 1.0 + 0.0 * s
+    t_sv = 0.6 + 0.8 * s
+    c = lawfit.fit_crossover(s, t_bf, t_sv)
+    assert c.sigma_star == pytest.approx(0.5, abs=1e-9)
+    assert c.faster_below == "sv"
+    assert (c.a_bf, c.b_bf) == pytest.approx((1.0, 0.0), abs=1e-9)
+    assert (c.a_sv, c.b_sv) == pytest.approx((0.6, 0.8), abs=1e-9)
+
+
+def test_crossover_absent_when_one_mode_always_wins():
+    s = np.linspace(0.0, 1.0, 11)
+    c = lawfit.fit_crossover(s, 1.0 + 0.01 * s, 1.5 + 0.5 * s)
+    assert c.sigma_star != c.sigma_star  # nan: no crossing in (0, 1)
+    assert c.faster_below == "bf"
+    with pytest.raises(ValueError):
+        lawfit.fit_crossover([0.1], [1.0], [2.0])
