@@ -192,28 +192,35 @@ def zonemap_i64(v):
 
 
 # -------------------------------------------------------------------- scans
+def _flags(zone_maps: bool, all_match: bool) -> int:
+    """Bit 0 zone maps, bit 1 the all-match shortcut (meaningful with zone maps)."""
+    return int(bool(zone_maps)) | (int(bool(all_match)) << 1)
+
+
 def scan_for(payload, n: int, b: int, lo: int, hi: int, refs=None, layout: int = 0,
-             zone_maps: bool = False) -> ScanResult:
+             zone_maps: bool = False, all_match: bool = False) -> ScanResult:
     payload = _u32(payload)
     refs = None if refs is None else _u32(refs)
     r = _Result()
-    _check(_load().orc_scan_for(_ptr(payload), _ptr(refs), n, b, layout, lo, hi, int(zone_maps),
+    _check(_load().orc_scan_for(_ptr(payload), _ptr(refs), n, b, layout, lo, hi, _flags(zone_maps, all_match),
                                 ctypes.byref(r)), "scan_for")
     return _res(r)
 
 
-def scan_delta(payload, bases, n: int, b: int, lo: int, hi: int, zone_maps: bool = False) -> ScanResult:
+def scan_delta(payload, bases, n: int, b: int, lo: int, hi: int, zone_maps: bool = False,
+               all_match: bool = False) -> ScanResult:
     payload, bases = _u32(payload), _i64(bases)
     r = _Result()
-    _check(_load().orc_scan_delta(_ptr(payload), _ptr(bases), n, b, lo, hi, int(zone_maps),
+    _check(_load().orc_scan_delta(_ptr(payload), _ptr(bases), n, b, lo, hi, _flags(zone_maps, all_match),
                                   ctypes.byref(r)), "scan_delta")
     return _res(r)
 
 
-def scan_dict(payload, dct, n: int, b: int, lo: int, hi: int, zone_maps: bool = False) -> ScanResult:
+def scan_dict(payload, dct, n: int, b: int, lo: int, hi: int, zone_maps: bool = False,
+              all_match: bool = False) -> ScanResult:
     payload, dct = _u32(payload), _i64(dct)
     r = _Result()
-    _check(_load().orc_scan_dict(_ptr(payload), _ptr(dct), len(dct), n, b, lo, hi, int(zone_maps),
+    _check(_load().orc_scan_dict(_ptr(payload), _ptr(dct), len(dct), n, b, lo, hi, _flags(zone_maps, all_match),
                                  ctypes.byref(r)), "scan_dict")
     return _res(r)
 

@@ -17,6 +17,12 @@
  * reports blocks_read = #{ k : not (max_k < lo or min_k >= hi) }; with zone
  * maps off, blocks_read = number of blocks.  An empty predicate (lo >= hi)
  * reads nothing: every output is 0.
+ * All-match shortcut (an extension of the zone-map idea, not in the paper): a
+ * block whose [min, max] lies inside [lo, hi) matches entirely, so a scan
+ * can take its count and its stored sum without decoding it.  COUNT and SUM
+ * are unchanged by definition; blocks_read then counts only the surviving
+ * blocks that are not entirely inside: #{ k : survives and not (min_k >= lo
+ * and max_k < hi) }.
  *
  * Format (the paper fixes only 1024-value blocks and the idea of a
  * row-major and a lane-transposed packing; the bit order below is this
@@ -245,7 +251,9 @@ static int64_t decode_for(const uint32_t* payload, const uint32_t* refs, uint64_
  * map is taken from them, and only then is the block tested and aggregated. */
 static int scan_generic(int enc, const uint32_t* payload, const uint32_t* refs, const int64_t* bases,
                         const int64_t* dict, uint32_t m, uint64_t n, uint32_t b, int layout,
-                        int64_t lo, int64_t hi, int use_zm, orc_result* out) {
+                        int64_t lo, int64_t hi, int flags, orc_result* out) {
+  /* flags: bit 0 zone maps, bit 1 all-match shortcut (with zone maps) */
+  const int use_zm = flags & 1, use_am = (flags & 3) == 3;
   acc_t acc = {0, 0};
   uint64_t nb = nblocks(n), read = 0;
   if (b < 1u || b > 32u) return -1;
@@ -276,6 +284,14 @@ static int scan_generic(int enc, const uint32_t* payload, const uint32_t* refs, 
         if (vals[i] > mx) mx = vals[i];
       }
       if (mx < lo || mn >= hi) continue; /* skipped: contributes nothing */
+      if (use_am && mn >= lo && mx < hi) {
+        /* entirely inside: every value matches; not a block read */
+        for (uint64_t i = 0; i < e - a; i++) {
+          acc.count++;
+          acc.sum += vals[i];
+        }
+        continue;
+      }
     }
     read++;
     for (uint64_t i = 0; i < e - a; i++) {
@@ -290,18 +306,18 @@ static int scan_generic(int enc, const uint32_t* payload, const uint32_t* refs, 
 }
 
 int orc_scan_for(const uint32_t* payload, const uint32_t* refs, uint64_t n, uint32_t b, int layout,
-                 int64_t lo, int64_t hi, int use_zm, orc_result* out) {
-  return scan_generic(0, payload, refs, NULL, NULL, 0, n, b, layout, lo, hi, use_zm, out);
+                 int64_t lo, int64_t hi, int flags, orc_result* out) {
+  return scan_generic(0, payload, refs, NULL, NULL, 0, n, b, layout, lo, hi, flags, out);
 }
 
 int orc_scan_delta(const uint32_t* payload, const int64_t* bases, uint64_t n, uint32_t b, int64_t lo,
-                   int64_t hi, int use_zm, orc_result* out) {
-  return scan_generic(1, payload, NULL, bases, NULL, 0, n, b, 0, lo, hi, use_zm, out);
+                   int64_t hi, int flags, orc_result* out) {
+  return scan_generic(1, payload, NULL, bases, NULL, 0, n, b, 0, lo, hi, flags, out);
 }
 
 int orc_scan_dict(const uint32_t* payload, const int64_t* dict, uint32_t m, uint64_t n, uint32_t b,
-                  int64_t lo, int64_t hi, int use_zm, orc_result* out) {
-  return scan_generic(2, payload, NULL, NULL, dict, m, n, b, 0, lo, hi, use_zm, out);
+                  int64_t lo, int64_t hi, int flags, orc_result* out) {
+  return scan_generic(2, payload, NULL, NULL, dict, m, n, b, 0, lo, hi, flags, out);
 }
 
 /* The plain definition on raw values, with no packing at all. */

@@ -238,3 +238,73 @@ def test_query_matches_numpy(rng):
             val = (a, dct[c], s)[sc].astype(np.int64)
             r = oracle.query(cols, n, filters, sc)
             assert (r.count, r.sum) == (int(mask.sum()), int(sum(int(x) for x in val[mask])))
+
+
+def _numpy_block_masks(v, lo, hi):
+    """(survives, inside) per 1024-value block, from numpy min/max."""
+    nb = (len(v) + 1023) // 1024
+    mn = np.array([v[k * 1024:(k + 1) * 1024].min() for k in range(nb)], dtype=np.int64)
+    mx = np.array([v[k * 1024:(k + 1) * 1024].max() for k in range(nb)], dtype=np.int64)
+    survive = ~((mx < lo) | (mn >= hi))
+    inside = (mn >= lo) & (mx < hi)
+    return survive, inside
+
+
+@pytest.mark.parametrize("n", [1, 1023, 1024, 5 * 1024 + 77])
+def test_all_match_counts_only_blocks_not_entirely_inside(rng, n):
+    """The all-match extension leaves COUNT and SUM alone; blocks_read drops
+    the surviving blocks whose [min, max] lies inside [lo, hi)."""
+    b = 12
+    base = np.sort(rng.integers(0, 1 << b, size=n)).astype(np.uint32)  # clustered: many blocks inside
+    for v in (base, rng.permutation(base)):
+        w = oracle.pack_rm(v, b)
+        for lo, hi in [(0, 1 << b), (100, 3000), (int(v[n // 2]), int(v[n // 2]) + 1), (5, 5), (-7, 1 << 40)]:
+            zm = oracle.scan_for(w, n, b, lo, hi, zone_maps=True)
+            am = oracle.scan_for(w, n, b, lo, hi, zone_maps=True, all_match=True)
+            assert (am.count, am.sum) == (zm.count, zm.sum)
+            if lo >= hi:
+                assert am.blocks_read == 0
+                continue
+            survive, inside = _numpy_block_masks(v.astype(np.int64), lo, hi)
+            assert zm.blocks_read == int(survive.sum())
+            assert am.blocks_read == int((survive & ~inside).sum())
+    # all-match without zone maps is ignored (the shortcut needs the zone maps)
+    w = oracle.pack_rm(base, b)
+    off = oracle.scan_for(w, n, b, 0, 1 << b, zone_maps=False, all_match=True)
+    assert off.blocks_read == (n + 1023) // 1024
+
+
+def test_all_match_on_the_sorted_column_reads_only_edge_blocks():
+    """Sorted values v_r = r >> 4: a predicate whose edges fall inside blocks
+    reads exactly those (at most two) edge blocks."""
+    n = 1 << 16
+    v = (np.arange(n) >> 4).astype(np.uint32)  # 64 distinct values per block
+    w = oracle.pack_rm(v, 12)
+    for lo, hi, edges in [(64, 128, 0), (70, 128, 1), (64, 1000, 1), (70, 1000, 2), (70, 75, 1)]:
+        r = oracle.scan_for(w, n, 12, lo, hi, zone_maps=True, all_match=True)
+        assert r.blocks_read == edges, (lo, hi, r)
+        assert r.count == 16 * (hi - lo)
+        assert r.sum == 16 * (hi - lo) * (lo + hi - 1) // 2
+
+
+def test_all_match_delta_and_dictionary(rng):
+    n = 3 * 1024 + 5
+    d = rng.integers(0, 8, size=n).astype(np.int64)
+    v = np.cumsum(d) + 1000
+    bases, codes = oracle.delta_encode(v, 3)
+    w = oracle.pack_rm(codes, 3)
+    lo, hi = int(v[100]), int(v[2500])
+    zm = oracle.scan_delta(w, bases, n, 3, lo, hi, zone_maps=True)
+    am = oracle.scan_delta(w, bases, n, 3, lo, hi, zone_maps=True, all_match=True)
+    survive, inside = _numpy_block_masks(v, lo, hi)
+    assert (am.count, am.sum) == (zm.count, zm.sum)
+    assert am.blocks_read == int((survive & ~inside).sum()) and int(inside.sum()) >= 1
+    dct = np.arange(0, 4096 * 3, 3, dtype=np.int64) - 5000
+    codes = np.sort(rng.integers(0, 4096, size=n)).astype(np.uint32)
+    w = oracle.pack_rm(codes, 12)
+    lo, hi = int(dct[500]), int(dct[3000])
+    zm = oracle.scan_dict(w, dct, n, 12, lo, hi, zone_maps=True)
+    am = oracle.scan_dict(w, dct, n, 12, lo, hi, zone_maps=True, all_match=True)
+    survive, inside = _numpy_block_masks(dct[codes], lo, hi)
+    assert (am.count, am.sum) == (zm.count, zm.sum)
+    assert am.blocks_read == int((survive & ~inside).sum()) and int(inside.sum()) >= 1
