@@ -182,8 +182,9 @@ def zonemap_leg(ctx, torch, n_log2, beta_gbs, reps=5):
     """Zone-map workload: N = 2^n_log2 values at b = 16, the sorted base
     v_r = r >> (n_log2 - 16) displaced by a noisy sort of s ranks (s = 0, 2^4,
     2^10, 2^16) or randomly permuted; predicate [lo, lo + w), w = round(sigma
-    2^16).  Zone maps on vs off (row-major direct decoder, branch-free), cold
-    cache, median of reps.  COUNT and SUM must be identical across every
+    2^16).  Zone maps with the all-match shortcut, zone maps alone, and no
+    zone maps (row-major direct decoder, branch-free), cold cache, median of
+    reps.  COUNT and SUM must be identical across every
     clustering level and both zone-map settings; on the sorted column they and
     blocks_read must equal their closed forms."""
     import numpy as np
@@ -206,15 +207,15 @@ def zonemap_leg(ctx, torch, n_log2, beta_gbs, reps=5):
         col = api.encode_for(vals.cpu().numpy().view(np.uint32), 16)
         del vals
         for sg, (lo, hi) in zip(sigmas, preds):
-            for zm in (1, 0):
-                s = strategy(DEC_RM_DIRECT, 0, zm)
+            for zm, am in ((1, 1), (1, 0), (0, 0)):
+                s = strategy(DEC_RM_DIRECT, 0, zm, am)
                 r = ctx.run(col, lo, hi, s)
                 key = (lo, hi)
                 if key not in want:
                     want[key] = (r["count"], r["sum"])
                 if (r["count"], r["sum"]) != want[key]:
                     raise RuntimeError("zone-map workload: results differ across levels (%s, %s)" % (lvl, key))
-                if lvl == 0 and zm:
+                if lvl == 0 and zm and not am:
                     closed = ((hi - lo) * per, per * (hi - lo) * (lo + hi - 1) // 2)
                     # each value fills per / 1024 whole blocks when per >= 1024
                     if (r["count"], r["sum"]) != closed or (per >= 1024 and r["blocks_read"] != (hi - lo) * per // 1024):
@@ -230,7 +231,8 @@ def zonemap_leg(ctx, torch, n_log2, beta_gbs, reps=5):
                     ts.append(e0.elapsed_time(e1) * 1e-3)
                 t = float(np.median(ts))
                 read_bytes = r["blocks_read"] * 2048 + (8 * nb if zm else 0)
-                rows.append({"s": lvl, "sigma": sg, "zone_maps": bool(zm), "ms": round(t * 1e3, 4),
+                rows.append({"s": lvl, "sigma": sg, "zone_maps": bool(zm), "all_match": bool(am),
+                             "ms": round(t * 1e3, 4),
                              "blocks_read_frac": round(r["blocks_read"] / nb, 6),
                              "logical_gvalues_per_s": round(n / t / 1e9, 1),
                              "decoded_gvalues_per_s": round(r["blocks_read"] * 1024 / t / 1e9, 1),
@@ -243,7 +245,7 @@ def zonemap_leg(ctx, torch, n_log2, beta_gbs, reps=5):
     # predicate edge grows with the displacement s); c_s = median(frac - sigma)
     model = {}
     for lvl in (0, 16, 1024, 65536, "random"):
-        d = [r["blocks_read_frac"] - r["sigma"] for r in rows if r["s"] == lvl and r["zone_maps"]]
+        d = [r["blocks_read_frac"] - r["sigma"] for r in rows if r["s"] == lvl and r["zone_maps"] and not r["all_match"]]
         model[str(lvl)] = round(float(np.median(d)), 6)
     return {"read_fraction_minus_sigma": model,"workload": "N=2^%d values at b=16, sorted base displaced by s in {0,2^4,2^10,2^16} ranks or random, "
                         "[lo, lo+round(sigma 2^16)), zone maps on vs off, cold cache, median of %d" % (n_log2, reps),

@@ -80,7 +80,7 @@ typedef struct {
 
 enum { SCAN_AGG_COUNT = 1u, SCAN_AGG_SUM = 2u };
 
-/* Strategy = decoder | (predicate mode << 2) | (zone maps << 3).
+/* Strategy = decoder | (predicate mode << 2) | (zone maps << 3) | (all-match << 4).
  *  decoder SCAN_DEC_RM_LDS:    row-major; a wavefront stages each block in LDS
  *                              and extracts values with funnel shifts;
  *  decoder SCAN_DEC_RM_DIRECT: row-major; each lane loads its own 32-value slice
@@ -90,6 +90,10 @@ enum { SCAN_AGG_COUNT = 1u, SCAN_AGG_SUM = 2u };
  *  mode SCAN_PRED_BF:  branch-free: every value is tested and added under a mask;
  *  mode SCAN_PRED_SV:  wavefront selection-vector compaction (ballot + mbcnt)
  *                      into LDS, aggregated over the compacted list.
+ *  SCAN_ALL_MATCH (with zone maps and block_sum): a block whose [min, max] lies
+ *                      inside [lo, hi) is not decoded; it adds its valid-value
+ *                      count to COUNT and block_sum[k] to SUM, and does not count
+ *                      in blocks_read (which then counts decoded blocks only).
  * SCAN_STRAT_AUTO lets the library choose (learned selector if loaded, else a
  * fixed heuristic). */
 enum {
@@ -99,6 +103,7 @@ enum {
   SCAN_DEC_BYTES = 3,
   SCAN_PRED_BF = 0,
   SCAN_PRED_SV = 1,
+  SCAN_ALL_MATCH = 16,
   SCAN_STRAT_AUTO = -1
 };
 #define SCAN_STRATEGY(dec, sv, zm) ((int32_t)((dec) | ((sv) << 2) | ((zm) << 3)))
@@ -113,6 +118,7 @@ typedef struct {
   const void* zone_min;       /* device: nb entries (u32, or int64 for DELTA_FOR); NULL = none */
   const void* zone_max;
   uint64_t n;                 /* values in the column */
+  const uint64_t* block_sum;  /* device: nb sums of each block's decoded values mod 2^64, or NULL */
 } scan_column;
 
 typedef struct {
@@ -367,6 +373,12 @@ scan_status scan_encode_delta(const int64_t* values, uint64_t n, uint32_t b, uin
 /* DICT: codes (indices into a dictionary of dict_len entries) packed row-major. */
 scan_status scan_encode_dict(const uint32_t* codes, uint64_t n, uint32_t b, uint32_t dict_len,
                              uint32_t* payload, uint32_t* zone_min, uint32_t* zone_max);
+/* Per-block sums of decoded values mod 2^64 (host pointers; out has nb
+ * entries) for scan_column.block_sum: enc SCAN_ENC_FOR takes u32 values,
+ * SCAN_ENC_DELTA_FOR int64 values, SCAN_ENC_DICT u32 codes and the dictionary
+ * (dict_len entries; a code >= dict_len -> SCAN_EINVAL). */
+scan_status scan_block_sums(int32_t enc, const void* values, uint64_t n, const int64_t* dict, uint32_t dict_len,
+                            uint64_t* out);
 
 /* ----------------------------------------------------- bandwidth probes */
 /* Streaming read of `bytes` (multiple of 16) from `buf` (device) with 16-byte

@@ -21,19 +21,21 @@ ENC_FOR, ENC_DELTA, ENC_DICT = 0, 1, 2
 LAYOUT_RM, LAYOUT_LI = 0, 1
 DEC_RM_LDS, DEC_RM_DIRECT, DEC_LI, DEC_BYTES = 0, 1, 2, 3
 PRED_BF, PRED_SV = 0, 1
+ALL_MATCH = 16
 STRAT_AUTO = -1
 AGG_COUNT, AGG_SUM = 1, 2
 
 
-def strategy(dec: int, sv: int = 0, zm: int = 0) -> int:
-    return dec | (sv << 2) | (zm << 3)
+def strategy(dec: int, sv: int = 0, zm: int = 0, am: int = 0) -> int:
+    return dec | (sv << 2) | (zm << 3) | (am << 4)
 
 
 def strategy_name(s: int) -> str:
     if s < 0:
         return "auto"
     dec = ("rm_lds", "rm_direct", "li", "bytes")[s & 3]
-    return "%s/%s/%s" % (dec, "sv" if (s >> 2) & 1 else "bf", "zm" if (s >> 3) & 1 else "nozm")
+    name = "%s/%s/%s" % (dec, "sv" if (s >> 2) & 1 else "bf", "zm" if (s >> 3) & 1 else "nozm")
+    return name + ("/am" if (s >> 4) & 1 else "")
 
 
 class ScanColumn(ctypes.Structure):
@@ -41,7 +43,7 @@ class ScanColumn(ctypes.Structure):
                 ("block_base", ctypes.c_void_p), ("dict", ctypes.c_void_p),
                 ("dict_len", ctypes.c_uint32), ("layout", ctypes.c_uint32),
                 ("zone_min", ctypes.c_void_p), ("zone_max", ctypes.c_void_p),
-                ("n", ctypes.c_uint64)]
+                ("n", ctypes.c_uint64), ("block_sum", ctypes.c_void_p)]
 
 
 class ScanPredicate(ctypes.Structure):
@@ -145,6 +147,7 @@ SIGNATURES = {
     "scan_encode_for": (_i32, [_vp, _u64, _u32, _u32, _i32, _vp, _vp, _vp, _vp]),
     "scan_encode_delta": (_i32, [_vp, _u64, _u32, _vp, _vp, _vp, _vp]),
     "scan_encode_dict": (_i32, [_vp, _u64, _u32, _u32, _vp, _vp, _vp]),
+    "scan_block_sums": (_i32, [_i32, _vp, _u64, _vp, _u32, _vp]),
     "scan_beta_read": (_i32, [_vp, _vp, _u64, _i32, _i32, _i32, _vp]),
     "scan_beta_triad": (_i32, [_vp, _vp, _vp, _vp, _f32, _u64]),
     "scan_cache_flush": (_i32, [_vp, _vp, _u64]),

@@ -89,6 +89,7 @@ class Column:
     dct: object = None
     zmin: object = None
     zmax: object = None
+    bsum: object = None      # per-block sums of decoded values (all-match shortcut)
     _keep: list = field(default_factory=list)
 
     def struct(self, zone_maps: bool = True) -> ScanColumn:
@@ -102,6 +103,7 @@ class Column:
         c.zone_min = _ptr(self.zmin) if zone_maps else None
         c.zone_max = _ptr(self.zmax) if zone_maps else None
         c.n = self.n
+        c.block_sum = _ptr(self.bsum) if zone_maps else None
         return c
 
     @property
@@ -119,6 +121,20 @@ class Column:
         return it
 
 
+def host_block_sums(enc: int, values, dct=None):
+    """Per-block sums of decoded values mod 2^64 (uint64 numpy), by the library's host code."""
+    lib = _lib.load()
+    if enc == ENC_DELTA:
+        v = np.ascontiguousarray(values, dtype=np.int64)
+    else:
+        v = np.ascontiguousarray(values, dtype=np.uint32)
+    d = None if dct is None else np.ascontiguousarray(dct, dtype=np.int64)
+    out = np.zeros(max(1, nblocks(len(v))), dtype=np.uint64)
+    _check(lib.scan_block_sums(enc, v.ctypes.data, len(v), None if d is None else d.ctypes.data,
+                               0 if d is None else len(d), out.ctypes.data), "scan_block_sums")
+    return out[:nblocks(len(v))]
+
+
 def _to_dev(a, device):
     import torch
     if a is None:
@@ -126,23 +142,27 @@ def _to_dev(a, device):
     return torch.from_numpy(np.ascontiguousarray(a)).to(device)
 
 
-def encode_for(values, b: int, layout: int = LAYOUT_RM, ref_policy: int = 0, device="cuda") -> Column:
+def encode_for(values, b: int, layout: int = LAYOUT_RM, ref_policy: int = 0, device="cuda",
+               block_sums: bool = True) -> Column:
     payload, refs, zmin, zmax = host_encode_for(values, b, layout, ref_policy)
+    bs = host_block_sums(ENC_FOR, values) if block_sums else None
     return Column(ENC_FOR, b, len(values), layout, _to_dev(payload, device), refs=_to_dev(refs, device),
-                  zmin=_to_dev(zmin, device), zmax=_to_dev(zmax, device))
+                  zmin=_to_dev(zmin, device), zmax=_to_dev(zmax, device), bsum=_to_dev(bs, device))
 
 
-def encode_delta(values, b: int, device="cuda") -> Column:
+def encode_delta(values, b: int, device="cuda", block_sums: bool = True) -> Column:
     payload, bases, zmin, zmax = host_encode_delta(values, b)
+    bs = host_block_sums(ENC_DELTA, values) if block_sums else None
     return Column(ENC_DELTA, b, len(values), LAYOUT_RM, _to_dev(payload, device), bases=_to_dev(bases, device),
-                  zmin=_to_dev(zmin, device), zmax=_to_dev(zmax, device))
+                  zmin=_to_dev(zmin, device), zmax=_to_dev(zmax, device), bsum=_to_dev(bs, device))
 
 
-def encode_dict(codes, b: int, dct, device="cuda") -> Column:
+def encode_dict(codes, b: int, dct, device="cuda", block_sums: bool = True) -> Column:
     dct = np.ascontiguousarray(dct, dtype=np.int64)
     payload, zmin, zmax = host_encode_dict(codes, b, len(dct))
+    bs = host_block_sums(ENC_DICT, codes, dct) if block_sums else None
     return Column(ENC_DICT, b, len(codes), LAYOUT_RM, _to_dev(payload, device), dct=_to_dev(dct, device),
-                  zmin=_to_dev(zmin, device), zmax=_to_dev(zmax, device))
+                  zmin=_to_dev(zmin, device), zmax=_to_dev(zmax, device), bsum=_to_dev(bs, device))
 
 
 # --------------------------------------------------------------- context

@@ -97,6 +97,8 @@ void plan_cols(scan_ctx* ctx, const scan_item* items, size_t n, uint32_t window,
     scan_status st = validate_column(ctx, &it.col, it.enc, it.b);
     if (st == SCAN_OK && it.col.layout != SCAN_LAYOUT_RM)
       st = fail(ctx, SCAN_EUNSUPPORTED, "batched scans read row-major columns");
+    if (st == SCAN_OK && it.strategy >= 0 && (it.strategy & SCAN_ALL_MATCH))
+      st = fail(ctx, SCAN_EUNSUPPORTED, "batched scans do not take the all-match shortcut");
     if (st == SCAN_OK && it.strategy >= 0) {
       st = check_strategy(ctx, &it.col, it.enc, it.b, it.strategy);
       const int dec = it.strategy & 3;
@@ -137,7 +139,7 @@ void plan_cols(scan_ctx* ctx, const scan_item* items, size_t n, uint32_t window,
     for (int q = 0; q < 8; ++q)
       if (zm || !((q >> 2) & 1)) mask |= 1u << q;
     c.valid_mask = mask;
-    int32_t h = heuristic_strategy(&it.col, it.enc, it.b);
+    int32_t h = heuristic_strategy(&it.col, it.enc, it.b) & ~SCAN_ALL_MATCH;
     if ((h & 3) != SCAN_DEC_RM_LDS && (h & 3) != SCAN_DEC_RM_DIRECT) h = (h & ~3) | SCAN_DEC_RM_DIRECT;
     c.heuristic = h;
     c.strategy = it.strategy >= 0 ? it.strategy : h;
@@ -296,6 +298,8 @@ scan_status selector_pick(scan_ctx* ctx, const scan_column* col, int32_t enc, ui
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "selector");
   *out = (int32_t)sc->mem.out_host[0].pad;
+  // the all-match shortcut only saves work: add it wherever zone maps are used and block sums exist
+  if (((*out >> 3) & 1) && col->block_sum) *out |= SCAN_ALL_MATCH;
   return SCAN_OK;
 }
 

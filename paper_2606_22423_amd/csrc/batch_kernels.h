@@ -78,6 +78,7 @@ __device__ __forceinline__ Params batch_params(const BatchCol& c) {
   p.dict = c.dict;
   p.zmin = c.zmin;
   p.zmax = c.zmax;
+  p.bsum = nullptr;  // batches do not take the all-match shortcut
   p.n = c.n;
   p.nb = c.nb;
   p.units = 0;
@@ -90,7 +91,7 @@ __device__ __forceinline__ Params batch_params(const BatchCol& c) {
   p.use_zm = (c.strategy >> 3) & 1;
   p.tail = c.tail;
   p.strategy = c.strategy;
-  p.pad0 = 0;
+  p.use_am = 0;
   p.partials = nullptr;
   p.ticket = nullptr;
   p.out = nullptr;

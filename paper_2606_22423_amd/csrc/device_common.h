@@ -39,6 +39,7 @@ struct Params {
   const int64_t* dict;     // DICT entries
   const void* zmin;        // per-block zone maps (u32 or int64), or null
   const void* zmax;
+  const uint64_t* bsum;    // per-block sums of decoded values (all-match shortcut), or null
   uint64_t n;              // values
   uint64_t nb;             // blocks
   uint64_t units;          // work units of G blocks
@@ -49,7 +50,7 @@ struct Params {
   uint32_t use_zm;
   uint32_t tail;           // valid values in the last block, 1..1024
   int32_t strategy;
-  uint32_t pad0;
+  uint32_t use_am;         // all-match shortcut (needs use_zm and bsum)
   Partial* partials;       // one per work-group
   uint32_t* ticket;        // zero between launches (the last work-group resets it)
   Result* out;

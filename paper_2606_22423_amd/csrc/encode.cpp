@@ -152,4 +152,30 @@ scan_status scan_encode_dict(const uint32_t* codes, uint64_t n, uint32_t b, uint
   return ok ? SCAN_OK : SCAN_EINVAL;
 }
 
+scan_status scan_block_sums(int32_t enc, const void* values, uint64_t n, const int64_t* dict, uint32_t dict_len,
+                            uint64_t* out) {
+  if (n && (!values || !out)) return SCAN_EINVAL;
+  if (enc == SCAN_ENC_DICT && n && !dict) return SCAN_EINVAL;
+  if (enc != SCAN_ENC_FOR && enc != SCAN_ENC_DELTA_FOR && enc != SCAN_ENC_DICT) return SCAN_EINVAL;
+  const uint64_t nb = blocks_of(n);
+  bool ok = parallel_blocks(nb, [&](uint64_t k) {
+    const uint64_t a = k * 1024ull, e = std::min<uint64_t>(n, a + 1024ull);
+    uint64_t sum = 0;  // mod 2^64
+    for (uint64_t i = a; i < e; ++i) {
+      if (enc == SCAN_ENC_FOR) {
+        sum += static_cast<const uint32_t*>(values)[i];
+      } else if (enc == SCAN_ENC_DELTA_FOR) {
+        sum += (uint64_t) static_cast<const int64_t*>(values)[i];
+      } else {
+        const uint32_t c = static_cast<const uint32_t*>(values)[i];
+        if (c >= dict_len) return false;
+        sum += (uint64_t)dict[c];
+      }
+    }
+    out[k] = sum;
+    return true;
+  });
+  return ok ? SCAN_OK : SCAN_EINVAL;
+}
+
 }  // extern "C"

@@ -102,15 +102,19 @@ scan_status validate_column(scan_ctx* ctx, const scan_column* col, int32_t enc, 
 
 int32_t heuristic_strategy(const scan_column* col, int32_t enc, uint32_t b) {
   const int zm = col->zone_min ? 1 : 0;
-  if (enc == SCAN_ENC_FOR && col->layout == SCAN_LAYOUT_LI) return SCAN_STRATEGY(SCAN_DEC_LI, SCAN_PRED_BF, zm);
+  // the all-match shortcut only ever saves work: on whenever it can be
+  const int32_t am = (zm && col->block_sum) ? SCAN_ALL_MATCH : 0;
+  if (enc == SCAN_ENC_FOR && col->layout == SCAN_LAYOUT_LI) return SCAN_STRATEGY(SCAN_DEC_LI, SCAN_PRED_BF, zm) | am;
   (void)b;
-  return SCAN_STRATEGY(SCAN_DEC_RM_DIRECT, SCAN_PRED_BF, zm);
+  return SCAN_STRATEGY(SCAN_DEC_RM_DIRECT, SCAN_PRED_BF, zm) | am;
 }
 
 scan_status check_strategy(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b, int32_t s) {
-  if (s < 0 || s > 15) return fail(ctx, SCAN_EINVAL, "strategy %d out of range", s);
-  const int dec = s & 3, zm = (s >> 3) & 1;
+  if (s < 0 || s > 31) return fail(ctx, SCAN_EINVAL, "strategy %d out of range", s);
+  const int dec = s & 3, zm = (s >> 3) & 1, am = (s >> 4) & 1;
   if (zm && !col->zone_min) return fail(ctx, SCAN_EUNSUPPORTED, "zone-map strategy on a column without zone maps");
+  if (am && (!zm || !col->block_sum))
+    return fail(ctx, SCAN_EUNSUPPORTED, "the all-match shortcut needs zone maps and block sums");
   if (dec == SCAN_DEC_LI) {
     if (enc != SCAN_ENC_FOR || col->layout != SCAN_LAYOUT_LI)
       return fail(ctx, SCAN_EUNSUPPORTED, "lane-interleaved decoder needs a FOR column in the LI layout");
@@ -211,6 +215,8 @@ scan_status prepare_scan(scan_ctx* ctx, const scan_column* col, int32_t enc, uin
   p.lo = pred->lo;
   p.hi = pred->hi;
   p.use_zm = (uint32_t)zm;
+  p.use_am = (uint32_t)((s >> 4) & 1);
+  p.bsum = col->block_sum;
   p.tail = (uint32_t)(col->n - (p.nb ? (p.nb - 1) : 0) * SCAN_BLOCK_VALUES);
   p.strategy = s;
   p.partials = ctx->partials;

@@ -183,28 +183,48 @@ __device__ __forceinline__ CodeRange block_range(const Params& p, uint32_t ref, 
 // ------------------------------------------------------ block windows
 
 // Survivors among blocks k0 .. k0+cnt-1 (cnt <= 64) of a FOR/DICT column,
-// without block `excl` (the partial last block, decoded separately).
+// without block `excl` (the partial last block, decoded separately).  With
+// the all-match shortcut, a surviving block whose [min, max] lies inside the
+// predicate is not returned: the lane testing it adds the block's 1024 values
+// to am_count and its stored sum to am_sum (per-lane accumulators).
 template <int ENC>
 __device__ __forceinline__ uint64_t window_live(const Params& p, uint64_t k0, uint32_t cnt, uint32_t clo, uint32_t chi,
-                                                uint64_t excl) {
+                                                uint64_t excl, uint64_t& am_count, uint64_t& am_sum) {
   const uint32_t lane = lane_id();
   bool keep = lane < cnt && (k0 + lane) != excl;
   if (p.use_zm && keep) {
     const uint32_t mn = static_cast<const uint32_t*>(p.zmin)[k0 + lane];
     const uint32_t mx = static_cast<const uint32_t*>(p.zmax)[k0 + lane];
-    if constexpr (ENC == ENC_DICT) keep = !(mx < clo || mn >= chi);
-    else keep = !(mx < p.lo32 || mn > p.hi32m1);
+    bool inside;
+    if constexpr (ENC == ENC_DICT) {
+      keep = !(mx < clo || mn >= chi);
+      inside = mn >= clo && mx < chi;
+    } else {
+      keep = !(mx < p.lo32 || mn > p.hi32m1);
+      inside = mn >= p.lo32 && mx <= p.hi32m1;
+    }
+    if (p.use_am && keep && inside) {
+      am_count += kBlockValues;
+      am_sum += p.bsum[k0 + lane];
+      keep = false;
+    }
   }
   return ballot(keep);
 }
 
-__device__ __forceinline__ uint64_t window_live_i64(const Params& p, uint64_t k0, uint32_t cnt, uint64_t excl) {
+__device__ __forceinline__ uint64_t window_live_i64(const Params& p, uint64_t k0, uint32_t cnt, uint64_t excl,
+                                                    uint64_t& am_count, uint64_t& am_sum) {
   const uint32_t lane = lane_id();
   bool keep = lane < cnt && (k0 + lane) != excl;
   if (p.use_zm && keep) {
     const int64_t mn = static_cast<const int64_t*>(p.zmin)[k0 + lane];
     const int64_t mx = static_cast<const int64_t*>(p.zmax)[k0 + lane];
     keep = !(mx < p.lo || mn >= p.hi);
+    if (p.use_am && keep && mn >= p.lo && mx < p.hi) {
+      am_count += kBlockValues;
+      am_sum += p.bsum[k0 + lane];
+      keep = false;
+    }
   }
   return ballot(keep);
 }
@@ -220,6 +240,21 @@ __device__ __forceinline__ bool block_survives(const Params& p, uint64_t k, uint
     const uint32_t mn = static_cast<const uint32_t*>(p.zmin)[k], mx = static_cast<const uint32_t*>(p.zmax)[k];
     if constexpr (ENC == ENC_DICT) return !(mx < clo || mn >= chi);
     else return !(mx < p.lo32 || mn > p.hi32m1);
+  }
+}
+
+// Whether a surviving block lies entirely inside the predicate (uniform; only
+// with the all-match shortcut).
+template <int ENC>
+__device__ __forceinline__ bool block_inside(const Params& p, uint64_t k, uint32_t clo, uint32_t chi) {
+  if (!p.use_am) return false;
+  if constexpr (ENC == ENC_DELTA) {
+    const int64_t mn = static_cast<const int64_t*>(p.zmin)[k], mx = static_cast<const int64_t*>(p.zmax)[k];
+    return mn >= p.lo && mx < p.hi;
+  } else {
+    const uint32_t mn = static_cast<const uint32_t*>(p.zmin)[k], mx = static_cast<const uint32_t*>(p.zmax)[k];
+    if constexpr (ENC == ENC_DICT) return mn >= clo && mx < chi;
+    else return mn >= p.lo32 && mx <= p.hi32m1;
   }
 }
 
@@ -397,7 +432,9 @@ __device__ __forceinline__ void run_pairs(const Params& p, WaveState<uint32_t>& 
                                           uint64_t ka, uint64_t ke, uint64_t stride, uint32_t win, uint64_t excl,
                                           const int64_t* dict_lds, uint32_t dict_last, uint32_t clo, uint32_t chi) {
   const uint32_t l = lane & 31u;
-  auto live_fn = [&](uint64_t k0, uint32_t cnt) { return window_live<ENC>(p, k0, cnt, clo, chi, excl); };
+  auto live_fn = [&](uint64_t k0, uint32_t cnt) {
+    return window_live<ENC>(p, k0, cnt, clo, chi, excl, s.lcount, s.lsum);
+  };
   PairCursor<P, decltype(live_fn)> cur{ka, ke, 0, 0, 0, list, ka, stride, win};
   // Two register buffers used alternately: the next step's loads are always
   // issued (a harmless reload of a valid block when there is no next step)
@@ -562,7 +599,9 @@ __device__ __forceinline__ void run_staged(const Params& p, WaveState<uint32_t>&
                                            uint64_t ka, uint64_t ke, uint64_t stride, uint32_t win, uint64_t excl,
                                            const int64_t* dict_lds, uint32_t dict_last, uint32_t clo, uint32_t chi) {
   constexpr int NL = Geo<B>::kStageLoads, SW = Geo<B>::kStageWords;
-  auto live_fn = [&](uint64_t k0, uint32_t cnt) { return window_live<ENC>(p, k0, cnt, clo, chi, excl); };
+  auto live_fn = [&](uint64_t k0, uint32_t cnt) {
+    return window_live<ENC>(p, k0, cnt, clo, chi, excl, s.lcount, s.lsum);
+  };
   BlockCursor<NB, decltype(live_fn)> cur{ka, ke, 0, 0, stride, win};
   uint64_t k0 = 0, m0 = 0, k1 = 0, m1 = 0;
   uint32_t r0[NB][NL], r1[NB][NL];
@@ -606,7 +645,9 @@ template <int B, int MODE, int ENC, int PF, int NB>
 __device__ __forceinline__ void run_bytes(const Params& p, WaveState<uint32_t>& s, uint32_t lane, uint64_t ka,
                                           uint64_t ke, uint64_t stride, uint32_t win, uint64_t excl) {
   constexpr int Q = B / 8;
-  auto live_fn = [&](uint64_t k0, uint32_t cnt) { return window_live<ENC>(p, k0, cnt, 0, 0, excl); };
+  auto live_fn = [&](uint64_t k0, uint32_t cnt) {
+    return window_live<ENC>(p, k0, cnt, 0, 0, excl, s.lcount, s.lsum);
+  };
   BlockCursor<NB, decltype(live_fn)> cur{ka, ke, 0, 0, stride, win};
   uint64_t k0 = 0, m0 = 0, k1 = 0, m1 = 0;
   uint4 x0[NB][Q], x1[NB][Q];
@@ -692,12 +733,18 @@ __device__ __forceinline__ void scan_range(const Params& p, WaveState<uint32_t>&
     run_bytes<B, MODE, ENC, PF, SMALL ? 1 : Geo<B>::kByteBlocks>(p, s, lane, ka, ke, stride, win, excl);
   }
   if (tail_partial && owns_block(last, ka, ke, stride, win) && block_survives<ENC>(p, last, clo, chi)) {
-    s.blocks += 1;
-    if constexpr (DEC == DEC_RM_DIRECT || DEC == DEC_LI) {
+    if (block_inside<ENC>(p, last, clo, chi)) {
+      // all-match: every valid value passes; lane 0 takes the block (no branch on the lane)
+      const uint64_t bs = p.bsum[last];
+      s.lcount += lane == 0 ? (uint64_t)p.tail : 0ull;
+      s.lsum += lane == 0 ? bs : 0ull;
+    } else if constexpr (DEC == DEC_RM_DIRECT || DEC == DEC_LI) {
+      s.blocks += 1;
       uint32_t w[B];
       load_pair_words<B, DEC>(p, last, lane & 31u, w);
       decode_pair<B, DEC, MODE, ENC, PF, true>(p, s, lane, w, last, lane < 32u, dict_lds, dict_last, clo, chi);
     } else if constexpr (DEC == DEC_RM_LDS) {
+      s.blocks += 1;
       uint32_t r[Geo<B>::kStageLoads];
       stage_load<B>(p.payload + last * (32u * B), lane, r);
       __builtin_amdgcn_wave_barrier();
@@ -706,6 +753,7 @@ __device__ __forceinline__ void scan_range(const Params& p, WaveState<uint32_t>&
       decode_staged<B, MODE, ENC, PF, true>(p, s, lane, st, last, dict_lds, dict_last, clo, chi);
       __builtin_amdgcn_wave_barrier();
     } else {
+      s.blocks += 1;
       uint4 x[B / 8];
       const uint4* blk = reinterpret_cast<const uint4*>(p.payload + last * (32u * B));
 #pragma unroll
@@ -933,7 +981,7 @@ __device__ __forceinline__ void delta_range(const Params& p, WaveState<RelT<B>>&
   const uint64_t last = p.nb - 1;
   const bool tail_partial = p.tail != kBlockValues;
   const uint64_t excl = tail_partial ? last : ~0ull;
-  auto live_fn = [&](uint64_t k0, uint32_t cnt) { return window_live_i64(p, k0, cnt, excl); };
+  auto live_fn = [&](uint64_t k0, uint32_t cnt) { return window_live_i64(p, k0, cnt, excl, s.lcount, s.lsum); };
   if constexpr (DEC == DEC_RM_DIRECT) {
     constexpr int P = SMALL ? 1 : Geo<B>::kPairs;
     const uint32_t l = lane & 31u;
@@ -1004,12 +1052,18 @@ __device__ __forceinline__ void delta_range(const Params& p, WaveState<RelT<B>>&
     }
   }
   if (tail_partial && owns_block(last, ka, ke, stride, win) && block_survives<ENC_DELTA>(p, last, 0, 0)) {
-    s.blocks += 1;
-    if constexpr (DEC == DEC_RM_DIRECT) {
+    if (block_inside<ENC_DELTA>(p, last, 0, 0)) {
+      // all-match: every valid value passes; lane 0 takes the block (no branch on the lane)
+      const uint64_t bs = p.bsum[last];
+      s.lcount += lane == 0 ? (uint64_t)p.tail : 0ull;
+      s.lsum += lane == 0 ? bs : 0ull;
+    } else if constexpr (DEC == DEC_RM_DIRECT) {
+      s.blocks += 1;
       uint32_t w[B];
       load_pair_words<B, DEC_RM_DIRECT>(p, last, lane & 31u, w);
       decode_delta_pair<B, MODE, true>(p, s, lane, w, last, lane < 32u);
     } else {
+      s.blocks += 1;
       uint32_t r[Geo<B>::kStageLoads];
       stage_load<B>(p.payload + last * (32u * B), lane, r);
       stage_store<B>(st, lane, r);

@@ -86,3 +86,20 @@ def test_encoder_argument_errors():
     assert lib.scan_encode_for(v.ctypes.data, 10, 8, 0, 1, out.ctypes.data, None, None, None) == _lib.SCAN_EINVAL
     assert lib.scan_encode_dict(v.ctypes.data, 10, 3, 9, out.ctypes.data, None, None) == _lib.SCAN_EINVAL
     assert lib.scan_payload_words(0, 5) == 0 and lib.scan_payload_words(1025, 5) == 2 * 32 * 5
+
+
+def test_block_sums_match_numpy(rng):
+    """scan_block_sums (library host code) against per-block numpy sums mod 2^64."""
+    for n in (1, 1023, 1024, 3 * 1024 + 17):
+        v = rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+        want = [int(v[k:k + 1024].astype(np.uint64).sum()) % (1 << 64) for k in range(0, n, 1024)]
+        assert api.host_block_sums(api.ENC_FOR, v).tolist() == want
+        d = np.cumsum(rng.integers(0, 1 << 20, size=n)).astype(np.int64) - (1 << 40)
+        want = [sum(int(x) for x in d[k:k + 1024]) % (1 << 64) for k in range(0, n, 1024)]
+        assert api.host_block_sums(api.ENC_DELTA, d).tolist() == want
+        dct = np.sort(rng.choice(np.arange(-(1 << 40), 1 << 40, 1 << 28), size=300, replace=False)).astype(np.int64)
+        codes = rng.integers(0, 300, size=n).astype(np.uint32)
+        want = [sum(int(dct[c]) for c in codes[k:k + 1024]) % (1 << 64) for k in range(0, n, 1024)]
+        assert api.host_block_sums(api.ENC_DICT, codes, dct).tolist() == want
+    with pytest.raises(_lib.ScanError):
+        api.host_block_sums(api.ENC_DICT, np.array([0, 300], dtype=np.uint32), np.arange(300, dtype=np.int64))

@@ -68,13 +68,13 @@ class Case:
             self.col = api.encode_dict(v, b, dct)
             self.words = oracle.pack_rm(v, b)
 
-    def want(self, lo, hi, zm):
+    def want(self, lo, hi, zm, am=False):
         s, b, n = self.spec, self.spec.b, self.spec.n
         if s.enc == ENC_FOR:
-            return oracle.scan_for(self.words, n, b, lo, hi, zone_maps=zm)
+            return oracle.scan_for(self.words, n, b, lo, hi, zone_maps=zm, all_match=am)
         if s.enc == ENC_DELTA:
-            return oracle.scan_delta(self.words, self.bases, n, b, lo, hi, zone_maps=zm)
-        return oracle.scan_dict(self.words, self.dct, n, b, lo, hi, zone_maps=zm)
+            return oracle.scan_delta(self.words, self.bases, n, b, lo, hi, zone_maps=zm, all_match=am)
+        return oracle.scan_dict(self.words, self.dct, n, b, lo, hi, zone_maps=zm, all_match=am)
 
     def zone_domain(self, lo, hi):
         """Zone maps and predicate in the domain the zone maps are kept in."""
@@ -104,7 +104,7 @@ def predicates(case, j):
 def check_item(case, got, lo, hi, what):
     assert got["status"] == 0, (what, got)
     s = got["strategy_used"]
-    want = case.want(lo, hi, zm=bool((s >> 3) & 1))
+    want = case.want(lo, hi, zm=bool((s >> 3) & 1), am=bool((s >> 4) & 1))
     assert (got["count"], got["sum"], got["blocks_read"], got["blocks_total"]) == \
         (want.count, want.sum, want.blocks_read, want.blocks_total), (what, got, want)
 
@@ -253,7 +253,9 @@ def test_selector_choice_is_network_argmin(ctx, cases):
         order = np.argsort(p, kind="stable")
         if p[order[1]] - p[order[0]] < 1e-3:  # fp32 near-tie: either choice is the network's
             continue
-        assert got["strategy_used"] == class_strategy(int(order[0])), (i, p, got)
+        # the library adds the all-match shortcut to zone-map classes (block sums exist)
+        assert got["strategy_used"] & ~16 == class_strategy(int(order[0])), (i, p, got)
+        assert bool(got["strategy_used"] & 16) == bool((order[0] >> 2) & 1), (i, got)
         checked += 1
     assert checked > len(res) // 2
 
@@ -268,7 +270,7 @@ def test_selector_file_round_trip(ctx, cases, tmp_path):
         ctx.selector_clear()
         assert not ctx.selector_loaded
         assert [ctx.run(c.col, c.lo, c.hi, -1)["strategy_used"] for c in cases[:24]] == \
-            [strategy(DEC_RM_DIRECT, 0, 1)] * 24  # heuristic without a selector
+            [strategy(DEC_RM_DIRECT, 0, 1, 1)] * 24  # heuristic without a selector (zone maps, all-match)
         ctx.selector_load(path)
         for c, s in zip(cases[:24], first):
             got = ctx.run(c.col, c.lo, c.hi, -1)

@@ -251,3 +251,83 @@ def test_launch_tuning_does_not_change_results(ctx):
                 if (s >> 3) & 1:
                     assert got["blocks_read"] == want.blocks_read
             ctx.set_tune(ENC_FOR, b, s, 0, 0, 0)
+
+
+def check_am(got, want, what):
+    assert (got["count"], got["sum"], got["blocks_read"], got["blocks_total"]) == \
+        (want.count, want.sum, want.blocks_read, want.blocks_total), (what, got, want)
+
+
+def am_strategies(b, enc=ENC_FOR, li=False):
+    if li:
+        return [strategy(DEC_LI, sv, 1, 1) for sv in (0, 1)]
+    decs = [DEC_RM_LDS, DEC_RM_DIRECT] + ([DEC_BYTES] if enc == ENC_FOR and b in (8, 16, 32) else [])
+    return [strategy(d, sv, 1, 1) for d in decs for sv in (0, 1)]
+
+
+@pytest.mark.parametrize("b", [1, 3, 8, 12, 16, 21, 31, 32])
+def test_all_match_for(ctx, b):
+    """Blocks entirely inside the predicate are counted from zone maps and
+    block sums, not decoded: same COUNT and SUM, blocks_read as the oracle's
+    all-match definition, in every decoder and predicate mode."""
+    top = 1 << b
+    for n in (1, 1024, 7 * 1024 + 99):
+        raw = synth.width_values(synth.pcg32(91, b, n), b)
+        srt = np.sort(raw)
+        for v in (srt, srt[::-1].copy(), raw):
+            w = oracle.pack_rm(v, b)
+            col, coli = api.encode_for(v, b), api.encode_for(v, b, layout=LAYOUT_LI)
+            preds = [(0, top), (int(srt[n // 3]), int(srt[2 * n // 3]) + 1), (int(srt[n // 2]), int(srt[n // 2]) + 1),
+                     (top // 4, top // 2 + 1), (-3, 1 << 40), (5, 5)]
+            for lo, hi in preds:
+                want = oracle.scan_for(w, n, b, lo, hi, zone_maps=True, all_match=True)
+                for s in am_strategies(b):
+                    check_am(ctx.run(col, lo, hi, s), want, (b, n, lo, hi, _lib.strategy_name(s)))
+                for s in am_strategies(b, li=True):
+                    check_am(ctx.run(coli, lo, hi, s), want, (b, n, lo, hi, _lib.strategy_name(s)))
+    # block references (per-block minimum) on sorted data
+    n = 6 * 1024 + 5
+    v = np.sort(synth.width_values(synth.pcg32(93, b, n), b)).astype(np.uint32)
+    refs, codes = oracle.for_encode(v, b, policy=1)
+    w = oracle.pack_rm(codes, b)
+    col = api.encode_for(v, b, ref_policy=1)
+    for lo, hi in [(int(v[1000]), int(v[5000]) + 1), (0, top)]:
+        want = oracle.scan_for(w, n, b, lo, hi, refs=refs, zone_maps=True, all_match=True)
+        for s in am_strategies(b):
+            check_am(ctx.run(col, lo, hi, s), want, ("refs", b, lo, hi, _lib.strategy_name(s)))
+
+
+@pytest.mark.parametrize("b", [1, 5, 16, 32])
+def test_all_match_delta_and_dict(ctx, b):
+    for n in (1, 2048, 5 * 1024 + 31):
+        d = synth.width_values(synth.pcg32(94, b, n), b).astype(np.int64)
+        v = np.cumsum(d) + 12345
+        bases, codes = oracle.delta_encode(v, b)
+        w = oracle.pack_rm(codes, b)
+        col = api.encode_delta(v, b)
+        for lo, hi in [(int(v[0]), int(v[-1]) + 1), (int(v[n // 4]), int(v[3 * n // 4]) + 1), (7, 7)]:
+            want = oracle.scan_delta(w, bases, n, b, lo, hi, zone_maps=True, all_match=True)
+            for s in am_strategies(b, ENC_DELTA):
+                check_am(ctx.run(col, lo, hi, s), want, ("delta", b, n, lo, hi, _lib.strategy_name(s)))
+        m = min(1 << b, 4096)
+        dct = synth.dict_entries(m, 95, b, 38)
+        cds = np.sort(synth.bounded(96, b, n, m)).astype(np.uint32)
+        w = oracle.pack_rm(cds, b)
+        col = api.encode_dict(cds, b, dct)
+        for lo, hi in [(int(dct[0]), int(dct[-1]) + 1), (int(dct[m // 4]), int(dct[(3 * m) // 4])), (int(dct[0]) - 5, int(dct[0]))]:
+            want = oracle.scan_dict(w, dct, n, b, lo, hi, zone_maps=True, all_match=True)
+            for s in am_strategies(b, ENC_DICT):
+                check_am(ctx.run(col, lo, hi, s), want, ("dict", b, n, lo, hi, _lib.strategy_name(s)))
+
+
+def test_all_match_needs_block_sums_and_is_the_default(ctx):
+    v = np.sort(synth.width_values(synth.pcg32(97, 10, 4096), 10))
+    col = api.encode_for(v, 10)
+    got = ctx.run(col, 100, 900, -1)
+    assert got["strategy_used"] == strategy(DEC_RM_DIRECT, 0, 1, 1)
+    bare = api.encode_for(v, 10, block_sums=False)
+    assert ctx.run(bare, 100, 900, -1)["strategy_used"] == strategy(DEC_RM_DIRECT, 0, 1)
+    with pytest.raises(_lib.ScanError):
+        ctx.run(bare, 100, 900, strategy(DEC_RM_DIRECT, 0, 1, 1))
+    with pytest.raises(_lib.ScanError):
+        ctx.run(col, 100, 900, strategy(DEC_RM_DIRECT, 0, 0, 1))  # all-match without zone maps
