@@ -85,6 +85,13 @@ def _load():
             f = getattr(lib, name)
             f.argtypes = args
             f.restype = ctypes.c_int
+        for name, args in {"orc_select": [i32, vp, vp, vp, u64, u32, i32, i64, i64, vp, u64],
+                           "orc_refine": [i32, vp, vp, vp, u32, i32, i64, i64, vp, u64, vp]}.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int64
+        lib.orc_gather.argtypes = [i32, vp, vp, vp, u32, i32, vp, u64, vp]
+        lib.orc_gather.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -258,3 +265,43 @@ def query(columns, n: int, filters, sum_col: int) -> ScanResult:
     _check(_load().orc_query(arr, n, len(filters), _ptr(fcol), _ptr(flo), _ptr(fhi), sum_col,
                              ctypes.byref(r)), "query")
     return _res(r)
+
+
+# ------------------------------------------------------ materializing select
+def select(enc: int, payload, n: int, b: int, lo: int, hi: int, refs=None, dct=None, layout: int = 0) -> np.ndarray:
+    """Ascending positions i with lo <= v_i < hi (frame of reference: enc 0; dictionary: enc 2)."""
+    payload = _u32(payload)
+    refs = None if refs is None else _u32(refs)
+    dct = None if dct is None else _i64(dct)
+    cnt = _load().orc_select(enc, _ptr(payload), _ptr(refs), _ptr(dct), n, b, layout, lo, hi, None, 0)
+    if cnt < 0:
+        raise ValueError("oracle select rejected its arguments")
+    out = np.zeros(max(cnt, 1), dtype=np.uint32)
+    _load().orc_select(enc, _ptr(payload), _ptr(refs), _ptr(dct), n, b, layout, lo, hi, _ptr(out), cnt)
+    return out[:cnt]
+
+
+def refine(enc: int, payload, b: int, lo: int, hi: int, positions, refs=None, dct=None, layout: int = 0) -> np.ndarray:
+    """The positions (ascending, kept in order) whose value in this column lies in [lo, hi)."""
+    payload = _u32(payload)
+    refs = None if refs is None else _u32(refs)
+    dct = None if dct is None else _i64(dct)
+    pos = _u32(positions)
+    out = np.zeros(max(len(pos), 1), dtype=np.uint32)
+    cnt = _load().orc_refine(enc, _ptr(payload), _ptr(refs), _ptr(dct), b, layout, lo, hi, _ptr(pos), len(pos),
+                             _ptr(out))
+    if cnt < 0:
+        raise ValueError("oracle refine rejected its arguments")
+    return out[:cnt]
+
+
+def gather(enc: int, payload, b: int, positions, refs=None, dct=None, layout: int = 0) -> np.ndarray:
+    """Decoded values at the positions (int64)."""
+    payload = _u32(payload)
+    refs = None if refs is None else _u32(refs)
+    dct = None if dct is None else _i64(dct)
+    pos = _u32(positions)
+    out = np.zeros(max(len(pos), 1), dtype=np.int64)
+    _check(_load().orc_gather(enc, _ptr(payload), _ptr(refs), _ptr(dct), b, layout, _ptr(pos), len(pos), _ptr(out)),
+           "gather")
+    return out[:len(pos)]

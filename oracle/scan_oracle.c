@@ -379,3 +379,51 @@ int orc_query(const orc_column* cols, uint64_t n, int nf, const int32_t* fcol, c
   finish(&acc, 0, nblocks(n), out);
   return 0;
 }
+
+/* ------------------------------------------------ materializing select */
+
+/* Decoded value i of a frame-of-reference (enc 0) or dictionary (enc 2)
+ * column; one value at a time, nothing shared with the scan above. */
+static int64_t value_at(int enc, const uint32_t* payload, const uint32_t* refs, const int64_t* dict, uint64_t i,
+                        uint32_t b, int layout) {
+  if (enc == 2) return dict[extract(payload, i, b, layout)];
+  return decode_for(payload, refs, i, b, layout);
+}
+
+/* Materializing select: the ascending positions i < n with lo <= v_i < hi.
+ * Writes at most cap of them to out and returns how many there are
+ * (negative on a bad width or encoding). */
+int64_t orc_select(int enc, const uint32_t* payload, const uint32_t* refs, const int64_t* dict, uint64_t n,
+                   uint32_t b, int layout, int64_t lo, int64_t hi, uint32_t* out, uint64_t cap) {
+  if (b < 1u || b > 32u || (enc != 0 && enc != 2)) return -1;
+  int64_t count = 0;
+  for (uint64_t i = 0; i < n && lo < hi; i++) {
+    int64_t v = value_at(enc, payload, refs, dict, i, b, layout);
+    if (lo <= v && v < hi) {
+      if ((uint64_t)count < cap) out[count] = (uint32_t)i;
+      count++;
+    }
+  }
+  return count;
+}
+
+/* Late materialization: the positions of pos[0..m) (ascending) whose value
+ * in this column lies in [lo, hi), in the same order. */
+int64_t orc_refine(int enc, const uint32_t* payload, const uint32_t* refs, const int64_t* dict, uint32_t b,
+                   int layout, int64_t lo, int64_t hi, const uint32_t* pos, uint64_t m, uint32_t* out) {
+  if (b < 1u || b > 32u || (enc != 0 && enc != 2)) return -1;
+  int64_t count = 0;
+  for (uint64_t q = 0; q < m && lo < hi; q++) {
+    int64_t v = value_at(enc, payload, refs, dict, pos[q], b, layout);
+    if (lo <= v && v < hi) out[count++] = pos[q];
+  }
+  return count;
+}
+
+/* The values at pos[0..m). */
+int orc_gather(int enc, const uint32_t* payload, const uint32_t* refs, const int64_t* dict, uint32_t b, int layout,
+               const uint32_t* pos, uint64_t m, int64_t* out) {
+  if (b < 1u || b > 32u || (enc != 0 && enc != 2)) return -1;
+  for (uint64_t q = 0; q < m; q++) out[q] = value_at(enc, payload, refs, dict, pos[q], b, layout);
+  return 0;
+}

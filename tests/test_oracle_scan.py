@@ -308,3 +308,33 @@ def test_all_match_delta_and_dictionary(rng):
     survive, inside = _numpy_block_masks(dct[codes], lo, hi)
     assert (am.count, am.sum) == (zm.count, zm.sum)
     assert am.blocks_read == int((survive & ~inside).sum()) and int(inside.sum()) >= 1
+
+
+@pytest.mark.parametrize("b", [1, 7, 16, 32])
+def test_select_is_the_plain_position_list(rng, b):
+    """Materializing select = numpy's nonzero on the raw values; refine and
+    gather are the same definition applied to a position list."""
+    for n in (0, 1, 1023, 1025, 4 * 1024 + 9):
+        v = rng.integers(0, 1 << b, size=n, dtype=np.uint64).astype(np.uint32)
+        w = oracle.pack_rm(v, b)
+        wl = oracle.pack_li(v, b)
+        for lo, hi in [(0, 1 << b), (5, 5), (1 << (b - 1), (1 << b) - 1), (-4, 3)]:
+            want = np.nonzero((v.astype(np.int64) >= lo) & (v.astype(np.int64) < hi))[0].astype(np.uint32)
+            got = oracle.select(0, w, n, b, lo, hi)
+            assert np.array_equal(got, want)
+            assert np.array_equal(oracle.select(0, wl, n, b, lo, hi, layout=1), want)
+            r = oracle.scan_for(w, n, b, lo, hi)
+            assert r.count == len(got) and r.sum == int(v[got].astype(np.uint64).sum())
+            assert np.array_equal(oracle.gather(0, w, b, got), v[got].astype(np.int64))
+            lo2, hi2 = 0, (1 << b) // 3 + 1
+            ref = oracle.refine(0, w, b, lo2, hi2, got)
+            assert np.array_equal(ref, got[(v[got] >= lo2) & (v[got] < hi2)])
+    # dictionary: values are entries
+    m = min(1 << b, 4096)
+    dct = np.sort(rng.choice(np.arange(-(1 << 36), 1 << 36, 1 << 20), size=m, replace=False)).astype(np.int64)
+    codes = rng.integers(0, m, size=3000).astype(np.uint32)
+    w = oracle.pack_rm(codes, b)
+    lo, hi = int(dct[m // 4]), int(dct[(3 * m) // 4]) + 1
+    want = np.nonzero((dct[codes] >= lo) & (dct[codes] < hi))[0].astype(np.uint32)
+    assert np.array_equal(oracle.select(2, w, 3000, b, lo, hi, dct=dct), want)
+    assert np.array_equal(oracle.gather(2, w, b, want, dct=dct), dct[codes[want]])
