@@ -530,6 +530,29 @@ def main():
                 sigma_fits["%s@%g" % (strategy_name(s), sg)] = {"T_dec_gvalues_per_s": round(ft.t_dec / 1e9, 1),
                                                                "b_star": round(ft.b_star, 2)}
 
+    # --- materializing select (positions to HBM) on the same resident columns
+    select_rows = []
+    for b in (8, 16, 32):
+        for sg in (1e-3, 0.1, 0.5):
+            hi = synth.lt_bound(sg, b)
+            ctx.select(cols_rm[b], 0, hi, zone_maps=False)  # warm-up (allocates the work space)
+            ts, cnt = [], 0
+            for _ in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                pos = ctx.select(cols_rm[b], 0, hi, zone_maps=False)
+                e1.record()
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1) * 1e-3)
+                cnt = int(pos.numel())
+                del pos
+            t = float(np.median(ts))
+            algo = N * b / 8 + 4 * cnt
+            select_rows.append({"b": b, "sigma": sg, "selected": cnt, "ms": round(t * 1e3, 4),
+                                "algorithmic_gb_per_s": round(algo / t / 1e9, 1),
+                                "f": round(algo / t / 1e9 / beta_gbs, 4)})
+    log("[bench] select: %s" % [(r["b"], r["sigma"], r["ms"]) for r in select_rows])
+
     # --- branch-free vs compaction crossover per width (needs the sigma sweep)
     crossover = None
     if len(sigmas) > 2:
@@ -615,6 +638,7 @@ def main():
                          "min_f_at_or_above_ridge": round(min(over_ridge), 4) if over_ridge else None},
         "law_fit_per_strategy": fits,
         "crossover_bf_sv": crossover,
+        "select": select_rows,
         "per_b": per_b,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -199,6 +199,31 @@ scan_status scan_autotune(scan_ctx* ctx, const scan_column* col, int32_t enc, ui
 scan_status scan_tune_save(scan_ctx* ctx, const char* path);
 scan_status scan_tune_load(scan_ctx* ctx, const char* path);
 
+/* ------------------------------------------------------ materializing select */
+/* The ascending positions (u32 row indices) of the rows with lo <= v < hi,
+ * written to positions (device, capacity entries) -- the materializing scan
+ * whose cost the paper's branch crossover concerns -- and late
+ * materialization on a position list.  Frame-of-reference (with or without
+ * block references) and dictionary columns, row-major, n < 2^32.
+ * flags: bit 0 zone maps (skip blocks that cannot match), bit 1 with bit 0 the
+ * all-match shortcut (a block inside the predicate writes its position range
+ * without being read).  Synchronous.  *n_selected (host) always receives the
+ * number of matches; if it exceeds capacity nothing is written and the call
+ * returns SCAN_ENOMEM (call again with a larger buffer).  Positions leave in
+ * row order (two passes: per-block counts, an exclusive scan, then the
+ * writes). */
+scan_status scan_select(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b, const scan_predicate* pred,
+                        uint32_t flags, uint32_t* positions, uint64_t capacity, uint64_t* n_selected);
+/* The positions of positions_in[0..n_in) (device, any order; a position >= n
+ * never passes) whose value in this column lies in [lo, hi), in input order, to positions_out (device, room
+ * for n_in); *n_out (host) receives how many.  Synchronous. */
+scan_status scan_refine(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b, const scan_predicate* pred,
+                        const uint32_t* positions_in, uint64_t n_in, uint32_t* positions_out, uint64_t* n_out);
+/* Decoded values at positions[0..n) into values (device int64; 0 for a
+ * position >= the column's n).  Synchronous. */
+scan_status scan_gather(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b, const uint32_t* positions,
+                        uint64_t n, int64_t* values);
+
 /* ---------------------------------------------------------------- batches */
 /* Many columns (mixed length, width, encoding, strategy) scanned by one
  * captured hipGraph: per-column setup, strategy selection on the device (the

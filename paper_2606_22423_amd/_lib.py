@@ -116,6 +116,9 @@ SIGNATURES = {
                              _P(ctypes.c_float)]),
     "scan_tune_save": (_i32, [_vp, ctypes.c_char_p]),
     "scan_tune_load": (_i32, [_vp, ctypes.c_char_p]),
+    "scan_select": (_i32, [_vp, _P(ScanColumn), _i32, _u32, _P(ScanPredicate), _u32, _vp, _u64, _P(_u64)]),
+    "scan_refine": (_i32, [_vp, _P(ScanColumn), _i32, _u32, _P(ScanPredicate), _vp, _u64, _vp, _P(_u64)]),
+    "scan_gather": (_i32, [_vp, _P(ScanColumn), _i32, _u32, _vp, _u64, _vp]),
     "scan_batch_prepare": (_i32, [_vp, _P(ScanItem), ctypes.c_size_t, _P(_u64)]),
     "scan_batch_replay": (_i32, [_vp, _u64, _P(ScanResult)]),
     "scan_batch_release": (_i32, [_vp, _u64]),

@@ -244,6 +244,43 @@ class Context:
     def tune_load(self, path: str):
         self.check(self.lib.scan_tune_load(self.h, path.encode()), "scan_tune_load")
 
+    # ------------------------------------------------ materializing select
+    def select(self, col: Column, lo: int, hi: int, zone_maps: bool = True, all_match: bool = True):
+        """Ascending positions (device uint32 tensor) of the rows with lo <= v < hi."""
+        import torch
+        c = col.struct(zone_maps)
+        pred = ScanPredicate(int(lo), int(hi))
+        flags = (1 if zone_maps and col.zmin is not None else 0)
+        flags |= 2 if flags and all_match and col.bsum is not None else 0
+        cnt = ctypes.c_uint64()
+        rc = self.lib.scan_select(self.h, ctypes.byref(c), col.enc, col.b, ctypes.byref(pred), flags, None, 0,
+                                  ctypes.byref(cnt))
+        if rc not in (0, _lib.SCAN_ENOMEM):
+            self.check(rc, "scan_select")
+        out = torch.empty(max(1, cnt.value), dtype=torch.int32, device="cuda")
+        if cnt.value:
+            self.check(self.lib.scan_select(self.h, ctypes.byref(c), col.enc, col.b, ctypes.byref(pred), flags,
+                                            _ptr(out), cnt.value, ctypes.byref(cnt)), "scan_select")
+        return out[:cnt.value]
+
+    def refine(self, col: Column, lo: int, hi: int, positions):
+        import torch
+        c = col.struct(False)
+        pred = ScanPredicate(int(lo), int(hi))
+        out = torch.empty(max(1, positions.numel()), dtype=torch.int32, device="cuda")
+        cnt = ctypes.c_uint64()
+        self.check(self.lib.scan_refine(self.h, ctypes.byref(c), col.enc, col.b, ctypes.byref(pred), _ptr(positions),
+                                        positions.numel(), _ptr(out), ctypes.byref(cnt)), "scan_refine")
+        return out[:cnt.value]
+
+    def gather(self, col: Column, positions):
+        import torch
+        c = col.struct(False)
+        out = torch.empty(max(1, positions.numel()), dtype=torch.int64, device="cuda")
+        self.check(self.lib.scan_gather(self.h, ctypes.byref(c), col.enc, col.b, _ptr(positions), positions.numel(),
+                                        _ptr(out)), "scan_gather")
+        return out[:positions.numel()]
+
     # ------------------------------------------------------------ batches
     @staticmethod
     def _items(items):

@@ -344,6 +344,7 @@ void scan_destroy(scan_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   destroy_batches(ctx);
   destroy_selector(ctx);
+  destroy_select(ctx);
   if (ctx->partials) (void)hipFree(ctx->partials);
   if (ctx->ticket) (void)hipFree(ctx->ticket);
   if (ctx->out_dev) (void)hipFree(ctx->out_dev);

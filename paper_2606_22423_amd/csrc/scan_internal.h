@@ -12,6 +12,7 @@
 
 struct SelectorState;
 struct BatchPlan;
+struct SelectWork;
 
 struct scan_ctx {
   int device = 0;
@@ -31,6 +32,7 @@ struct scan_ctx {
   SelectorState* selector = nullptr;
   std::map<uint64_t, BatchPlan*> batches;
   bool batch_kernels_loaded = false;  // batch graph kernels launched once outside capture
+  SelectWork* select = nullptr;       // materializing select work space
   uint64_t next_batch = 1;
 };
 
@@ -55,3 +57,6 @@ void destroy_selector(scan_ctx* ctx);
 
 // Batched scans (batch.cpp).
 void destroy_batches(scan_ctx* ctx);
+
+// Materializing select (select.cpp).
+void destroy_select(scan_ctx* ctx);

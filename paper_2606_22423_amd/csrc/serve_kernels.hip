@@ -1,52 +1,12 @@
 // Conjunctive multi-column query kernels (see serve_kernels.h).
 #include "device_common.h"
+#include "runtime_decode.h"
 #include "serve_kernels.h"
 
 namespace scan_dev {
 
 namespace {
-
-constexpr uint32_t kStageWords = 32u * 32u + 4u;  // one block of b <= 32, plus the funnel's spill word
 constexpr int kWavesPerWg = 4;
-
-__device__ __forceinline__ uint32_t lower_bound_global(const int64_t* d, uint32_t m, int64_t x) {
-  uint32_t lo = 0, e = m;
-  while (lo < e) {
-    const uint32_t mid = (lo + e) >> 1;
-    if (d[mid] < x) lo = mid + 1u;
-    else e = mid;
-  }
-  return lo;
-}
-
-// Block k of column c into the wavefront's LDS slot (16-byte loads).
-__device__ __forceinline__ void stage_block(uint32_t* st, const QCol& c, uint64_t k, uint32_t lane) {
-  const uint32_t words = 32u * c.b;
-  const uint4* src = reinterpret_cast<const uint4*>(c.payload + k * words);
-  uint4* dst = reinterpret_cast<uint4*>(st);
-  __builtin_amdgcn_wave_barrier();
-  for (uint32_t i = lane; i < words / 4u; i += 64u) dst[i] = src[i];
-  st[words] = 0u;  // every lane writes the same pad word
-  __builtin_amdgcn_wave_barrier();
-}
-
-// Code of value j = lane + 64 t of the staged block (width b at run time).
-struct Extract {
-  const uint32_t* sp;
-  uint32_t sh, mask, step;
-  __device__ __forceinline__ Extract(const uint32_t* st, uint32_t lane, uint32_t b) {
-    const uint32_t bit0 = lane * b;
-    sp = st + (bit0 >> 5);
-    sh = bit0 & 31u;
-    mask = b >= 32u ? 0xFFFFFFFFu : ((1u << b) - 1u);
-    step = 2u * b;  // words between t and t + 1
-  }
-  __device__ __forceinline__ uint32_t operator()(uint32_t t) const {
-    const uint32_t* w = sp + step * t;
-    return funnel(w[1], w[0], sh) & mask;
-  }
-};
-
 }  // namespace
 
 __global__ __launch_bounds__(256) void query_setup_kernel(QArgs a) {
@@ -74,7 +34,7 @@ __global__ __launch_bounds__(256) void query_setup_kernel(QArgs a) {
 }
 
 __global__ __launch_bounds__(256) void query_scan_kernel(const QArgs a) {
-  __shared__ __align__(16) uint32_t lds[kWavesPerWg][kStageWords];
+  __shared__ __align__(16) uint32_t lds[kWavesPerWg][kRtStageWords];
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
   uint32_t* st = lds[wave];
   while (true) {
@@ -119,7 +79,7 @@ __global__ __launch_bounds__(256) void query_scan_kernel(const QArgs a) {
           rows = 0u;
           break;
         }
-        stage_block(st, c, k, lane);
+        stage_rt_block(st, c.payload, c.b, k, lane);
         const Extract ex(st, lane, c.b);
         const uint32_t lo32 = (uint32_t)clo, wm1 = (uint32_t)(chi - clo - 1);
         uint32_t keep = 0;
@@ -130,7 +90,7 @@ __global__ __launch_bounds__(256) void query_scan_kernel(const QArgs a) {
       if (!ballot(rows != 0u)) continue;
       // the SUM column under the mask
       const QCol& s = a.cols[d.sum_col];
-      stage_block(st, s, k, lane);
+      stage_rt_block(st, s.payload, s.b, k, lane);
       const Extract ex(st, lane, s.b);
       const uint32_t nsel = (uint32_t)__builtin_popcount(rows);
       lcount += nsel;
