@@ -92,6 +92,10 @@ def _load():
             f.restype = ctypes.c_int64
         lib.orc_gather.argtypes = [i32, vp, vp, vp, u32, i32, vp, u64, vp]
         lib.orc_gather.restype = ctypes.c_int
+        lib.orc_rle_encode.argtypes = [vp, u64, vp, vp, vp]
+        lib.orc_rle_encode.restype = ctypes.c_int64
+        lib.orc_rle_decode.argtypes = [vp, vp, vp, u64, vp]
+        lib.orc_rle_decode.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -305,3 +309,25 @@ def gather(enc: int, payload, b: int, positions, refs=None, dct=None, layout: in
     _check(_load().orc_gather(enc, _ptr(payload), _ptr(refs), _ptr(dct), b, layout, _ptr(pos), len(pos), _ptr(out)),
            "gather")
     return out[:len(pos)]
+
+
+# ---------------------------------------------------------------- run length
+def rle_encode(values):
+    """(run values u32, run lengths u16, block run starts u64 [nb + 1]); runs stay inside 1024-value blocks."""
+    v = _u32(values)
+    n = len(v)
+    rv = np.zeros(max(n, 1), dtype=np.uint32)
+    rl = np.zeros(max(n, 1), dtype=np.uint16)
+    br = np.zeros(nblocks(n) + 1, dtype=np.uint64)
+    runs = _load().orc_rle_encode(_ptr(v), n, _ptr(rv), _ptr(rl), _ptr(br))
+    return rv[:runs].copy(), rl[:runs].copy(), br
+
+
+def rle_decode(rv, rl, br) -> np.ndarray:
+    rv, br = _u32(rv), np.ascontiguousarray(br, dtype=np.uint64)
+    rl = np.ascontiguousarray(rl, dtype=np.uint16)
+    nb = len(br) - 1
+    n = int(rl.astype(np.uint64).sum())
+    out = np.zeros(max(n, 1), dtype=np.uint32)
+    _check(_load().orc_rle_decode(_ptr(rv), _ptr(rl), _ptr(br), nb, _ptr(out)), "rle_decode")
+    return out[:n]

@@ -427,3 +427,36 @@ int orc_gather(int enc, const uint32_t* payload, const uint32_t* refs, const int
   for (uint64_t q = 0; q < m; q++) out[q] = value_at(enc, payload, refs, dict, pos[q], b, layout);
   return 0;
 }
+
+/* ------------------------------------------------------------- run length */
+
+/* Run-length encoding of a u32 column, block by block (runs never cross a
+ * 1024-value block): run r has value rv[r] and length rl[r] (1..1024);
+ * block k owns runs br[k] .. br[k+1]-1.  Returns the number of runs.  The
+ * arrays must hold n runs and nb + 1 block starts. */
+int64_t orc_rle_encode(const uint32_t* v, uint64_t n, uint32_t* rv, uint16_t* rl, uint64_t* br) {
+  uint64_t runs = 0, nb = nblocks(n);
+  for (uint64_t k = 0; k < nb; k++) {
+    br[k] = runs;
+    uint64_t a = k * ORC_L, e = (a + ORC_L < n) ? a + ORC_L : n;
+    for (uint64_t i = a; i < e; i++) {
+      if (i == a || v[i] != v[i - 1]) {
+        rv[runs] = v[i];
+        rl[runs] = 0;
+        runs++;
+      }
+      rl[runs - 1]++;
+    }
+  }
+  br[nb] = runs;
+  return (int64_t)runs;
+}
+
+/* Expand the runs back into values (the definition of the format). */
+int orc_rle_decode(const uint32_t* rv, const uint16_t* rl, const uint64_t* br, uint64_t nb, uint32_t* v) {
+  uint64_t i = 0;
+  for (uint64_t k = 0; k < nb; k++)
+    for (uint64_t r = br[k]; r < br[k + 1]; r++)
+      for (uint32_t t = 0; t < rl[r]; t++) v[i++] = rv[r];
+  return 0;
+}

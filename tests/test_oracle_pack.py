@@ -146,3 +146,23 @@ def test_dict_encode(rng):
     assert np.array_equal(oracle.dict_encode(dct[codes], dct), codes)
     with pytest.raises(ValueError):
         oracle.dict_encode(np.array([dct[0] - 1]), dct)
+
+
+def test_rle_round_trip_and_block_boundaries(rng):
+    """Run-length format: runs never cross a 1024-value block, the lengths of
+    a block sum to its value count, and decoding gives the values back."""
+    for n in (0, 1, 1023, 1024, 1025, 5000):
+        for v in (np.repeat(rng.integers(0, 50, size=n // 7 + 1), 7)[:n].astype(np.uint32),
+                  rng.integers(0, 3, size=n).astype(np.uint32), np.zeros(n, dtype=np.uint32)):
+            rv, rl, br = oracle.rle_encode(v)
+            nb = (n + 1023) // 1024
+            assert len(br) == nb + 1 and br[0] == 0 and br[-1] == len(rv)
+            for k in range(nb):
+                lens = rl[br[k]:br[k + 1]].astype(np.int64)
+                assert lens.sum() == min(1024, n - 1024 * k) and lens.min() >= 1
+                vals = rv[br[k]:br[k + 1]]
+                assert np.all(vals[1:] != vals[:-1])  # maximal runs inside a block
+            assert np.array_equal(oracle.rle_decode(rv, rl, br), v)
+    # a constant column has exactly one run per block
+    rv, rl, br = oracle.rle_encode(np.full(4096 + 3, 9, dtype=np.uint32))
+    assert len(rv) == 5 and list(rl) == [1024] * 4 + [3]
