@@ -202,10 +202,13 @@ def zonemap_leg(ctx, torch, n_log2, beta_gbs, reps=5):
     out = torch.zeros(8, dtype=torch.int64, device="cuda")
     rows, want = [], {}
     t0 = time.time()
+    rle_rows = []
     for lvl in (0, 16, 1024, 65536, "random"):
         vals = synth.config3_column(n, s=lvl, device="cuda")
-        col = api.encode_for(vals.cpu().numpy().view(np.uint32), 16)
-        del vals
+        host_vals = vals.cpu().numpy().view(np.uint32)
+        col = api.encode_for(host_vals, 16)
+        rle = api.encode_rle(host_vals)
+        del vals, host_vals
         for sg, (lo, hi) in zip(sigmas, preds):
             for zm, am in ((1, 1), (1, 0), (0, 0)):
                 s = strategy(DEC_RM_DIRECT, 0, zm, am)
@@ -237,6 +240,26 @@ def zonemap_leg(ctx, torch, n_log2, beta_gbs, reps=5):
                              "logical_gvalues_per_s": round(n / t / 1e9, 1),
                              "decoded_gvalues_per_s": round(r["blocks_read"] * 1024 / t / 1e9, 1),
                              "f_on_bytes_read": round(read_bytes / t / 1e9 / beta_gbs, 4)})
+        # run-length encoded copy of the same column: bytes = 6 per run + 8 per block
+        rle_bytes = rle.runs * 6 + (nb + 1) * 8
+        for sg, (lo, hi) in zip(sigmas, preds):
+            for zm in (1, 0):
+                r = ctx.run_rle(rle, lo, hi, zone_maps=bool(zm), all_match=bool(zm))
+                if (r["count"], r["sum"]) != want[(lo, hi)]:
+                    raise RuntimeError("run-length scan differs from the bit-packed scan at %s" % ((lvl, lo, hi),))
+                ts = []
+                for _ in range(reps):
+                    ctx.cache_flush(evict, evict.numel() * 4)
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    ctx.run_rle(rle, lo, hi, zone_maps=bool(zm), all_match=bool(zm))
+                    e1.record()
+                    e1.synchronize()
+                    ts.append(e0.elapsed_time(e1) * 1e-3)
+                rle_rows.append({"s": lvl, "sigma": sg, "zone_maps_all_match": bool(zm),
+                                 "ms": round(float(np.median(ts)) * 1e3, 4), "runs": rle.runs,
+                                 "bytes": int(rle_bytes), "blocks_read_frac": round(r["blocks_read"] / nb, 6)})
+        del rle
         del col
         log("[bench] zone maps: level %s done" % lvl)
     log("[bench] zone-map workload in %.0f s" % (time.time() - t0))
@@ -247,8 +270,10 @@ def zonemap_leg(ctx, torch, n_log2, beta_gbs, reps=5):
     for lvl in (0, 16, 1024, 65536, "random"):
         d = [r["blocks_read_frac"] - r["sigma"] for r in rows if r["s"] == lvl and r["zone_maps"] and not r["all_match"]]
         model[str(lvl)] = round(float(np.median(d)), 6)
-    return {"read_fraction_minus_sigma": model,"workload": "N=2^%d values at b=16, sorted base displaced by s in {0,2^4,2^10,2^16} ranks or random, "
-                        "[lo, lo+round(sigma 2^16)), zone maps on vs off, cold cache, median of %d" % (n_log2, reps),
+    return {"read_fraction_minus_sigma": model, "rle": rle_rows,
+            "workload": "N=2^%d values at b=16, sorted base displaced by s in {0,2^4,2^10,2^16} ranks or random, "
+                        "[lo, lo+round(sigma 2^16)), zone maps (+ all-match) vs off, bit-packed and run-length "
+                        "copies, cold cache, median of %d" % (n_log2, reps),
             "identical_across_levels_and_zone_maps": True, "sorted_closed_forms": True, "points": rows}
 
 

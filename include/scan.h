@@ -199,6 +199,26 @@ scan_status scan_autotune(scan_ctx* ctx, const scan_column* col, int32_t enc, ui
 scan_status scan_tune_save(scan_ctx* ctx, const char* path);
 scan_status scan_tune_load(scan_ctx* ctx, const char* path);
 
+/* ------------------------------------------------------------- run length */
+/* Run-length encoded u32 column: runs never cross a 1024-value block; run r
+ * has value run_value[r] and length run_len[r] (1..1024); block k owns runs
+ * block_run[k] .. block_run[k+1]-1.  The scan tests the predicate once per run
+ * and adds the run's length to COUNT and value x length to SUM (mod 2^64). */
+typedef struct {
+  const uint32_t* run_value;  /* device */
+  const uint16_t* run_len;    /* device */
+  const uint64_t* block_run;  /* device: nb + 1 entries */
+  const uint32_t* zone_min;   /* device: per-block min / max of the values, or NULL */
+  const uint32_t* zone_max;
+  uint64_t n;                 /* values (sum of the run lengths) */
+} scan_rle_column;
+
+/* Synchronous scan; flags: bit 0 zone maps, bit 1 with bit 0 the all-match
+ * shortcut (a block inside the predicate is taken whole).  Same result
+ * contract as scan_run; strategy_used reports the flags. */
+scan_status scan_run_rle(scan_ctx* ctx, const scan_rle_column* col, const scan_predicate* pred, uint32_t flags,
+                         scan_result* out);
+
 /* ------------------------------------------------------ materializing select */
 /* The ascending positions (u32 row indices) of the rows with lo <= v < hi,
  * written to positions (device, capacity entries) -- the materializing scan
@@ -398,6 +418,11 @@ scan_status scan_encode_delta(const int64_t* values, uint64_t n, uint32_t b, uin
 /* DICT: codes (indices into a dictionary of dict_len entries) packed row-major. */
 scan_status scan_encode_dict(const uint32_t* codes, uint64_t n, uint32_t b, uint32_t dict_len,
                              uint32_t* payload, uint32_t* zone_min, uint32_t* zone_max);
+/* Run-length encoder (host pointers): run_value / run_len hold up to n runs,
+ * block_run nb + 1 entries, zone_min / zone_max nb entries (may be NULL);
+ * *n_runs receives the number of runs. */
+scan_status scan_rle_encode(const uint32_t* values, uint64_t n, uint32_t* run_value, uint16_t* run_len,
+                            uint64_t* block_run, uint32_t* zone_min, uint32_t* zone_max, uint64_t* n_runs);
 /* Per-block sums of decoded values mod 2^64 (host pointers; out has nb
  * entries) for scan_column.block_sum: enc SCAN_ENC_FOR takes u32 values,
  * SCAN_ENC_DELTA_FOR int64 values, SCAN_ENC_DICT u32 codes and the dictionary

@@ -71,6 +71,11 @@ class ScanTune(ctypes.Structure):
                 ("window_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class ScanRleColumn(ctypes.Structure):
+    _fields_ = [("run_value", ctypes.c_void_p), ("run_len", ctypes.c_void_p), ("block_run", ctypes.c_void_p),
+                ("zone_min", ctypes.c_void_p), ("zone_max", ctypes.c_void_p), ("n", ctypes.c_uint64)]
+
+
 class ScanTableColumn(ctypes.Structure):
     _fields_ = [("col", ScanColumn), ("enc", ctypes.c_int32), ("b", ctypes.c_uint32)]
 
@@ -116,6 +121,8 @@ SIGNATURES = {
                              _P(ctypes.c_float)]),
     "scan_tune_save": (_i32, [_vp, ctypes.c_char_p]),
     "scan_tune_load": (_i32, [_vp, ctypes.c_char_p]),
+    "scan_run_rle": (_i32, [_vp, _P(ScanRleColumn), _P(ScanPredicate), _u32, _P(ScanResult)]),
+    "scan_rle_encode": (_i32, [_vp, _u64, _vp, _vp, _vp, _vp, _vp, _P(_u64)]),
     "scan_select": (_i32, [_vp, _P(ScanColumn), _i32, _u32, _P(ScanPredicate), _u32, _vp, _u64, _P(_u64)]),
     "scan_refine": (_i32, [_vp, _P(ScanColumn), _i32, _u32, _P(ScanPredicate), _vp, _u64, _vp, _P(_u64)]),
     "scan_gather": (_i32, [_vp, _P(ScanColumn), _i32, _u32, _vp, _u64, _vp]),

@@ -165,6 +165,54 @@ def encode_dict(codes, b: int, dct, device="cuda", block_sums: bool = True) -> C
                   zmin=_to_dev(zmin, device), zmax=_to_dev(zmax, device), bsum=_to_dev(bs, device))
 
 
+@dataclass
+class RleColumn:
+    """A run-length encoded u32 column in device memory."""
+    n: int
+    run_value: object
+    run_len: object
+    block_run: object
+    zmin: object = None
+    zmax: object = None
+
+    @property
+    def runs(self) -> int:
+        return int(self.run_value.numel())
+
+    def struct(self, zone_maps: bool = True) -> "_lib.ScanRleColumn":
+        c = _lib.ScanRleColumn()
+        c.run_value = _ptr(self.run_value)
+        c.run_len = _ptr(self.run_len)
+        c.block_run = _ptr(self.block_run)
+        c.zone_min = _ptr(self.zmin) if zone_maps else None
+        c.zone_max = _ptr(self.zmax) if zone_maps else None
+        c.n = self.n
+        return c
+
+
+def host_encode_rle(values):
+    """(run values, run lengths, block run starts, zmin, zmax) by the library's host encoder."""
+    lib = _lib.load()
+    v = np.ascontiguousarray(values, dtype=np.uint32)
+    n = len(v)
+    rv = np.empty(max(n, 1), dtype=np.uint32)
+    rl = np.empty(max(n, 1), dtype=np.uint16)
+    br = np.empty(nblocks(n) + 1, dtype=np.uint64)
+    zmin = np.empty(max(nblocks(n), 1), dtype=np.uint32)
+    zmax = np.empty(max(nblocks(n), 1), dtype=np.uint32)
+    runs = ctypes.c_uint64()
+    _check(lib.scan_rle_encode(_ptr(v), n, _ptr(rv), _ptr(rl), _ptr(br), _ptr(zmin), _ptr(zmax), ctypes.byref(runs)),
+           "scan_rle_encode")
+    r = runs.value
+    return rv[:r], rl[:r], br, zmin[:nblocks(n)], zmax[:nblocks(n)]
+
+
+def encode_rle(values, device="cuda") -> RleColumn:
+    rv, rl, br, zmin, zmax = host_encode_rle(values)
+    return RleColumn(len(values), _to_dev(rv.view(np.int32), device), _to_dev(rl.view(np.int16), device),
+                     _to_dev(br.view(np.int64), device), _to_dev(zmin, device), _to_dev(zmax, device))
+
+
 # --------------------------------------------------------------- context
 class Context:
     """One scan_ctx bound to a device and to torch's current stream on it."""
@@ -243,6 +291,16 @@ class Context:
 
     def tune_load(self, path: str):
         self.check(self.lib.scan_tune_load(self.h, path.encode()), "scan_tune_load")
+
+    def run_rle(self, col: RleColumn, lo: int, hi: int, zone_maps: bool = True, all_match: bool = True) -> dict:
+        c = col.struct(zone_maps)
+        flags = (1 if zone_maps and col.zmin is not None else 0)
+        flags |= 2 if flags and all_match else 0
+        r = ScanResult()
+        pred = ScanPredicate(int(lo), int(hi))
+        self.check(self.lib.scan_run_rle(self.h, ctypes.byref(c), ctypes.byref(pred), flags, ctypes.byref(r)),
+                   "scan_run_rle")
+        return r.as_dict()
 
     # ------------------------------------------------ materializing select
     def select(self, col: Column, lo: int, hi: int, zone_maps: bool = True, all_match: bool = True):

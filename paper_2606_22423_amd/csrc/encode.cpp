@@ -178,4 +178,45 @@ scan_status scan_block_sums(int32_t enc, const void* values, uint64_t n, const i
   return ok ? SCAN_OK : SCAN_EINVAL;
 }
 
+scan_status scan_rle_encode(const uint32_t* values, uint64_t n, uint32_t* run_value, uint16_t* run_len,
+                            uint64_t* block_run, uint32_t* zone_min, uint32_t* zone_max, uint64_t* n_runs) {
+  if (!n_runs || !block_run || (n && (!values || !run_value || !run_len))) return SCAN_EINVAL;
+  const uint64_t nb = blocks_of(n);
+  // pass 1: runs per block (in parallel), then block starts; pass 2: the runs
+  std::vector<uint64_t> per(nb + 1, 0);
+  parallel_blocks(nb, [&](uint64_t k) {
+    const uint64_t a = k * 1024ull, e = std::min<uint64_t>(n, a + 1024ull);
+    uint64_t r = 0;
+    for (uint64_t i = a; i < e; ++i) r += (i == a || values[i] != values[i - 1]) ? 1u : 0u;
+    per[k] = r;
+    return true;
+  });
+  uint64_t acc = 0;
+  for (uint64_t k = 0; k < nb; ++k) {
+    block_run[k] = acc;
+    acc += per[k];
+  }
+  block_run[nb] = acc;
+  *n_runs = acc;
+  parallel_blocks(nb, [&](uint64_t k) {
+    const uint64_t a = k * 1024ull, e = std::min<uint64_t>(n, a + 1024ull);
+    uint64_t r = block_run[k];
+    uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+    for (uint64_t i = a; i < e; ++i) {
+      if (i == a || values[i] != values[i - 1]) {
+        run_value[r] = values[i];
+        run_len[r] = 0;
+        ++r;
+      }
+      ++run_len[r - 1];
+      mn = std::min(mn, values[i]);
+      mx = std::max(mx, values[i]);
+    }
+    if (zone_min) zone_min[k] = mn;
+    if (zone_max) zone_max[k] = mx;
+    return true;
+  });
+  return SCAN_OK;
+}
+
 }  // extern "C"

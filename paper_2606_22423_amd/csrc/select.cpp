@@ -144,10 +144,10 @@ scan_status scan_select(scan_ctx* ctx, const scan_column* col, int32_t enc, uint
   const uint64_t total = *ctx->select->host_total;
   *n_selected = total;
   if (total == 0) return SCAN_OK;
-  if (!positions) return fail(ctx, SCAN_EINVAL, "positions must not be NULL");
   if (total > capacity)
     return fail(ctx, SCAN_ENOMEM, "%llu positions selected, capacity %llu", (unsigned long long)total,
                 (unsigned long long)capacity);
+  if (!positions) return fail(ctx, SCAN_EINVAL, "positions must not be NULL");
   e = launch_select_write(p, positions, grid, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   return e == hipSuccess ? SCAN_OK : hip_fail(ctx, e, "select write");

@@ -103,3 +103,16 @@ def test_block_sums_match_numpy(rng):
         assert api.host_block_sums(api.ENC_DICT, codes, dct).tolist() == want
     with pytest.raises(_lib.ScanError):
         api.host_block_sums(api.ENC_DICT, np.array([0, 300], dtype=np.uint32), np.arange(300, dtype=np.int64))
+
+
+def test_rle_encoder_matches_oracle(rng):
+    """The library's run-length encoder and the oracle's give identical arrays."""
+    for n in (0, 1, 1023, 1025, 6000):
+        for v in (np.repeat(rng.integers(0, 100, size=n // 5 + 1), 5)[:n].astype(np.uint32),
+                  rng.integers(0, 2, size=n).astype(np.uint32)):
+            rv, rl, br, zmin, zmax = api.host_encode_rle(v)
+            orv, orl, obr = oracle.rle_encode(v)
+            assert np.array_equal(rv, orv) and np.array_equal(rl, orl) and np.array_equal(br, obr)
+            if n:
+                omin, omax = oracle.zonemap_u32(v)
+                assert np.array_equal(zmin, omin) and np.array_equal(zmax, omax)
