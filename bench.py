@@ -557,15 +557,16 @@ def main():
 
     # --- materializing select (positions to HBM) on the same resident columns
     select_rows = []
+    sel_out = torch.empty(N, dtype=torch.int32, device="cuda")  # capacity n: one call, one wait
     for b in (8, 16, 32):
         for sg in (1e-3, 0.1, 0.5):
             hi = synth.lt_bound(sg, b)
-            ctx.select(cols_rm[b], 0, hi, zone_maps=False)  # warm-up (allocates the work space)
+            ctx.select(cols_rm[b], 0, hi, zone_maps=False, out=sel_out)  # warm-up (allocates the work space)
             ts, cnt = [], 0
             for _ in range(3):
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record()
-                pos = ctx.select(cols_rm[b], 0, hi, zone_maps=False)
+                pos = ctx.select(cols_rm[b], 0, hi, zone_maps=False, out=sel_out)
                 e1.record()
                 e1.synchronize()
                 ts.append(e0.elapsed_time(e1) * 1e-3)
@@ -576,6 +577,7 @@ def main():
             select_rows.append({"b": b, "sigma": sg, "selected": cnt, "ms": round(t * 1e3, 4),
                                 "algorithmic_gb_per_s": round(algo / t / 1e9, 1),
                                 "f": round(algo / t / 1e9 / beta_gbs, 4)})
+    del sel_out
     log("[bench] select: %s" % [(r["b"], r["sigma"], r["ms"]) for r in select_rows])
 
     # --- branch-free vs compaction crossover per width (needs the sigma sweep)

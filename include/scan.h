@@ -229,9 +229,11 @@ scan_status scan_run_rle(scan_ctx* ctx, const scan_rle_column* col, const scan_p
  * all-match shortcut (a block inside the predicate writes its position range
  * without being read).  Synchronous.  *n_selected (host) always receives the
  * number of matches; if it exceeds capacity nothing is written and the call
- * returns SCAN_ENOMEM (call again with a larger buffer).  Positions leave in
- * row order (two passes: per-block counts, an exclusive scan, then the
- * writes). */
+ * returns SCAN_ENOMEM (call again with a larger buffer).  With capacity >= n
+ * the buffer holds any outcome and the passes run back to back with one wait
+ * at the end; otherwise the call waits for the count before writing.
+ * Positions leave in row order (two passes: per-block counts, an exclusive
+ * scan, then the writes). */
 scan_status scan_select(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b, const scan_predicate* pred,
                         uint32_t flags, uint32_t* positions, uint64_t capacity, uint64_t* n_selected);
 /* The positions of positions_in[0..n_in) (device, any order; a position >= n

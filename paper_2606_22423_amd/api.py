@@ -303,14 +303,26 @@ class Context:
         return r.as_dict()
 
     # ------------------------------------------------ materializing select
-    def select(self, col: Column, lo: int, hi: int, zone_maps: bool = True, all_match: bool = True):
-        """Ascending positions (device uint32 tensor) of the rows with lo <= v < hi."""
+    def select(self, col: Column, lo: int, hi: int, zone_maps: bool = True, all_match: bool = True,
+               out=None):
+        """Ascending positions (device uint32 tensor) of the rows with lo <= v < hi.
+
+        With `out` (a device int32 tensor of at least col.n entries, reused
+        across calls) the count and the writes run in one call with a single
+        wait; without it the matches are counted first and a buffer of that
+        size is allocated."""
         import torch
         c = col.struct(zone_maps)
         pred = ScanPredicate(int(lo), int(hi))
         flags = (1 if zone_maps and col.zmin is not None else 0)
         flags |= 2 if flags and all_match and col.bsum is not None else 0
         cnt = ctypes.c_uint64()
+        if out is not None:
+            if out.dtype != torch.int32 or not out.is_cuda or out.numel() < col.n:
+                raise ValueError("out must be a device int32 tensor of at least %d entries" % col.n)
+            self.check(self.lib.scan_select(self.h, ctypes.byref(c), col.enc, col.b, ctypes.byref(pred), flags,
+                                            _ptr(out), out.numel(), ctypes.byref(cnt)), "scan_select")
+            return out[:cnt.value]
         rc = self.lib.scan_select(self.h, ctypes.byref(c), col.enc, col.b, ctypes.byref(pred), flags, None, 0,
                                   ctypes.byref(cnt))
         if rc not in (0, _lib.SCAN_ENOMEM):

@@ -21,7 +21,7 @@ struct SelectWork {
 namespace {
 
 // Work-space layout for `m` counted units (blocks or chunks of positions):
-// [zrange 2 x i64][total u32 + pad][counts m][offsets m][tile sums][ballots 16 per unit when refining]
+// [zrange 2 x i64][total u32 + pad][counts m][offsets m][tile sums][ballots 16 per unit]
 struct WsLayout {
   int64_t* zrange;
   uint32_t* total;
@@ -91,6 +91,7 @@ SelParams make_params(const scan_column* col, int32_t enc, uint32_t b, const sca
   p.zmin = static_cast<const uint32_t*>(col->zone_min);
   p.zmax = static_cast<const uint32_t*>(col->zone_max);
   p.zrange = L.zrange;
+  p.marks = L.ballots;
   p.counts = L.counts;
   p.offsets = L.offsets;
   p.n = col->n;
@@ -130,13 +131,23 @@ scan_status scan_select(scan_ctx* ctx, const scan_column* col, int32_t enc, uint
   if (col->n == 0 || pred->lo >= pred->hi) return SCAN_OK;
   const uint64_t nb = (col->n + SCAN_BLOCK_VALUES - 1) / SCAN_BLOCK_VALUES;
   WsLayout L;
-  st = get_ws(ctx, nb, false, L);
+  st = get_ws(ctx, nb, true, L);  // 16 pass ballots per block
   if (st != SCAN_OK) return st;
   const SelParams p = make_params(col, enc, b, pred, zm, am, L);
   const uint32_t grid = (uint32_t)ctx->cus * 8u;
   hipError_t e = launch_select_setup(p, L.zrange, ctx->stream);
-  if (e == hipSuccess) e = launch_select_count(p, grid, ctx->stream);
+  if (e == hipSuccess) e = launch_select_mark(p, grid, ctx->stream);
   if (e == hipSuccess) e = launch_exclusive_scan(L.counts, nb, L.offsets, L.tiles, L.total, ctx->stream);
+  if (positions && capacity >= col->n) {
+    // every outcome fits: write without waiting for the count
+    if (e == hipSuccess) e = launch_select_write(p, positions, grid, ctx->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(ctx->select->host_total, L.total, 4, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "select");
+    *n_selected = *ctx->select->host_total;
+    return SCAN_OK;
+  }
   if (e == hipSuccess)
     e = hipMemcpyAsync(ctx->select->host_total, L.total, 4, hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);

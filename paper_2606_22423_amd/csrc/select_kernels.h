@@ -15,6 +15,7 @@ struct SelParams {
   const uint32_t* zmin;    // zone maps (values / codes), or null
   const uint32_t* zmax;
   const int64_t* zrange;   // device: the predicate in the zone-map / code domain (written by setup)
+  uint64_t* marks;         // select: 16 pass ballots per block (bit l of word t: value l + 64 t)
   uint32_t* counts;        // per block (select) or per chunk of positions (refine)
   uint32_t* offsets;       // exclusive prefix of counts
   uint64_t n, nb;
@@ -23,7 +24,7 @@ struct SelParams {
 };
 
 hipError_t launch_select_setup(const SelParams& p, int64_t* zrange, hipStream_t st);
-hipError_t launch_select_count(const SelParams& p, uint32_t grid, hipStream_t st);
+hipError_t launch_select_mark(const SelParams& p, uint32_t grid, hipStream_t st);
 hipError_t launch_exclusive_scan(const uint32_t* in, uint64_t m, uint32_t* out, uint32_t* tile_sums,
                                  uint32_t* total, hipStream_t st);
 hipError_t launch_select_write(const SelParams& p, uint32_t* positions, uint32_t grid, hipStream_t st);

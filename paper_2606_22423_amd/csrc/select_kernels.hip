@@ -3,49 +3,48 @@
 // list (refine by another column's predicate, gather values).
 //
 // Select runs in three steps so that the output order is the row order:
-//  1. count: every wavefront takes blocks k = w, w + W, ... (W wavefronts),
-//     tests the zone map, stages and decodes the block (values j = lane + 64 t)
-//     and stores the block's match count;
+//  1. mark (one kernel per width b): every wavefront takes groups of
+//     G = max(1, 32 / b) consecutive blocks (at most 4 KB of words), groups
+//     g = w, w + W, ... (W wavefronts); it tests the zone maps, stages the
+//     blocks that need decoding in LDS, decodes them (values j = lane + 64 t)
+//     and stores each block's 16 pass ballots (one bit per value, 128 bytes)
+//     and match count.  The next group's words are in flight in registers
+//     while the current group decodes from LDS, and the zone maps and block
+//     references arrive one group further ahead, so no load waits in the
+//     steady state;
 //  2. an exclusive scan of the counts gives each block its output offset
 //     (tiles of 1024 counts per work-group, one work-group over the tile
 //     totals, then the tile offsets added back);
-//  3. write: blocks with matches are decoded again and the matches of step t
-//     are compacted with ballot + mbcnt at offset + (matches of steps < t),
-//     so positions leave in ascending order.  A block entirely inside the
-//     predicate (all-match, with zone maps) writes its position range without
-//     being read.
+//  3. write: groups of 16 consecutive blocks per wavefront; the ballots of the
+//     group's blocks with matches arrive in one round of loads, each nonzero
+//     ballot gets its output offset (the block's offset plus a prefix sum of
+//     the popcounts of the block's earlier steps) and its matches leave with
+//     mbcnt, so every position lands at its rank in row order.  The payload
+//     is not read again.
+//     A block entirely inside the predicate (all-match, with zone maps) has
+//     no ballots: its position range is written without being read.
 // Work loops use a wave-uniform block index (readfirstlane), so their
 // control flow is the same in every lane.
 #include "device_common.h"
 #include "runtime_decode.h"
 #include "select_kernels.h"
 
+#include <utility>
+
 namespace scan_dev {
 
 namespace {
 
 constexpr int kSelWaves = 4;
+constexpr uint32_t kWriteGroup = 16;  // blocks per wavefront step of the write pass
 
-// Code-space window [clo, chi) of block k (FOR: minus the block reference,
-// clipped to [0, 2^b); dictionary: the code range itself).
+// The predicate in the zone-map / code domain, as written by the setup kernel.
 struct ZRange {
-  int64_t lo, hi;  // the predicate in the zone-map / code domain
+  int64_t lo, hi;
 };
 
 __device__ __forceinline__ ZRange load_range(const SelParams& p) {
   return ZRange{p.zrange[0], p.zrange[1]};
-}
-
-__device__ __forceinline__ void block_code_range(const SelParams& p, const ZRange& zr, uint64_t k, int64_t& clo,
-                                                 int64_t& chi) {
-  clo = zr.lo;
-  chi = zr.hi;
-  if (p.enc != ENC_DICT) {
-    const int64_t ref = p.refs ? (int64_t)p.refs[k] : 0;
-    const int64_t top = int64_t(1) << p.b;
-    clo = clo - ref > 0 ? clo - ref : 0;
-    chi = chi - ref < top ? chi - ref : top;
-  }
 }
 
 // 0: skip the block, 1: decode it, 2: every valid value matches (all-match).
@@ -58,48 +57,162 @@ __device__ __forceinline__ int block_class(const SelParams& p, const ZRange& zr,
   return 1;
 }
 
-__device__ __forceinline__ uint32_t block_valid(const SelParams& p, uint64_t k) {
-  return k == p.nb - 1 ? (uint32_t)(p.n - k * kBlockValues) : kBlockValues;
+// Pass ballots of a staged block (b = B, `valid` values) for the code window
+// [clo, chi): lane t < 16 receives the ballot of step t (bit l: value l + 64 t
+// passes), `cnt` (uniform) the number of passing values.
+template <uint32_t B>
+__device__ __forceinline__ uint64_t block_marks(int64_t clo, int64_t chi, const uint32_t* st, uint32_t valid,
+                                                uint32_t lane, uint32_t& cnt) {
+  cnt = 0;
+  if (clo >= chi) return 0;
+  const Extract ex(st, lane, B);
+  const uint32_t lo32 = (uint32_t)clo, wm1 = (uint32_t)(chi - clo - 1);
+  uint64_t mine = 0;
+  if (valid == kBlockValues) {
+#pragma unroll
+    for (uint32_t t = 0; t < 16u; ++t) {
+      const uint64_t m = ballot((ex(t) - lo32) <= wm1);
+      mine = lane == t ? m : mine;
+      cnt += (uint32_t)__builtin_popcountll(m);
+    }
+  } else {
+#pragma unroll
+    for (uint32_t t = 0; t < 16u; ++t) {
+      const uint64_t m = ballot(((ex(t) - lo32) <= wm1) && (lane + 64u * t < valid));
+      mine = lane == t ? m : mine;
+      cnt += (uint32_t)__builtin_popcountll(m);
+    }
+  }
+  return mine;
 }
 
-// Pass bits of the staged block: bit t of the result is value lane + 64 t.
-__device__ __forceinline__ uint32_t block_pass_bits(const SelParams& p, const ZRange& zr, const uint32_t* st,
-                                                    uint64_t k, uint32_t lane) {
-  int64_t clo, chi;
-  block_code_range(p, zr, k, clo, chi);
-  if (clo >= chi) return 0u;
-  const uint32_t valid = block_valid(p, k);
-  const Extract ex(st, lane, p.b);
-  const uint32_t lo32 = (uint32_t)clo, wm1 = (uint32_t)(chi - clo - 1);
-  uint32_t bits = 0;
-#pragma unroll
-  for (uint32_t t = 0; t < 16u; ++t) {
-    const bool ok = ((ex(t) - lo32) <= wm1) && (lane + 64u * t < valid);
-    bits |= ok ? (1u << t) : 0u;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Group geometry of the mark pass for width B.
+template <uint32_t B>
+struct MarkGroup {
+  static constexpr uint32_t kBlocks = B >= 32u ? 1u : 32u / B;      // G
+  static constexpr uint32_t kWords = 32u * B;                       // words per block
+  static constexpr uint32_t kPiecesPerBlock = 8u * B;               // 16-byte pieces per block
+  static constexpr uint32_t kPieces = kBlocks * kPiecesPerBlock;    // at most 256
+};
+
+// Zone maps and reference of one group's blocks: lane j < G holds block
+// k0 + j's (loads issued by `issue`, consumed later by `classify` and the
+// decode).
+struct GroupInfo {
+  uint32_t zmn, zmx, ref;
+  __device__ __forceinline__ void issue(const SelParams& p, uint64_t k0, uint32_t G, uint32_t lane) {
+    const uint64_t k = k0 + lane;
+    const bool in = lane < G && k < p.nb;
+    zmn = in && p.use_zm ? p.zmin[k] : 0u;
+    zmx = in && p.use_zm ? p.zmax[k] : 0u;
+    ref = in && p.refs ? p.refs[k] : 0u;
   }
-  return bits;
+  // 0: skip, 1: decode, 2: all-match (lanes past the group or the column: 0)
+  __device__ __forceinline__ uint32_t classify(const SelParams& p, const ZRange& zr, uint64_t k0, uint32_t G,
+                                               uint32_t lane) const {
+    if (!(lane < G && k0 + lane < p.nb) || zr.lo >= zr.hi) return 0u;
+    if (!p.use_zm) return 1u;
+    if ((int64_t)zmx < zr.lo || (int64_t)zmn >= zr.hi) return 0u;
+    if (p.use_am && (int64_t)zmn >= zr.lo && (int64_t)zmx < zr.hi) return 2u;
+    return 1u;
+  }
+};
+
+// A group's words in registers: lane takes 16-byte pieces lane + 64 q, only
+// those of blocks whose bit is set in `need` (pieces of other blocks are
+// neither loaded nor staged).  A native vector type, so that the copies stay
+// register moves (HIP's uint4 is a struct copied by memcpy).
+template <uint32_t B>
+struct GroupRegs {
+  using Geo = MarkGroup<B>;
+  u32x4 r0, r1, r2, r3;
+  __device__ __forceinline__ static bool has(uint32_t need, uint32_t q) {
+    return q < Geo::kPieces && ((need >> (q / Geo::kPiecesPerBlock)) & 1u);
+  }
+  __device__ __forceinline__ void load(const SelParams& p, uint64_t k0, uint32_t need, uint32_t lane) {
+    const u32x4* src = reinterpret_cast<const u32x4*>(p.payload + k0 * Geo::kWords);
+    if (has(need, lane)) r0 = src[lane];
+    if (Geo::kPieces > 64u && has(need, lane + 64u)) r1 = src[lane + 64u];
+    if (Geo::kPieces > 128u && has(need, lane + 128u)) r2 = src[lane + 128u];
+    if (Geo::kPieces > 192u && has(need, lane + 192u)) r3 = src[lane + 192u];
+  }
+  __device__ __forceinline__ void store(uint32_t* st, uint32_t need, uint32_t lane) const {
+    u32x4* dst = reinterpret_cast<u32x4*>(st);
+    __builtin_amdgcn_wave_barrier();
+    if (has(need, lane)) dst[lane] = r0;
+    if (Geo::kPieces > 64u && has(need, lane + 64u)) dst[lane + 64u] = r1;
+    if (Geo::kPieces > 128u && has(need, lane + 128u)) dst[lane + 128u] = r2;
+    if (Geo::kPieces > 192u && has(need, lane + 192u)) dst[lane + 192u] = r3;
+    st[Geo::kBlocks * Geo::kWords] = 0u;  // the funnel's spill word; every lane writes the same value
+    __builtin_amdgcn_wave_barrier();
+  }
+};
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, uint32_t l) {
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, l);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(x >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
 }
 
 }  // namespace
 
-__global__ __launch_bounds__(256) void select_count_kernel(const SelParams p) {
+template <uint32_t B>
+__global__ __launch_bounds__(256) void select_mark_kernel(const SelParams p) {
+  using Geo = MarkGroup<B>;
+  constexpr uint32_t G = Geo::kBlocks;
   __shared__ __align__(16) uint32_t lds[kSelWaves][kRtStageWords];
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   uint32_t* st = lds[wave];
   const ZRange zr = load_range(p);
+  const uint64_t ng = (p.nb + G - 1) / G;
   const uint64_t tw = (uint64_t)gridDim.x * kSelWaves;
-  for (uint64_t k = (uint64_t)blockIdx.x * kSelWaves + wave; k < p.nb; k += tw) {
-    const int cls = block_class(p, zr, k);
-    uint32_t cnt = 0;
-    if (cls == 2) {
-      cnt = block_valid(p, k);
-    } else if (cls == 1) {
-      stage_rt_block(st, p.payload, p.b, k, lane);
-      const uint32_t bits = block_pass_bits(p, zr, st, k, lane);
-      cnt = (uint32_t)wave_sum_u64(__builtin_popcount(bits));
+  const int64_t top = int64_t(1) << B;
+  uint64_t g = (uint64_t)blockIdx.x * kSelWaves + wave;
+  if (g >= ng) return;
+  GroupRegs<B> regs;
+  GroupInfo cur, nxt;
+  cur.issue(p, g * G, G, lane);
+  uint32_t cls = cur.classify(p, zr, g * G, G, lane);
+  uint32_t need = (uint32_t)ballot(cls == 1u);
+  if (need) regs.load(p, g * G, need, lane);
+  nxt.issue(p, (g + tw) * G, G, lane);
+  // Vector loads retire in order: a group's words are issued before the zone
+  // maps of the group after it, and whatever a group's decode needs was loaded
+  // an iteration earlier, so the waits below are for loads long in flight.
+  for (; g < ng; g += tw) {
+    regs.store(st, need, lane);
+    const uint64_t k0 = g * G;
+    const uint32_t cls_c = cls, need_c = need, ref_c = cur.ref;
+    const uint64_t gn = g + tw;
+    cls = nxt.classify(p, zr, gn * G, G, lane);
+    need = (uint32_t)ballot(cls == 1u);
+    if (need) regs.load(p, gn * G, need, lane);  // in flight while this group decodes
+    cur = nxt;
+    nxt.issue(p, (gn + tw) * G, G, lane);
+    uint32_t cnt_v = 0;
+#pragma unroll 1
+    for (uint32_t j = 0; j < G; ++j) {
+      const uint64_t k = k0 + j;
+      if (k >= p.nb) break;
+      const uint32_t c = __builtin_amdgcn_readlane(cls_c, j);
+      const uint32_t valid = k == p.nb - 1 ? (uint32_t)(p.n - k * kBlockValues) : kBlockValues;
+      uint32_t cnt = c == 2u ? valid : 0u;
+      if ((need_c >> j) & 1u) {
+        int64_t clo = zr.lo, chi = zr.hi;
+        if (p.enc != ENC_DICT) {
+          const int64_t ref = (int64_t)__builtin_amdgcn_readlane(ref_c, j);
+          clo = clo - ref > 0 ? clo - ref : 0;
+          chi = chi - ref < top ? chi - ref : top;
+        }
+        const uint64_t mine = block_marks<B>(clo, chi, st + j * Geo::kWords, valid, lane, cnt);
+        if (lane < 16u) p.marks[k * 16u + lane] = mine;
+      }
+      cnt_v = lane == j ? cnt : cnt_v;
     }
-    p.counts[k] = cnt;  // every lane stores the same value
+    if (lane < G && k0 + lane < p.nb) p.counts[k0 + lane] = cnt_v;
   }
 }
 
@@ -172,31 +285,59 @@ __global__ __launch_bounds__(256) void scan_add_kernel(uint32_t* out, uint64_t m
   if (i < m) out[i] += tile_sums[i / kScanTile];
 }
 
+// Write pass: wavefront step = kWriteGroup consecutive blocks.  Lane j < 16
+// holds block g + j's count, offset and class; the ballots of the blocks that
+// have matches and no all-match shortcut arrive in four 8-byte loads per lane
+// (load i, lane l: block 4 i + l / 16, step l % 16).
 __global__ __launch_bounds__(256) void select_write_kernel(const SelParams p, uint32_t* positions) {
-  __shared__ __align__(16) uint32_t lds[kSelWaves][kRtStageWords];
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  uint32_t* st = lds[wave];
   const ZRange zr = load_range(p);
+  const uint64_t ngroups = (p.nb + kWriteGroup - 1) / kWriteGroup;
   const uint64_t tw = (uint64_t)gridDim.x * kSelWaves;
-  for (uint64_t k = (uint64_t)blockIdx.x * kSelWaves + wave; k < p.nb; k += tw) {
-    const uint32_t cnt = __builtin_amdgcn_readfirstlane(p.counts[k]);
-    if (cnt == 0u) continue;
-    const uint32_t base = __builtin_amdgcn_readfirstlane(p.offsets[k]);
-    const uint32_t first = (uint32_t)(k * kBlockValues);
-    if (block_class(p, zr, k) == 2) {
-      for (uint32_t j = lane; j < cnt; j += 64u) positions[base + j] = first + j;
-      continue;
-    }
-    stage_rt_block(st, p.payload, p.b, k, lane);
-    const uint32_t bits = block_pass_bits(p, zr, st, k, lane);
-    uint32_t off = base;
+  for (uint64_t g = (uint64_t)blockIdx.x * kSelWaves + wave; g < ngroups; g += tw) {
+    const uint64_t k0 = g * kWriteGroup;
+    const uint64_t kl = k0 + lane;
+    const bool in = lane < kWriteGroup && kl < p.nb;
+    const uint32_t cnt = in ? p.counts[kl] : 0u;
+    const uint32_t off = in ? p.offsets[kl] : 0u;
+    const bool whole = cnt > 0u && p.use_am && block_class(p, zr, kl) == 2;
+    const uint64_t has = ballot(cnt > 0u);          // blocks with matches
+    const uint64_t read = has & ~ballot(whole);     // ... that have ballots
+    uint64_t mk[4];
 #pragma unroll
-    for (uint32_t t = 0; t < 16u; ++t) {
-      const bool ok = (bits >> t) & 1u;
-      const uint64_t m = ballot(ok);
-      if (ok) positions[off + mbcnt(m)] = first + lane + 64u * t;
-      off += (uint32_t)__builtin_popcountll(m);
+    for (uint32_t i = 0; i < 4u; ++i) {
+      const uint32_t blk = 4u * i + (lane >> 4);
+      mk[i] = ((read >> blk) & 1ull) ? p.marks[(k0 + blk) * 16u + (lane & 15u)] : 0ull;
+    }
+    // all-match blocks: their position ranges, unread
+    for (uint64_t rest = has & ~read; rest; rest &= rest - 1) {
+      const uint32_t j = (uint32_t)__builtin_ctzll(rest);
+      const uint32_t c = __builtin_amdgcn_readlane(cnt, j);
+      const uint32_t o = __builtin_amdgcn_readlane(off, j);
+      const uint32_t first = (uint32_t)((k0 + j) * kBlockValues);
+      for (uint32_t q = lane; q < c; q += 64u) positions[o + q] = first + q;
+    }
+    // blocks with ballots: each nonzero ballot at its block's offset plus the
+    // matches of the block's earlier steps (prefix sum over 16 lanes)
+#pragma unroll
+    for (uint32_t i = 0; i < 4u; ++i) {
+      const uint64_t w = mk[i];
+      const uint32_t pc = (uint32_t)__builtin_popcountll(w);
+      uint32_t incl = pc;
+#pragma unroll
+      for (uint32_t d = 1; d < 16u; d <<= 1) {
+        const uint32_t y = __shfl_up(incl, d, 16);
+        if ((lane & 15u) >= d) incl += y;
+      }
+      const uint32_t wo = __shfl(off, 4u * i + (lane >> 4), 64) + incl - pc;
+      for (uint64_t nz = ballot(w != 0ull); nz; nz &= nz - 1) {
+        const uint32_t l = (uint32_t)__builtin_ctzll(nz);
+        const uint64_t m = readlane64(w, l);
+        const uint32_t o = __builtin_amdgcn_readlane(wo, l);
+        const uint32_t first = (uint32_t)((k0 + 4u * i + (l >> 4)) * kBlockValues) + 64u * (l & 15u);
+        if ((m >> lane) & 1ull) positions[o + mbcnt(m)] = first + lane;
+      }
     }
   }
 }
@@ -290,8 +431,22 @@ __global__ void select_setup_kernel(const SelParams p, int64_t* zrange) {
 
 // ------------------------------------------------------------ launchers
 
-hipError_t launch_select_count(const SelParams& p, uint32_t grid, hipStream_t st) {
-  hipLaunchKernelGGL(select_count_kernel, dim3(grid), dim3(64 * kSelWaves), 0, st, p);
+namespace {
+using MarkFn = void (*)(SelParams);
+template <uint32_t... Bs>
+struct MarkTable {
+  static constexpr MarkFn fns[sizeof...(Bs)] = {select_mark_kernel<Bs + 1>...};
+};
+template <size_t... I>
+constexpr auto make_mark_table(std::index_sequence<I...>) {
+  return MarkTable<(uint32_t)I...>{};
+}
+using MarkTableT = decltype(make_mark_table(std::make_index_sequence<32>{}));
+}  // namespace
+
+hipError_t launch_select_mark(const SelParams& p, uint32_t grid, hipStream_t st) {
+  if (p.b < 1 || p.b > 32) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(MarkTableT::fns[p.b - 1], dim3(grid), dim3(64 * kSelWaves), 0, st, p);
   return hipGetLastError();
 }
 

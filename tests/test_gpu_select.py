@@ -91,6 +91,22 @@ def test_select_capacity_and_errors(ctx):
         ctx.select(delta, 0, 10)
 
 
+def test_select_into_full_capacity_buffer(ctx):
+    """capacity >= n: count, scan and writes in one call with one wait; the
+    same buffer reused by calls on different columns and predicates."""
+    buf = torch.full((6 * 1024 + 500,), -1, dtype=torch.int32, device="cuda")
+    for b, n in ((8, 6 * 1024 + 500), (17, 2 * 1024 + 9), (3, 1)):
+        v = synth.width_values(synth.pcg32(511, b, n), b)
+        w = oracle.pack_rm(v, b)
+        col = api.encode_for(v, b)
+        for lo, hi in preds(v, b):
+            for zm in (False, True):
+                got = u32(ctx.select(col, lo, hi, zone_maps=zm, out=buf))
+                assert np.array_equal(got, oracle.select(0, w, n, b, lo, hi)), (b, n, lo, hi, zm)
+    with pytest.raises(ValueError):
+        ctx.select(api.encode_for(np.zeros(buf.numel() + 1, dtype=np.uint32), 1), 0, 1, out=buf)
+
+
 def test_refine_and_gather_match_oracle(ctx):
     n = 12 * 1024 + 11
     a = synth.width_values(synth.pcg32(506, 12, n), 12)
@@ -130,6 +146,8 @@ def test_select_large_column_properties(ctx):
     pos = u32(ctx.select(col, lo, hi))
     r = ctx.run(col, lo, hi, _lib.strategy(_lib.DEC_RM_DIRECT))
     assert len(pos) == r["count"]
+    full = u32(ctx.select(col, lo, hi, out=torch.empty(n, dtype=torch.int32, device="cuda")))
+    assert np.array_equal(full, pos)
     assert np.all(np.diff(pos.astype(np.int64)) > 0)
     assert np.all((v[pos] >= lo) & (v[pos] < hi))
     assert int(v[pos].astype(np.uint64).sum()) == r["sum"]
