@@ -74,6 +74,60 @@ def read_trace(path, last):
     return {k: v[-last:] for k, v in per.items()}
 
 
+SELECT_STEPS = ("select_setup_kernel", "select_mark_kernel", "scan_tiles_kernel", "scan_top_kernel",
+                "scan_add_kernel", "select_write_kernel", "__amd_rocclr_copyBuffer")
+
+
+def select_section(trace_path, bench_line, command):
+    """Per-kernel durations of the bench's materializing-select leg: each
+    (b, sigma) row of the bench line is one warm-up call and three timed calls,
+    each call a run of SELECT_STEPS starting at its setup kernel; the table
+    averages the timed calls."""
+    rows = []
+    with open(trace_path) as fh:
+        for row in csv.DictReader(fh):
+            nm = re.sub(r"\(.*", "", row["Kernel_Name"]).replace("void ", "").replace("scan_dev::", "")
+            nm = re.sub(r"<.*>", "", nm)
+            if nm in SELECT_STEPS:
+                rows.append((int(row["Dispatch_Id"]), nm, int(row["End_Timestamp"]) - int(row["Start_Timestamp"]),
+                             int(row["Start_Timestamp"]), int(row["End_Timestamp"])))
+    rows.sort()
+    calls, cur = [], None
+    for d, nm, t, s0, s1 in rows:
+        if nm == "select_setup_kernel":
+            cur = []
+            calls.append(cur)
+        if cur is not None and nm in SELECT_STEPS:
+            cur.append((nm, t, s0, s1))
+    sel = bench_line["select"]
+    lines = ["# rocprofv3 summary: materializing select on one MI355X", "", "Commands (repository root):", ""]
+    lines += ["    " + c for c in command.split(" ;; ")]
+    n = bench_line["config"]["values_per_step"] // 32
+    lines += ["", "Workload: the bench's select leg on its resident columns (2^%d frame-of-reference values per "
+              "width, uniform in [0, 2^b), predicate v < round(sigma * 2^b), zone maps off, an output buffer of "
+              "n entries so that one call runs every pass with one wait).  Per row: the mean over the three "
+              "timed calls of each kernel's duration (us) and of the call's span from the first kernel's start "
+              "to the last one's end; the bench's own figure (HIP events around the call) beside it."
+              % (n.bit_length() - 1), ""]
+    hdr = ["b", "sigma", "selected"] + [k.replace("_kernel", "").replace("__amd_rocclr_copyBuffer", "copy total")
+                                        for k in SELECT_STEPS] + ["span us", "bench ms"]
+    lines += ["| " + " | ".join(hdr) + " |", "|" + "---|" * len(hdr)]
+    if len(calls) < 4 * len(sel):
+        lines.append("(trace holds %d select calls, expected %d)" % (len(calls), 4 * len(sel)))
+        return lines
+    calls = calls[-4 * len(sel):]
+    for i, r in enumerate(sel):
+        timed = calls[4 * i + 1: 4 * i + 4]
+        avg = {}
+        for k in SELECT_STEPS:
+            v = [t for c in timed for nm, t, _, _ in c if nm == k]
+            avg[k] = sum(v) / len(v) / 1e3 if v else 0.0
+        span = sum((c[-1][3] - c[0][2]) for c in timed) / len(timed) / 1e3
+        lines.append("| %d | %g | %d | %s | %.1f | %.4f |" % (
+            r["b"], r["sigma"], r["selected"], " | ".join("%.1f" % avg[k] for k in SELECT_STEPS), span, r["ms"]))
+    return lines
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True, help="kernel_trace.csv of the --kernel-trace run")
@@ -86,6 +140,7 @@ def main(argv=None):
     ap.add_argument("--out", required=True)
     ap.add_argument("--traffic-json")
     ap.add_argument("--sq", help="counter_collection.csv of an SQ_* pass")
+    ap.add_argument("--select-out", help="with --bench-json: also write the select leg's kernel table here")
     args = ap.parse_args(argv)
 
     if args.bench_json:
@@ -186,6 +241,13 @@ def main(argv=None):
                 vals["SQ_ACTIVE_INST_VALU"] / vals["SQ_WAVE_CYCLES"] if vals["SQ_WAVE_CYCLES"] else 0.0))
     with open(args.out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
+    if args.select_out and args.bench_json:
+        with open(args.bench_json) as fh:
+            bl = json.loads([ln for ln in fh if ln.startswith("{")][-1])
+        cmd = args.command.replace(" --out profiles/scan_sweep_2p28_timed_region.md",
+                                   " --select-out %s --out profiles/scan_sweep_2p28_timed_region.md" % args.select_out)
+        with open(args.select_out, "w") as fh:
+            fh.write("\n".join(select_section(args.trace, bl, cmd)) + "\n")
     if args.traffic_json and traffic:
         with open(args.traffic_json, "w") as fh:
             json.dump({"kernel_source": kernel_source_hash(), "kernels": traffic}, fh, indent=1)
