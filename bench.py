@@ -252,7 +252,7 @@ def zonemap_leg(ctx, torch, n_log2, beta_gbs, reps=5):
                     ctx.cache_flush(evict, evict.numel() * 4)
                     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                     e0.record()
-                    ctx.run_rle(rle, lo, hi, zone_maps=bool(zm), all_match=bool(zm))
+                    ctx.run_rle_async(rle, lo, hi, out, zone_maps=bool(zm), all_match=bool(zm))
                     e1.record()
                     e1.synchronize()
                     ts.append(e0.elapsed_time(e1) * 1e-3)

@@ -205,8 +205,8 @@ scan_status scan_tune_load(scan_ctx* ctx, const char* path);
  * block_run[k] .. block_run[k+1]-1.  The scan tests the predicate once per run
  * and adds the run's length to COUNT and value x length to SUM (mod 2^64). */
 typedef struct {
-  const uint32_t* run_value;  /* device */
-  const uint16_t* run_len;    /* device */
+  const uint32_t* run_value;  /* device, 16-byte aligned */
+  const uint16_t* run_len;    /* device, 8-byte aligned */
   const uint64_t* block_run;  /* device: nb + 1 entries */
   const uint32_t* zone_min;   /* device: per-block min / max of the values, or NULL */
   const uint32_t* zone_max;
@@ -215,9 +215,17 @@ typedef struct {
 
 /* Synchronous scan; flags: bit 0 zone maps, bit 1 with bit 0 the all-match
  * shortcut (a block inside the predicate is taken whole).  Same result
- * contract as scan_run; strategy_used reports the flags. */
+ * contract as scan_run; strategy_used reports the flags.  Errors: flags
+ * outside 0..3, NULL or misaligned run arrays (n > 0) -> SCAN_EINVAL; zone
+ * maps requested without them -> SCAN_EUNSUPPORTED. */
 scan_status scan_run_rle(scan_ctx* ctx, const scan_rle_column* col, const scan_predicate* pred, uint32_t flags,
                          scan_result* out);
+/* Enqueue the same scan on the context stream; the whole result (count, sum,
+ * blocks_read, blocks_total, strategy_used, status 0) lands in *out_dev
+ * (device memory, one scan_result) when the stream reaches it.  No host sync;
+ * scan_sync() waits.  Validation errors return before anything is enqueued. */
+scan_status scan_run_rle_async(scan_ctx* ctx, const scan_rle_column* col, const scan_predicate* pred,
+                               uint32_t flags, scan_result* out_dev);
 
 /* ------------------------------------------------------ materializing select */
 /* The ascending positions (u32 row indices) of the rows with lo <= v < hi,

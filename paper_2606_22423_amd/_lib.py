@@ -122,6 +122,7 @@ SIGNATURES = {
     "scan_tune_save": (_i32, [_vp, ctypes.c_char_p]),
     "scan_tune_load": (_i32, [_vp, ctypes.c_char_p]),
     "scan_run_rle": (_i32, [_vp, _P(ScanRleColumn), _P(ScanPredicate), _u32, _P(ScanResult)]),
+    "scan_run_rle_async": (_i32, [_vp, _P(ScanRleColumn), _P(ScanPredicate), _u32, _vp]),
     "scan_rle_encode": (_i32, [_vp, _u64, _vp, _vp, _vp, _vp, _vp, _P(_u64)]),
     "scan_select": (_i32, [_vp, _P(ScanColumn), _i32, _u32, _P(ScanPredicate), _u32, _vp, _u64, _P(_u64)]),
     "scan_refine": (_i32, [_vp, _P(ScanColumn), _i32, _u32, _P(ScanPredicate), _vp, _u64, _vp, _P(_u64)]),

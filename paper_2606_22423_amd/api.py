@@ -302,6 +302,16 @@ class Context:
                    "scan_run_rle")
         return r.as_dict()
 
+    def run_rle_async(self, col: RleColumn, lo: int, hi: int, out_dev, zone_maps: bool = True,
+                      all_match: bool = True):
+        """Enqueue; the 40-byte result lands in out_dev (a device tensor of >= 40 bytes)."""
+        c = col.struct(zone_maps)
+        flags = (1 if zone_maps and col.zmin is not None else 0)
+        flags |= 2 if flags and all_match else 0
+        pred = ScanPredicate(int(lo), int(hi))
+        self.check(self.lib.scan_run_rle_async(self.h, ctypes.byref(c), ctypes.byref(pred), flags,
+                                               ctypes.c_void_p(_ptr(out_dev))), "scan_run_rle_async")
+
     # ------------------------------------------------ materializing select
     def select(self, col: Column, lo: int, hi: int, zone_maps: bool = True, all_match: bool = True,
                out=None):

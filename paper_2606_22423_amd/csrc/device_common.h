@@ -164,9 +164,11 @@ __device__ __forceinline__ uint64_t all_blocks(uint32_t cnt) {
 
 // Work-group reduction of the per-wave (count, sum, blocks) into one partial,
 // then the last work-group to finish folds every partial into *out and resets
-// the ticket, so consecutive launches need no memset.
-__device__ __forceinline__ void finish_scan(const Params& p, uint64_t count, uint64_t lane_sum,
-                                            uint64_t blocks) {
+// the ticket, so consecutive launches need no memset.  `count` and `blocks`
+// are wave-uniform, `lane_sum` per lane.
+__device__ __forceinline__ void finish_partials(Partial* partials, uint32_t* ticket, Result* out,
+                                                uint64_t blocks_total, int32_t strategy, uint64_t count,
+                                                uint64_t lane_sum, uint64_t blocks) {
   __shared__ uint64_t red[16][3];
   __shared__ bool last;
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -184,11 +186,11 @@ __device__ __forceinline__ void finish_scan(const Params& p, uint64_t count, uin
       t += red[w][1];
       b += red[w][2];
     }
-    Partial* q = p.partials + blockIdx.x;
+    Partial* q = partials + blockIdx.x;
     q->count = c;
     q->sum = t;
     q->blocks = b;
-    uint32_t prev = __hip_atomic_fetch_add(p.ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     last = (prev == gridDim.x - 1);
   }
   __syncthreads();
@@ -196,7 +198,7 @@ __device__ __forceinline__ void finish_scan(const Params& p, uint64_t count, uin
   __atomic_thread_fence(__ATOMIC_ACQUIRE);
   uint64_t c = 0, t = 0, b = 0;
   for (uint32_t i = threadIdx.x; i < gridDim.x; i += blockDim.x) {
-    const Partial* q = p.partials + i;
+    const Partial* q = partials + i;
     c += __hip_atomic_load(&q->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     t += __hip_atomic_load(&q->sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     b += __hip_atomic_load(&q->blocks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -221,12 +223,17 @@ __device__ __forceinline__ void finish_scan(const Params& p, uint64_t count, uin
     r.count = red[0][0];
     r.sum = (int64_t)red[0][1];
     r.blocks_read = red[0][2];
-    r.blocks_total = p.nb;
-    r.strategy_used = p.strategy;
+    r.blocks_total = blocks_total;
+    r.strategy_used = strategy;
     r.status = 0;
-    *p.out = r;
-    __hip_atomic_store(p.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *out = r;
+    __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+}
+
+__device__ __forceinline__ void finish_scan(const Params& p, uint64_t count, uint64_t lane_sum,
+                                            uint64_t blocks) {
+  finish_partials(p.partials, p.ticket, p.out, p.nb, p.strategy, count, lane_sum, blocks);
 }
 
 }  // namespace scan_dev

@@ -11,10 +11,14 @@ struct RleParams {
   const uint64_t* block_run;  // nb + 1 run starts
   const uint32_t* zmin;       // zone maps of the values, or null
   const uint32_t* zmax;
-  Result* out;                // count, sum, blocks_read (cleared by the launch)
+  Result* out;                // device result (written whole by the launch)
+  Partial* partials;          // per-work-group partials (at least grid entries)
+  uint32_t* ticket;           // last-work-group counter, zero between launches
   uint64_t nb;
   int64_t lo, hi;
   uint32_t use_zm, use_am;
+  int32_t strategy_used;      // reported flags
+  uint32_t empty;             // n == 0 or lo >= hi: only the cleared result is written
 };
 
 hipError_t launch_rle_scan(const RleParams& p, uint32_t grid, hipStream_t st);
