@@ -41,8 +41,12 @@ enum PredForm {
 template <int B>
 struct Geo {
   // block pairs per step (half-wavefront decoders): about 4 KiB per wavefront,
-  // at most 4 pairs (below b = 4 the decode is compute-bound anyway)
-  static constexpr int kPairs = B >= 16 ? 1 : (16 / B > 4 ? 4 : 16 / B);
+  // at most 4 pairs (below b = 4 the decode is compute-bound anyway); from
+  // b = 24 on two pairs (12-16 KiB per step), which measured faster there with
+  // the one or two wavefronts per SIMD the autotuner picks at those widths
+  static constexpr int kPairs = B >= 24 ? 2 : B >= 16 ? 1 : (16 / B > 4 ? 4 : 16 / B);
+  // the delta decoders (prefix scan per pair) keep one pair per step from b = 16
+  static constexpr int kDeltaPairs = B >= 16 ? 1 : (16 / B > 4 ? 4 : 16 / B);
   // blocks staged per step (RM-LDS), at most 8
   static constexpr int kLdsBlocks = B >= 32 ? 1 : (32 / B > 8 ? 8 : 32 / B);
   static constexpr int kStageWords = 32 * B + 4;            // one staged block plus an over-read pad
@@ -983,7 +987,7 @@ __device__ __forceinline__ void delta_range(const Params& p, WaveState<RelT<B>>&
   const uint64_t excl = tail_partial ? last : ~0ull;
   auto live_fn = [&](uint64_t k0, uint32_t cnt) { return window_live_i64(p, k0, cnt, excl, s.lcount, s.lsum); };
   if constexpr (DEC == DEC_RM_DIRECT) {
-    constexpr int P = SMALL ? 1 : Geo<B>::kPairs;
+    constexpr int P = SMALL ? 1 : Geo<B>::kDeltaPairs;
     const uint32_t l = lane & 31u;
     PairCursor<P, decltype(live_fn)> cur{ka, ke, 0, 0, 0, list, ka, stride, win};
     uint64_t k0b[P], k1b[P];
