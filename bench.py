@@ -463,7 +463,7 @@ def main():
         t0 = time.time()
         for b in widths:
             for s in cands(b):
-                cfg, ms = ctx.autotune(col_for(b, s), 0, bounds[b], s, reps=3)
+                cfg, ms = ctx.autotune(col_for(b, s), 0, bounds[b], s, reps=5)
                 tuned["%d/%s" % (b, strategy_name(s))] = list(cfg) + [round(ms, 5)]
         log("[bench] autotuned %d (width, strategy) pairs in %.1f s" % (len(tuned), time.time() - t0))
 

@@ -187,8 +187,8 @@ scan_status scan_set_tune(scan_ctx* ctx, int32_t enc, uint32_t b, int32_t strate
 scan_status scan_get_tune(scan_ctx* ctx, int32_t enc, uint32_t b, int32_t strategy, scan_tune* t);
 
 /* Autotuner: times every launch configuration of a small grid (work-group
- * size {64,128,256} x work-groups per CU {1,2,4,8} x window {4,16,64} blocks)
- * for one column and strategy, median of `reps` runs each with HIP events on
+ * size {64,128,256} x work-groups per CU {1,2,4,8} x window {2,4,8,16,64}
+ * blocks) for one column and strategy, median of `reps` runs each with HIP events on
  * the context stream (a 512 MiB read before each run keeps the column out of
  * the 256 MB last-level cache), and keeps the fastest with scan_set_tune.
  * *out (host, may be NULL) receives it, *ms_out (may be NULL) its time in ms.

@@ -469,7 +469,7 @@ scan_status scan_autotune(scan_ctx* ctx, const scan_column* col, int32_t enc, ui
   const bool had = ctx->tunes.count(std::make_tuple(enc, b, strategy)) > 0;
   static const int kWg[] = {64, 128, 256};
   static const int kPerCu[] = {1, 2, 4, 8};
-  static const int kWin[] = {4, 16, 64};
+  static const int kWin[] = {2, 4, 8, 16, 64};
   float best_ms = 1e30f;
   scan_tune best = saved;
   for (int wg : kWg)
