@@ -40,11 +40,14 @@ enum PredForm {
 
 template <int B>
 struct Geo {
-  // block pairs per step (half-wavefront decoders): about 4 KiB per wavefront,
-  // at most 4 pairs (below b = 4 the decode is compute-bound anyway); from
-  // b = 24 on two pairs (12-16 KiB per step), which measured faster there with
-  // the one or two wavefronts per SIMD the autotuner picks at those widths
-  static constexpr int kPairs = B >= 24 ? 2 : B >= 16 ? 1 : (16 / B > 4 ? 4 : 16 / B);
+  // block pairs per step (half-wavefront decoders).  Branch-free: about
+  // 8 KiB per wavefront below b = 16 (32/b pairs, at most 8), one pair at
+  // b = 16-23, two from b = 24 (12-16 KiB); with the one or two wavefronts per
+  // SIMD the autotuner picks, these deeper steps measured faster (b = 12:
+  // 18 %).  Compaction keeps about 4 KiB (its ring and masks need the
+  // registers; deeper steps spill).
+  static constexpr int kPairs = B >= 24 ? 2 : B >= 16 ? 1 : (32 / B > 8 ? 8 : 32 / B);
+  static constexpr int kPairsSV = B >= 16 ? 1 : (16 / B > 4 ? 4 : 16 / B);
   // the delta decoders (prefix scan per pair) keep one pair per step from b = 16
   static constexpr int kDeltaPairs = B >= 16 ? 1 : (16 / B > 4 ? 4 : 16 / B);
   // blocks staged per step (RM-LDS), at most 8
@@ -728,8 +731,8 @@ __device__ __forceinline__ void scan_range(const Params& p, WaveState<uint32_t>&
   const bool tail_partial = p.tail != kBlockValues;
   const uint64_t excl = tail_partial ? last : ~0ull;
   if constexpr (DEC == DEC_RM_DIRECT || DEC == DEC_LI) {
-    run_pairs<B, DEC, MODE, ENC, PF, SMALL ? 1 : Geo<B>::kPairs>(p, s, lane, list, ka, ke, stride, win, excl, dict_lds,
-                                                                 dict_last, clo, chi);
+    constexpr int P = SMALL ? 1 : (MODE == MODE_BF ? Geo<B>::kPairs : Geo<B>::kPairsSV);
+    run_pairs<B, DEC, MODE, ENC, PF, P>(p, s, lane, list, ka, ke, stride, win, excl, dict_lds, dict_last, clo, chi);
   } else if constexpr (DEC == DEC_RM_LDS) {
     run_staged<B, MODE, ENC, PF, SMALL ? 1 : Geo<B>::kLdsBlocks>(p, s, lane, st, ka, ke, stride, win, excl, dict_lds,
                                                                  dict_last, clo, chi);
