@@ -354,6 +354,55 @@ struct BlockCursor {
   }
 };
 
+// Branch-free COUNT and SUM of the 32 codes a lane holds, for B = 1, 2, 4 or
+// 8 (frame of reference, full blocks): SIMD within a register.  The codes are
+// spread into fields of F = 2B bits (odd and even codes apart), so every
+// field has B spare bits: one subtraction tests all fields of a register
+// against the code window with no borrow between fields, and the top bit of
+// each field is its pass flag.  v_bcnt counts the flags; an unsigned dot
+// product of the fields with the 0/1 flags (dot8 of nibbles, dot4 of bytes,
+// dot2 of halves) adds the passing codes.  B = 1 needs only a popcount per
+// word.  Code c passes iff (c - loc) <= wm1 (PF_LO0: loc = 0).
+template <int B, int PF>
+__device__ __forceinline__ void swar_count_sum(const uint32_t (&w)[B], uint32_t loc, uint32_t wm1, uint32_t& lc,
+                                               uint32_t& part) {
+  if constexpr (B == 1) {
+    const uint32_t pc = (uint32_t)__builtin_popcount(w[0]);
+    const bool p0 = loc == 0u;                         // code 0 in the window
+    const bool p1 = loc <= 1u && loc + wm1 >= 1u;      // code 1 in the window
+    lc += (p0 ? 32u - pc : 0u) + (p1 ? pc : 0u);
+    part += p1 ? pc : 0u;
+  } else {
+    constexpr int F = 2 * B;
+    constexpr uint32_t rep = F == 4 ? 0x11111111u : F == 8 ? 0x01010101u : 0x00010001u;
+    constexpr uint32_t vmask = ((1u << B) - 1u) * rep;  // the code bits of every field
+    constexpr uint32_t hm = (1u << (F - 1)) * rep;      // the flag bit of every field
+    const uint32_t locr = loc * rep;
+    const uint32_t wr = ((1u << (F - 1)) + wm1) * rep;
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const uint32_t x = (k ? (w[i] >> B) : w[i]) & vmask;
+        // field: c - loc when c >= loc; when c < loc the field value exceeds
+        // any wm1 (its flag bit is clear and the rest is >= 2^(F-1) - loc)
+        const uint32_t g = PF == PF_LO0 ? x : (((x | hm) - locr) & ~hm);
+        const uint32_t flags = (wr - g) & hm;  // flag set iff field <= wm1
+        lc += (uint32_t)__builtin_popcount(flags);
+        const uint32_t f01 = flags >> (F - 1);
+        if constexpr (F == 4) {
+          part = __builtin_amdgcn_udot8(x, f01, part, false);
+        } else if constexpr (F == 8) {
+          part = __builtin_amdgcn_udot4(x, f01, part, false);
+        } else {
+          typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+          part = __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, x), __builtin_bit_cast(u16x2, f01), part, false);
+        }
+      }
+    }
+  }
+}
+
 // -------------------------------------------- half-wavefront pair decoding
 
 // Decode the 32 codes each lane holds for one block (lanes 0-31: one block,
@@ -371,7 +420,15 @@ __device__ __forceinline__ void decode_pair(const Params& p, WaveState<uint32_t>
   if (act_m == 0) return;
   const uint32_t limit = (TAIL && kb == p.nb - 1) ? p.tail : kBlockValues;
   PartT<B, ENC> part = 0;
-  if constexpr (MODE == MODE_BF) {
+  if constexpr (MODE == MODE_BF && ENC == ENC_FOR && !TAIL && (B == 1 || B == 2 || B == 4 || B == 8)) {
+    uint32_t lc = 0, sp = 0;
+    swar_count_sum<B, PF>(w, cr.loc, cr.wm1, lc, sp);
+    if (act) {
+      s.lcount += lc;
+      s.lsum += (uint64_t)sp;
+      if constexpr (PF == PF_REFS) s.lsum += (uint64_t)lc * ref;
+    }
+  } else if constexpr (MODE == MODE_BF) {
     // Branch-free: per-lane count and masked add; the compare's mask stays in
     // VCC and feeds a select and a carry-add (no ballot, no scalar work).
     uint32_t lc = 0;
