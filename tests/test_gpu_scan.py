@@ -124,6 +124,42 @@ def test_for_block_references(ctx, b):
             check(ctx.run(col, lo, hi, s), want, (s >> 3) & 1, (b, lo, hi, s), want_off)
 
 
+@pytest.mark.parametrize("b", [1, 2, 4, 8])
+def test_packed_field_widths_every_code_window(ctx, b):
+    """b = 1, 2, 4, 8 take the packed-field (SWAR) path on full blocks: every
+    code window [lo, hi) at b <= 4 (and 300 at b = 8, with the extremes), on
+    both register decoders, with and without block references, against the
+    oracle.  The ragged last block goes through the per-code loop."""
+    n = 3 * 1024 + 517
+    top = 1 << b
+    v = synth.width_values(synth.pcg32(7, b, n), b)
+    w = oracle.pack_rm(v, b)
+    col, coli = api.encode_for(v, b), api.encode_for(v, b, layout=LAYOUT_LI)
+    base = (np.repeat(np.arange(4, dtype=np.uint64) * 1_000_003, 1024)[:n]).astype(np.uint64)
+    vr = (base + v.astype(np.uint64)).astype(np.uint32)
+    refs, codes = oracle.for_encode(vr, b, policy=1)
+    wr = oracle.pack_rm(codes, b)
+    colr = api.encode_for(vr, b, ref_policy=1)
+    if b <= 4:
+        windows = [(lo, hi) for lo in range(top + 1) for hi in range(lo, top + 2)]
+    else:
+        rng = np.random.default_rng(8)
+        windows = [(0, 1), (0, top), (top - 1, top), (0, top - 1), (1, top), (5, 6)] + \
+            [tuple(sorted(int(t) for t in rng.integers(0, top + 1, size=2))) for _ in range(300)]
+    bf = [strategy(DEC_RM_DIRECT, 0, 0), strategy(DEC_LI, 0, 0)]
+    for lo, hi in windows:
+        want = oracle.scan_for(w, n, b, lo, hi)
+        for s, c in zip(bf, (col, coli)):
+            got = ctx.run(c, lo, hi, s)
+            assert (got["count"], got["sum"]) == (want.count, want.sum), (b, lo, hi, _lib.strategy_name(s))
+        # the same window shifted into each block's frame (references 0, 1000003, ...)
+        for k in range(4):
+            rlo, rhi = lo + k * 1_000_003, hi + k * 1_000_003
+            want = oracle.scan_for(wr, n, b, rlo, rhi, refs=refs)
+            got = ctx.run(colr, rlo, rhi, strategy(DEC_RM_DIRECT, 0, 0))
+            assert (got["count"], got["sum"]) == (want.count, want.sum), (b, rlo, rhi, "refs")
+
+
 @pytest.mark.parametrize("b", [1, 2, 7, 13, 16, 17, 22, 23, 28, 32])
 def test_delta_every_strategy(ctx, b):
     for n in (1, 1024, 4 * 1024 + 333):
