@@ -96,8 +96,10 @@ def batch_leg(ctx, torch, ncols, reps, selector_path):
     (ii) asynchronous launches on one stream and one final sync.  Learned: the
     same launches with the strategy the trained selector picks per column (the
     device time of feature extraction and the network for all columns is
-    reported beside it).  The captured single-graph form is disabled in the
-    library, so it is reported as such.  Results of every column must agree."""
+    reported beside it).  Batched: one prepared batch (a fixed sequence of
+    launches for all columns), replays timed, with the default strategy and
+    with the selector choosing on the device inside each replay.  Results of
+    every column must agree."""
     import numpy as np
 
     import synth
@@ -154,8 +156,27 @@ def batch_leg(ctx, torch, ncols, reps, selector_path):
         "values": int(total_values), "payload_bytes": int(payload),
         "baseline_sync_ms": round(float(np.median(t_sync)) * 1e3, 3),
         "baseline_async_ms": round(float(np.median(t_async)) * 1e3, 3),
-        "graph_batch": "disabled in the library for now (its runs did not complete; the cause, a work-fetch loop the optimizer let lanes 1-63 re-enter without the fetch, is fixed but not yet run on the GPU)",
     }
+
+    def check_batch(got, what):
+        for i, r in enumerate(res_sync):
+            if (got[i]["count"], got[i]["sum"]) != (r["count"], r["sum"]):
+                raise RuntimeError("%s: column %d differs: %s vs %s" % (what, i, got[i], r))
+
+    def batched(items, what):
+        """Plan once, then time replays (each a fixed sequence of launches)."""
+        h = ctx.batch_prepare(items)
+        try:
+            got = ctx.batch_replay(h, len(items))
+            check_batch(got, what)
+            ts = [timed(lambda: ctx.batch_replay(h, wait=False)) for _ in range(reps)]
+            check_batch(ctx.batch_replay(h, len(items)), what)
+        finally:
+            ctx.batch_release(h)
+        return float(np.median(ts)), got
+
+    t_bd, _ = batched([c.item(lo, hi, default) for c, lo, hi in cols], "batched default")
+    res["batched_default_ms"] = round(t_bd * 1e3, 3)
     if selector_path and os.path.exists(selector_path):
         ctx.selector_load(selector_path)
         learned = [ctx.run(c, lo, hi, -1)["strategy_used"] for c, lo, hi in cols]
@@ -169,10 +190,19 @@ def batch_leg(ctx, torch, ncols, reps, selector_path):
         t_learn = [timed(lambda: launch_all(learned)) for _ in range(reps)]
         check("async learned")
         counts = np.bincount([st.STRATEGIES.index(s) for s in learned], minlength=8)
+        # batched + learned: the selector runs on the device inside each replay
+        ctx.selector_load(selector_path)
+        t_bl, got = batched([c.item(lo, hi, -1) for c, lo, hi in cols], "batched learned")
+        ctx.selector_clear()
+        if [g["strategy_used"] for g in got] != learned:
+            raise RuntimeError("batched selection differs from scan_run's")
         res.update({"learned_async_ms": round(float(np.median(t_learn)) * 1e3, 3),
                     "selection_ms": round(t_sel * 1e3, 3),
                     "learned_class_counts": counts.tolist(),
-                    "speedup_learned_vs_default": round(float(np.median(t_async)) / float(np.median(t_learn)), 3)})
+                    "speedup_learned_vs_default": round(float(np.median(t_async)) / float(np.median(t_learn)), 3),
+                    "batched_learned_ms": round(t_bl * 1e3, 3),
+                    "speedup_batched_learned_vs_per_column_async": round(float(np.median(t_async)) / t_bl, 2),
+                    "speedup_batched_learned_vs_per_column_sync": round(float(np.median(t_sync)) / t_bl, 2)})
     log("[bench] batch: %s" % {k: v for k, v in res.items() if k.endswith("_ms") or k.startswith("speedup")})
     del cols
     return res

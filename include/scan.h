@@ -255,27 +255,28 @@ scan_status scan_gather(scan_ctx* ctx, const scan_column* col, int32_t enc, uint
                         uint64_t n, int64_t* values);
 
 /* ---------------------------------------------------------------- batches */
-/* Many columns (mixed length, width, encoding, strategy) scanned by one
- * captured hipGraph: per-column setup, strategy selection on the device (the
- * loaded selector for SCAN_STRAT_AUTO items, else the heuristic), then one
- * persistent kernel per (encoding, decoder, predicate mode) class draining
- * windows of blocks from all its columns.  Columns must be row-major; explicit
- * strategies must use the SCAN_DEC_RM_LDS or SCAN_DEC_RM_DIRECT decoder.
- * Results equal scan_run's for every item, bit for bit.
+/* Many columns (mixed length, width, encoding, strategy) scanned by one fixed
+ * sequence of launches, whatever the number of columns: per-column setup,
+ * strategy selection on the device (the loaded selector for SCAN_STRAT_AUTO
+ * items, else the heuristic), binning of the columns' windows of blocks by
+ * (encoding, decoder, predicate mode), then one persistent kernel per class
+ * walking its windows on a static schedule.  Columns must be row-major;
+ * explicit strategies must use the SCAN_DEC_RM_LDS or SCAN_DEC_RM_DIRECT
+ * decoder.  Results equal scan_run's for every item, bit for bit.
  *
- * scan_batch_prepare validates the items, uploads their descriptors and
- * captures the graph once; the selector state and the tuning stored for
- * (enc -1, b 0, strategy -1) at that moment are baked in (tuning: work-groups
- * per CU of the class kernels and the window, at most 64 blocks).  An invalid
- * item does not fail the call: its result carries the error in `status`.
- * `items` (host) may be freed after the call; the columns' device buffers must
- * stay alive until the handle is released.  *handle (host) receives an id. */
+ * scan_batch_prepare validates the items and uploads their descriptors and
+ * windows once; the selector state and the tuning stored for (enc -1, b 0,
+ * strategy -1) at that moment are baked in (tuning: work-groups per CU of the
+ * class kernels and the window, at most 64 blocks).  An invalid item does not
+ * fail the call: its result carries the error in `status`.  `items` (host)
+ * may be freed after the call; the columns' device buffers must stay alive
+ * until the handle is released.  *handle (host) receives an id. */
 scan_status scan_batch_prepare(scan_ctx* ctx, const scan_item* items, size_t n_items, uint64_t* handle);
-/* Launch the batch's graph on the context stream.  With out (host, n_items
- * results) non-NULL, waits and fills it; with out NULL, only enqueues.  May be
- * replayed any number of times. */
+/* Enqueue the batch's launches on the context stream.  With out (host,
+ * n_items results) non-NULL, waits and fills it; with out NULL, only
+ * enqueues.  May be replayed any number of times. */
 scan_status scan_batch_replay(scan_ctx* ctx, uint64_t handle, scan_result* out);
-/* Wait for the stream and free the batch's graph and buffers. */
+/* Wait for the stream and free the batch's buffers. */
 scan_status scan_batch_release(scan_ctx* ctx, uint64_t handle);
 /* prepare + replay + release. */
 scan_status scan_batch_run(scan_ctx* ctx, const scan_item* items, size_t n_items, scan_result* out);

@@ -1,13 +1,15 @@
 // Batched scans: host side.  A batch is planned once (validation, column
-// descriptors, work items, device buffers) and captured into one hipGraph:
-//   setup (clear slots, dictionary code ranges)
+// descriptors, work items, device buffers); a replay enqueues its launches on
+// the context stream:
+//   setup (clear slots and class counts, dictionary code ranges)
 //   -> [features -> selector MLP]  (when a selector is loaded)
 //   -> select (strategy per column, written on the device)
 //   -> bin (items into twelve class lists)
-//   -> twelve persistent class scans
-// Replaying the graph is one host call; the 32-byte result slots come back
-// with one copy.  The same column descriptors serve the single-column
-// selector (scan_run with SCAN_STRAT_AUTO) and the feature export.
+//   -> twelve persistent class scans (static schedule over each list)
+// so a replay is 15-17 launches whatever the number of columns; the 32-byte
+// result slots come back with one copy.  The same column descriptors serve the
+// single-column selector (scan_run with SCAN_STRAT_AUTO) and the feature
+// export.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,8 +28,6 @@ hipError_t launch_batch_select(BatchCol* cols, uint32_t n_cols, const float* sco
                                hipStream_t st);
 hipError_t launch_batch_bin(const BatchArgs& a, hipStream_t st);
 hipError_t launch_mlp_forward(const float* theta, const float* X, uint32_t rows, float* out, hipStream_t st);
-hipError_t preload_batch_aux();
-hipError_t preload_mlp();
 }  // namespace scan_dev
 
 namespace {
@@ -39,7 +39,7 @@ struct BatchBuffers {
   BatchCol* cols = nullptr;
   BatchWork* work = nullptr;
   uint32_t* lists = nullptr;
-  uint32_t* counters = nullptr;  // counts [12] then cursors [12]
+  uint32_t* counters = nullptr;  // per-class item counts [12]
   BatchOut* out = nullptr;
   BatchOut* out_host = nullptr;  // pinned
   float* feats = nullptr;
@@ -58,7 +58,7 @@ struct BatchBuffers {
     if ((e = hipMalloc(&cols, sizeof(BatchCol) * nc)) != hipSuccess) return e;
     if ((e = hipMalloc(&work, sizeof(BatchWork) * nw)) != hipSuccess) return e;
     if ((e = hipMalloc(&lists, sizeof(uint32_t) * nw * kBatchClasses)) != hipSuccess) return e;
-    if ((e = hipMalloc(&counters, sizeof(uint32_t) * 2 * kBatchClasses)) != hipSuccess) return e;
+    if ((e = hipMalloc(&counters, sizeof(uint32_t) * kBatchClasses)) != hipSuccess) return e;
     if ((e = hipMalloc(&out, sizeof(BatchOut) * nc)) != hipSuccess) return e;
     if ((e = hipMalloc(&feats, sizeof(float) * 6 * nc)) != hipSuccess) return e;
     if ((e = hipMalloc(&scores, sizeof(float) * 8 * nc)) != hipSuccess) return e;
@@ -72,7 +72,6 @@ BatchArgs make_args(const BatchBuffers& m, uint32_t n_cols, uint32_t n_work, int
   a.work = m.work;
   a.lists = m.lists;
   a.counts = m.counters;
-  a.cursors = m.counters + kBatchClasses;
   a.out = m.out;
   a.n_cols = n_cols;
   a.n_work = n_work;
@@ -174,16 +173,10 @@ struct BatchPlan {
   BatchBuffers mem;
   bool selector = false;
   uint32_t grid = 0;
-  hipStream_t stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
 };
 
 static void free_plan(BatchPlan* b) {
   if (!b) return;
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
-  if (b->stream) (void)hipStreamDestroy(b->stream);
   b->mem.release();
   delete b;
 }
@@ -207,23 +200,6 @@ void destroy_batches(scan_ctx* ctx) {
     delete it->second;
     ps.erase(it);
   }
-}
-
-// Every kernel a batch graph contains is loaded and launched once (with no
-// work) outside stream capture, before the first capture on the context:
-// with deferred code-object loading, a kernel's first launch loads its
-// module (device allocations and copies), which must not happen while a
-// stream is being captured.
-static hipError_t preload_graph_kernels(scan_ctx* ctx, const BatchBuffers& m) {
-  if (ctx->batch_kernels_loaded) return hipSuccess;
-  hipError_t e = preload_batch_aux();
-  if (e == hipSuccess) e = preload_mlp();
-  if (e == hipSuccess) e = launch_batch_setup(make_args(m, 0, 0, 0), ctx->stream);  // zeroes the class counters
-  for (int cls = 0; cls < kBatchClasses && e == hipSuccess; ++cls)
-    e = batch_class_fn(cls)(make_args(m, 0, 0, cls), 1, 256, ctx->stream, nullptr);  // no items: exits at once
-  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  if (e == hipSuccess) ctx->batch_kernels_loaded = true;
-  return e;
 }
 
 static hipError_t enqueue_batch(scan_ctx* ctx, BatchPlan* b, hipStream_t st) {
@@ -305,21 +281,8 @@ scan_status selector_pick(scan_ctx* ctx, const scan_column* col, int32_t enc, ui
 
 extern "C" {
 
-// The captured class-kernel graph is switched off: its first runs on MI355X
-// did not complete (the host waited in this call until the test's time limit).
-// The cause was the class kernels' work fetch (lane 0 took the item with an
-// atomic, a lane shuffle broadcast it): the optimizer routed lanes 1-63 back
-// to the broadcast without passing the fetch, so with lane 0 held outside
-// that path they re-read item 0 forever.  The fetch is now wave-uniform
-// (wave_next_item), the same fix the query kernel runs with, but this path
-// has not been run on the GPU since, so it stays off.
-constexpr bool kGraphBatchEnabled = false;
-
 scan_status scan_batch_prepare(scan_ctx* ctx, const scan_item* items, size_t n_items, uint64_t* handle) {
   if (!ctx) return SCAN_EINVAL;
-  if (!kGraphBatchEnabled)
-    return fail(ctx, SCAN_EUNSUPPORTED,
-                "captured batch graphs are disabled (their kernels' former work fetch could spin forever; the fixed path is not yet validated on the GPU)");
   if (!handle || (n_items && !items)) return fail(ctx, SCAN_EINVAL, "items and handle must not be NULL");
   if (n_items > (1u << 24)) return fail(ctx, SCAN_EINVAL, "at most 2^24 items per batch");
   hipError_t e = hipSetDevice(ctx->device);
@@ -345,22 +308,9 @@ scan_status scan_batch_prepare(scan_ctx* ctx, const scan_item* items, size_t n_i
   if (n_items) e = hipMemcpy(b->mem.cols, b->cols.data(), sizeof(BatchCol) * n_items, hipMemcpyHostToDevice);
   if (e == hipSuccess && !work.empty())
     e = hipMemcpy(b->mem.work, work.data(), sizeof(BatchWork) * work.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = preload_graph_kernels(ctx, b->mem);
-  // Capture on a private stream of default priority; replays go to the
-  // context's stream.
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
-  if (e == hipSuccess) {
-    e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-      const hipError_t e2 = enqueue_batch(ctx, b, b->stream);
-      e = hipStreamEndCapture(b->stream, &b->graph);
-      if (e2 != hipSuccess) e = e2;
-    }
-  }
-  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
   if (e != hipSuccess) {
     free_plan(b);
-    return hip_fail(ctx, e, "batch graph");
+    return hip_fail(ctx, e, "batch upload");
   }
   const uint64_t h = ctx->next_batch++;
   ctx->batches[h] = b;
@@ -374,7 +324,7 @@ scan_status scan_batch_replay(scan_ctx* ctx, uint64_t handle, scan_result* out) 
   if (it == ctx->batches.end()) return fail(ctx, SCAN_EINVAL, "unknown batch handle %llu", (unsigned long long)handle);
   BatchPlan* b = it->second;
   hipError_t e = hipSetDevice(ctx->device);
-  if (e == hipSuccess) e = hipGraphLaunch(b->exec, ctx->stream);
+  if (e == hipSuccess) e = enqueue_batch(ctx, b, ctx->stream);
   if (e == hipSuccess && out && b->n_items)
     e = hipMemcpyAsync(b->mem.out_host, b->mem.out, sizeof(BatchOut) * b->n_items, hipMemcpyDeviceToHost,
                        ctx->stream);

@@ -24,14 +24,11 @@ BatchLaunchFn batch_class_fn(int cls) {
 
 // Per column: clear the result slot, find a dictionary's code range
 // [lower_bound(D, lo), lower_bound(D, hi)) by binary search in global memory.
-// Thread 0 also clears the per-class counters and cursors.
+// Thread 0 also clears the per-class item counters.
 __global__ __launch_bounds__(256) void batch_setup_kernel(BatchArgs a) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
-    for (int c = 0; c < kBatchClasses; ++c) {
-      a.counts[c] = 0;
-      a.cursors[c] = 0;
-    }
+    for (int c = 0; c < kBatchClasses; ++c) a.counts[c] = 0;
   }
   if (i >= a.n_cols) return;
   a.out[i] = BatchOut{0, 0, 0, 0};
@@ -177,21 +174,6 @@ __global__ __launch_bounds__(256) void batch_bin_kernel(BatchArgs a) {
   const int cls = batch_class(c.enc, c.strategy);
   const uint32_t pos = atomicAdd(&a.counts[cls], 1u);
   a.lists[(size_t)cls * a.n_work + pos] = i;
-}
-
-// Loads the code objects of this unit's kernels (deferred loading would
-// otherwise load them at their first launch, possibly inside a graph capture).
-hipError_t preload_batch_aux() {
-  hipFuncAttributes attr;
-  const void* fns[] = {reinterpret_cast<const void*>(&batch_setup_kernel),
-                       reinterpret_cast<const void*>(&batch_features_kernel),
-                       reinterpret_cast<const void*>(&batch_select_kernel),
-                       reinterpret_cast<const void*>(&batch_bin_kernel)};
-  for (const void* f : fns) {
-    const hipError_t e = hipFuncGetAttributes(&attr, f);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
 }
 
 hipError_t launch_batch_setup(const BatchArgs& a, hipStream_t st) {

@@ -1,15 +1,17 @@
 // Batched scans: thousands of columns of mixed length, width, encoding and
-// strategy in one captured graph.
+// strategy in one sequence of launches.
 //
 // Each column is cut into work items of up to G blocks.  A binning kernel
 // sorts the items into twelve classes (encoding x decoder x predicate mode),
 // reading each column's strategy from device memory (so a selector kernel that
-// ran earlier in the same graph decides it), and one persistent kernel per
-// class drains its item list through an atomic cursor: a wavefront takes an
-// item, switches (wave-uniformly) on the column's width to the same templated
-// range decoders the single-column kernels use, and adds its exact partial
-// (count, sum mod 2^64, blocks read) to the column's slot with three 64-bit
-// atomics.  Zone maps on/off is a per-column run-time flag.
+// ran earlier on the same stream decides it), and one persistent kernel per
+// class walks its item list on a static schedule: wavefront w of W takes items
+// w, w + W, ... below the class count (no shared cursor, every loop bounded
+// by counts fixed before the launch).  For an item it switches
+// (wave-uniformly) on the column's width to the same templated range
+// decoders the single-column kernels use, and adds its exact partial (count,
+// sum mod 2^64, blocks read) to the column's slot with three 64-bit atomics.
+// Zone maps on/off is a per-column run-time flag.
 #pragma once
 
 #include "scan_kernels.h"
@@ -58,8 +60,7 @@ struct BatchArgs {
   BatchCol* cols;
   const BatchWork* work;
   uint32_t* lists;     // kBatchClasses lists of n_work item indices
-  uint32_t* counts;    // kBatchClasses item counts
-  uint32_t* cursors;   // kBatchClasses atomic cursors
+  uint32_t* counts;    // kBatchClasses item counts (appended to by the binning kernel)
   BatchOut* out;       // per column
   uint32_t n_cols, n_work;
   int32_t cls;         // class handled by this launch
@@ -149,11 +150,11 @@ __global__ __launch_bounds__(256) void batch_scan(const BatchArgs a) {
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
   uint32_t* list = reinterpret_cast<uint32_t*>(smem) + wave * kBatchWaveWords;
   uint32_t* st = list + kListWords;
-  const uint32_t n = a.counts[a.cls];
+  const uint32_t cnt = __builtin_amdgcn_readfirstlane(a.counts[a.cls]);
+  const uint32_t n = cnt < a.n_work ? cnt : a.n_work;
   const uint32_t* items = a.lists + (size_t)a.cls * a.n_work;
-  while (true) {
-    const uint32_t idx = wave_next_item(&a.cursors[a.cls], lane);
-    if (idx >= n) break;
+  const uint32_t tw = gridDim.x * (blockDim.x >> 6);
+  for (uint32_t idx = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + wave); idx < n; idx += tw) {
     const BatchWork w = a.work[items[idx]];
     const BatchCol c = a.cols[w.col];
     const Params p = batch_params(c);

@@ -191,12 +191,6 @@ __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ theta, co
   theta[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
 }
 
-// Loads the code object of the forward kernel (see preload_batch_aux).
-hipError_t preload_mlp() {
-  hipFuncAttributes attr;
-  return hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&mlp_forward_kernel));
-}
-
 hipError_t launch_mlp_forward(const float* theta, const float* X, uint32_t rows, float* out, hipStream_t st) {
   if (rows == 0) return hipSuccess;
   hipLaunchKernelGGL(mlp_forward_kernel, dim3((rows + 63) / 64), dim3(64), 0, st, theta, X, rows, out);

@@ -31,7 +31,6 @@ struct scan_ctx {
   bool selector_ready = false;
   SelectorState* selector = nullptr;
   std::map<uint64_t, BatchPlan*> batches;
-  bool batch_kernels_loaded = false;  // batch graph kernels launched once outside capture
   SelectWork* select = nullptr;       // materializing select work space
   uint64_t next_batch = 1;
 };
