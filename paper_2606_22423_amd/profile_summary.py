@@ -203,12 +203,20 @@ def main(argv=None):
                   "| kernel | FETCH KiB (median) | WRITE KiB (median) | scaled bytes per launch | algorithmic bytes | ratio |",
                   "|---|---|---|---|---|---|"]
         keys = sorted(algo)
+        extra = []
         if args.bench_json:
-            # every per-width scan kernel of the bench: algorithmic bytes n * b / 8
+            # every per-width scan kernel of the bench's timed region (shown),
+            # and every other strategy its sweep ran on the same columns (kept
+            # in the traffic table only): algorithmic bytes n * b / 8
             for k in run["timed_kernels"]:
                 if k in fetch and k in write and k not in algo:
                     algo[k] = run["n"] * int(re.match(r"code_scan<B=(\d+),", k).group(1)) // 8
                     keys.append(k)
+            for k in sorted(fetch):
+                m = re.match(r"code_scan<B=(\d+),[a-z_]+/[a-z]+/nozm>", k)
+                if m and k in write and k not in algo:
+                    algo[k] = run["n"] * int(m.group(1)) // 8
+                    extra.append(k)
             keys.sort(key=lambda k: -algo[k])
         for k in keys:
             fv, wv = sorted(fetch.get(k, [])), sorted(write.get(k, []))
@@ -218,6 +226,19 @@ def main(argv=None):
             tb = fm * 1024 / sf + wm * 1024 / sw
             traffic[k] = {"bytes_per_launch": int(tb), "fetch_kib": fm, "write_kib": wm}
             lines.append("| `%s` | %.0f | %.1f | %.0f | %d | %.3f |" % (k, fm, wm, tb, algo[k], tb / algo[k]))
+        ratios = []
+        for k in extra:
+            fv, wv = sorted(fetch[k]), sorted(write[k])
+            if not fv or not wv or not sf or not sw:
+                continue
+            fm, wm = fv[len(fv) // 2], wv[len(wv) // 2]
+            tb = fm * 1024 / sf + wm * 1024 / sw
+            traffic[k] = {"bytes_per_launch": int(tb), "fetch_kib": fm, "write_kib": wm}
+            ratios.append(tb / algo[k])
+        if ratios:
+            lines += ["", "The sweep's other %d (width, strategy) kernels on the same columns (in the traffic table, "
+                      "not shown): scaled bytes / algorithmic bytes between %.3f and %.3f."
+                      % (len(ratios), min(ratios), max(ratios))]
     if args.sq:
         names = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM", "SQ_ACTIVE_INST_VALU",
                  "SQ_WAVE_CYCLES")
