@@ -370,7 +370,7 @@ class Context:
         return arr
 
     def batch_prepare(self, items) -> int:
-        """Capture a batch of ScanItem (see Column.item); returns its handle."""
+        """Plan a batch of ScanItem (see Column.item) once; returns its handle."""
         arr = self._items(items)
         h = ctypes.c_uint64()
         self.check(self.lib.scan_batch_prepare(self.h, arr, len(items), ctypes.byref(h)), "scan_batch_prepare")

@@ -1,4 +1,4 @@
-// Batch graph kernels around the class scans: per-column setup, zone-map
+// Batch kernels around the class scans: per-column setup, zone-map
 // features for the selector, strategy selection and item binning.
 #include "batch_kernels.h"
 
