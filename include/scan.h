@@ -364,8 +364,8 @@ typedef struct {
  * 184 bytes each) past hbm_budget_bytes.  Batching: a free stream launches the
  * oldest pending queries (at most max_batch) when the batch is full, when the
  * oldest has waited batch_window_us, when no stream is busy, or when a stream
- * has just completed.  window_blocks (0 = 16, at most 64) and wgs_per_cu
- * (0 = 2) shape the kernel launch. */
+ * has just completed.  window_blocks (0 = 64, at most 64) and wgs_per_cu
+ * (0 = as many as fit on a CU) shape the kernel launch. */
 typedef struct {
   uint64_t hbm_budget_bytes;
   uint32_t max_inflight;
@@ -385,7 +385,8 @@ void scan_table_destroy(scan_table* t);
  * n results.  Bad filter or sum column indices -> SCAN_EINVAL. */
 scan_status scan_query_run(scan_ctx* ctx, const scan_table* t, const scan_query* queries, size_t n,
                            scan_query_result* out);
-/* Launch shape of scan_query_run (0 = default). */
+/* Launch shape of scan_query_run (0 = default: 64-block windows, as many
+ * work-groups per CU as fit). */
 scan_status scan_query_set_tune(scan_ctx* ctx, int32_t wgs_per_cu, int32_t window_blocks);
 
 /* Start a server on the context's device (its own host thread and streams;

@@ -39,6 +39,17 @@ struct scan_table {
 
 namespace {
 
+// Default launch shape of the query kernel: 64-block windows, and as many
+// work-groups per CU as fit (the kernel is bound by dependent-load latency,
+// so every resident wavefront helps).
+constexpr uint32_t kDefaultWindow = 64;
+
+uint32_t default_wgs_per_cu() {
+  int occ = 0;
+  if (query_scan_occupancy(&occ) != hipSuccess || occ < 1) return 2u;
+  return (uint32_t)std::min(occ, 16);
+}
+
 double now_us() {
   using namespace std::chrono;
   return (double)duration_cast<nanoseconds>(steady_clock::now().time_since_epoch()).count() * 1e-3;
@@ -298,8 +309,9 @@ scan_status scan_query_run(scan_ctx* ctx, const scan_table* t, const scan_query*
     scan_status st = check_query(ctx, t, queries[i]);
     if (st != SCAN_OK) return st;
   }
-  const scan_tune tn = effective_tune(ctx, -2, 0, -1);
-  const uint32_t G = (uint32_t)std::clamp(tn.window_blocks, 1, 64);
+  const auto tit = ctx->tunes.find(std::make_tuple((int32_t)-2, 0u, (int32_t)-1));
+  const scan_tune tn = tit != ctx->tunes.end() ? tit->second : scan_tune{0, 0, 0, 0};
+  const uint32_t G = tn.window_blocks > 0 ? (uint32_t)std::min(tn.window_blocks, 64) : kDefaultWindow;
   if (((t->nb + G - 1) / G) * (uint64_t)n >= (1ull << 31)) return fail(ctx, SCAN_EINVAL, "too many work items");
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
@@ -311,7 +323,8 @@ scan_status scan_query_run(scan_ctx* ctx, const scan_table* t, const scan_query*
   }
   for (size_t i = 0; i < n; ++i) s.q_host[i] = make_desc(queries[i]);
   const double t0 = now_us();
-  const uint32_t grid = (uint32_t)ctx->cus * (uint32_t)std::clamp(tn.wgs_per_cu, 1, 16);
+  const uint32_t grid = (uint32_t)ctx->cus * (tn.wgs_per_cu > 0 ? (uint32_t)std::min(tn.wgs_per_cu, 16)
+                                                                   : default_wgs_per_cu());
   e = enqueue_queries(t, s, (uint32_t)n, G, grid, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   const double t1 = now_us();
@@ -346,7 +359,7 @@ scan_status scan_server_create(scan_ctx* ctx, const scan_table* t, const scan_se
   if (!t || !out) return fail(ctx, SCAN_EINVAL, "table and out must not be NULL");
   scan_status st = check_config(ctx, cfg);
   if (st != SCAN_OK) return st;
-  const uint32_t G = cfg->window_blocks ? cfg->window_blocks : 16u;
+  const uint32_t G = cfg->window_blocks ? cfg->window_blocks : kDefaultWindow;
   if (((t->nb + G - 1) / G) * (uint64_t)cfg->max_batch >= (1ull << 31))
     return fail(ctx, SCAN_EINVAL, "max_batch x windows exceeds 2^31 work items");
   *out = nullptr;
@@ -357,7 +370,7 @@ scan_status scan_server_create(scan_ctx* ctx, const scan_table* t, const scan_se
   s->table = t;
   s->pol.cfg = *cfg;
   s->G = G;
-  s->grid = (uint32_t)ctx->cus * (cfg->wgs_per_cu ? cfg->wgs_per_cu : 2u);
+  s->grid = (uint32_t)ctx->cus * (cfg->wgs_per_cu ? cfg->wgs_per_cu : default_wgs_per_cu());
   const uint32_t ns = cfg->n_streams;
   s->streams.assign(ns, nullptr);
   s->done_ev.assign(ns, nullptr);

@@ -66,5 +66,6 @@ struct QArgs {
 
 hipError_t launch_query_setup(const QArgs& a, hipStream_t st);
 hipError_t launch_query_scan(const QArgs& a, uint32_t grid, hipStream_t st);
+hipError_t query_scan_occupancy(int* wgs_per_cu);
 
 }  // namespace scan_dev
