@@ -200,7 +200,10 @@ scan_status scan_tune_save(scan_ctx* ctx, const char* path);
 scan_status scan_tune_load(scan_ctx* ctx, const char* path);
 
 /* ------------------------------------------------------------- run length */
-/* Run-length encoded u32 column: runs never cross a 1024-value block; run r
+/* Run-length encoding (the paper, "Method": implemented there alongside the
+ * bit-packed decoders, no result reported; the format below is this
+ * library's).
+ * Run-length encoded u32 column: runs never cross a 1024-value block; run r
  * has value run_value[r] and length run_len[r] (1..1024); block k owns runs
  * block_run[k] .. block_run[k+1]-1.  The scan tests the predicate once per run
  * and adds the run's length to COUNT and value x length to SUM (mod 2^64). */
@@ -255,7 +258,8 @@ scan_status scan_gather(scan_ctx* ctx, const scan_column* col, int32_t enc, uint
                         uint64_t n, int64_t* values);
 
 /* ---------------------------------------------------------------- batches */
-/* Many columns (mixed length, width, encoding, strategy) scanned by one fixed
+/* Not in the paper (the workload's mixed-column batch).
+ * Many columns (mixed length, width, encoding, strategy) scanned by one fixed
  * sequence of launches, whatever the number of columns: per-column setup,
  * strategy selection on the device (the loaded selector for SCAN_STRAT_AUTO
  * items, else the heuristic), binning of the columns' windows of blocks by
@@ -284,7 +288,8 @@ scan_status scan_batch_run(scan_ctx* ctx, const scan_item* items, size_t n_items
 scan_status scan_batch_set_tune(scan_ctx* ctx, const scan_tune* t);
 
 /* --------------------------------------------------------------- selector */
-/* The strategy selector is a fully connected fp32 network 6 -> 64 -> 64 -> 8
+/* Not in the paper (the workload's learned strategy choice).
+ * The strategy selector is a fully connected fp32 network 6 -> 64 -> 64 -> 8
  * (ReLU after both hidden layers) predicting a log-time for each of the eight
  * row-major strategies: class c = decoder (c & 1: RM_LDS or RM_DIRECT),
  * predicate mode ((c >> 1) & 1), zone maps ((c >> 2) & 1).  The library picks
@@ -323,7 +328,9 @@ scan_status scan_adam_step(scan_ctx* ctx, float* theta, const float* grad, float
                            int32_t step, float lr, float beta1, float beta2, float eps);
 
 /* ---------------------------------------------------------------- serving */
-/* A table: columns of equal row count, each row-major frame-of-reference
+/* Not in the paper (the workload's serving loop); each query is the paper's
+ * fused scan ("Method") over a conjunction of range predicates.
+ * A table: columns of equal row count, each row-major frame-of-reference
  * (optional per-block references) or dictionary, any width 1..32, all with
  * zone maps.  A query: COUNT and SUM(sum_col) over the rows where every filter
  * conjunct filter_col[f] in [lo_f, hi_f) holds (1..3 conjuncts; values for FOR
@@ -435,7 +442,9 @@ scan_status scan_encode_dict(const uint32_t* codes, uint64_t n, uint32_t b, uint
  * *n_runs receives the number of runs. */
 scan_status scan_rle_encode(const uint32_t* values, uint64_t n, uint32_t* run_value, uint16_t* run_len,
                             uint64_t* block_run, uint32_t* zone_min, uint32_t* zone_max, uint64_t* n_runs);
-/* Per-block sums of decoded values mod 2^64 (host pointers; out has nb
+/* Per-block sums for the all-match shortcut (an extension of the paper's
+ * per-block zone maps, "Method"; not in the paper).
+ * Per-block sums of decoded values mod 2^64 (host pointers; out has nb
  * entries) for scan_column.block_sum: enc SCAN_ENC_FOR takes u32 values,
  * SCAN_ENC_DELTA_FOR int64 values, SCAN_ENC_DICT u32 codes and the dictionary
  * (dict_len entries; a code >= dict_len -> SCAN_EINVAL). */
@@ -443,7 +452,10 @@ scan_status scan_block_sums(int32_t enc, const void* values, uint64_t n, const i
                             uint64_t* out);
 
 /* ----------------------------------------------------- bandwidth probes */
-/* Streaming read of `bytes` (multiple of 16) from `buf` (device) with 16-byte
+/* The paper measures beta per machine as the empirical sequential-read
+ * maximum (buffers much larger than the last-level cache) and reports STREAM
+ * triad beside it ("Method"); these probes measure both on the device.
+ * Streaming read of `bytes` (multiple of 16) from `buf` (device) with 16-byte
  * loads; `wgs` work-groups of `wg_size` threads (0 = defaults); `unroll`
  * independent loads in flight per thread (1, 2, 4 or 8).  Writes a checksum
  * into sink[0] (device u64) so the reads cannot be elided.  Enqueue only. */
