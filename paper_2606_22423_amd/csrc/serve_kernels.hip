@@ -33,7 +33,10 @@ __global__ __launch_bounds__(256) void query_setup_kernel(QArgs a) {
   d.empty = empty;
 }
 
-__global__ __launch_bounds__(256) void query_scan_kernel(const QArgs a) {
+// At most 64 VGPRs (the occupancy hint), so that eight work-groups (32
+// wavefronts, the most a CU holds) are resident: the kernel waits on
+// dependent loads and every resident wavefront hides latency.
+__global__ __launch_bounds__(256, 8) void query_scan_kernel(const QArgs a) {
   __shared__ __align__(16) uint32_t lds[kWavesPerWg][kRtStageWords];
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
   uint32_t* st = lds[wave];
