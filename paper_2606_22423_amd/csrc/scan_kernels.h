@@ -354,15 +354,17 @@ struct BlockCursor {
   }
 };
 
-// Branch-free COUNT and SUM of the 32 codes a lane holds, for B = 1, 2, 4 or
-// 8 (frame of reference, full blocks): SIMD within a register.  The codes are
-// spread into fields of F = 2B bits (odd and even codes apart), so every
-// field has B spare bits: one subtraction tests all fields of a register
-// against the code window with no borrow between fields, and the top bit of
-// each field is its pass flag.  v_bcnt counts the flags; an unsigned dot
-// product of the fields with the 0/1 flags (dot8 of nibbles, dot4 of bytes,
-// dot2 of halves) adds the passing codes.  B = 1 needs only a popcount per
-// word.  Code c passes iff (c - loc) <= wm1 (PF_LO0: loc = 0).
+// Branch-free COUNT and SUM of the 32 codes a lane holds, for B <= 8 (frame
+// of reference, full blocks): SIMD within a register.  The codes are spread
+// into fields with spare bits above each code (B = 2, 4, 8: fields of 2B
+// bits, odd and even codes apart; B = 3, 5, 6, 7: four consecutive codes
+// shifted into the four bytes of a register), so one subtraction tests all
+// fields of a register against the code window with no borrow between
+// fields, and the top bit of each field is its pass flag.  v_bcnt counts the
+// flags; an unsigned dot product of the fields with the 0/1 flags (dot8 of
+// nibbles, dot4 of bytes, dot2 of halves) adds the passing codes.  B = 1
+// needs only a popcount per word.  Code c passes iff (c - loc) <= wm1
+// (PF_LO0: loc = 0).
 template <int B, int PF>
 __device__ __forceinline__ void swar_count_sum(const uint32_t (&w)[B], uint32_t loc, uint32_t wm1, uint32_t& lc,
                                                uint32_t& part) {
@@ -372,6 +374,26 @@ __device__ __forceinline__ void swar_count_sum(const uint32_t (&w)[B], uint32_t 
     const bool p1 = loc <= 1u && loc + wm1 >= 1u;      // code 1 in the window
     lc += (p0 ? 32u - pc : 0u) + (p1 ? pc : 0u);
     part += p1 ? pc : 0u;
+  } else if constexpr (B == 3 || B == 5 || B == 6 || B == 7) {
+    constexpr uint32_t m0 = (1u << B) - 1u;
+    constexpr uint32_t hm = 0x80808080u;
+    const uint32_t locr = loc * 0x01010101u;
+    const uint32_t wr = (0x80u + wm1) * 0x01010101u;
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+      // codes 4g .. 4g+3: stream bits [4Bg, 4Bg + 4B)
+      const int bit = 4 * B * g, wi = bit >> 5, sh = bit & 31;
+      const int wn = wi + 1 < B ? wi + 1 : wi;  // only read when the group straddles a word
+      const uint32_t chunk = sh + 4 * B <= 32 ? (w[wi] >> sh) : funnel(w[wn], w[wi], sh);
+      uint32_t x = chunk & m0;
+      x |= (chunk << (8 - B)) & (m0 << 8);
+      x |= (chunk << (16 - 2 * B)) & (m0 << 16);
+      x |= (chunk << (24 - 3 * B)) & (m0 << 24);
+      const uint32_t g8 = PF == PF_LO0 ? x : (((x | hm) - locr) & ~hm);
+      const uint32_t flags = (wr - g8) & hm;
+      lc += (uint32_t)__builtin_popcount(flags);
+      part = __builtin_amdgcn_udot4(x, flags >> 7, part, false);
+    }
   } else {
     constexpr int F = 2 * B;
     constexpr uint32_t rep = F == 4 ? 0x11111111u : F == 8 ? 0x01010101u : 0x00010001u;
@@ -420,7 +442,7 @@ __device__ __forceinline__ void decode_pair(const Params& p, WaveState<uint32_t>
   if (act_m == 0) return;
   const uint32_t limit = (TAIL && kb == p.nb - 1) ? p.tail : kBlockValues;
   PartT<B, ENC> part = 0;
-  if constexpr (MODE == MODE_BF && ENC == ENC_FOR && !TAIL && (B == 1 || B == 2 || B == 4 || B == 8)) {
+  if constexpr (MODE == MODE_BF && ENC == ENC_FOR && !TAIL && B <= 8) {
     uint32_t lc = 0, sp = 0;
     swar_count_sum<B, PF>(w, cr.loc, cr.wm1, lc, sp);
     if (act) {

@@ -124,12 +124,12 @@ def test_for_block_references(ctx, b):
             check(ctx.run(col, lo, hi, s), want, (s >> 3) & 1, (b, lo, hi, s), want_off)
 
 
-@pytest.mark.parametrize("b", [1, 2, 4, 8])
+@pytest.mark.parametrize("b", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_packed_field_widths_every_code_window(ctx, b):
-    """b = 1, 2, 4, 8 take the packed-field (SWAR) path on full blocks: every
-    code window [lo, hi) at b <= 4 (and 300 at b = 8, with the extremes), on
-    both register decoders, with and without block references, against the
-    oracle.  The ragged last block goes through the per-code loop."""
+    """b <= 8 takes the packed-field (SWAR) path on full blocks: every code
+    window [lo, hi) at b <= 4 (300 and the extremes above), on both register
+    decoders, with and without block references, against the oracle.  The
+    ragged last block goes through the per-code loop."""
     n = 3 * 1024 + 517
     top = 1 << b
     v = synth.width_values(synth.pcg32(7, b, n), b)
