@@ -354,17 +354,17 @@ struct BlockCursor {
   }
 };
 
-// Branch-free COUNT and SUM of the 32 codes a lane holds, for B <= 8 (frame
+// Branch-free COUNT and SUM of the 32 codes a lane holds, for B <= 15 (frame
 // of reference, full blocks): SIMD within a register.  The codes are spread
 // into fields with spare bits above each code (B = 2, 4, 8: fields of 2B
 // bits, odd and even codes apart; B = 3, 5, 6, 7: four consecutive codes
-// shifted into the four bytes of a register), so one subtraction tests all
-// fields of a register against the code window with no borrow between
-// fields, and the top bit of each field is its pass flag.  v_bcnt counts the
-// flags; an unsigned dot product of the fields with the 0/1 flags (dot8 of
-// nibbles, dot4 of bytes, dot2 of halves) adds the passing codes.  B = 1
-// needs only a popcount per word.  Code c passes iff (c - loc) <= wm1
-// (PF_LO0: loc = 0).
+// shifted into the four bytes of a register; B = 9-15: two consecutive codes
+// into the two halves), so one subtraction tests all fields of a register
+// against the code window with no borrow between fields, and the top bit of
+// each field is its pass flag.  v_bcnt counts the flags; an unsigned dot
+// product of the fields with the 0/1 flags (dot8 of nibbles, dot4 of bytes,
+// dot2 of halves) adds the passing codes.  B = 1 needs only a popcount per
+// word.  Code c passes iff (c - loc) <= wm1 (PF_LO0: loc = 0).
 template <int B, int PF>
 __device__ __forceinline__ void swar_count_sum(const uint32_t (&w)[B], uint32_t loc, uint32_t wm1, uint32_t& lc,
                                                uint32_t& part) {
@@ -393,6 +393,25 @@ __device__ __forceinline__ void swar_count_sum(const uint32_t (&w)[B], uint32_t 
       const uint32_t flags = (wr - g8) & hm;
       lc += (uint32_t)__builtin_popcount(flags);
       part = __builtin_amdgcn_udot4(x, flags >> 7, part, false);
+    }
+  } else if constexpr (B >= 9 && B <= 15) {
+    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+    constexpr uint32_t m0 = (1u << B) - 1u;
+    constexpr uint32_t hm = 0x80008000u;
+    const uint32_t locr = loc * 0x00010001u;
+    const uint32_t wr = (0x8000u + wm1) * 0x00010001u;
+#pragma unroll
+    for (int g = 0; g < 16; ++g) {
+      // codes 2g, 2g+1: stream bits [2Bg, 2Bg + 2B), into the two halves
+      const int bit = 2 * B * g, wi = bit >> 5, sh = bit & 31;
+      const int wn = wi + 1 < B ? wi + 1 : wi;  // only read when the pair straddles a word
+      const uint32_t chunk = sh + 2 * B <= 32 ? (w[wi] >> sh) : funnel(w[wn], w[wi], sh);
+      const uint32_t x = (chunk & m0) | ((chunk << (16 - B)) & (m0 << 16));
+      const uint32_t g16 = PF == PF_LO0 ? x : (((x | hm) - locr) & ~hm);
+      const uint32_t flags = (wr - g16) & hm;
+      lc += (uint32_t)__builtin_popcount(flags);
+      part = __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, x), __builtin_bit_cast(u16x2, flags >> 15), part,
+                                    false);
     }
   } else {
     constexpr int F = 2 * B;
@@ -442,7 +461,7 @@ __device__ __forceinline__ void decode_pair(const Params& p, WaveState<uint32_t>
   if (act_m == 0) return;
   const uint32_t limit = (TAIL && kb == p.nb - 1) ? p.tail : kBlockValues;
   PartT<B, ENC> part = 0;
-  if constexpr (MODE == MODE_BF && ENC == ENC_FOR && !TAIL && B <= 8) {
+  if constexpr (MODE == MODE_BF && ENC == ENC_FOR && !TAIL && B <= 15) {
     uint32_t lc = 0, sp = 0;
     swar_count_sum<B, PF>(w, cr.loc, cr.wm1, lc, sp);
     if (act) {

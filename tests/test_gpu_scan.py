@@ -124,9 +124,9 @@ def test_for_block_references(ctx, b):
             check(ctx.run(col, lo, hi, s), want, (s >> 3) & 1, (b, lo, hi, s), want_off)
 
 
-@pytest.mark.parametrize("b", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("b", list(range(1, 16)))
 def test_packed_field_widths_every_code_window(ctx, b):
-    """b <= 8 takes the packed-field (SWAR) path on full blocks: every code
+    """b <= 15 takes the packed-field (SWAR) path on full blocks: every code
     window [lo, hi) at b <= 4 (300 and the extremes above), on both register
     decoders, with and without block references, against the oracle.  The
     ragged last block goes through the per-code loop."""
@@ -135,7 +135,7 @@ def test_packed_field_widths_every_code_window(ctx, b):
     v = synth.width_values(synth.pcg32(7, b, n), b)
     w = oracle.pack_rm(v, b)
     col, coli = api.encode_for(v, b), api.encode_for(v, b, layout=LAYOUT_LI)
-    base = (np.repeat(np.arange(4, dtype=np.uint64) * 1_000_003, 1024)[:n]).astype(np.uint64)
+    base = (np.repeat(np.arange(4, dtype=np.uint64) * 1_000_003, 1024)[:n]).astype(np.uint64)  # u32-safe for b <= 15
     vr = (base + v.astype(np.uint64)).astype(np.uint32)
     refs, codes = oracle.for_encode(vr, b, policy=1)
     wr = oracle.pack_rm(codes, b)
