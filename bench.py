@@ -228,7 +228,7 @@ def zonemap_leg(ctx, torch, n_log2, beta_gbs, reps=5):
     per = n >> 16  # copies of each value
     sigmas = (1e-4, 1e-3, 1e-2, 0.1, 0.3, 0.5)
     preds = [synth.config3_predicate(sg) for sg in sigmas]
-    evict = torch.empty(128 << 20, dtype=torch.int32, device="cuda")
+    evict = torch.empty(256 << 20, dtype=torch.int32, device="cuda")
     out = torch.zeros(8, dtype=torch.int64, device="cuda")
     rows, want = [], {}
     t0 = time.time()
@@ -305,6 +305,105 @@ def zonemap_leg(ctx, torch, n_log2, beta_gbs, reps=5):
                         "[lo, lo+round(sigma 2^16)), zone maps (+ all-match) vs off, bit-packed and run-length "
                         "copies, cold cache, median of %d" % (n_log2, reps),
             "identical_across_levels_and_zone_maps": True, "sorted_closed_forms": True, "points": rows}
+
+
+def controls_leg(ctx, torch, beta_gbs, cols_rm, reps=7, burst=50):
+    """Negative control on the cache (section 3: data that fits the last-level
+    cache reads faster than the memory bandwidth allows).  GPU form: FOR columns
+    at b = 32 and b = 8 whose payload ranges from 1 MiB (workload 1, N = 2^20
+    at b = 8) through the 256 MiB last-level cache to 1 GiB, predicate
+    v < round(0.1 2^b), branch-free row-major direct decoder, launch shape
+    autotuned per column.  Warm: one launch, then `burst` launches back to back
+    between two events, time per launch = total / burst; cold: the cache flushed
+    before each single launch, median of reps.  f = payload bytes / time / beta.
+    Results are checked against a numpy count and sum of the host values."""
+    import numpy as np
+
+    import synth
+    from paper_2606_22423_amd import api
+    from paper_2606_22423_amd._lib import DEC_RM_DIRECT, ENC_FOR, strategy
+
+    s = strategy(DEC_RM_DIRECT, 0, 0)
+    saved = {b: ctx.get_tune(ENC_FOR, b, s) for b in (8, 32)}
+    evict = torch.empty(256 << 20, dtype=torch.int32, device="cuda")
+    out = torch.zeros(5, dtype=torch.int64, device="cuda")
+    draws = synth.config2_draws(1 << 26)
+    cases = [(8, 20, "workload 1")] + [(8, n, None) for n in (24, 26, 27)] + \
+            [(32, n, None) for n in (20, 22, 23, 24, 25, 26, 28)]
+    rows = []
+    for b, nl, tag in cases:
+        n = 1 << nl
+        if tag:
+            v, lo, hi = synth.config1(n)
+        else:
+            lo, hi = 0, synth.lt_bound(0.1, b)
+            v = None if (b == 32 and nl == 28) else synth.config2_column(draws[:n], b)
+        col = cols_rm[32] if v is None else api.encode_for(v, b)
+        if v is not None:
+            sel = v[(v >= lo) & (v < hi)].astype(np.int64)
+            want = (int(sel.size), int(sel.sum()))
+            del sel
+        else:
+            want = None
+        ctx.autotune(col, lo, hi, s, reps=5)
+        r = ctx.run(col, lo, hi, s)
+        if want is not None and (r["count"], r["sum"]) != want:
+            raise RuntimeError("cache control b=%d N=2^%d: %s vs numpy %s" % (b, nl, r, want))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        warm = []
+        for _ in range(3):
+            ctx.run_async(col, lo, hi, s, out)
+            e0.record()
+            for _ in range(burst):
+                ctx.run_async(col, lo, hi, s, out)
+            e1.record()
+            e1.synchronize()
+            warm.append(e0.elapsed_time(e1) * 1e-3 / burst)
+        cold = []
+        for _ in range(reps):
+            ctx.cache_flush(evict, evict.numel() * 4)
+            e0.record()
+            ctx.run_async(col, lo, hi, s, out)
+            e1.record()
+            e1.synchronize()
+            cold.append(e0.elapsed_time(e1) * 1e-3)
+        tw, tc = float(np.median(warm)), float(np.median(cold))
+        nbytes = n * b // 8
+        rows.append({"b": b, "n_log2": nl, "payload_mib": nbytes / 2**20, "workload": tag,
+                     "warm_us": round(tw * 1e6, 2), "cold_us": round(tc * 1e6, 2),
+                     "f_warm": round(nbytes / tw / 1e9 / beta_gbs, 4),
+                     "f_cold": round(nbytes / tc / 1e9 / beta_gbs, 4)})
+        log("[bench] cache control b=%d N=2^%d: warm %.1f us (f %.2f), cold %.1f us (f %.2f)" %
+            (b, nl, tw * 1e6, rows[-1]["f_warm"], tc * 1e6, rows[-1]["f_cold"]))
+        # the same column k times in one batch: ~1 GiB of logical reads per
+        # replay with no launch per re-read
+        k = max(1, (1 << 30) // nbytes)
+        h = ctx.batch_prepare([col.item(lo, hi, s, zone_maps=False)] * k)
+        try:
+            got = ctx.batch_replay(h, k)
+            if any((g["count"], g["sum"]) != (r["count"], r["sum"]) for g in got):
+                raise RuntimeError("cache control b=%d N=2^%d: batched re-reads differ" % (b, nl))
+            tb = []
+            for _ in range(3):
+                e0.record()
+                ctx.batch_replay(h, wait=False)
+                e1.record()
+                e1.synchronize()
+                tb.append(e0.elapsed_time(e1) * 1e-3)
+        finally:
+            ctx.batch_release(h)
+        tb = float(np.median(tb))
+        rows[-1].update({"batched_rereads": k, "batched_us": round(tb * 1e6, 2),
+                         "f_batched": round(k * nbytes / tb / 1e9 / beta_gbs, 4)})
+        log("[bench]   %d re-reads in one batch: %.1f us (f %.2f)" % (k, tb * 1e6, rows[-1]["f_batched"]))
+        del col
+    for b, t in saved.items():
+        ctx.set_tune(ENC_FOR, b, s, *t)
+    in_cache = [r["f_warm"] for r in rows if r["payload_mib"] <= 128 and r["f_cold"] <= 1.0]
+    return {"workload": "FOR b=8 (N=2^20 workload 1, 2^24, 2^26, 2^27) and b=32 (N=2^20..2^26, 2^28), "
+                        "v < round(0.1 2^b) (v < 26 for workload 1), rm-direct branch-free, autotuned per column; "
+                        "warm = %d back-to-back launches, cold = flushed single launch, median of %d" % (burst, reps),
+            "max_f_warm_in_cache": max(in_cache) if in_cache else None, "points": rows}
 
 
 def serve_leg(ctx, torch, rows_log2, nq, lambdas=(0.25, 0.5, 0.8, 0.95), warm=500):
@@ -415,6 +514,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--detail", default=None, help="write the full sweep as JSON to this file")
     ap.add_argument("--no-autotune", action="store_true", help="library default launch shapes")
+    ap.add_argument("--no-controls", action="store_true", help="skip the cache negative control")
     ap.add_argument("--batch-cols", type=int, default=4096, help="mixed-column workload size (0: skip it)")
     ap.add_argument("--zonemap-log2", type=int, default=30, help="zone-map workload rows (0: skip the leg)")
     ap.add_argument("--serve-rows-log2", type=int, default=28, help="serving table rows (0: skip the serving leg)")
@@ -610,6 +710,21 @@ def main():
     del sel_out
     log("[bench] select: %s" % [(r["b"], r["sigma"], r["ms"]) for r in select_rows])
 
+    # --- negative controls of section 3
+    controls = {}
+    if not args.no_controls:
+        controls["cache"] = controls_leg(ctx, torch, beta_gbs, cols_rm)
+    # byte-aligned widths: the plain-load decoder against the best generic one
+    # (branch-free and compaction each), same columns, headline selectivity
+    ba = {}
+    for b in (8, 16, 32):
+        for sv in (0, 1):
+            tb = sweep[(SIGMA, strategy(DEC_BYTES, sv, 0))][b]
+            tg = min(sweep[(SIGMA, strategy(d, sv, 0))][b] for d in (DEC_RM_LDS, DEC_RM_DIRECT, DEC_LI))
+            ba["%d/%s" % (b, "sv" if sv else "bf")] = {"bytes_ms": round(tb * 1e3, 4), "generic_ms": round(tg * 1e3, 4),
+                                                      "ratio": round(tb / tg, 4)}
+    controls["byte_aligned_vs_generic"] = ba
+
     # --- branch-free vs compaction crossover per width (needs the sigma sweep)
     crossover = None
     if len(sigmas) > 2:
@@ -676,6 +791,8 @@ def main():
     zonemap = None
     if args.zonemap_log2 > 0:
         zonemap = zonemap_leg(ctx, torch, args.zonemap_log2, beta_gbs)
+        rnd = [r["blocks_read_frac"] for r in zonemap["points"] if r["s"] == "random" and r["zone_maps"]]
+        controls["random_zone_maps_min_read_frac"] = min(rnd)
 
     serving = None
     if args.serve_rows_log2 > 0:
@@ -701,6 +818,7 @@ def main():
         "cpu_baseline": cpu,
         "batch": batch,
         "zonemap": zonemap,
+        "controls": controls,
         "serving": serving,
     }
     if args.detail:

@@ -464,7 +464,11 @@ scan_status scan_beta_read(scan_ctx* ctx, const void* buf, uint64_t bytes, int32
 /* STREAM triad a[i] = b[i] + s*c[i] over n floats (device). Enqueue only. */
 scan_status scan_beta_triad(scan_ctx* ctx, float* a, const float* b, const float* c, float s,
                             uint64_t n);
-/* Overwrite `bytes` of device scratch so that later reads miss the caches. Enqueue only. */
+/* Read `bytes` (multiple of 16) of device scratch `buf` so that later reads
+ * of other data miss the caches; the lines it leaves cached are clean, so no
+ * write-back competes with the next kernel.  Use a buffer several times the
+ * 256 MiB last-level cache.  The contents of `buf` are left as they were, except
+ * that its first 16 bytes may be overwritten.  Enqueue only. */
 scan_status scan_cache_flush(scan_ctx* ctx, void* buf, uint64_t bytes);
 
 #ifdef __cplusplus

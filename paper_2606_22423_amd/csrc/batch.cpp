@@ -173,6 +173,7 @@ struct BatchPlan {
   BatchBuffers mem;
   bool selector = false;
   uint32_t grid = 0;
+  uint32_t grid_cls[kBatchClasses] = {};  // grid clamped to the work-groups that fit at once
 };
 
 static void free_plan(BatchPlan* b) {
@@ -208,7 +209,8 @@ static hipError_t enqueue_batch(scan_ctx* ctx, BatchPlan* b, hipStream_t st) {
   e = launch_batch_bin(make_args(b->mem, (uint32_t)b->n_items, b->n_work, 0), st);
   if (e != hipSuccess) return e;
   for (int cls = 0; cls < kBatchClasses; ++cls) {
-    e = batch_class_fn(cls)(make_args(b->mem, (uint32_t)b->n_items, b->n_work, cls), b->grid, 256, st, nullptr);
+    e = batch_class_fn(cls)(make_args(b->mem, (uint32_t)b->n_items, b->n_work, cls), b->grid_cls[cls], 256, st,
+                            nullptr);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -293,6 +295,14 @@ scan_status scan_batch_prepare(scan_ctx* ctx, const scan_item* items, size_t n_i
   b->n_items = n_items;
   b->selector = ctx->selector_ready;
   b->grid = (uint32_t)ctx->cus * (uint32_t)std::clamp(t.wgs_per_cu, 1, 16);
+  // dictionary classes hold the dictionary in LDS: fewer of their work-groups
+  // fit on a compute unit, and their static shares are sized by the grid
+  for (int cls = 0; cls < kBatchClasses; ++cls) {
+    int occ = 0;
+    b->grid_cls[cls] = b->grid;
+    if (batch_class_fn(cls)(make_args(b->mem, 0, 0, cls), 0, 256, ctx->stream, &occ) == hipSuccess && occ > 0)
+      b->grid_cls[cls] = std::min<uint32_t>(b->grid, (uint32_t)ctx->cus * (uint32_t)occ);
+  }
   std::vector<BatchWork> work;
   plan_cols(ctx, items, n_items, window, b->cols, b->status, &work);
   if (work.size() > 0xFFFFFFFFull) {

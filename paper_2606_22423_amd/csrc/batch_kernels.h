@@ -7,7 +7,8 @@
 // ran earlier on the same stream decides it), and one persistent kernel per
 // class walks its item list on a static schedule: wavefront w of W takes items
 // w, w + W, ... below the class count (no shared cursor, every loop bounded
-// by counts fixed before the launch).  For an item it switches
+// by counts fixed before the launch; dictionary classes split the list among
+// work-groups instead, see batch_dict_share).  For an item it switches
 // (wave-uniformly) on the column's width to the same templated range
 // decoders the single-column kernels use, and adds its exact partial (count,
 // sum mod 2^64, blocks read) to the column's slot with three 64-bit atomics.
@@ -135,6 +136,29 @@ __device__ __forceinline__ void batch_item(const Params& p, const BatchCol& c, u
   }
 }
 
+// Dictionary classes.  A per-value gather of dictionary entries from global
+// memory is bound by the vector memory unit's per-lane address processing, so
+// the dictionary (at most kMaxDict int64 entries) is staged in LDS; one copy
+// per wavefront does not fit, so the wavefronts of a work-group take items
+// together: the work-group walks its contiguous share of the class list, its
+// wavefronts split each item's blocks, and the dictionary is staged again only
+// when the column changes.  A wavefront keeps its partial across the items of
+// one column and adds it to the column's slot when the column changes.
+template <int MODE>
+__device__ __forceinline__ void dict_flush(WaveState<uint32_t>& s, uint32_t lane, const int64_t* dict_lds,
+                                           uint32_t dlast, BatchOut* out) {
+  if constexpr (MODE == MODE_SV) sv_drain_rest<ENC_DICT, uint32_t>(s, lane, dict_lds, dlast);
+  const uint64_t count = s.count + wave_sum_u64(s.lcount);
+  const uint64_t sum = wave_sum_u64(s.lsum + (lane == 0 ? s.refsum : 0ull));
+  if (lane == 0 && (count | sum | s.blocks)) {
+    atomicAdd(reinterpret_cast<unsigned long long*>(&out->count), (unsigned long long)count);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&out->sum), (unsigned long long)sum);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&out->blocks), (unsigned long long)s.blocks);
+  }
+  s.count = s.blocks = s.refsum = s.lsum = s.lcount = 0;
+  s.head = s.tail = 0;
+}
+
 #define SCAN_WIDTHS_ALL(F)                                                                                \
   F(1) F(2) F(3) F(4) F(5) F(6) F(7) F(8) F(9) F(10) F(11) F(12) F(13) F(14) F(15) F(16) F(17) F(18) F(19) F(20) \
       F(21) F(22) F(23) F(24) F(25) F(26) F(27) F(28) F(29) F(30) F(31) F(32)
@@ -144,24 +168,78 @@ __device__ __forceinline__ void batch_item(const Params& p, const BatchCol& c, u
     batch_item<B, ENC, DEC, MODE>(p, c, w.k0, w.k0 + w.nblk, lane, list, st, out); \
     break;
 
+#define BATCH_DICT_CASE(B)                                                                                    \
+  case B:                                                                                                     \
+    scan_range<B, DEC, MODE, ENC_DICT, PF_RANGE, true>(p, s, lane, list, st, w.k0 + b0, w.k0 + b1, 64, 64, dict, \
+                                                       dlast, c.clo, c.chi);                                  \
+    break;
+
+constexpr uint32_t kBatchDictBytes = kMaxDict * 8u;
+
+template <int DEC, int MODE>
+__device__ __forceinline__ void batch_dict_share(const BatchArgs& a, const uint32_t* items, uint32_t n,
+                                                 int64_t* dict, uint32_t* list, uint32_t* st, uint32_t lane,
+                                                 uint32_t wave) {
+  const uint32_t nw = blockDim.x >> 6;
+  const uint32_t per = n / gridDim.x + (n % gridDim.x ? 1u : 0u);
+  const uint64_t i0 = (uint64_t)blockIdx.x * per;
+  const uint64_t i1 = i0 + per < (uint64_t)n ? i0 + per : (uint64_t)n;
+  WaveState<uint32_t> s;
+  s.ring = st + 32u * 32u + 4u;
+  uint32_t cur = 0xFFFFFFFFu, dlast = 0;
+  for (uint64_t idx = i0; idx < i1; ++idx) {
+    const BatchWork w = a.work[items[idx]];
+    const uint32_t col = __builtin_amdgcn_readfirstlane(w.col);
+    if (col != cur) {
+      if (cur != 0xFFFFFFFFu) dict_flush<MODE>(s, lane, dict, dlast, a.out + cur);
+      __syncthreads();  // every wavefront is done with the previous dictionary
+      const int64_t* src = a.cols[col].dict;
+      const uint32_t len = a.cols[col].dict_len < kMaxDict ? a.cols[col].dict_len : kMaxDict;
+      for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) dict[i] = src[i];
+      __syncthreads();
+      cur = col;
+      dlast = len ? len - 1u : 0u;
+    }
+    const BatchCol c = a.cols[col];
+    const Params p = batch_params(c);
+    // this wavefront's share of the item's blocks
+    const uint32_t q = (w.nblk + nw - 1u) / nw;
+    const uint32_t b0 = wave * q < w.nblk ? wave * q : w.nblk;
+    const uint32_t b1 = b0 + q < w.nblk ? b0 + q : w.nblk;
+    if (b0 < b1) {
+      switch (c.b) {
+        SCAN_WIDTHS_ALL(BATCH_DICT_CASE)
+        default: break;
+      }
+    }
+  }
+  if (cur != 0xFFFFFFFFu) dict_flush<MODE>(s, lane, dict, dlast, a.out + cur);
+}
+
 template <int ENC, int DEC, int MODE>
 __global__ __launch_bounds__(256) void batch_scan(const BatchArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-  uint32_t* list = reinterpret_cast<uint32_t*>(smem) + wave * kBatchWaveWords;
+  constexpr uint32_t kDictBytes = ENC == ENC_DICT ? kBatchDictBytes : 0u;
+  uint32_t* list = reinterpret_cast<uint32_t*>(smem + kDictBytes) + wave * kBatchWaveWords;
   uint32_t* st = list + kListWords;
   const uint32_t cnt = __builtin_amdgcn_readfirstlane(a.counts[a.cls]);
   const uint32_t n = cnt < a.n_work ? cnt : a.n_work;
   const uint32_t* items = a.lists + (size_t)a.cls * a.n_work;
-  const uint32_t tw = gridDim.x * (blockDim.x >> 6);
-  for (uint32_t idx = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + wave); idx < n; idx += tw) {
-    const BatchWork w = a.work[items[idx]];
-    const BatchCol c = a.cols[w.col];
-    const Params p = batch_params(c);
-    BatchOut* out = a.out + w.col;
-    switch (c.b) {
-      SCAN_WIDTHS_ALL(BATCH_CASE)
-      default: break;
+  if constexpr (ENC == ENC_DICT) {
+    batch_dict_share<DEC, MODE>(a, items, n, reinterpret_cast<int64_t*>(smem), list, st, lane, wave);
+  } else {
+    const uint32_t tw = gridDim.x * (blockDim.x >> 6);
+    for (uint32_t idx = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + wave); idx < n;
+         idx += tw) {
+      const BatchWork w = a.work[items[idx]];
+      const BatchCol c = a.cols[w.col];
+      const Params p = batch_params(c);
+      BatchOut* out = a.out + w.col;
+      switch (c.b) {
+        SCAN_WIDTHS_ALL(BATCH_CASE)
+        default: break;
+      }
     }
   }
 }
@@ -170,7 +248,7 @@ using BatchLaunchFn = hipError_t (*)(const BatchArgs&, uint32_t grid, uint32_t b
 
 template <int ENC, int DEC, int MODE>
 hipError_t launch_batch_class(const BatchArgs& a, uint32_t grid, uint32_t block, hipStream_t st, int* occ) {
-  const uint32_t lds = (block / 64u) * kBatchWaveWords * 4u;
+  const uint32_t lds = (ENC == ENC_DICT ? kBatchDictBytes : 0u) + (block / 64u) * kBatchWaveWords * 4u;
   if (occ) return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, batch_scan<ENC, DEC, MODE>, (int)block, lds);
   hipLaunchKernelGGL((batch_scan<ENC, DEC, MODE>), dim3(grid), dim3(block), lds, st, a);
   return hipGetLastError();

@@ -174,6 +174,36 @@ def test_batch_window_and_occupancy_do_not_change_results(ctx, cases):
         ctx.batch_set_tune(0, 0)
 
 
+def test_dict_classes_many_items_per_work_group(ctx):
+    """Dictionary classes split their item list among work-groups, stage each
+    column's dictionary in LDS and carry a wavefront's partial across the items
+    of one column.  One-block windows and one work-group per compute unit give
+    each work-group several items spanning column changes, in every dictionary
+    class (both decoders, both predicate modes, zone maps on and off)."""
+    specs = [sp for sp in synth.config4_specs(150, seed=synth.SEED_BASE + 41, log2_min=12.0, log2_max=16.0, bmax=32)
+             if sp.enc == ENC_DICT]
+    dcases = [Case(sp) for sp in specs]
+    items, meta = [], []
+    for cls in range(4):
+        for j, c in enumerate(dcases):
+            zm = (j + cls) % 3 != 0
+            strat = strategy(cls & 1, (cls >> 1) & 1, 1 if zm else 0)
+            items.append(c.col.item(c.lo, c.hi, strat, zone_maps=zm))
+            meta.append((c, strat))
+    blocks = sum((c.spec.n + 1023) // 1024 for c in dcases)
+    say("dictionary batch:", len(dcases), "columns,", blocks, "blocks per class")
+    assert blocks >= 4 * 256  # with one-block windows: four or more items per work-group (256 compute units)
+    try:
+        for per_cu, win in ((1, 1), (1, 3), (0, 0)):
+            ctx.batch_set_tune(per_cu, win)
+            res = ctx.batch_run(items)
+            for (c, strat), got in zip(meta, res):
+                assert got["strategy_used"] == strat
+                check_item(c, got, c.lo, c.hi, (c.spec.index, c.spec.b, c.spec.n, strat, per_cu, win))
+    finally:
+        ctx.batch_set_tune(0, 0)
+
+
 def test_batch_invalid_items_report_status(ctx, cases):
     c = cases[5]
     good = c.col.item(c.lo, c.hi, class_strategy(1))
