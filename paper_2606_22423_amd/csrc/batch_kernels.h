@@ -1,7 +1,8 @@
 // Batched scans: thousands of columns of mixed length, width, encoding and
 // strategy in one sequence of launches.
 //
-// Each column is cut into work items of up to G blocks.  A binning kernel
+// Each column is cut into work items of up to G blocks (4G for dictionary
+// columns, whose items a work-group's four wavefronts share).  A binning kernel
 // sorts the items into twelve classes (encoding x decoder x predicate mode),
 // reading each column's strategy from device memory (so a selector kernel that
 // ran earlier on the same stream decides it), and one persistent kernel per
