@@ -143,9 +143,12 @@ void plan_cols(scan_ctx* ctx, const scan_item* items, size_t n, uint32_t window,
     c.heuristic = h;
     c.strategy = it.strategy >= 0 ? it.strategy : h;
     cols[i] = c;
-    // dictionary items are shared by the four wavefronts of a work-group:
-    // four windows each, so that every wavefront still scans a window
-    const uint64_t span = it.enc == SCAN_ENC_DICT ? 4u * (uint64_t)window : (uint64_t)window;
+    // items of four windows: fewer items (each costs its descriptor loads,
+    // pipeline start and result atomics) at little cost in balance; a
+    // dictionary item is shared by the four wavefronts of a work-group, one
+    // window each (measured on the mixed 4096-column batch: 3.13 -> 2.85 ms
+    // against one-window items for the other encodings)
+    const uint64_t span = 4u * (uint64_t)window;
     if (work && !empty)
       for (uint64_t k = 0; k < c.nb; k += span)
         work->push_back(BatchWork{(uint32_t)i, (uint32_t)std::min<uint64_t>(span, c.nb - k), k});
