@@ -399,11 +399,32 @@ def controls_leg(ctx, torch, beta_gbs, cols_rm, reps=7, burst=50):
         del col
     for b, t in saved.items():
         ctx.set_tune(ENC_FOR, b, s, *t)
+    # the same protocol on the plain sequential-read probe: what the cache
+    # itself delivers to a kernel that only reads
+    sink = torch.zeros(1, dtype=torch.int64, device="cuda")
+    read_rows = []
+    for mib in (16, 64, 128, 256, 1024):
+        nbytes = mib << 20
+        buf = evict[: nbytes // 4]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        warm = []
+        for _ in range(3):
+            ctx.beta_read(buf, nbytes, sink)
+            e0.record()
+            for _ in range(burst):
+                ctx.beta_read(buf, nbytes, sink)
+            e1.record()
+            e1.synchronize()
+            warm.append(e0.elapsed_time(e1) * 1e-3 / burst)
+        tw = float(np.median(warm))
+        read_rows.append({"mib": mib, "warm_us": round(tw * 1e6, 2), "f_warm": round(nbytes / tw / 1e9 / beta_gbs, 4)})
+        log("[bench] cache control: read probe %d MiB warm %.1f us (f %.2f)" % (mib, tw * 1e6, read_rows[-1]["f_warm"]))
     in_cache = [r["f_warm"] for r in rows if r["payload_mib"] <= 128 and r["f_cold"] <= 1.0]
     return {"workload": "FOR b=8 (N=2^20 workload 1, 2^24, 2^26, 2^27) and b=32 (N=2^20..2^26, 2^28), "
                         "v < round(0.1 2^b) (v < 26 for workload 1), rm-direct branch-free, autotuned per column; "
                         "warm = %d back-to-back launches, cold = flushed single launch, median of %d" % (burst, reps),
-            "max_f_warm_in_cache": max(in_cache) if in_cache else None, "points": rows}
+            "max_f_warm_in_cache": max(in_cache) if in_cache else None, "points": rows,
+            "read_probe": read_rows}
 
 
 def serve_leg(ctx, torch, rows_log2, nq, lambdas=(0.25, 0.5, 0.8, 0.95), warm=500):
