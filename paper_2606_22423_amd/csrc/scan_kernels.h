@@ -16,6 +16,8 @@
 //  * RM-LDS: the wavefront stages whole blocks in LDS with coalesced loads and
 //    lane l extracts values j = l + 64 t with a funnel shift;
 //  * byte-aligned (B = 8, 16, 32): plain u8/u16/u32 vector loads.
+// The decoders whose loads read whole cache lines across the wavefront
+// (lane-interleaved, the RM-LDS staging, byte-aligned) load non-temporally.
 // Per value: extract, one unsigned compare in code space
 // ((c - lo_c) <= w - 1; just c <= w - 1 when lo_c = 0), ballot of the compare
 // (the compare's lane mask), scalar popcount for COUNT, and the selected value
@@ -678,13 +680,20 @@ __device__ __forceinline__ void decode_bytes(const Params& p, WaveState<uint32_t
 
 // Coalesced staging loads of one block into registers (lane takes words
 // lane + 64 i), and their store into the block's LDS slot.
+// 16-byte non-temporal load (whole-line streaming reads, see load_pair_words).
+__device__ __forceinline__ uint4 load_stream16(const uint4* p) {
+  typedef uint32_t v4 __attribute__((ext_vector_type(4)));
+  const v4 v = __builtin_nontemporal_load(reinterpret_cast<const v4*>(p));
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 template <int B>
 __device__ __forceinline__ void stage_load(const uint32_t* __restrict__ blk, uint32_t lane,
                                            uint32_t (&r)[Geo<B>::kStageLoads]) {
 #pragma unroll
   for (int i = 0; i < Geo<B>::kStageLoads; ++i) {
     const uint32_t w = lane + 64u * i;
-    r[i] = ((32 * B) % 64 == 0 || w < 32u * B) ? blk[w] : 0u;
+    r[i] = ((32 * B) % 64 == 0 || w < 32u * B) ? __builtin_nontemporal_load(blk + w) : 0u;
   }
 }
 
@@ -767,7 +776,7 @@ __device__ __forceinline__ void run_bytes(const Params& p, WaveState<uint32_t>& 
     for (int j = 0; j < NB; ++j) {
       const uint4* blk = reinterpret_cast<const uint4*>(p.payload + step_block(base, mask, j) * (32u * B));
 #pragma unroll
-      for (int q = 0; q < Q; ++q) dst[j][q] = blk[64 * q + lane];
+      for (int q = 0; q < Q; ++q) dst[j][q] = load_stream16(blk + 64 * q + lane);
     }
   };
   auto decode = [&](uint64_t base, uint64_t mask, const uint4 (&src)[NB][Q]) {
