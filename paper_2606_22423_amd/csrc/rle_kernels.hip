@@ -35,8 +35,9 @@ __device__ __forceinline__ void take_runs(const RleParams& p, uint64_t q, uint64
   if (q >= r1) return;
   uint32_t v[4], l[4];
   if (q + 4u <= total) {
-    const u32x4 vv = *reinterpret_cast<const u32x4*>(p.run_value + q);
-    const u16x4 ll = *reinterpret_cast<const u16x4*>(p.run_len + q);
+    // adjacent lanes read adjacent runs: whole lines, streamed (non-temporal)
+    const u32x4 vv = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p.run_value + q));
+    const u16x4 ll = __builtin_nontemporal_load(reinterpret_cast<const u16x4*>(p.run_len + q));
     v[0] = vv.x, v[1] = vv.y, v[2] = vv.z, v[3] = vv.w;
     l[0] = ll.x, l[1] = ll.y, l[2] = ll.z, l[3] = ll.w;
   } else {
