@@ -3,7 +3,7 @@
 Builds frame-of-reference columns of 2^n_log2 uniform values at the given
 widths (row-major and lane-interleaved), autotunes each (width, strategy)
 pair exactly as bench.py does, then launches each pair `launches` times on a
-cold cache (a 512 MiB overwrite between launches).  For the HBM byte
+cold cache (a 512 MiB read of scratch between launches).  For the HBM byte
 counters it also runs two calibration kernels of known traffic: a streaming
 read of exactly 1 GiB (beta_read) and a triad over 2^26 floats (8 bytes read
 and 4 written per float).

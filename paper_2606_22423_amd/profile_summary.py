@@ -168,7 +168,7 @@ def main(argv=None):
                   "events in the same run." % (run["n"].bit_length() - 1, args.last, run["bench_avg_launch_ms"]), ""]
     else:
         lines += ["", "Workload: FOR columns of 2^%d uniform values, predicate v < round(0.1 * 2^b), zone maps off, "
-                  "cold cache per launch (512 MiB overwrite between launches); each (width, strategy) pair autotuned "
+                  "cold cache per launch (512 MiB read of scratch between launches); each (width, strategy) pair autotuned "
                   "as in bench.py, then launched %d times; the rows below are those %d launches (kernel trace)."
                   % (run["n"].bit_length() - 1, args.last, args.last), ""]
     lines += [

@@ -6,7 +6,8 @@
    seed of its own so that they never coincide with evaluation columns.
 2. Times each of the eight row-major strategies on each column: one scan
    launch between two HIP events on the context stream, after a cache-evicting
-   overwrite of a 512 MiB buffer, median of `reps`.
+   read of a 512 MiB scratch buffer (the shipped parameters were trained when
+   the eviction overwrote it), median of `reps`.
 3. Computes each column's selector features on the device (zone maps only).
 4. Fits the 6 -> 64 -> 64 -> 8 network to log-time per strategy (masked mean
    squared error, Adam, mini-batches) with the library's device kernels.
