@@ -131,27 +131,17 @@ scan_status check_strategy(scan_ctx* ctx, const scan_column* col, int32_t enc, u
 scan_tune default_tune(int32_t enc, uint32_t b, int32_t s) {
   (void)enc;
   scan_tune t;
-  // From the autotuner on MI355X (2^28-value columns, cold): few resident
-  // wavefronts, each streaming its own windows, beat full occupancy (fewer
-  // concurrent streams into HBM); narrow widths are compute-bound and want
-  // more wavefronts and longer windows.
+  // From the autotuner on MI355X (2^28-value columns, cold, branch-free):
+  // few resident wavefronts, each streaming its own windows, beat full
+  // occupancy (fewer concurrent streams into HBM); narrow widths want long
+  // windows, and b = 1 and 3 a second work-group per CU (four measured 1.6x
+  // slower); the transposed decoder wants longer windows than the row-major
+  // ones at high widths.
   t.wg_size = 256;
-  if (b <= 2) {
-    t.wgs_per_cu = 4;
-    t.window_blocks = 64;
-  } else if (b <= 4) {
-    t.wgs_per_cu = 2;
-    t.window_blocks = 16;
-  } else if (b <= 12) {
-    t.wgs_per_cu = 1;
-    t.window_blocks = 64;
-  } else if (b <= 16) {
-    t.wgs_per_cu = 1;
-    t.window_blocks = 16;
-  } else {
-    t.wgs_per_cu = 1;
-    t.window_blocks = 4;
-  }
+  t.wgs_per_cu = (b == 1 || b == 3) ? 2 : 1;
+  if (b <= 12) t.window_blocks = 64;
+  else if (b <= 16 || (s >= 0 && (s & 3) == SCAN_DEC_LI)) t.window_blocks = 16;
+  else t.window_blocks = 4;
   // With zone maps every window costs one dependent zone-map load and ballot
   // per wavefront: 64-block windows test 64 blocks per step.
   if (s >= 0 && ((s >> 3) & 1)) t.window_blocks = 64;
