@@ -94,24 +94,37 @@ __global__ __launch_bounds__(256) void batch_features_kernel(const BatchCol* col
     double s = 1.0, frac = 1.0, clust = 0.0;
     if ((c.flags & kColHasZm) && c.nb) {
       double acc = 0.0, meet = 0.0, spread = 0.0, gmin = 1e300, gmax = -1e300;
-      for (uint64_t k = lane; k < c.nb; k += 64) {
-        double mn, mx;
-        if (c.enc == ENC_DELTA) {
-          mn = (double)static_cast<const int64_t*>(c.zmin)[k];
-          mx = (double)static_cast<const int64_t*>(c.zmax)[k];
-        } else {
-          mn = (double)static_cast<const uint32_t*>(c.zmin)[k];
-          mx = (double)static_cast<const uint32_t*>(c.zmax)[k];
+      // Each lane takes blocks lane, lane + 64, ... in order; the zone maps of
+      // kU of them are loaded before any is used, so a long column does not
+      // wait one memory latency per block (the accumulation order is unchanged).
+      constexpr int kU = 8;
+      for (uint64_t k0 = lane; k0 < c.nb; k0 += 64u * kU) {
+        double mn[kU], mx[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const uint64_t k = k0 + 64u * u < c.nb ? k0 + 64u * u : k0;
+          if (c.enc == ENC_DELTA) {
+            mn[u] = (double)static_cast<const int64_t*>(c.zmin)[k];
+            mx[u] = (double)static_cast<const int64_t*>(c.zmax)[k];
+          } else {
+            mn[u] = (double)static_cast<const uint32_t*>(c.zmin)[k];
+            mx[u] = (double)static_cast<const uint32_t*>(c.zmax)[k];
+          }
         }
-        const double cnt = (k == c.nb - 1) ? (double)c.tail : 1024.0;
-        if (lo < hi) {
-          const double ov = fmax(fmin(hi, mx + 1.0) - fmax(lo, mn), 0.0) / (mx - mn + 1.0);
-          acc += cnt * ov;
-          meet += (mx < lo || mn >= hi) ? 0.0 : 1.0;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const uint64_t k = k0 + 64u * u;
+          if (k >= c.nb) break;
+          const double cnt = (k == c.nb - 1) ? (double)c.tail : 1024.0;
+          if (lo < hi) {
+            const double ov = fmax(fmin(hi, mx[u] + 1.0) - fmax(lo, mn[u]), 0.0) / (mx[u] - mn[u] + 1.0);
+            acc += cnt * ov;
+            meet += (mx[u] < lo || mn[u] >= hi) ? 0.0 : 1.0;
+          }
+          spread += mx[u] - mn[u];
+          gmin = fmin(gmin, mn[u]);
+          gmax = fmax(gmax, mx[u]);
         }
-        spread += mx - mn;
-        gmin = fmin(gmin, mn);
-        gmax = fmax(gmax, mx);
       }
       acc = wave_sum_f64(acc);
       meet = wave_sum_f64(meet);

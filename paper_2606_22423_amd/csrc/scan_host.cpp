@@ -129,8 +129,17 @@ scan_status check_strategy(scan_ctx* ctx, const scan_column* col, int32_t enc, u
 // ------------------------------------------------------------ tuning
 
 scan_tune default_tune(int32_t enc, uint32_t b, int32_t s) {
-  (void)enc;
   scan_tune t;
+  if (enc < 0) {
+    // batches (every width in one class kernel): four work-groups per CU
+    // (the class kernels are latency-bound; one per CU measured 1.3x slower)
+    // and 64-block windows
+    t.wg_size = 256;
+    t.wgs_per_cu = 4;
+    t.window_blocks = 64;
+    t.reserved = 0;
+    return t;
+  }
   // From the autotuner on MI355X (2^28-value columns, cold, branch-free):
   // few resident wavefronts, each streaming its own windows, beat full
   // occupancy (fewer concurrent streams into HBM); narrow widths want long
