@@ -427,6 +427,95 @@ def controls_leg(ctx, torch, beta_gbs, cols_rm, reps=7, burst=50):
             "read_probe": read_rows}
 
 
+def encodings_leg(ctx, torch, beta_gbs, draws, reps=5):
+    """Delta-FOR and dictionary columns of the sweep's length (section 3: the
+    delta and dictionary encodings).  Delta: v = cumulative sum of the stream's
+    top-b bits (b = 4, 8, 12, 16, 20, 24), predicate [v(0.45 n), v(0.55 n)).
+    Dictionary: codes = the stream's top-b bits (b = 4, 8, 12; 2^b sorted int64
+    entries), predicate on the entry values covering round(0.1 m) codes.
+    Zone maps off (every block decoded) and on, branch-free, row-major direct
+    and LDS decoders, launch shape autotuned per column, cold cache, median of
+    reps; f = payload bytes / time / beta.  COUNT and SUM are checked against
+    numpy (SUM mod 2^64)."""
+    import numpy as np
+
+    import synth
+    from paper_2606_22423_amd import api, lawfit
+    from paper_2606_22423_amd._lib import DEC_RM_DIRECT, DEC_RM_LDS, strategy, strategy_name
+
+    n = len(draws)
+    evict = torch.empty(256 << 20, dtype=torch.int32, device="cuda")
+    out = torch.zeros(5, dtype=torch.int64, device="cuda")
+    rows = []
+
+    def to_i64(x):
+        x %= 1 << 64
+        return x - (1 << 64) if x >= 1 << 63 else x
+
+    def measure(kind, b, col, lo, hi, want, extra):
+        for zm in (0, 1):
+            for dec in (DEC_RM_DIRECT, DEC_RM_LDS):
+                s = strategy(dec, 0, zm)
+                ctx.autotune(col, lo, hi, s, reps=3)
+                r = ctx.run(col, lo, hi, s)
+                if (r["count"], r["sum"]) != want:
+                    raise RuntimeError("%s b=%d %s: %s vs numpy %s" % (kind, b, strategy_name(s), r, want))
+                ts = []
+                for _ in range(reps):
+                    ctx.cache_flush(evict, evict.numel() * 4)
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    ctx.run_async(col, lo, hi, s, out)
+                    e1.record()
+                    e1.synchronize()
+                    ts.append(e0.elapsed_time(e1) * 1e-3)
+                t = float(np.median(ts))
+                pay = n * b / 8
+                rows.append({"encoding": kind, "b": b, "strategy": strategy_name(s), "ms": round(t * 1e3, 4),
+                             "gvalues_per_s": round(n / t / 1e9, 1), "f": round(pay / t / 1e9 / beta_gbs, 4),
+                             "blocks_read_frac": round(r["blocks_read"] / r["blocks_total"], 4), **extra})
+
+    for b in (4, 8, 12, 16, 20, 24):
+        d = synth.config2_column(draws, b).astype(np.int64)
+        v = np.cumsum(d, dtype=np.int64)
+        del d
+        lo, hi = int(v[int(0.45 * n)]), int(v[int(0.55 * n)])
+        a, z = np.searchsorted(v, lo, "left"), np.searchsorted(v, hi, "left")
+        want = (int(z - a), to_i64(int(v[a:z].view(np.uint64).sum(dtype=np.uint64))))
+        col = api.encode_delta(v, b, block_sums=False)
+        del v
+        measure("delta", b, col, lo, hi, want, {})
+        del col
+        log("[bench] encodings: delta b=%d done" % b)
+    for b in (4, 8, 12):
+        m = 1 << b
+        dct = synth.dict_entries(m, synth.SEED_BASE + 1, 1 << 35, 38)
+        codes = synth.config2_column(draws, b)
+        cw = max(1, round(0.1 * m))
+        clo = (m - cw) // 2
+        lo, hi = int(dct[clo]), int(dct[clo + cw])
+        cnt = np.bincount(codes, minlength=m)
+        sel = slice(clo, clo + cw)
+        want = (int(cnt[sel].sum()), to_i64(sum(int(c) * int(e) for c, e in zip(cnt[sel], dct[sel]))))
+        col = api.encode_dict(codes, b, dct, block_sums=False)
+        del codes
+        measure("dictionary", b, col, lo, hi, want, {"entries": m})
+        del col
+        log("[bench] encodings: dictionary b=%d done" % b)
+    fits = {}
+    beta = beta_gbs * 1e9
+    for kind in ("delta", "dictionary"):
+        for name in sorted({r["strategy"] for r in rows if r["encoding"] == kind and "nozm" in r["strategy"]}):
+            pts = sorted((r["b"], r["ms"] * 1e-3) for r in rows if r["encoding"] == kind and r["strategy"] == name)
+            ft = lawfit.fit_tdec([p[0] for p in pts], [lawfit.bandwidth_fraction(n, bb, t, beta) for bb, t in pts], beta)
+            fits["%s %s" % (kind, name)] = {"T_dec_gvalues_per_s": round(ft.t_dec / 1e9, 1),
+                                            "b_star": round(ft.b_star, 2)}
+    return {"workload": "N=2^%d; delta: cumulative sums of b-bit draws, b in 4..24, predicate [v(0.45N), "
+                        "v(0.55N)); dictionary: b-bit codes, 2^b sorted int64 entries, round(0.1*2^b) codes "
+                        "selected; zone maps off/on, branch-free, autotuned, cold, median of %d" % (int(np.log2(n)), reps),
+            "law_fit": fits, "points": rows}
+
+
 def serve_leg(ctx, torch, rows_log2, nq, lambdas=(0.25, 0.5, 0.8, 0.95), warm=500):
     """Serving workload: 16 columns x 2^rows_log2 rows (widths 4..20, FOR on
     even and dictionary on odd columns, columns 0-7 clustered by a noisy sort,
@@ -536,6 +625,7 @@ def main():
     ap.add_argument("--detail", default=None, help="write the full sweep as JSON to this file")
     ap.add_argument("--no-autotune", action="store_true", help="library default launch shapes")
     ap.add_argument("--no-controls", action="store_true", help="skip the cache negative control")
+    ap.add_argument("--no-encodings", action="store_true", help="skip the delta and dictionary columns")
     ap.add_argument("--batch-cols", type=int, default=4096, help="mixed-column workload size (0: skip it)")
     ap.add_argument("--zonemap-log2", type=int, default=30, help="zone-map workload rows (0: skip the leg)")
     ap.add_argument("--serve-rows-log2", type=int, default=28, help="serving table rows (0: skip the serving leg)")
@@ -746,6 +836,10 @@ def main():
                                                       "ratio": round(tb / tg, 4)}
     controls["byte_aligned_vs_generic"] = ba
 
+    encodings = None
+    if not args.no_encodings:
+        encodings = encodings_leg(ctx, torch, beta_gbs, synth.config2_draws(N))
+
     # --- branch-free vs compaction crossover per width (needs the sigma sweep)
     crossover = None
     if len(sigmas) > 2:
@@ -840,6 +934,7 @@ def main():
         "batch": batch,
         "zonemap": zonemap,
         "controls": controls,
+        "encodings": encodings,
         "serving": serving,
     }
     if args.detail:
