@@ -132,11 +132,12 @@ struct GroupRegs {
     return q < Geo::kPieces && ((need >> (q / Geo::kPiecesPerBlock)) & 1u);
   }
   __device__ __forceinline__ void load(const SelParams& p, uint64_t k0, uint32_t need, uint32_t lane) {
+    // adjacent lanes read adjacent 16 bytes: whole lines, streamed (non-temporal)
     const u32x4* src = reinterpret_cast<const u32x4*>(p.payload + k0 * Geo::kWords);
-    if (has(need, lane)) r0 = src[lane];
-    if (Geo::kPieces > 64u && has(need, lane + 64u)) r1 = src[lane + 64u];
-    if (Geo::kPieces > 128u && has(need, lane + 128u)) r2 = src[lane + 128u];
-    if (Geo::kPieces > 192u && has(need, lane + 192u)) r3 = src[lane + 192u];
+    if (has(need, lane)) r0 = __builtin_nontemporal_load(src + lane);
+    if (Geo::kPieces > 64u && has(need, lane + 64u)) r1 = __builtin_nontemporal_load(src + lane + 64u);
+    if (Geo::kPieces > 128u && has(need, lane + 128u)) r2 = __builtin_nontemporal_load(src + lane + 128u);
+    if (Geo::kPieces > 192u && has(need, lane + 192u)) r3 = __builtin_nontemporal_load(src + lane + 192u);
   }
   __device__ __forceinline__ void store(uint32_t* st, uint32_t need, uint32_t lane) const {
     u32x4* dst = reinterpret_cast<u32x4*>(st);
