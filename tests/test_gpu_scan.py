@@ -367,3 +367,20 @@ def test_all_match_needs_block_sums_and_is_the_default(ctx):
         ctx.run(bare, 100, 900, strategy(DEC_RM_DIRECT, 0, 1, 1))
     with pytest.raises(_lib.ScanError):
         ctx.run(col, 100, 900, strategy(DEC_RM_DIRECT, 0, 0, 1))  # all-match without zone maps
+
+
+def test_cache_flush_only_reads_its_buffer(ctx):
+    """The eviction reads its scratch buffer (no dirty lines for the next
+    kernel to write back); the contents stay as they were, and a scan
+    launched after it is unchanged."""
+    buf = torch.arange(1 << 20, dtype=torch.int32, device="cuda")
+    want = buf.clone()
+    for _ in range(3):
+        ctx.cache_flush(buf, buf.numel() * 4)
+    torch.cuda.synchronize()
+    assert torch.equal(buf, want)
+    v = synth.width_values(synth.pcg32(11, 3, 5197), 12)
+    col = api.encode_for(v, 12)
+    r = ctx.run(col, 100, 900, strategy(DEC_RM_DIRECT, 0, 0))
+    want = oracle.scan_for(oracle.pack_rm(v, 12), len(v), 12, 100, 900)
+    assert (r["count"], r["sum"]) == (want.count, want.sum)
