@@ -262,16 +262,19 @@ scan_status scan_gather(scan_ctx* ctx, const scan_column* col, int32_t enc, uint
  * Many columns (mixed length, width, encoding, strategy) scanned by one fixed
  * sequence of launches, whatever the number of columns: per-column setup,
  * strategy selection on the device (the loaded selector for SCAN_STRAT_AUTO
- * items, else the heuristic), binning of the columns' windows of blocks by
- * (encoding, decoder, predicate mode), then one persistent kernel per class
- * walking its windows on a static schedule.  Columns must be row-major;
+ * items, else the heuristic), binning of the columns' work items (four
+ * windows of blocks each) by (encoding, decoder, predicate mode), then one
+ * persistent kernel per class walking its items on a static schedule
+ * (dictionary classes: a work-group per item, the dictionary in LDS).
+ * Columns must be row-major;
  * explicit strategies must use the SCAN_DEC_RM_LDS or SCAN_DEC_RM_DIRECT
  * decoder.  Results equal scan_run's for every item, bit for bit.
  *
  * scan_batch_prepare validates the items and uploads their descriptors and
  * windows once; the selector state and the tuning stored for (enc -1, b 0,
  * strategy -1) at that moment are baked in (tuning: work-groups per CU of the
- * class kernels and the window, at most 64 blocks).  An invalid item does not
+ * class kernels, default 4, at most the number that fit, and the window,
+ * default and at most 64 blocks).  An invalid item does not
  * fail the call: its result carries the error in `status`.  `items` (host)
  * may be freed after the call; the columns' device buffers must stay alive
  * until the handle is released.  *handle (host) receives an id. */
