@@ -264,8 +264,9 @@ scan_status scan_gather(scan_ctx* ctx, const scan_column* col, int32_t enc, uint
  * strategy selection on the device (the loaded selector for SCAN_STRAT_AUTO
  * items, else the heuristic), binning of the columns' work items (four
  * windows of blocks each) by (encoding, decoder, predicate mode), then one
- * persistent kernel per class walking its items on a static schedule
- * (dictionary classes: a work-group per item, the dictionary in LDS).
+ * persistent kernel per class walking its items on a static schedule (a
+ * work-group per item, one window per wavefront; dictionary classes hold the
+ * column's dictionary in LDS).
  * Columns must be row-major;
  * explicit strategies must use the SCAN_DEC_RM_LDS or SCAN_DEC_RM_DIRECT
  * decoder.  Results equal scan_run's for every item, bit for bit.

@@ -143,11 +143,9 @@ void plan_cols(scan_ctx* ctx, const scan_item* items, size_t n, uint32_t window,
     c.heuristic = h;
     c.strategy = it.strategy >= 0 ? it.strategy : h;
     cols[i] = c;
-    // items of four windows: fewer items (each costs its descriptor loads,
-    // pipeline start and result atomics) at little cost in balance; a
-    // dictionary item is shared by the four wavefronts of a work-group, one
-    // window each (measured on the mixed 4096-column batch: 3.13 -> 2.85 ms
-    // against one-window items for the other encodings)
+    // items of four windows, one per wavefront of the work-group that takes
+    // the item: fewer items (each costs its descriptor loads, pipeline start
+    // and result atomics) and no wavefront alone on a dense item
     const uint64_t span = 4u * (uint64_t)window;
     if (work && !empty)
       for (uint64_t k = 0; k < c.nb; k += span)

@@ -1,18 +1,20 @@
 // Batched scans: thousands of columns of mixed length, width, encoding and
 // strategy in one sequence of launches.
 //
-// Each column is cut into work items of up to G blocks (4G for dictionary
-// columns, whose items a work-group's four wavefronts share).  A binning kernel
+// Each column is cut into work items of up to four windows of G blocks, which
+// the four wavefronts of a work-group share.  A binning kernel
 // sorts the items into twelve classes (encoding x decoder x predicate mode),
 // reading each column's strategy from device memory (so a selector kernel that
 // ran earlier on the same stream decides it), and one persistent kernel per
-// class walks its item list on a static schedule: wavefront w of W takes items
-// w, w + W, ... below the class count (no shared cursor, every loop bounded
-// by counts fixed before the launch; dictionary classes split the list among
-// work-groups instead, see batch_dict_share).  For an item it switches
+// class walks its item list on a static schedule: work-group g of G takes
+// items g, g + G, ... below the class count, its four wavefronts one window
+// each (no shared cursor, every loop bounded by counts fixed before the
+// launch; dictionary classes give each work-group a contiguous share of the
+// list instead, see batch_dict_share).  For an item it switches
 // (wave-uniformly) on the column's width to the same templated range
-// decoders the single-column kernels use, and adds its exact partial (count,
-// sum mod 2^64, blocks read) to the column's slot with three 64-bit atomics.
+// decoders the single-column kernels use, and each wavefront adds its exact
+// partial (count, sum mod 2^64, blocks read) to the column's slot with three
+// 64-bit atomics.
 // Zone maps on/off is a per-column run-time flag.
 #pragma once
 
@@ -164,9 +166,9 @@ __device__ __forceinline__ void dict_flush(WaveState<uint32_t>& s, uint32_t lane
   F(1) F(2) F(3) F(4) F(5) F(6) F(7) F(8) F(9) F(10) F(11) F(12) F(13) F(14) F(15) F(16) F(17) F(18) F(19) F(20) \
       F(21) F(22) F(23) F(24) F(25) F(26) F(27) F(28) F(29) F(30) F(31) F(32)
 
-#define BATCH_CASE(B)                                                              \
-  case B:                                                                          \
-    batch_item<B, ENC, DEC, MODE>(p, c, w.k0, w.k0 + w.nblk, lane, list, st, out); \
+#define BATCH_SHARE_CASE(B)                                                                 \
+  case B:                                                                                   \
+    batch_item<B, ENC, DEC, MODE>(p, c, w.k0 + b0, w.k0 + b1, lane, list, st, out);         \
     break;
 
 #define BATCH_DICT_CASE(B)                                                                                    \
@@ -230,16 +232,24 @@ __global__ __launch_bounds__(256) void batch_scan(const BatchArgs a) {
   if constexpr (ENC == ENC_DICT) {
     batch_dict_share<DEC, MODE>(a, items, n, reinterpret_cast<int64_t*>(smem), list, st, lane, wave);
   } else {
-    const uint32_t tw = gridDim.x * (blockDim.x >> 6);
-    for (uint32_t idx = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + wave); idx < n;
-         idx += tw) {
+    // The four wavefronts of a work-group split every item: the items whose
+    // blocks survive the zone maps are dense (a sorted delta column's
+    // survivors are one contiguous range), and no wavefront decodes a whole
+    // dense item alone.
+    const uint32_t nw = blockDim.x >> 6;
+    for (uint32_t idx = blockIdx.x; idx < n; idx += gridDim.x) {
       const BatchWork w = a.work[items[idx]];
       const BatchCol c = a.cols[w.col];
       const Params p = batch_params(c);
       BatchOut* out = a.out + w.col;
-      switch (c.b) {
-        SCAN_WIDTHS_ALL(BATCH_CASE)
-        default: break;
+      const uint32_t q = (w.nblk + nw - 1u) / nw;
+      const uint32_t b0 = wave * q < w.nblk ? wave * q : w.nblk;
+      const uint32_t b1 = b0 + q < w.nblk ? b0 + q : w.nblk;
+      if (b0 < b1) {
+        switch (c.b) {
+          SCAN_WIDTHS_ALL(BATCH_SHARE_CASE)
+          default: break;
+        }
       }
     }
   }
