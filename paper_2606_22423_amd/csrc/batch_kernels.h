@@ -98,7 +98,6 @@ __device__ __forceinline__ Params batch_params(const BatchCol& c) {
   p.strategy = c.strategy;
   p.use_am = 0;
   p.partials = nullptr;
-  p.ticket = nullptr;
   p.out = nullptr;
   return p;
 }

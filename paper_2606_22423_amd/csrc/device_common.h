@@ -52,7 +52,6 @@ struct Params {
   int32_t strategy;
   uint32_t use_am;         // all-match shortcut (needs use_zm and bsum)
   Partial* partials;       // one per work-group
-  uint32_t* ticket;        // zero between launches (the last work-group resets it)
   Result* out;
 };
 
@@ -162,17 +161,22 @@ __device__ __forceinline__ uint64_t all_blocks(uint32_t cnt) {
   return cnt >= 64 ? ~0ull : ((1ull << cnt) - 1ull);
 }
 
-// Work-group reduction of the per-wave (count, sum, blocks) into one partial,
-// then the last work-group to finish folds every partial into *out and resets
-// the ticket, so consecutive launches need no memset.  `count` and `blocks`
-// are wave-uniform, `lane_sum` per lane.
-__device__ __forceinline__ void finish_partials(Partial* partials, uint32_t* ticket, Result* out,
-                                                uint64_t blocks_total, int32_t strategy, uint64_t count,
-                                                uint64_t lane_sum, uint64_t blocks) {
+// Folds partials[0, n) into *out (one work-group; fold.hip).  Enqueued after
+// every kernel that ends in write_partial, on the same stream.
+hipError_t launch_fold(const Partial* partials, uint32_t n, Result* out, uint64_t blocks_total, int32_t strategy,
+                       hipStream_t st);
+
+// Work-group reduction of the per-wave (count, sum, blocks) into the
+// work-group's partial; a second launch (fold_partials_kernel, enqueued right
+// after on the same stream) folds the partials into the result.  A
+// last-work-group ticket instead needs an agent-scope release per
+// work-group, i.e. an L2 write-back on this multi-XCD part, and cost 5-11 us
+// per launch; stream order makes the partials visible to the fold for free.
+// `count` and `blocks` are wave-uniform, `lane_sum` per lane.
+__device__ __forceinline__ void write_partial(Partial* partials, uint64_t count, uint64_t lane_sum, uint64_t blocks) {
   __shared__ uint64_t red[16][3];
-  __shared__ bool last;
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  uint64_t s = wave_sum_u64(lane_sum);
+  const uint64_t s = wave_sum_u64(lane_sum);
   if (lane == 0) {
     red[wave][0] = count;
     red[wave][1] = s;
@@ -190,50 +194,12 @@ __device__ __forceinline__ void finish_partials(Partial* partials, uint32_t* tic
     q->count = c;
     q->sum = t;
     q->blocks = b;
-    uint32_t prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __atomic_thread_fence(__ATOMIC_ACQUIRE);
-  uint64_t c = 0, t = 0, b = 0;
-  for (uint32_t i = threadIdx.x; i < gridDim.x; i += blockDim.x) {
-    const Partial* q = partials + i;
-    c += __hip_atomic_load(&q->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    t += __hip_atomic_load(&q->sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    b += __hip_atomic_load(&q->blocks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  c = wave_sum_u64(c);
-  t = wave_sum_u64(t);
-  b = wave_sum_u64(b);
-  __syncthreads();
-  if (lane == 0) {
-    red[wave][0] = c;
-    red[wave][1] = t;
-    red[wave][2] = b;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (uint32_t w = 1; w < nw; ++w) {
-      red[0][0] += red[w][0];
-      red[0][1] += red[w][1];
-      red[0][2] += red[w][2];
-    }
-    Result r;
-    r.count = red[0][0];
-    r.sum = (int64_t)red[0][1];
-    r.blocks_read = red[0][2];
-    r.blocks_total = blocks_total;
-    r.strategy_used = strategy;
-    r.status = 0;
-    *out = r;
-    __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
 __device__ __forceinline__ void finish_scan(const Params& p, uint64_t count, uint64_t lane_sum,
                                             uint64_t blocks) {
-  finish_partials(p.partials, p.ticket, p.out, p.nb, p.strategy, count, lane_sum, blocks);
+  write_partial(p.partials, count, lane_sum, blocks);
 }
 
 }  // namespace scan_dev

@@ -1,0 +1,49 @@
+// Fold of the per-work-group partials into a scan's result (see write_partial
+// in device_common.h): one work-group, launched after the scan on its stream.
+#include "device_common.h"
+
+namespace scan_dev {
+
+__global__ __launch_bounds__(256) void fold_partials_kernel(const Partial* __restrict__ partials, uint32_t n,
+                                                            Result* out, uint64_t blocks_total, int32_t strategy) {
+  __shared__ uint64_t red[4][3];
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  uint64_t c = 0, t = 0, b = 0;
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    c += partials[i].count;
+    t += partials[i].sum;
+    b += partials[i].blocks;
+  }
+  c = wave_sum_u64(c);
+  t = wave_sum_u64(t);
+  b = wave_sum_u64(b);
+  if (lane == 0) {
+    red[wave][0] = c;
+    red[wave][1] = t;
+    red[wave][2] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (uint32_t w = 1; w < 4u; ++w) {
+      red[0][0] += red[w][0];
+      red[0][1] += red[w][1];
+      red[0][2] += red[w][2];
+    }
+    Result r;
+    r.count = red[0][0];
+    r.sum = (int64_t)red[0][1];
+    r.blocks_read = red[0][2];
+    r.blocks_total = blocks_total;
+    r.strategy_used = strategy;
+    r.status = 0;
+    *out = r;
+  }
+}
+
+hipError_t launch_fold(const Partial* partials, uint32_t n, Result* out, uint64_t blocks_total, int32_t strategy,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(fold_partials_kernel, dim3(1), dim3(256), 0, st, partials, n, out, blocks_total, strategy);
+  return hipGetLastError();
+}
+
+}  // namespace scan_dev

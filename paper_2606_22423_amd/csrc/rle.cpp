@@ -33,7 +33,6 @@ scan_status enqueue_rle(scan_ctx* ctx, const scan_rle_column* col, const scan_pr
   p.zmax = col->zone_max;
   p.out = out;
   p.partials = ctx->partials;
-  p.ticket = ctx->ticket;
   p.nb = (col->n + SCAN_BLOCK_VALUES - 1) / SCAN_BLOCK_VALUES;
   p.lo = pred->lo;
   p.hi = pred->hi;

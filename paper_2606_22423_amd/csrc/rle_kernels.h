@@ -13,7 +13,6 @@ struct RleParams {
   const uint32_t* zmax;
   Result* out;                // device result (written whole by the launch)
   Partial* partials;          // per-work-group partials (at least grid entries)
-  uint32_t* ticket;           // last-work-group counter, zero between launches
   uint64_t nb;
   int64_t lo, hi;
   uint32_t use_zm, use_am;

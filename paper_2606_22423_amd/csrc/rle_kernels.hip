@@ -73,7 +73,7 @@ __global__ __launch_bounds__(512) void rle_scan_kernel(const RleParams p) {
 #pragma unroll
       for (uint32_t u = 0; u < kRleUnroll; ++u) take_runs(p, q + 256ull * u, 0, total, total, count, sum);
     }
-    finish_partials(p.partials, p.ticket, p.out, p.nb, p.strategy_used, wave_sum_u64(count), sum, blocks);
+    write_partial(p.partials, wave_sum_u64(count), sum, blocks);
     return;
   }
   for (uint64_t c = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave; c < nchunks; c += tw) {
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(512) void rle_scan_kernel(const RleParams p) {
       for (uint32_t u = 0; u < kRleUnroll; ++u) take_runs(p, q + 256ull * u, r0, r1, total, count, sum);
     }
   }
-  finish_partials(p.partials, p.ticket, p.out, p.nb, p.strategy_used, wave_sum_u64(count), sum, blocks);
+  write_partial(p.partials, wave_sum_u64(count), sum, blocks);
 }
 
 __global__ void rle_clear_kernel(Result* out, uint64_t blocks_total, int32_t strategy_used) {
@@ -112,9 +112,13 @@ __global__ void rle_clear_kernel(Result* out, uint64_t blocks_total, int32_t str
 }
 
 hipError_t launch_rle_scan(const RleParams& p, uint32_t grid, hipStream_t st) {
-  if (p.empty) hipLaunchKernelGGL(rle_clear_kernel, dim3(1), dim3(64), 0, st, p.out, p.nb, p.strategy_used);
-  else hipLaunchKernelGGL(rle_scan_kernel, dim3(grid), dim3(512), 0, st, p);
-  return hipGetLastError();
+  if (p.empty) {
+    hipLaunchKernelGGL(rle_clear_kernel, dim3(1), dim3(64), 0, st, p.out, p.nb, p.strategy_used);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(rle_scan_kernel, dim3(grid), dim3(512), 0, st, p);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? launch_fold(p.partials, grid, p.out, p.nb, p.strategy_used, st) : e;
 }
 
 }  // namespace scan_dev

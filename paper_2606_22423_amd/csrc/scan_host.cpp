@@ -219,7 +219,6 @@ scan_status prepare_scan(scan_ctx* ctx, const scan_column* col, int32_t enc, uin
   p.tail = (uint32_t)(col->n - (p.nb ? (p.nb - 1) : 0) * SCAN_BLOCK_VALUES);
   p.strategy = s;
   p.partials = ctx->partials;
-  p.ticket = ctx->ticket;
   p.out = out_dev;
   trivially_empty = (col->n == 0 || pred->lo >= pred->hi);
   int pf = PF_RANGE;
@@ -279,6 +278,7 @@ scan_status enqueue_scan(scan_ctx* ctx, const scan_column* col, int32_t enc, uin
     return SCAN_OK;
   }
   hipError_t e = fn(p, grid, block, ctx->stream, nullptr);
+  if (e == hipSuccess) e = launch_fold(p.partials, grid, p.out, p.nb, p.strategy, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "scan kernel launch");
   return SCAN_OK;
 }
@@ -386,6 +386,7 @@ scan_status scan_run(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_
       host_done = true;
     } else {
       e = fn(p, grid, block, ctx->stream, nullptr);
+      if (e == hipSuccess) e = launch_fold(p.partials, grid, p.out, p.nb, p.strategy, ctx->stream);
       if (e != hipSuccess) return hip_fail(ctx, e, "scan kernel launch");
     }
   }
