@@ -41,9 +41,8 @@ scan_status enqueue_rle(scan_ctx* ctx, const scan_rle_column* col, const scan_pr
   p.strategy_used = (int32_t)flags;
   p.empty = (col->n == 0 || pred->lo >= pred->hi) ? 1u : 0u;
   hipError_t e = hipSetDevice(ctx->device);
-  // two 512-thread work-groups per CU: enough wavefronts in flight, and few
-  // work-groups, since each takes one ticket on the finisher's shared counter
-  // (same-address atomics serialise); one partial per work-group
+  // two 512-thread work-groups per CU: enough wavefronts in flight; one
+  // partial per work-group, folded by the fold kernel launched after it
   const uint32_t grid = std::min<uint32_t>((uint32_t)ctx->cus * 2u, ctx->max_grid);
   if (e == hipSuccess) e = launch_rle_scan(p, grid, ctx->stream);
   return e == hipSuccess ? SCAN_OK : hip_fail(ctx, e, "rle scan");

@@ -13,8 +13,8 @@
 // the span from the first to the last block not skipped stream through the
 // lanes, four consecutive runs per lane and load (one compare per run, COUNT += len,
 // SUM += value * len mod 2^64).  Per-lane partials meet in a work-group
-// reduction, one partial per work-group, folded by the last work-group to
-// finish (no same-address atomics beyond one ticket per work-group).
+// reduction, one partial per work-group, folded by a one-work-group kernel
+// launched after it (no same-address atomics).
 #include "device_common.h"
 #include "rle_kernels.h"
 

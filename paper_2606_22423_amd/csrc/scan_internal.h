@@ -20,7 +20,7 @@ struct scan_ctx {
   int cus = 0;
   uint32_t max_grid = 0;
   scan_dev::Partial* partials = nullptr;  // per-work-group partial results (device)
-  uint32_t* ticket = nullptr;             // last-work-group counter (device, zero between launches)
+  uint32_t* ticket = nullptr;             // 256 bytes of device scratch (the autotuner's read-probe sink)
   scan_dev::Result* out_dev = nullptr;    // result slot of synchronous scans (device)
   scan_dev::Result* out_host = nullptr;   // pinned staging for it
   uint32_t flush_salt = 0;
