@@ -142,12 +142,12 @@ scan_tune default_tune(int32_t enc, uint32_t b, int32_t s) {
   }
   // From the autotuner on MI355X (2^28-value columns, cold, branch-free):
   // few resident wavefronts, each streaming its own windows, beat full
-  // occupancy (fewer concurrent streams into HBM); narrow widths want long
-  // windows, and b = 1 and 3 a second work-group per CU (four measured 1.6x
-  // slower); the transposed decoder wants longer windows than the row-major
-  // ones at high widths.
+  // occupancy from b = 8 on (fewer concurrent streams into HBM); narrower,
+  // compute-bound widths want more work-groups (four up to b = 3, two up to
+  // b = 7) and long windows; the transposed decoder wants longer windows than
+  // the row-major ones at high widths.
   t.wg_size = 256;
-  t.wgs_per_cu = (b == 1 || b == 3) ? 2 : 1;
+  t.wgs_per_cu = b <= 3 ? 4 : b <= 7 ? 2 : 1;
   if (b <= 12) t.window_blocks = 64;
   else if (b <= 16 || (s >= 0 && (s & 3) == SCAN_DEC_LI)) t.window_blocks = 16;
   else t.window_blocks = 4;
