@@ -613,6 +613,135 @@ def api_encode_dict(vals, b, dct):
     return api.encode_dict(vals, b, dct)
 
 
+def host_threads() -> int:
+    """Host threads this process may use: its CPU affinity, capped by OMP_NUM_THREADS when set."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def cpu_baseline_leg(widths=(1, 2, 4, 8, 12, 16, 24, 32), n_log2=24, reps=5):
+    """The oracle, unchanged, timed on the host on 2^n_log2 values of the
+    sweep's stream per width: on one thread, then on every host thread, each
+    thread scanning a contiguous range of whole blocks (a block range of a
+    row-major payload is itself a packed column) and the exact partials added
+    as integers (SUM mod 2^64).  The oracle's C core runs without Python's
+    lock, so the threads run in parallel."""
+    import concurrent.futures as cf
+
+    import numpy as np
+
+    import oracle
+    import synth
+
+    threads = host_threads()
+    n = 1 << n_log2
+    d = synth.config2_draws(n)
+    t1 = t1v = tall = tallv = 0.0
+    with cf.ThreadPoolExecutor(threads) as ex:
+        for b in widths:
+            v = synth.config2_column(d, b)
+            pw = oracle.pack_rm(v, b)
+            hi = synth.lt_bound(SIGMA, b)
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                want = oracle.scan_for(pw, n, b, 0, hi)
+                ts.append(time.perf_counter() - t0)
+            t1 += float(np.median(ts))
+            t1v += n
+            nb = n // 1024
+            cuts = [nb * i // threads for i in range(threads + 1)]
+
+            def part(i, pw=pw, b=b, hi=hi, cuts=cuts):
+                k0, k1 = cuts[i], cuts[i + 1]
+                return oracle.scan_for(pw[k0 * 32 * b: k1 * 32 * b], (k1 - k0) * 1024, b, 0, hi)
+
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                parts = list(ex.map(part, range(threads)))
+                ts.append(time.perf_counter() - t0)
+            tall += float(np.median(ts))
+            tallv += n
+            # the parallel run must give the one-thread oracle's exact result
+            got_c = sum(p.count for p in parts)
+            got_s = sum(p.sum for p in parts) % (1 << 64)
+            if (got_c, got_s) != (want.count, want.sum % (1 << 64)):
+                raise RuntimeError("threaded oracle differs at b=%d" % b)
+            del pw, v
+    return {"value": round(tallv / tall, 1), "unit": "values/s", "cores": threads, "kind": "oracle",
+            "sample": "2^%d values per width of the sweep's stream at b in %s, v < round(0.1*2^b), serial "
+                      "decode + filter + exact sum per thread over whole-block ranges, median of %d"
+                      % (n_log2, list(widths), reps),
+            "one_core_value": round(t1v / t1, 1)}
+
+
+def _pick(d, *keys):
+    return None if d is None else {k: d.get(k) for k in keys if k in d}
+
+
+def compact_line(full: dict, detail_path: str) -> dict:
+    """The headline record: every figure the benchmark is judged on, in one
+    line of at most a few KB (the full record, with every sweep point, goes to
+    the detail file)."""
+    line = {k: full[k] for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                                 "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config",
+                                 "beta_GBps", "triad_GBps", "law_fit_best", "roofline", "cpu_baseline")}
+    line["f_per_b"] = [round(r["f"], 3) for r in full["per_b"]]
+    line["law_fit_per_strategy"] = {k: [v["T_dec_gvalues_per_s"], v["b_star"]]
+                                    for k, v in full["law_fit_per_strategy"].items()}
+    if full.get("launch_cost"):
+        line["launch_cost"] = full["launch_cost"]
+    cr = full.get("crossover_bf_sv")
+    if cr:
+        line["crossover_bf_sv"] = {dec: {"widths": len(rows),
+                                         "bf_faster_everywhere": sum(1 for r in rows if r["sigma_star"] is None
+                                                                     and r["faster_below"] == "bf")}
+                                   for dec, rows in cr.items()}
+    sel = full.get("select")
+    if sel:
+        line["select"] = [[r["b"], r["sigma"], r["ms"], r["f"]] for r in sel]
+    bt = full.get("batch")
+    if bt:
+        line["batch"] = {k: v for k, v in bt.items() if k not in ("workload", "learned_class_counts")}
+    zm = full.get("zonemap")
+    if zm:
+        pts = zm["points"]
+        line["zonemap"] = {
+            "sorted_read_frac_sigma_1e-3": next((p["blocks_read_frac"] for p in pts if p["s"] == 0 and
+                                                 p["sigma"] == 1e-3 and p["zone_maps"] and not p["all_match"]), None),
+            "random_min_read_frac": min((p["blocks_read_frac"] for p in pts if p["s"] == "random" and
+                                         p["zone_maps"]), default=None),
+            "best_logical_gvalues_per_s": max((p["logical_gvalues_per_s"] for p in pts), default=None),
+            "identical_across_levels": zm.get("identical_across_levels_and_zone_maps"),
+        }
+        if zm.get("read_model"):
+            line["zonemap"]["read_model"] = zm["read_model"]
+    enc = full.get("encodings")
+    if enc:
+        line["encodings"] = {"law_fit": {k: [v["T_dec_gvalues_per_s"], v["b_star"]] for k, v in enc["law_fit"].items()},
+                             "dict_f_bf_nozm": {str(r["b"]): r["f"] for r in enc["points"] if r["encoding"] ==
+                                                "dictionary" and r["strategy"].endswith("bf/nozm") and
+                                                r["strategy"].startswith("rm_direct")}}
+    ctl = full.get("controls") or {}
+    line["controls"] = {"max_f_warm_in_cache": (ctl.get("cache") or {}).get("max_f_warm_in_cache"),
+                        "random_zone_maps_min_read_frac": ctl.get("random_zone_maps_min_read_frac"),
+                        "byte_aligned_vs_generic": {k: v["ratio"] for k, v in
+                                                    (ctl.get("byte_aligned_vs_generic") or {}).items()}}
+    sv = full.get("serving")
+    if sv:
+        line["serving"] = {"saturation_qps": sv["saturation_qps"], "isolation_checked": sv.get("isolation_checked"),
+                           "p50_p99_us": {str(r["lambda"]): [r["p50_us"], r["p99_us"]] for r in sv["rates"]}}
+    line["detail_file"] = os.path.basename(detail_path)
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -796,6 +925,43 @@ def main():
                 sigma_fits["%s@%g" % (strategy_name(s), sg)] = {"T_dec_gvalues_per_s": round(ft.t_dec / 1e9, 1),
                                                                "b_star": round(ft.b_star, 2)}
 
+    # --- fixed cost of one scan (scan kernel + fold kernel) apart from decoding:
+    # a one-block column (the first block of each width's column) with the
+    # width's timed strategy, launched back to back; the law refitted on the
+    # times with that cost taken out
+    launch_cost = None
+    if True:
+        out1 = torch.zeros(5, dtype=torch.int64, device="cuda")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fixed = {}
+        for b in widths:
+            s = best[b]
+            src_col = col_for(b, s)
+            one = api.Column(src_col.enc, b, 1024, src_col.layout, src_col.payload[: 32 * b])
+            burst = []
+            for _ in range(3):
+                ctx.run_async(one, 0, bounds[b], s, out1)
+                e0.record()
+                for _ in range(50):
+                    ctx.run_async(one, 0, bounds[b], s, out1)
+                e1.record()
+                e1.synchronize()
+                burst.append(e0.elapsed_time(e1) * 1e-3 / 50)
+            fixed[b] = float(np.median(burst))
+        net = {b: max(float(np.median(per_kernel[b])) - fixed[b], 1e-9) for b in widths}
+        f_net = [lawfit.bandwidth_fraction(N, b, net[b], beta) for b in widths]
+        ft_net = lawfit.fit_tdec(widths, f_net, beta)
+        launch_cost = {"fixed_us_median": round(float(np.median(list(fixed.values()))) * 1e6, 2),
+                       "fixed_us_b1_b32": [round(fixed[1] * 1e6, 2), round(fixed[32] * 1e6, 2)],
+                       "share_of_time_b1": round(fixed[1] / float(np.median(per_kernel[1])), 3),
+                       "law_fit_without_fixed_cost": {"T_dec_gvalues_per_s": round(ft_net.t_dec / 1e9, 1),
+                                                      "b_star": round(ft_net.b_star, 2),
+                                                      "median_abs_err": round(ft_net.median_err, 4)},
+                       "median_abs_err_with_fixed_cost": round(ft_best.median_err, 4)}
+        log("[bench] fixed launch cost %.1f us (b=1: %.0f%% of its time); law without it: T_dec %.3g, b* %.1f, "
+            "median err %.3f" % (launch_cost["fixed_us_median"], 100 * launch_cost["share_of_time_b1"],
+                                 ft_net.t_dec, ft_net.b_star, ft_net.median_err))
+
     # --- materializing select (positions to HBM) on the same resident columns
     select_rows = []
     sel_out = torch.empty(N, dtype=torch.int32, device="cuda")  # capacity n: one call, one wait
@@ -861,7 +1027,9 @@ def main():
     dom_t = float(np.mean(per_kernel[dom_b]))
     dom_bytes = N * dom_b / 8
     dom_name = "code_scan<B=%d,%s>" % (dom_b, strategy_name(best[dom_b]))
-    traffic = None
+    # HBM traffic and the kernel-only duration of the same kernel, from the
+    # committed rocprofv3 summary when it was taken on the current kernel source
+    traffic, trace_us = None, None
     tfile = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if os.path.exists(tfile):
         try:
@@ -869,35 +1037,24 @@ def main():
             ent = tj.get("kernels", {}).get(dom_name)
             if tj.get("kernel_source") == kernel_source_hash() and ent:
                 traffic = ent.get("bytes_per_launch")
+                trace_us = ent.get("trace_avg_us")
         except (ValueError, OSError):
-            traffic = None
+            traffic, trace_us = None, None
+    # achieved: HIP events around each launch of the timed region, which
+    # bracket the scan kernel and the one-work-group fold kernel after it
     roofline = {"bound": "hbm", "achieved": round(dom_bytes / dom_t / 1e9, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(dom_bytes / dom_t / 1e9 / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": dom_name, "algorithmic_bytes_per_launch": int(dom_bytes),
-                "avg_launch_ms": round(dom_t * 1e3, 4)}
+                "avg_launch_ms": round(dom_t * 1e3, 4), "timing": "hip events: scan + fold kernel",
+                "frac_kernel_only_from_trace": None if not trace_us else round(dom_bytes / (trace_us * 1e-6) / 1e9 /
+                                                                               HBM_PEAK_GBPS, 4)}
 
     # --- CPU baseline: the oracle as it stands, on a bounded sample
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        sample_w = (1, 2, 4, 8, 12, 16, 24, 32)
-        ns = 1 << 24
-        d = synth.config2_draws(ns)
-        tot_t, tot_v = 0.0, 0
-        for b in sample_w:
-            v = synth.config2_column(d, b)
-            pw = oracle.pack_rm(v, b)
-            ts = []
-            for _ in range(5):
-                t0 = time.perf_counter()
-                r = oracle.scan_for(pw, ns, b, 0, synth.lt_bound(SIGMA, b))
-                ts.append(time.perf_counter() - t0)
-            tot_t += float(np.median(ts))
-            tot_v += ns
-        cpu = {"value": round(tot_v / tot_t, 1), "unit": "values/s", "cores": 1, "kind": "oracle",
-               "sample": "first 2^24 values of the same stream at b in %s, predicate v < round(0.1*2^b), "
-                         "serial decode + filter + exact sum, median of 5 per width" % (list(sample_w),)}
-        log("[bench] cpu oracle %.3g values/s" % (tot_v / tot_t))
+        cpu = cpu_baseline_leg()
+        log("[bench] cpu oracle %.3g values/s on %d threads (%.3g on one)" %
+            (cpu["value"], cpu["cores"], cpu["one_core_value"]))
 
     batch = None
     if args.batch_cols > 0:
@@ -913,7 +1070,7 @@ def main():
     if args.serve_rows_log2 > 0:
         serving = serve_leg(ctx, torch, args.serve_rows_log2, args.serve_queries)
 
-    line = {
+    full = {
         "metric": METRIC, "value": round(value, 1), "unit": "decoded values/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(total_s / args.steps * 1e3, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
@@ -936,12 +1093,15 @@ def main():
         "controls": controls,
         "encodings": encodings,
         "serving": serving,
+        "launch_cost": launch_cost,
     }
-    if args.detail:
-        with open(args.detail, "w") as fh:
-            json.dump({"line": line, "sigma_fits": sigma_fits, "autotuned": tuned,
-                       "sweep_ms": {"%s@%g" % (strategy_name(s), sg): {b: round(t * 1e3, 5) for b, t in tb.items()}
-                                    for (sg, s), tb in sweep.items()}}, fh, indent=1)
+    detail_path = args.detail or os.path.join(os.getcwd(), "bench_detail.json")
+    with open(detail_path, "w") as fh:
+        json.dump({"line": full, "sigma_fits": sigma_fits, "autotuned": tuned,
+                   "sweep_ms": {"%s@%g" % (strategy_name(s), sg): {b: round(t * 1e3, 5) for b, t in tb.items()}
+                                for (sg, s), tb in sweep.items()}}, fh, indent=1)
+    log("[bench] full record written to %s" % detail_path)
+    line = compact_line(full, detail_path)
     print(json.dumps(line), flush=True)
     ctx.close()
 

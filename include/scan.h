@@ -157,7 +157,10 @@ typedef struct {
  * (a hipStream_t, or NULL for the null stream).  Allocates the context's
  * device scratch (partials, counters, result slots). */
 scan_status scan_create(scan_ctx** out, int device, void* hip_stream);
-/* Change the stream later calls enqueue on. */
+/* Change the stream later calls enqueue on.  The new stream is first made to
+ * wait (an event, no host wait) for the work already enqueued on the old one,
+ * since every scan of a context writes the same device partials and result
+ * slot.  HIP failure -> SCAN_EDEVICE (the stream is then unchanged). */
 scan_status scan_set_stream(scan_ctx* ctx, void* hip_stream);
 /* Waits for the context's stream, then frees everything the context owns. */
 void scan_destroy(scan_ctx* ctx);
@@ -195,7 +198,10 @@ scan_status scan_get_tune(scan_ctx* ctx, int32_t enc, uint32_t b, int32_t strate
  * The context allocates its 512 MiB eviction buffer on first use. */
 scan_status scan_autotune(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b,
                           const scan_predicate* pred, int32_t strategy, int32_t reps, scan_tune* out, float* ms_out);
-/* Persist / restore every tuning of the context as JSON (one entry per line). */
+/* Persist / restore every tuning of the context as JSON (one entry per line).
+ * scan_tune_load installs nothing and returns SCAN_EINVAL when the file cannot
+ * be read, holds no entry, or has an entry line that does not parse or holds
+ * an invalid tuning (the message names the line). */
 scan_status scan_tune_save(scan_ctx* ctx, const char* path);
 scan_status scan_tune_load(scan_ctx* ctx, const char* path);
 
@@ -260,36 +266,53 @@ scan_status scan_gather(scan_ctx* ctx, const scan_column* col, int32_t enc, uint
 /* ---------------------------------------------------------------- batches */
 /* Not in the paper (the workload's mixed-column batch).
  * Many columns (mixed length, width, encoding, strategy) scanned by one fixed
- * sequence of launches, whatever the number of columns: per-column setup,
+ * sequence of kernels, whatever the number of columns: per-column setup,
  * strategy selection on the device (the loaded selector for SCAN_STRAT_AUTO
- * items, else the heuristic), binning of the columns' work items (four
- * windows of blocks each) by (encoding, decoder, predicate mode), then one
- * persistent kernel per class walking its items on a static schedule (a
- * work-group per item, one window per wavefront; dictionary classes hold the
- * column's dictionary in LDS).
+ * items: zone-map features, the network, the argmin; else the heuristic),
+ * binning of the columns' work items (four windows of blocks each) by
+ * (encoding, decoder, predicate mode), then one persistent kernel per class
+ * that can occur, walking its items on a static schedule (a work-group per
+ * item, one window per wavefront; dictionary classes hold the column's
+ * dictionary in LDS).
  * Columns must be row-major;
  * explicit strategies must use the SCAN_DEC_RM_LDS or SCAN_DEC_RM_DIRECT
  * decoder.  Results equal scan_run's for every item, bit for bit.
  *
- * scan_batch_prepare validates the items and uploads their descriptors and
- * windows once; the selector state and the tuning stored for (enc -1, b 0,
- * strategy -1) at that moment are baked in (tuning: work-groups per CU of the
- * class kernels, default 4, at most the number that fit, and the window,
- * default and at most 64 blocks).  An invalid item does not
- * fail the call: its result carries the error in `status`.  `items` (host)
- * may be freed after the call; the columns' device buffers must stay alive
- * until the handle is released.  *handle (host) receives an id. */
+ * scan_batch_prepare validates the items, uploads their descriptors, windows
+ * and zone-map segments once, and captures the replay sequence into a HIP
+ * graph (the class kernels forked over up to four branches; with graphs
+ * turned off by scan_batch_set_graph, or if capture fails, replays enqueue the
+ * kernels one by one: same results).  Baked in at that moment: the selector
+ * (its parameters are copied), and the tuning stored for (enc -1, b 0,
+ * strategy -1) (work-groups per CU of the class kernels, default 4, at most
+ * the number that fit, and the window, default and at most 64 blocks).  An
+ * invalid item does not fail the call: its result carries the error in
+ * `status`.  `items` (host) may be freed after the call; the columns' device
+ * buffers must stay alive until the handle is released.  *handle (host)
+ * receives an id.  Up to 2^24 items; more -> SCAN_EINVAL. */
 scan_status scan_batch_prepare(scan_ctx* ctx, const scan_item* items, size_t n_items, uint64_t* handle);
-/* Enqueue the batch's launches on the context stream.  With out (host,
- * n_items results) non-NULL, waits and fills it; with out NULL, only
- * enqueues.  May be replayed any number of times. */
+/* Enqueue the batch on the context stream (one graph launch).  With out
+ * (host, n_items results) non-NULL, also copies the results back, waits and
+ * fills it; with out NULL, only enqueues.  May be replayed any number of
+ * times; replays on one context's stream run one after another. */
 scan_status scan_batch_replay(scan_ctx* ctx, uint64_t handle, scan_result* out);
-/* Wait for the stream and free the batch's buffers. */
+/* Wait for the stream and free the batch's buffers and graph. */
 scan_status scan_batch_release(scan_ctx* ctx, uint64_t handle);
 /* prepare + replay + release. */
 scan_status scan_batch_run(scan_ctx* ctx, const scan_item* items, size_t n_items, scan_result* out);
 /* Launch tuning of the batch class kernels (wgs_per_cu, window_blocks). */
 scan_status scan_batch_set_tune(scan_ctx* ctx, const scan_tune* t);
+/* Whether later scan_batch_prepare calls capture a graph (1, the default) or
+ * leave replays to direct launches (0).  Other values -> SCAN_EINVAL. */
+scan_status scan_batch_set_graph(scan_ctx* ctx, int32_t enabled);
+typedef struct {
+  int32_t captured;           /* 1: a replay is one graph launch */
+  uint32_t kernels;           /* kernels in one replay */
+  uint32_t class_mask;        /* class scans launched (bit enc*4 + decoder*2 + mode) */
+  uint32_t work_items;        /* work items of the batch's columns */
+} scan_batch_stats;
+/* Plan facts of a prepared batch into *out (host).  Unknown handle -> SCAN_EINVAL. */
+scan_status scan_batch_info(scan_ctx* ctx, uint64_t handle, scan_batch_stats* out);
 
 /* --------------------------------------------------------------- selector */
 /* Not in the paper (the workload's learned strategy choice).

@@ -71,6 +71,11 @@ class ScanTune(ctypes.Structure):
                 ("window_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class ScanBatchStats(ctypes.Structure):
+    _fields_ = [("captured", ctypes.c_int32), ("kernels", ctypes.c_uint32), ("class_mask", ctypes.c_uint32),
+                ("work_items", ctypes.c_uint32)]
+
+
 class ScanRleColumn(ctypes.Structure):
     _fields_ = [("run_value", ctypes.c_void_p), ("run_len", ctypes.c_void_p), ("block_run", ctypes.c_void_p),
                 ("zone_min", ctypes.c_void_p), ("zone_max", ctypes.c_void_p), ("n", ctypes.c_uint64)]
@@ -132,6 +137,8 @@ SIGNATURES = {
     "scan_batch_release": (_i32, [_vp, _u64]),
     "scan_batch_run": (_i32, [_vp, _P(ScanItem), ctypes.c_size_t, _P(ScanResult)]),
     "scan_batch_set_tune": (_i32, [_vp, _P(ScanTune)]),
+    "scan_batch_set_graph": (_i32, [_vp, _i32]),
+    "scan_batch_info": (_i32, [_vp, _u64, _P(ScanBatchStats)]),
     "scan_mlp_param_count": (ctypes.c_int, []),
     "scan_selector_set": (_i32, [_vp, _vp, ctypes.c_size_t]),
     "scan_selector_clear": (_i32, [_vp]),

@@ -394,6 +394,16 @@ class Context:
         self.check(self.lib.scan_batch_run(self.h, arr, len(items), out), "scan_batch_run")
         return [out[i].as_dict() for i in range(len(items))]
 
+    def batch_set_graph(self, enabled: bool):
+        """Capture later prepared batches into HIP graphs (default) or replay them launch by launch."""
+        self.check(self.lib.scan_batch_set_graph(self.h, 1 if enabled else 0), "scan_batch_set_graph")
+
+    def batch_info(self, handle: int) -> dict:
+        s = _lib.ScanBatchStats()
+        self.check(self.lib.scan_batch_info(self.h, handle, ctypes.byref(s)), "scan_batch_info")
+        return {"captured": bool(s.captured), "kernels": int(s.kernels), "class_mask": int(s.class_mask),
+                "work_items": int(s.work_items)}
+
     def batch_set_tune(self, wgs_per_cu=0, window_blocks=0):
         t = ScanTune(0, wgs_per_cu, window_blocks, 0)
         self.check(self.lib.scan_batch_set_tune(self.h, ctypes.byref(t)), "scan_batch_set_tune")

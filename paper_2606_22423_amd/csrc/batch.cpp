@@ -1,15 +1,17 @@
 // Batched scans: host side.  A batch is planned once (validation, column
-// descriptors, work items, device buffers); a replay enqueues its launches on
-// the context stream:
+// descriptors, work items, zone-map segments, device buffers) and its replay
+// sequence is captured into a HIP graph:
 //   setup (clear slots and class counts, dictionary code ranges)
-//   -> [features -> selector MLP]  (when a selector is loaded)
+//   -> [zone-map features -> selector MLP]  (when a selector is loaded)
 //   -> select (strategy per column, written on the device)
 //   -> bin (items into twelve class lists)
-//   -> twelve persistent class scans (static schedule over each list)
-// so a replay is 15-17 launches whatever the number of columns; the 32-byte
-// result slots come back with one copy.  The same column descriptors serve the
-// single-column selector (scan_run with SCAN_STRAT_AUTO) and the feature
-// export.
+//   -> the persistent class scans that can occur (static schedule over each
+//      list), forked over up to four graph branches
+// so a replay is one hipGraphLaunch whatever the number of columns; the
+// 32-byte result slots come back with one copy.  If capture or instantiation
+// fails the same sequence is enqueued launch by launch.  The same column
+// descriptors serve the single-column selector (scan_run with
+// SCAN_STRAT_AUTO) and the feature export.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,7 +25,8 @@ using namespace scan_dev;
 
 namespace scan_dev {
 hipError_t launch_batch_setup(const BatchArgs& a, hipStream_t st);
-hipError_t launch_batch_features(const BatchCol* cols, uint32_t n_cols, float* X, uint32_t grid, hipStream_t st);
+hipError_t launch_batch_features(const BatchCol* cols, uint32_t n_cols, const BatchWork* segs, uint32_t n_segs,
+                                 FeatPart* parts, float* X, hipStream_t st);
 hipError_t launch_batch_select(BatchCol* cols, uint32_t n_cols, const float* scores, int32_t k, BatchOut* out,
                                hipStream_t st);
 hipError_t launch_batch_bin(const BatchArgs& a, hipStream_t st);
@@ -33,6 +36,8 @@ hipError_t launch_mlp_forward(const float* theta, const float* X, uint32_t rows,
 namespace {
 
 constexpr uint32_t kMaxWindow = 64;  // a wavefront's block-survivor list holds 64 entries
+constexpr int kMaxBranches = 4;      // graph branches the class scans are forked over
+constexpr uint32_t kThetaFloats = 64 * 6 + 64 + 64 * 64 + 64 + 8 * 64 + 8;
 
 // Device buffers of a batch (or of the one-column selector scratch).
 struct BatchBuffers {
@@ -44,16 +49,21 @@ struct BatchBuffers {
   BatchOut* out_host = nullptr;  // pinned
   float* feats = nullptr;
   float* scores = nullptr;
+  BatchWork* segs = nullptr;     // zone-map segments (selector features)
+  FeatPart* fparts = nullptr;    // their sums
+  float* theta = nullptr;        // the batch's own copy of the selector parameters
+  uint32_t n_segs = 0;
 
   void release() {
-    for (void* p : {(void*)cols, (void*)work, (void*)lists, (void*)counters, (void*)out, (void*)feats, (void*)scores})
+    for (void* p : {(void*)cols, (void*)work, (void*)lists, (void*)counters, (void*)out, (void*)feats, (void*)scores,
+                    (void*)segs, (void*)fparts, (void*)theta})
       if (p) (void)hipFree(p);
     if (out_host) (void)hipHostFree(out_host);
     *this = BatchBuffers();
   }
 
-  hipError_t allocate(size_t n_cols, size_t n_work) {
-    const size_t nc = std::max<size_t>(1, n_cols), nw = std::max<size_t>(1, n_work);
+  hipError_t allocate(size_t n_cols, size_t n_work, size_t n_seg, bool with_theta) {
+    const size_t nc = std::max<size_t>(1, n_cols), nw = std::max<size_t>(1, n_work), ns = std::max<size_t>(1, n_seg);
     hipError_t e;
     if ((e = hipMalloc(&cols, sizeof(BatchCol) * nc)) != hipSuccess) return e;
     if ((e = hipMalloc(&work, sizeof(BatchWork) * nw)) != hipSuccess) return e;
@@ -62,6 +72,10 @@ struct BatchBuffers {
     if ((e = hipMalloc(&out, sizeof(BatchOut) * nc)) != hipSuccess) return e;
     if ((e = hipMalloc(&feats, sizeof(float) * 6 * nc)) != hipSuccess) return e;
     if ((e = hipMalloc(&scores, sizeof(float) * 8 * nc)) != hipSuccess) return e;
+    if ((e = hipMalloc(&segs, sizeof(BatchWork) * ns)) != hipSuccess) return e;
+    if ((e = hipMalloc(&fparts, sizeof(FeatPart) * ns)) != hipSuccess) return e;
+    if (with_theta && (e = hipMalloc(&theta, sizeof(float) * kThetaFloats)) != hipSuccess) return e;
+    n_segs = (uint32_t)n_seg;
     return hipHostMalloc(&out_host, sizeof(BatchOut) * nc, hipHostMallocDefault);
   }
 };
@@ -83,7 +97,8 @@ BatchArgs make_args(const BatchBuffers& m, uint32_t n_cols, uint32_t n_work, int
 // Host descriptors of the columns, their validation status and the work
 // items (windows of up to `window` blocks of every non-empty valid column).
 void plan_cols(scan_ctx* ctx, const scan_item* items, size_t n, uint32_t window, std::vector<BatchCol>& cols,
-               std::vector<int32_t>& status, std::vector<BatchWork>* work) {
+               std::vector<int32_t>& status, std::vector<BatchWork>* work, std::vector<BatchWork>& segs) {
+  segs.clear();
   cols.resize(n);
   status.assign(n, SCAN_OK);
   for (size_t i = 0; i < n; ++i) {
@@ -142,6 +157,13 @@ void plan_cols(scan_ctx* ctx, const scan_item* items, size_t n, uint32_t window,
     if ((h & 3) != SCAN_DEC_RM_LDS && (h & 3) != SCAN_DEC_RM_DIRECT) h = (h & ~3) | SCAN_DEC_RM_DIRECT;
     c.heuristic = h;
     c.strategy = it.strategy >= 0 ? it.strategy : h;
+    // zone-map segments of every column with zone maps (the selector's
+    // features read them, also for an empty predicate)
+    c.fseg0 = (uint32_t)segs.size();
+    if (zm)
+      for (uint64_t k = 0; k < c.nb; k += kFeatSegBlocks)
+        segs.push_back(BatchWork{(uint32_t)i, (uint32_t)std::min<uint64_t>(kFeatSegBlocks, c.nb - k), k});
+    c.fsegs = (uint32_t)segs.size() - c.fseg0;
     cols[i] = c;
     // items of four windows, one per wavefront of the work-group that takes
     // the item: fewer items (each costs its descriptor loads, pipeline start
@@ -153,18 +175,32 @@ void plan_cols(scan_ctx* ctx, const scan_item* items, size_t n, uint32_t window,
   }
 }
 
-// Setup, then (with a selector) features and network scores, then selection:
-// enqueued on `st`.
-hipError_t enqueue_select(scan_ctx* ctx, const BatchBuffers& m, uint32_t n_cols, bool use_selector, hipStream_t st) {
+// Setup, then (with selector parameters) features and network scores, then
+// selection: enqueued on `st`.
+hipError_t enqueue_select(const BatchBuffers& m, uint32_t n_cols, const float* theta, hipStream_t st) {
   hipError_t e = launch_batch_setup(make_args(m, n_cols, 0, 0), st);
   if (e != hipSuccess || n_cols == 0) return e;
-  if (use_selector) {
-    e = launch_batch_features(m.cols, n_cols, m.feats, (uint32_t)ctx->cus * 4u, st);
+  if (theta) {
+    e = launch_batch_features(m.cols, n_cols, m.segs, m.n_segs, m.fparts, m.feats, st);
     if (e != hipSuccess) return e;
-    e = launch_mlp_forward(selector_theta(ctx), m.feats, n_cols, m.scores, st);
+    e = launch_mlp_forward(theta, m.feats, n_cols, m.scores, st);
     if (e != hipSuccess) return e;
   }
-  return launch_batch_select(m.cols, n_cols, use_selector ? m.scores : nullptr, 8, m.out, st);
+  return launch_batch_select(m.cols, n_cols, theta ? m.scores : nullptr, 8, m.out, st);
+}
+
+// Class scans that can occur: an explicit strategy fixes its column's class,
+// the selector may pick any decoder and mode of the column's encoding, the
+// heuristic fixes one.
+uint32_t possible_classes(const std::vector<BatchCol>& cols, bool selector) {
+  uint32_t mask = 0;
+  for (const BatchCol& c : cols) {
+    if (c.flags & (kColEmpty | kColSkip)) continue;
+    if (c.requested >= 0) mask |= 1u << batch_class(c.enc, c.requested);
+    else if (selector) mask |= 0xFu << (4 * c.enc);
+    else mask |= 1u << batch_class(c.enc, c.heuristic);
+  }
+  return mask;
 }
 
 }  // namespace
@@ -178,10 +214,14 @@ struct BatchPlan {
   bool selector = false;
   uint32_t grid = 0;
   uint32_t grid_cls[kBatchClasses] = {};  // grid clamped to the work-groups that fit at once
+  uint32_t cls_mask = 0;                  // class scans a replay launches
+  uint32_t kernels = 0;                   // kernels per replay
+  hipGraphExec_t exec = nullptr;          // the captured replay (null: direct launches)
 };
 
 static void free_plan(BatchPlan* b) {
   if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
   b->mem.release();
   delete b;
 }
@@ -207,17 +247,69 @@ void destroy_batches(scan_ctx* ctx) {
   }
 }
 
-static hipError_t enqueue_batch(scan_ctx* ctx, BatchPlan* b, hipStream_t st) {
-  hipError_t e = enqueue_select(ctx, b->mem, (uint32_t)b->n_items, b->selector, st);
-  if (e != hipSuccess || b->n_work == 0) return e;
+// The replay sequence on `st`.  With nbr > 0 branch streams (graph capture)
+// the class scans are forked over them after the binning kernel (ev[0]) and
+// joined back (ev[1..nbr]): class scans touch disjoint columns, so they may
+// run concurrently.
+static hipError_t enqueue_batch(BatchPlan* b, hipStream_t st, const hipStream_t* br, int nbr, const hipEvent_t* ev) {
+  hipError_t e = enqueue_select(b->mem, (uint32_t)b->n_items, b->selector ? b->mem.theta : nullptr, st);
+  if (e != hipSuccess || b->n_work == 0 || b->cls_mask == 0) return e;
   e = launch_batch_bin(make_args(b->mem, (uint32_t)b->n_items, b->n_work, 0), st);
   if (e != hipSuccess) return e;
+  if (nbr > 0) {
+    e = hipEventRecord(ev[0], st);
+    for (int i = 0; i < nbr && e == hipSuccess; ++i) e = hipStreamWaitEvent(br[i], ev[0], 0);
+    if (e != hipSuccess) return e;
+  }
+  int k = 0;
   for (int cls = 0; cls < kBatchClasses; ++cls) {
-    e = batch_class_fn(cls)(make_args(b->mem, (uint32_t)b->n_items, b->n_work, cls), b->grid_cls[cls], 256, st,
+    if (!((b->cls_mask >> cls) & 1u)) continue;
+    const hipStream_t s = nbr > 0 ? br[k++ % nbr] : st;
+    e = batch_class_fn(cls)(make_args(b->mem, (uint32_t)b->n_items, b->n_work, cls), b->grid_cls[cls], 256, s,
                             nullptr);
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  for (int i = 0; i < nbr && e == hipSuccess; ++i) {
+    e = hipEventRecord(ev[1 + i], br[i]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, ev[1 + i], 0);
+  }
+  return e;
+}
+
+// Capture the replay sequence into b->exec.  Any failure leaves b->exec null
+// (replays then enqueue the launches directly) and clears the error state.
+static void capture_batch(scan_ctx* ctx, BatchPlan* b) {
+  const int ncls = __builtin_popcount(b->cls_mask);
+  const int nbr = std::min(kMaxBranches, ncls);
+  hipStream_t cs = nullptr;
+  hipStream_t br[kMaxBranches] = {};
+  hipEvent_t ev[kMaxBranches + 1] = {};
+  hipGraph_t g = nullptr;
+  hipGraphExec_t x = nullptr;
+  bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
+  for (int i = 0; i < nbr && ok; ++i) ok = hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking) == hipSuccess;
+  for (int i = 0; i <= nbr && ok; ++i) ok = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) == hipSuccess;
+  if (ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+    const hipError_t le = enqueue_batch(b, cs, br, nbr, ev);
+    const hipError_t ee = hipStreamEndCapture(cs, &g);
+    ok = le == hipSuccess && ee == hipSuccess && g != nullptr;
+    if (ok) ok = hipGraphInstantiate(&x, g, nullptr, nullptr, 0) == hipSuccess;
+  } else {
+    ok = false;
+  }
+  if (g) (void)hipGraphDestroy(g);
+  for (int i = 0; i <= nbr; ++i)
+    if (ev[i]) (void)hipEventDestroy(ev[i]);
+  for (int i = 0; i < nbr; ++i)
+    if (br[i]) (void)hipStreamDestroy(br[i]);
+  if (cs) (void)hipStreamDestroy(cs);
+  if (!ok && x) {
+    (void)hipGraphExecDestroy(x);
+    x = nullptr;
+  }
+  (void)hipGetLastError();
+  (void)ctx;
+  b->exec = ok ? x : nullptr;
 }
 
 static void fill_results(const BatchPlan* b, scan_result* out) {
@@ -259,13 +351,19 @@ scan_status selector_pick(scan_ctx* ctx, const scan_column* col, int32_t enc, ui
   it.strategy = SCAN_STRAT_AUTO;
   std::vector<BatchCol> cols;
   std::vector<int32_t> status;
-  plan_cols(ctx, &it, 1, kMaxWindow, cols, status, nullptr);
+  std::vector<BatchWork> segs;
+  plan_cols(ctx, &it, 1, kMaxWindow, cols, status, nullptr, segs);
   if (status[0] != SCAN_OK) return (scan_status)status[0];
   auto& ps = pick_scratch();
   PickScratch*& sc = ps[ctx];
+  if (sc && sc->mem.n_segs < segs.size()) {  // grown for a longer column
+    sc->mem.release();
+    delete sc;
+    sc = nullptr;
+  }
   if (!sc) {
     sc = new PickScratch();
-    const hipError_t e = sc->mem.allocate(1, 1);
+    const hipError_t e = sc->mem.allocate(1, 1, std::max<size_t>(segs.size(), 64), false);
     if (e != hipSuccess) {
       sc->mem.release();
       delete sc;
@@ -274,7 +372,14 @@ scan_status selector_pick(scan_ctx* ctx, const scan_column* col, int32_t enc, ui
     }
   }
   hipError_t e = hipMemcpyAsync(sc->mem.cols, cols.data(), sizeof(BatchCol), hipMemcpyHostToDevice, ctx->stream);
-  if (e == hipSuccess) e = enqueue_select(ctx, sc->mem, 1, true, ctx->stream);
+  if (e == hipSuccess && !segs.empty())
+    e = hipMemcpyAsync(sc->mem.segs, segs.data(), sizeof(BatchWork) * segs.size(), hipMemcpyHostToDevice,
+                       ctx->stream);
+  if (e == hipSuccess) {
+    BatchBuffers m = sc->mem;
+    m.n_segs = (uint32_t)segs.size();
+    e = enqueue_select(m, 1, selector_theta(ctx), ctx->stream);
+  }
   if (e == hipSuccess)
     e = hipMemcpyAsync(sc->mem.out_host, sc->mem.out, sizeof(BatchOut), hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -307,14 +412,15 @@ scan_status scan_batch_prepare(scan_ctx* ctx, const scan_item* items, size_t n_i
     if (batch_class_fn(cls)(make_args(b->mem, 0, 0, cls), 0, 256, ctx->stream, &occ) == hipSuccess && occ > 0)
       b->grid_cls[cls] = std::min<uint32_t>(b->grid, (uint32_t)ctx->cus * (uint32_t)occ);
   }
-  std::vector<BatchWork> work;
-  plan_cols(ctx, items, n_items, window, b->cols, b->status, &work);
-  if (work.size() > 0xFFFFFFFFull) {
+  std::vector<BatchWork> work, segs;
+  plan_cols(ctx, items, n_items, window, b->cols, b->status, &work, segs);
+  if (work.size() > 0xFFFFFFFFull || segs.size() > 0xFFFFFFFFull) {
     free_plan(b);
     return fail(ctx, SCAN_EINVAL, "too many work items");
   }
   b->n_work = (uint32_t)work.size();
-  e = b->mem.allocate(n_items, work.size());
+  b->cls_mask = possible_classes(b->cols, b->selector);
+  e = b->mem.allocate(n_items, work.size(), b->selector ? segs.size() : 0, b->selector);
   if (e != hipSuccess) {
     free_plan(b);
     return fail(ctx, SCAN_ENOMEM, "batch buffers: %s", hipGetErrorString(e));
@@ -322,10 +428,23 @@ scan_status scan_batch_prepare(scan_ctx* ctx, const scan_item* items, size_t n_i
   if (n_items) e = hipMemcpy(b->mem.cols, b->cols.data(), sizeof(BatchCol) * n_items, hipMemcpyHostToDevice);
   if (e == hipSuccess && !work.empty())
     e = hipMemcpy(b->mem.work, work.data(), sizeof(BatchWork) * work.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && b->selector && !segs.empty())
+    e = hipMemcpy(b->mem.segs, segs.data(), sizeof(BatchWork) * segs.size(), hipMemcpyHostToDevice);
+  // the selector as it is now is part of the batch: a later change of the
+  // context's selector does not reach replays of this one
+  if (e == hipSuccess && b->selector) {
+    e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess)
+      e = hipMemcpy(b->mem.theta, selector_theta(ctx), sizeof(float) * kThetaFloats, hipMemcpyDeviceToDevice);
+  }
   if (e != hipSuccess) {
     free_plan(b);
     return hip_fail(ctx, e, "batch upload");
   }
+  b->kernels = n_items == 0 ? 1u
+                            : 2u + (b->selector ? 2u + (b->mem.n_segs ? 1u : 0u) : 0u) +
+                                  (b->n_work && b->cls_mask ? 1u + (uint32_t)__builtin_popcount(b->cls_mask) : 0u);
+  if (ctx->batch_graph) capture_batch(ctx, b);
   const uint64_t h = ctx->next_batch++;
   ctx->batches[h] = b;
   *handle = h;
@@ -338,7 +457,7 @@ scan_status scan_batch_replay(scan_ctx* ctx, uint64_t handle, scan_result* out) 
   if (it == ctx->batches.end()) return fail(ctx, SCAN_EINVAL, "unknown batch handle %llu", (unsigned long long)handle);
   BatchPlan* b = it->second;
   hipError_t e = hipSetDevice(ctx->device);
-  if (e == hipSuccess) e = enqueue_batch(ctx, b, ctx->stream);
+  if (e == hipSuccess) e = b->exec ? hipGraphLaunch(b->exec, ctx->stream) : enqueue_batch(b, ctx->stream, nullptr, 0, nullptr);
   if (e == hipSuccess && out && b->n_items)
     e = hipMemcpyAsync(b->mem.out_host, b->mem.out, sizeof(BatchOut) * b->n_items, hipMemcpyDeviceToHost,
                        ctx->stream);
@@ -379,6 +498,26 @@ scan_status scan_batch_set_tune(scan_ctx* ctx, const scan_tune* t) {
   return SCAN_OK;
 }
 
+scan_status scan_batch_set_graph(scan_ctx* ctx, int32_t enabled) {
+  if (!ctx) return SCAN_EINVAL;
+  if (enabled != 0 && enabled != 1) return fail(ctx, SCAN_EINVAL, "enabled must be 0 or 1");
+  ctx->batch_graph = enabled == 1;
+  return SCAN_OK;
+}
+
+scan_status scan_batch_info(scan_ctx* ctx, uint64_t handle, scan_batch_stats* out) {
+  if (!ctx) return SCAN_EINVAL;
+  if (!out) return fail(ctx, SCAN_EINVAL, "out is NULL");
+  auto it = ctx->batches.find(handle);
+  if (it == ctx->batches.end()) return fail(ctx, SCAN_EINVAL, "unknown batch handle %llu", (unsigned long long)handle);
+  const BatchPlan* b = it->second;
+  out->captured = b->exec ? 1 : 0;
+  out->kernels = b->kernels;
+  out->class_mask = b->cls_mask;
+  out->work_items = b->n_work;
+  return SCAN_OK;
+}
+
 scan_status scan_features(scan_ctx* ctx, const scan_item* items, size_t n_items, float* X_dev) {
   if (!ctx) return SCAN_EINVAL;
   if (n_items == 0) return SCAN_OK;
@@ -386,16 +525,20 @@ scan_status scan_features(scan_ctx* ctx, const scan_item* items, size_t n_items,
   if (n_items > (1u << 24)) return fail(ctx, SCAN_EINVAL, "at most 2^24 items");
   std::vector<BatchCol> cols;
   std::vector<int32_t> status;
-  plan_cols(ctx, items, n_items, kMaxWindow, cols, status, nullptr);
+  std::vector<BatchWork> segs;
+  plan_cols(ctx, items, n_items, kMaxWindow, cols, status, nullptr, segs);
   for (size_t i = 0; i < n_items; ++i)
     if (status[i] != SCAN_OK) return (scan_status)status[i];
   BatchBuffers m;
-  hipError_t e = m.allocate(n_items, 1);
+  hipError_t e = m.allocate(n_items, 1, segs.size(), false);
   if (e == hipSuccess)
     e = hipMemcpyAsync(m.cols, cols.data(), sizeof(BatchCol) * n_items, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess && !segs.empty())
+    e = hipMemcpyAsync(m.segs, segs.data(), sizeof(BatchWork) * segs.size(), hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) e = launch_batch_setup(make_args(m, (uint32_t)n_items, 0, 0), ctx->stream);
   if (e == hipSuccess)
-    e = launch_batch_features(m.cols, (uint32_t)n_items, X_dev, (uint32_t)ctx->cus * 4u, ctx->stream);
+    e = launch_batch_features(m.cols, (uint32_t)n_items, m.segs, (uint32_t)segs.size(), m.fparts, X_dev,
+                              ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   m.release();
   if (e != hipSuccess) return hip_fail(ctx, e, "features");

@@ -67,8 +67,7 @@ __device__ __forceinline__ double wave_max_f64(double x) {
   return x;
 }
 
-// Selector features of each column from its zone maps only (one wavefront per
-// column, fp64 accumulation):
+// Selector features of each column from its zone maps only (fp64 sums):
 //   f0 = b/32, f1 = log2(n)/24,
 //   f2 = log10(max(s, 1e-6))/6 with s = sum_k c_k overlap_k / n, overlap_k the
 //        share of block k's [min, max] covered by [lo, hi) (values spread evenly),
@@ -77,74 +76,106 @@ __device__ __forceinline__ double wave_max_f64(double x) {
 //   f5 = encoding / 2.
 // Dictionary columns use codes and the code range; columns without zone maps
 // get s = 1, f3 = 1, f4 = 0.
-__global__ __launch_bounds__(256) void batch_features_kernel(const BatchCol* cols, uint32_t n_cols, float* X) {
+// Two launches: every segment of up to 256 blocks of a column is summed by
+// one wavefront (four zone-map pairs per lane, all loaded before any is used:
+// one memory latency per segment, so a 2^24-value column costs no more than
+// a short one), then one wavefront per column adds its segments' sums in a
+// fixed order (lane j takes segments j, j + 64, ..., then a fixed butterfly),
+// so the features are the same bits on every run.
+__device__ __forceinline__ void feat_bounds(const BatchCol& c, double& lo, double& hi) {
+  if (c.enc == ENC_DICT) {
+    lo = (double)c.clo;
+    hi = (double)c.chi;
+  } else {
+    lo = (double)c.lo;
+    hi = (double)c.hi;
+  }
+}
+
+__global__ __launch_bounds__(256) void batch_feat_seg_kernel(const BatchCol* cols, const BatchWork* segs,
+                                                             uint32_t n_segs, FeatPart* parts) {
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const uint32_t tw = (gridDim.x * blockDim.x) >> 6;
-  for (uint32_t col = gw; col < n_cols; col += tw) {
-    const BatchCol c = cols[col];
-    double lo, hi;
-    if (c.enc == ENC_DICT) {
-      lo = (double)c.clo;
-      hi = (double)c.chi;
+  const uint32_t seg = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (seg >= n_segs) return;  // wave-uniform
+  const BatchWork w = segs[seg];
+  const BatchCol& c = cols[w.col];
+  double lo, hi;
+  feat_bounds(c, lo, hi);
+  constexpr int kU = kFeatSegBlocks / 64;
+  double mn[kU], mx[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const uint32_t j = lane + 64u * u;
+    const uint64_t k = w.k0 + (j < w.nblk ? j : 0u);
+    if (c.enc == ENC_DELTA) {
+      mn[u] = (double)static_cast<const int64_t*>(c.zmin)[k];
+      mx[u] = (double)static_cast<const int64_t*>(c.zmax)[k];
     } else {
-      lo = (double)c.lo;
-      hi = (double)c.hi;
+      mn[u] = (double)static_cast<const uint32_t*>(c.zmin)[k];
+      mx[u] = (double)static_cast<const uint32_t*>(c.zmax)[k];
     }
-    double s = 1.0, frac = 1.0, clust = 0.0;
-    if ((c.flags & kColHasZm) && c.nb) {
-      double acc = 0.0, meet = 0.0, spread = 0.0, gmin = 1e300, gmax = -1e300;
-      // Each lane takes blocks lane, lane + 64, ... in order; the zone maps of
-      // kU of them are loaded before any is used, so a long column does not
-      // wait one memory latency per block (the accumulation order is unchanged).
-      constexpr int kU = 8;
-      for (uint64_t k0 = lane; k0 < c.nb; k0 += 64u * kU) {
-        double mn[kU], mx[kU];
+  }
+  double acc = 0.0, meet = 0.0, spread = 0.0, gmin = 1e300, gmax = -1e300;
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const uint64_t k = k0 + 64u * u < c.nb ? k0 + 64u * u : k0;
-          if (c.enc == ENC_DELTA) {
-            mn[u] = (double)static_cast<const int64_t*>(c.zmin)[k];
-            mx[u] = (double)static_cast<const int64_t*>(c.zmax)[k];
-          } else {
-            mn[u] = (double)static_cast<const uint32_t*>(c.zmin)[k];
-            mx[u] = (double)static_cast<const uint32_t*>(c.zmax)[k];
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const uint64_t k = k0 + 64u * u;
-          if (k >= c.nb) break;
-          const double cnt = (k == c.nb - 1) ? (double)c.tail : 1024.0;
-          if (lo < hi) {
-            const double ov = fmax(fmin(hi, mx[u] + 1.0) - fmax(lo, mn[u]), 0.0) / (mx[u] - mn[u] + 1.0);
-            acc += cnt * ov;
-            meet += (mx[u] < lo || mn[u] >= hi) ? 0.0 : 1.0;
-          }
-          spread += mx[u] - mn[u];
-          gmin = fmin(gmin, mn[u]);
-          gmax = fmax(gmax, mx[u]);
-        }
-      }
-      acc = wave_sum_f64(acc);
-      meet = wave_sum_f64(meet);
-      spread = wave_sum_f64(spread);
-      gmin = wave_min_f64(gmin);
-      gmax = wave_max_f64(gmax);
-      s = acc / (double)c.n;
-      frac = meet / (double)c.nb;
-      clust = 1.0 - (spread / (double)c.nb) / (gmax - gmin + 1.0);
+  for (int u = 0; u < kU; ++u) {
+    const uint32_t j = lane + 64u * u;
+    if (j >= w.nblk) break;
+    const uint64_t k = w.k0 + j;
+    const double cnt = (k == c.nb - 1) ? (double)c.tail : 1024.0;
+    if (lo < hi) {
+      const double ov = fmax(fmin(hi, mx[u] + 1.0) - fmax(lo, mn[u]), 0.0) / (mx[u] - mn[u] + 1.0);
+      acc += cnt * ov;
+      meet += (mx[u] < lo || mn[u] >= hi) ? 0.0 : 1.0;
     }
-    if (!(lo < hi)) s = 0.0;
-    if (lane == 0) {
-      float* x = X + (size_t)col * 6u;
-      x[0] = (float)((double)c.b / 32.0);
-      x[1] = (float)(log2((double)c.n) / 24.0);
-      x[2] = (float)(log10(fmax(s, 1e-6)) / 6.0);
-      x[3] = (float)frac;
-      x[4] = (float)clust;
-      x[5] = (float)((double)c.enc / 2.0);
+    spread += mx[u] - mn[u];
+    gmin = fmin(gmin, mn[u]);
+    gmax = fmax(gmax, mx[u]);
+  }
+  acc = wave_sum_f64(acc);
+  meet = wave_sum_f64(meet);
+  spread = wave_sum_f64(spread);
+  gmin = wave_min_f64(gmin);
+  gmax = wave_max_f64(gmax);
+  if (lane == 0) parts[seg] = FeatPart{acc, meet, spread, gmin, gmax};
+}
+
+__global__ __launch_bounds__(256) void batch_feat_col_kernel(const BatchCol* cols, uint32_t n_cols,
+                                                             const FeatPart* parts, float* X) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t col = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (col >= n_cols) return;  // wave-uniform
+  const BatchCol c = cols[col];
+  double lo, hi;
+  feat_bounds(c, lo, hi);
+  double s = 1.0, frac = 1.0, clust = 0.0;
+  if ((c.flags & kColHasZm) && c.nb && c.fsegs) {
+    double acc = 0.0, meet = 0.0, spread = 0.0, gmin = 1e300, gmax = -1e300;
+    for (uint32_t j = lane; j < c.fsegs; j += 64u) {
+      const FeatPart q = parts[c.fseg0 + j];
+      acc += q.acc;
+      meet += q.meet;
+      spread += q.spread;
+      gmin = fmin(gmin, q.gmin);
+      gmax = fmax(gmax, q.gmax);
     }
+    acc = wave_sum_f64(acc);
+    meet = wave_sum_f64(meet);
+    spread = wave_sum_f64(spread);
+    gmin = wave_min_f64(gmin);
+    gmax = wave_max_f64(gmax);
+    s = acc / (double)c.n;
+    frac = meet / (double)c.nb;
+    clust = 1.0 - (spread / (double)c.nb) / (gmax - gmin + 1.0);
+  }
+  if (!(lo < hi)) s = 0.0;
+  if (lane == 0) {
+    float* x = X + (size_t)col * 6u;
+    x[0] = (float)((double)c.b / 32.0);
+    x[1] = (float)(log2((double)c.n) / 24.0);
+    x[2] = (float)(log10(fmax(s, 1e-6)) / 6.0);
+    x[3] = (float)frac;
+    x[4] = (float)clust;
+    x[5] = (float)((double)c.enc / 2.0);
   }
 }
 
@@ -209,8 +240,15 @@ hipError_t launch_batch_setup(const BatchArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_batch_features(const BatchCol* cols, uint32_t n_cols, float* X, uint32_t grid, hipStream_t st) {
-  hipLaunchKernelGGL(batch_features_kernel, dim3(grid), dim3(256), 0, st, cols, n_cols, X);
+hipError_t launch_batch_features(const BatchCol* cols, uint32_t n_cols, const BatchWork* segs, uint32_t n_segs,
+                                 FeatPart* parts, float* X, hipStream_t st) {
+  if (n_segs) {
+    hipLaunchKernelGGL(batch_feat_seg_kernel, dim3((n_segs + 3) / 4), dim3(256), 0, st, cols, segs, n_segs, parts);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (n_cols == 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_feat_col_kernel, dim3((n_cols + 3) / 4), dim3(256), 0, st, cols, n_cols, parts, X);
   return hipGetLastError();
 }
 

@@ -44,6 +44,8 @@ struct BatchCol {
   uint32_t valid_mask;    // selector classes allowed for this column (bit c)
   uint32_t flags;         // kColEmpty | kColHasZm | kColSkip
   int32_t heuristic;      // strategy used when no selector is loaded
+  uint32_t fseg0;         // first zone-map segment of the column (selector features)
+  uint32_t fsegs;         // number of its segments (0: no zone maps or no blocks)
   uint32_t pad;
 };
 
@@ -54,6 +56,16 @@ struct BatchWork {
   uint32_t nblk;
   uint64_t k0;
 };
+
+// Zone-map sums of one segment of a column's blocks (selector features; see
+// batch_feat_seg_kernel).
+struct FeatPart {
+  double acc, meet, spread, gmin, gmax;
+};
+
+// Blocks per zone-map segment: one wavefront reads four zone-map pairs per
+// lane at once.
+constexpr uint32_t kFeatSegBlocks = 256;
 
 struct BatchOut {
   uint64_t count, sum, blocks;

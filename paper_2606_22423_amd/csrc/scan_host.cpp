@@ -9,6 +9,7 @@
 #include <map>
 #include <string>
 #include <tuple>
+#include <vector>
 
 #include "../../include/scan.h"
 #include "launch_tables.h"
@@ -323,6 +324,11 @@ scan_status scan_create(scan_ctx** out, int device, void* hip_stream) {
     scan_destroy(ctx);
     return SCAN_ENOMEM;
   }
+  if (hipEventCreateWithFlags(&ctx->order_event, hipEventDisableTiming) != hipSuccess) {
+    ctx->order_event = nullptr;
+    scan_destroy(ctx);
+    return SCAN_EDEVICE;
+  }
   if (hipMemset(ctx->ticket, 0, 256) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     scan_destroy(ctx);
     return SCAN_EDEVICE;
@@ -333,7 +339,15 @@ scan_status scan_create(scan_ctx** out, int device, void* hip_stream) {
 
 scan_status scan_set_stream(scan_ctx* ctx, void* hip_stream) {
   if (!ctx) return SCAN_EINVAL;
-  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  hipStream_t next = static_cast<hipStream_t>(hip_stream);
+  if (next == ctx->stream) return SCAN_OK;
+  // Every scan writes the context's partials and result slot: work enqueued
+  // on the new stream must not start before what the old stream still holds.
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = hipEventRecord(ctx->order_event, ctx->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(next, ctx->order_event, 0);
+  if (e != hipSuccess) return hip_fail(ctx, e, "ordering the new stream after the old one");
+  ctx->stream = next;
   return SCAN_OK;
 }
 
@@ -349,6 +363,7 @@ void scan_destroy(scan_ctx* ctx) {
   if (ctx->out_dev) (void)hipFree(ctx->out_dev);
   if (ctx->out_host) (void)hipHostFree(ctx->out_host);
   if (ctx->evict_buf) (void)hipFree(ctx->evict_buf);
+  if (ctx->order_event) (void)hipEventDestroy(ctx->order_event);
   delete ctx;
 }
 
@@ -532,21 +547,38 @@ scan_status scan_tune_load(scan_ctx* ctx, const char* path) {
   if (!path) return fail(ctx, SCAN_EINVAL, "path is NULL");
   FILE* f = std::fopen(path, "r");
   if (!f) return fail(ctx, SCAN_EINVAL, "cannot read %s", path);
+  // Entries are parsed first and installed only if the whole file is valid:
+  // a line naming an entry that does not parse or holds an invalid tuning,
+  // or a file without any entry, is an error and changes nothing.
   char line[512];
-  int loaded = 0;
+  std::vector<std::pair<std::tuple<int32_t, uint32_t, int32_t>, scan_tune>> got;
+  int lineno = 0, bad = 0;
   while (std::fgets(line, sizeof line, f)) {
+    ++lineno;
+    if (!std::strstr(line, "\"enc\"")) continue;  // the header and the closing bracket
     int enc, strat, wg, pc, win;
     unsigned b;
     if (std::sscanf(line,
                     " {\"enc\": %d, \"b\": %u, \"strategy\": %d, \"wg_size\": %d, \"wgs_per_cu\": %d, "
                     "\"window_blocks\": %d}",
-                    &enc, &b, &strat, &wg, &pc, &win) == 6) {
-      scan_tune t{wg, pc, win, 0};
-      if (scan_set_tune(ctx, enc, b, strat, &t) == SCAN_OK) ++loaded;
+                    &enc, &b, &strat, &wg, &pc, &win) != 6) {
+      if (!bad) bad = lineno;
+      continue;
     }
+    const scan_tune t{wg, pc, win, 0};
+    const bool ok = (wg == 0 || (wg >= 64 && wg <= 256 && wg % 64 == 0)) && pc >= 0 && pc <= 64 && win >= 0 &&
+                    win <= 64;
+    if (!ok) {
+      if (!bad) bad = lineno;
+      continue;
+    }
+    got.emplace_back(std::make_tuple((int32_t)enc, (uint32_t)b, (int32_t)strat), t);
   }
   std::fclose(f);
-  return loaded >= 0 ? SCAN_OK : SCAN_EINVAL;
+  if (bad) return fail(ctx, SCAN_EINVAL, "%s: line %d is not a valid tuning entry", path, bad);
+  if (got.empty()) return fail(ctx, SCAN_EINVAL, "%s holds no tuning entry", path);
+  for (const auto& kv : got) ctx->tunes[kv.first] = kv.second;
+  return SCAN_OK;
 }
 
 scan_status scan_beta_read(scan_ctx* ctx, const void* buf, uint64_t bytes, int32_t wgs, int32_t wg_size,

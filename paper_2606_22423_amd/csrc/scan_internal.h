@@ -25,6 +25,7 @@ struct scan_ctx {
   scan_dev::Result* out_host = nullptr;   // pinned staging for it
   uint32_t flush_salt = 0;
   void* evict_buf = nullptr;              // autotuner's cache-evicting read buffer
+  hipEvent_t order_event = nullptr;       // orders a new stream after the old one (scan_set_stream)
   std::string err;
   std::map<std::tuple<int32_t, uint32_t, int32_t>, scan_tune> tunes;
   std::map<std::pair<const void*, uint32_t>, int> occupancy;
@@ -33,6 +34,7 @@ struct scan_ctx {
   std::map<uint64_t, BatchPlan*> batches;
   SelectWork* select = nullptr;       // materializing select work space
   uint64_t next_batch = 1;
+  bool batch_graph = true;            // capture prepared batches into HIP graphs
 };
 
 scan_status fail(scan_ctx* ctx, scan_status st, const char* fmt, ...);

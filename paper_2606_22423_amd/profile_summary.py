@@ -92,13 +92,19 @@ def select_section(trace_path, bench_line, command):
                 rows.append((int(row["Dispatch_Id"]), nm, int(row["End_Timestamp"]) - int(row["Start_Timestamp"]),
                              int(row["Start_Timestamp"]), int(row["End_Timestamp"])))
     rows.sort()
-    calls, cur = [], None
+    # A call runs from its setup kernel through the first copy after its
+    # write pass (the count back to the host); copies dispatched later by
+    # other parts of the program do not belong to it.
+    calls, cur, closed = [], None, True
     for d, nm, t, s0, s1 in rows:
         if nm == "select_setup_kernel":
-            cur = []
+            cur, closed = [], False
             calls.append(cur)
-        if cur is not None and nm in SELECT_STEPS:
-            cur.append((nm, t, s0, s1))
+        if cur is None or closed:
+            continue
+        cur.append((nm, t, s0, s1))
+        if nm == "__amd_rocclr_copyBuffer" and any(k == "select_write_kernel" for k, _, _, _ in cur):
+            closed = True
     sel = bench_line["select"]
     lines = ["# rocprofv3 summary: materializing select on one MI355X", "", "Commands (repository root):", ""]
     lines += ["    " + c for c in command.split(" ;; ")]
@@ -122,10 +128,22 @@ def select_section(trace_path, bench_line, command):
         for k in SELECT_STEPS:
             v = [t for c in timed for nm, t, _, _ in c if nm == k]
             avg[k] = sum(v) / len(v) / 1e3 if v else 0.0
-        span = sum((c[-1][3] - c[0][2]) for c in timed) / len(timed) / 1e3
+        span = sum((max(e for _, _, _, e in c) - c[0][2]) for c in timed) / len(timed) / 1e3
         lines.append("| %d | %g | %d | %s | %.1f | %.4f |" % (
             r["b"], r["sigma"], r["selected"], " | ".join("%.1f" % avg[k] for k in SELECT_STEPS), span, r["ms"]))
     return lines
+
+
+def load_bench_record(path):
+    """The full bench record: bench.py's detail file (its "line" object), or
+    an older stdout holding the whole record as its last JSON line."""
+    with open(path) as fh:
+        text = fh.read()
+    try:
+        d = json.loads(text)
+        return d["line"] if "line" in d else d
+    except ValueError:
+        return json.loads([ln for ln in text.splitlines() if ln.startswith("{")][-1])
 
 
 def main(argv=None):
@@ -144,8 +162,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.bench_json:
-        with open(args.bench_json) as fh:
-            line = json.loads([ln for ln in fh if ln.startswith("{")][-1])
+        line = load_bench_record(args.bench_json)
         rf = line["roofline"]
         m = re.match(r"code_scan<B=(\d+),([a-z_]+)/([a-z]+)/nozm>", rf["kernel"])
         run = {"n": line["config"]["values_per_step"] // 32,
@@ -263,13 +280,15 @@ def main(argv=None):
     with open(args.out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     if args.select_out and args.bench_json:
-        with open(args.bench_json) as fh:
-            bl = json.loads([ln for ln in fh if ln.startswith("{")][-1])
+        bl = load_bench_record(args.bench_json)
         cmd = args.command.replace(" --out profiles/scan_sweep_2p28_timed_region.md",
                                    " --select-out %s --out profiles/scan_sweep_2p28_timed_region.md" % args.select_out)
         with open(args.select_out, "w") as fh:
             fh.write("\n".join(select_section(args.trace, bl, cmd)) + "\n")
     if args.traffic_json and traffic:
+        for k, ts in trace.items():
+            if k in traffic and ts:
+                traffic[k]["trace_avg_us"] = round(sum(ts) / len(ts) / 1e3, 2)
         with open(args.traffic_json, "w") as fh:
             json.dump({"kernel_source": kernel_source_hash(), "kernels": traffic}, fh, indent=1)
     print("\n".join(lines))

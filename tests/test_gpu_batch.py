@@ -24,10 +24,10 @@ from paper_2606_22423_amd._lib import DEC_RM_DIRECT, DEC_RM_LDS, ENC_DELTA, ENC_
 
 K = 8  # selector classes
 
-# Batches run as one fixed sequence of launches on the context stream; the
-# class kernels walk their window lists on a static schedule (no shared work
-# counter, no captured graph), every loop bounded by counts fixed before the
-# launch.
+# A prepared batch is one captured HIP graph (or, with graphs off, the same
+# kernels launched one by one); the class kernels walk their window lists on a
+# static schedule (no shared work counter), every loop bounded by counts fixed
+# before the launch.
 
 
 def say(*a):
@@ -161,6 +161,58 @@ def test_batch_replays_repeat(ctx, cases):
         ctx.batch_release(h)
     for (c, lo, hi, strat, zm), got in zip(meta, first):
         check_item(c, got, lo, hi, (c.spec.index, strat))
+
+
+@pytest.mark.parametrize("with_selector", [False, True])
+def test_batch_graph_replays_equal_direct_launches(ctx, cases, with_selector):
+    """The captured graph (features, network, selection, binning and the class
+    scans forked over branches) gives, replay after replay with eager work in
+    between, exactly the results of the same batch launched kernel by kernel,
+    and every result equals the oracle's."""
+    import os
+    items, meta = build_items(cases[:60])
+    if with_selector:
+        ctx.selector_load(os.path.join(os.path.dirname(api.__file__), "selector_mi355x.txt"))
+    try:
+        ctx.batch_set_graph(False)
+        hd = ctx.batch_prepare(items)
+        ctx.batch_set_graph(True)
+        hg = ctx.batch_prepare(items)
+        try:
+            info_d, info_g = ctx.batch_info(hd), ctx.batch_info(hg)
+            say("direct", info_d, "graph", info_g)
+            assert not info_d["captured"] and info_g["captured"]
+            assert info_g["kernels"] == info_d["kernels"] and info_g["class_mask"] == info_d["class_mask"]
+            direct = ctx.batch_replay(hd, len(items))
+            x = torch.ones(1 << 20, device="cuda")
+            for rep in range(4):
+                got = ctx.batch_replay(hg, len(items))
+                assert got == direct, rep
+                x.mul_(1.5)            # eager work between replays on the same stream
+                ctx.batch_replay(hd, wait=False)
+                torch.cuda.synchronize()
+        finally:
+            ctx.batch_release(hd)
+            ctx.batch_release(hg)
+    finally:
+        ctx.batch_set_graph(True)
+        if with_selector:
+            ctx.selector_clear()
+    for (c, lo, hi, strat, zm), g in zip(meta, direct):
+        check_item(c, g, lo, hi, (c.spec.index, strat, with_selector))
+
+
+def test_batch_info_and_graph_flag_errors(ctx, cases):
+    with pytest.raises(_lib.ScanError):
+        ctx.batch_info(987654321)
+    assert ctx.lib.scan_batch_set_graph(ctx.h, 2) == _lib.SCAN_EINVAL
+    h = ctx.batch_prepare([])
+    try:
+        info = ctx.batch_info(h)
+        assert info["work_items"] == 0 and info["class_mask"] == 0
+        assert ctx.batch_replay(h, 0) == []
+    finally:
+        ctx.batch_release(h)
 
 
 def test_batch_window_and_occupancy_do_not_change_results(ctx, cases):

@@ -289,6 +289,38 @@ def test_launch_tuning_does_not_change_results(ctx):
             ctx.set_tune(ENC_FOR, b, s, 0, 0, 0)
 
 
+def test_tune_file_round_trip_and_errors(ctx, tmp_path):
+    """scan_tune_save / scan_tune_load: a saved file restores every entry; a
+    file without entries or with a malformed or invalid entry is refused
+    (SCAN_EINVAL) and installs nothing."""
+    s = strategy(DEC_RM_DIRECT, 0, 0)
+    ctx.set_tune(ENC_FOR, 7, s, 128, 2, 8)
+    good = str(tmp_path / "good.json")
+    ctx.tune_save(good)
+    ctx.set_tune(ENC_FOR, 7, s, 0, 0, 0)
+    ctx.tune_load(good)
+    assert ctx.get_tune(ENC_FOR, 7, s) == (128, 2, 8)
+    ctx.set_tune(ENC_FOR, 7, s, 0, 0, 0)
+    before = ctx.get_tune(ENC_FOR, 7, s)
+    cases = {
+        "empty.json": '{"format": "scan-autotune-1", "entries": [\n]}\n',
+        "garbled.json": '{"format": "scan-autotune-1", "entries": [\n'
+                        '  {"enc": 0, "b": 7, "strategy": 1, "wg_size": 128, "wgs_per_cu": 2, "window_blocks": 8},\n'
+                        '  {"enc": 0, "b": 9, "strategy": oops}\n]}\n',
+        "invalid.json": '{"format": "scan-autotune-1", "entries": [\n'
+                        '  {"enc": 0, "b": 7, "strategy": 1, "wg_size": 100, "wgs_per_cu": 2, "window_blocks": 8}\n]}\n',
+    }
+    for name, text in cases.items():
+        path = tmp_path / name
+        path.write_text(text)
+        with pytest.raises(_lib.ScanError) as ei:
+            ctx.tune_load(str(path))
+        assert ei.value.status == _lib.SCAN_EINVAL, name
+        assert ctx.get_tune(ENC_FOR, 7, s) == before, name
+    with pytest.raises(_lib.ScanError):
+        ctx.tune_load(str(tmp_path / "missing.json"))
+
+
 def check_am(got, want, what):
     assert (got["count"], got["sum"], got["blocks_read"], got["blocks_total"]) == \
         (want.count, want.sum, want.blocks_read, want.blocks_total), (what, got, want)

@@ -338,3 +338,35 @@ def test_select_is_the_plain_position_list(rng, b):
     want = np.nonzero((dct[codes] >= lo) & (dct[codes] < hi))[0].astype(np.uint32)
     assert np.array_equal(oracle.select(2, w, 3000, b, lo, hi, dct=dct), want)
     assert np.array_equal(oracle.gather(2, w, b, want, dct=dct), dct[codes[want]])
+
+
+@pytest.mark.parametrize("n", [1, 1023, 1024, 1025, 5 * 1024 + 77])
+def test_zonemaps_are_per_block_min_max_of_valid_values(rng, n):
+    """The oracle's zone maps (the paper's per-block min/max, "Method") against
+    numpy's reductions over each 1024-value block, the last block holding only
+    its n - 1024 k valid values: a partial block must not count its padding
+    (a padded zero would lower the minimum, a padded extreme raise the
+    maximum)."""
+    L = 1024
+    nb = (n + L - 1) // L
+    # u32: values kept away from 0 so a counted padding slot would show
+    v = rng.integers(1 << 20, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+    mn, mx = oracle.zonemap_u32(v)
+    assert mn.shape == (nb,) and mx.shape == (nb,)
+    for k in range(nb):
+        blk = v[k * L: min(n, (k + 1) * L)]
+        assert int(mn[k]) == int(blk.min()) and int(mx[k]) == int(blk.max()), (n, k)
+    # int64, including both extremes of the type
+    w = rng.integers(-(1 << 62), 1 << 62, size=n, dtype=np.int64)
+    w[0] = np.iinfo(np.int64).min
+    w[-1] = np.iinfo(np.int64).max
+    if n > 2:
+        w[n // 2] = -1
+    mn, mx = oracle.zonemap_i64(w)
+    for k in range(nb):
+        blk = w[k * L: min(n, (k + 1) * L)]
+        assert int(mn[k]) == int(blk.min()) and int(mx[k]) == int(blk.max()), (n, k)
+    # an all-negative partial last block: padding read as 0 would become the maximum
+    z = -rng.integers(1, 1 << 40, size=n, dtype=np.int64)
+    mn, mx = oracle.zonemap_i64(z)
+    assert int(mx[-1]) == int(z[(nb - 1) * L:].max()) < 0
