@@ -175,16 +175,19 @@ def batch_leg(ctx, torch, ncols, reps, selector_path):
             ctx.batch_release(h)
         return float(np.median(ts)), got
 
-    t_bd, _ = batched([c.item(lo, hi, default) for c, lo, hi in cols], "batched default")
-    res["batched_default_ms"] = round(t_bd * 1e3, 3)
+    # the default strategy as one replay: direct launches (0), one graph (1),
+    # one graph with the class scans forked over branches (2, the library default)
+    by_mode = {}
+    for mode in (0, 1, 2):
+        ctx.batch_set_graph(mode)
+        t_m, _ = batched([c.item(lo, hi, default) for c, lo, hi in cols], "batched default (mode %d)" % mode)
+        by_mode[mode] = t_m
+    ctx.batch_set_graph(2)
+    res["batched_default_ms"] = round(by_mode[2] * 1e3, 3)
+    res["batched_default_ms_direct_graph_forked"] = [round(by_mode[m] * 1e3, 3) for m in (0, 1, 2)]
     if selector_path and os.path.exists(selector_path):
         ctx.selector_load(selector_path)
         learned = [ctx.run(c, lo, hi, -1)["strategy_used"] for c, lo, hi in cols]
-        items = [c.item(lo, hi, -1) for c, lo, hi in cols]
-        X = torch.zeros(ncols, 6, dtype=torch.float32, device="cuda")
-        theta = torch.from_numpy(np.loadtxt(selector_path, skiprows=1, dtype=np.float32)).cuda()
-        scores = torch.zeros(ncols, 8, dtype=torch.float32, device="cuda")
-        t_sel = timed(lambda: (ctx.features(items, X), ctx.mlp_forward(theta, X, scores)))
         ctx.selector_clear()
         launch_all(learned)
         t_learn = [timed(lambda: launch_all(learned)) for _ in range(reps)]
@@ -196,11 +199,15 @@ def batch_leg(ctx, torch, ncols, reps, selector_path):
         ctx.selector_clear()
         if [g["strategy_used"] for g in got] != learned:
             raise RuntimeError("batched selection differs from scan_run's")
+        # the same choices as explicit strategies: the replay without the
+        # selection kernels (features, network, argmin)
+        t_be, _ = batched([c.item(lo, hi, s) for (c, lo, hi), s in zip(cols, learned)], "batched learned explicit")
         res.update({"learned_async_ms": round(float(np.median(t_learn)) * 1e3, 3),
-                    "selection_ms": round(t_sel * 1e3, 3),
                     "learned_class_counts": counts.tolist(),
                     "speedup_learned_vs_default": round(float(np.median(t_async)) / float(np.median(t_learn)), 3),
                     "batched_learned_ms": round(t_bl * 1e3, 3),
+                    "batched_learned_explicit_ms": round(t_be * 1e3, 3),
+                    "selection_in_replay_ms": round((t_bl - t_be) * 1e3, 3),
                     "speedup_batched_learned_vs_per_column_async": round(float(np.median(t_async)) / t_bl, 2),
                     "speedup_batched_learned_vs_per_column_sync": round(float(np.median(t_sync)) / t_bl, 2)})
     log("[bench] batch: %s" % {k: v for k, v in res.items() if k.endswith("_ms") or k.startswith("speedup")})

@@ -280,9 +280,9 @@ scan_status scan_gather(scan_ctx* ctx, const scan_column* col, int32_t enc, uint
  *
  * scan_batch_prepare validates the items, uploads their descriptors, windows
  * and zone-map segments once, and captures the replay sequence into a HIP
- * graph (the class kernels forked over up to four branches; with graphs
- * turned off by scan_batch_set_graph, or if capture fails, replays enqueue the
- * kernels one by one: same results).  Baked in at that moment: the selector
+ * graph (by default the class kernels forked over up to four branches; see
+ * scan_batch_set_graph; if capture fails, replays enqueue the kernels one by
+ * one: same results).  Baked in at that moment: the selector
  * (its parameters are copied), and the tuning stored for (enc -1, b 0,
  * strategy -1) (work-groups per CU of the class kernels, default 4, at most
  * the number that fit, and the window, default and at most 64 blocks).  An
@@ -302,11 +302,13 @@ scan_status scan_batch_release(scan_ctx* ctx, uint64_t handle);
 scan_status scan_batch_run(scan_ctx* ctx, const scan_item* items, size_t n_items, scan_result* out);
 /* Launch tuning of the batch class kernels (wgs_per_cu, window_blocks). */
 scan_status scan_batch_set_tune(scan_ctx* ctx, const scan_tune* t);
-/* Whether later scan_batch_prepare calls capture a graph (1, the default) or
- * leave replays to direct launches (0).  Other values -> SCAN_EINVAL. */
-scan_status scan_batch_set_graph(scan_ctx* ctx, int32_t enabled);
+/* How later scan_batch_prepare calls build the replay: 0 direct launches,
+ * 1 one graph with the class scans in sequence, 2 (the default) one graph with
+ * the class scans forked over up to four branches.  Results are the same.
+ * Other values -> SCAN_EINVAL. */
+scan_status scan_batch_set_graph(scan_ctx* ctx, int32_t mode);
 typedef struct {
-  int32_t captured;           /* 1: a replay is one graph launch */
+  int32_t captured;           /* 0: direct launches; 1: one graph launch; 2: one graph, forked class scans */
   uint32_t kernels;           /* kernels in one replay */
   uint32_t class_mask;        /* class scans launched (bit enc*4 + decoder*2 + mode) */
   uint32_t work_items;        /* work items of the batch's columns */
@@ -321,7 +323,8 @@ scan_status scan_batch_info(scan_ctx* ctx, uint64_t handle, scan_batch_stats* ou
  * row-major strategies: class c = decoder (c & 1: RM_LDS or RM_DIRECT),
  * predicate mode ((c >> 1) & 1), zone maps ((c >> 2) & 1).  The library picks
  * the class of smallest prediction among those valid for the column (zone-map
- * classes need zone maps; ties to the lowest class).  Parameters: W1[64][6],
+ * classes need zone maps; ties to the lowest class), subject to the fallback
+ * margin below.  Parameters: W1[64][6],
  * b1[64], W2[64][64], b2[64], W3[8][64], b3[8], row-major, in that order. */
 int scan_mlp_param_count(void);
 /* Install parameters (host, scan_mlp_param_count() finite floats). */
@@ -329,9 +332,17 @@ scan_status scan_selector_set(scan_ctx* ctx, const float* theta_host, size_t cou
 /* Back to the heuristic. */
 scan_status scan_selector_clear(scan_ctx* ctx);
 int scan_selector_loaded(const scan_ctx* ctx);
-/* Text file: "scan-mlp-v1 <count>" then the parameters, whitespace separated. */
+/* Text file: "scan-mlp-v1 <count>" then the parameters, whitespace
+ * separated, then optionally "margin <x>" (loading a file without it sets
+ * margin 0).  Anything else -> SCAN_EINVAL. */
 scan_status scan_selector_load(scan_ctx* ctx, const char* path);
 scan_status scan_selector_save(scan_ctx* ctx, const char* path);
+/* Fallback margin of the selector (default 0): for a column the library keeps
+ * the heuristic's strategy unless the network predicts for it a log-time at
+ * least `margin` above the smallest prediction among the column's valid
+ * classes (then the argmin, ties to the lowest class).  Margin 0 is the plain
+ * argmin.  Negative or non-finite -> SCAN_EINVAL. */
+scan_status scan_selector_set_margin(scan_ctx* ctx, float margin);
 /* The selector's input features of n_items columns, written to X_dev (device,
  * n_items x 6 floats, row-major), from zone maps and descriptors only:
  *   b/32, log2(n)/24, log10(max(s, 1e-6))/6 (s: selectivity estimated from the

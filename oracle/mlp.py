@@ -95,6 +95,21 @@ def argmin_strategy(pred, valid=None) -> np.ndarray:
     return np.argmin(p, axis=1)
 
 
+def choose_with_margin(pred, valid, heuristic, margin: float) -> np.ndarray:
+    """The selector's choice per row with a fallback margin: the heuristic's
+    class h unless pred[h] exceeds the smallest valid prediction by at least
+    `margin` (then the argmin over the valid classes, ties to the lowest
+    index).  margin = 0 is the plain argmin."""
+    p = np.array(pred, dtype=np.float64, copy=True)
+    valid = np.asarray(valid, dtype=bool)
+    h = np.asarray(heuristic, dtype=np.int64)
+    best = argmin_strategy(p, valid)
+    rows = np.arange(p.shape[0])
+    pm = np.where(valid, p, np.inf)
+    keep = valid[rows, h] & (p[rows, h] - pm[rows, best] < margin)
+    return np.where(keep, h, best)
+
+
 # ------------------------------------------------------------- features
 def features(b: int, n: int, enc: int, zmin, zmax, lo, hi, counts=None) -> np.ndarray:
     """Selector features of one column, from its zone maps only.

@@ -145,6 +145,7 @@ SIGNATURES = {
     "scan_selector_loaded": (ctypes.c_int, [_vp]),
     "scan_selector_load": (_i32, [_vp, ctypes.c_char_p]),
     "scan_selector_save": (_i32, [_vp, ctypes.c_char_p]),
+    "scan_selector_set_margin": (_i32, [_vp, _f32]),
     "scan_features": (_i32, [_vp, _P(ScanItem), ctypes.c_size_t, _vp]),
     "scan_mlp_forward": (_i32, [_vp, _vp, _vp, _u32, _vp]),
     "scan_mlp_loss_grad": (_i32, [_vp, _vp, _vp, _vp, _vp, _u32, _f32, _vp, _vp]),

@@ -394,14 +394,15 @@ class Context:
         self.check(self.lib.scan_batch_run(self.h, arr, len(items), out), "scan_batch_run")
         return [out[i].as_dict() for i in range(len(items))]
 
-    def batch_set_graph(self, enabled: bool):
-        """Capture later prepared batches into HIP graphs (default) or replay them launch by launch."""
-        self.check(self.lib.scan_batch_set_graph(self.h, 1 if enabled else 0), "scan_batch_set_graph")
+    def batch_set_graph(self, mode: int):
+        """Replay form of later prepared batches: 0 direct launches, 1 one graph,
+        2 one graph with the class scans forked over branches (the default)."""
+        self.check(self.lib.scan_batch_set_graph(self.h, int(mode)), "scan_batch_set_graph")
 
     def batch_info(self, handle: int) -> dict:
         s = _lib.ScanBatchStats()
         self.check(self.lib.scan_batch_info(self.h, handle, ctypes.byref(s)), "scan_batch_info")
-        return {"captured": bool(s.captured), "kernels": int(s.kernels), "class_mask": int(s.class_mask),
+        return {"captured": int(s.captured), "kernels": int(s.kernels), "class_mask": int(s.class_mask),
                 "work_items": int(s.work_items)}
 
     def batch_set_tune(self, wgs_per_cu=0, window_blocks=0):
@@ -417,6 +418,10 @@ class Context:
         """Install network parameters (any array-like of param_count floats)."""
         a = np.ascontiguousarray(np.asarray(theta, dtype=np.float32).ravel())
         self.check(self.lib.scan_selector_set(self.h, a.ctypes.data, a.size), "scan_selector_set")
+
+    def selector_set_margin(self, margin: float):
+        """Keep the heuristic unless the network predicts a log-time gain of at least `margin`."""
+        self.check(self.lib.scan_selector_set_margin(self.h, float(margin)), "scan_selector_set_margin")
 
     def selector_clear(self):
         self.check(self.lib.scan_selector_clear(self.h), "scan_selector_clear")

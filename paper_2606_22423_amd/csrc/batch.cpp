@@ -27,8 +27,8 @@ namespace scan_dev {
 hipError_t launch_batch_setup(const BatchArgs& a, hipStream_t st);
 hipError_t launch_batch_features(const BatchCol* cols, uint32_t n_cols, const BatchWork* segs, uint32_t n_segs,
                                  FeatPart* parts, float* X, hipStream_t st);
-hipError_t launch_batch_select(BatchCol* cols, uint32_t n_cols, const float* scores, int32_t k, BatchOut* out,
-                               hipStream_t st);
+hipError_t launch_batch_select(BatchCol* cols, uint32_t n_cols, const float* scores, int32_t k, float margin,
+                               BatchOut* out, hipStream_t st);
 hipError_t launch_batch_bin(const BatchArgs& a, hipStream_t st);
 hipError_t launch_mlp_forward(const float* theta, const float* X, uint32_t rows, float* out, hipStream_t st);
 }  // namespace scan_dev
@@ -177,7 +177,7 @@ void plan_cols(scan_ctx* ctx, const scan_item* items, size_t n, uint32_t window,
 
 // Setup, then (with selector parameters) features and network scores, then
 // selection: enqueued on `st`.
-hipError_t enqueue_select(const BatchBuffers& m, uint32_t n_cols, const float* theta, hipStream_t st) {
+hipError_t enqueue_select(const BatchBuffers& m, uint32_t n_cols, const float* theta, float margin, hipStream_t st) {
   hipError_t e = launch_batch_setup(make_args(m, n_cols, 0, 0), st);
   if (e != hipSuccess || n_cols == 0) return e;
   if (theta) {
@@ -186,7 +186,7 @@ hipError_t enqueue_select(const BatchBuffers& m, uint32_t n_cols, const float* t
     e = launch_mlp_forward(theta, m.feats, n_cols, m.scores, st);
     if (e != hipSuccess) return e;
   }
-  return launch_batch_select(m.cols, n_cols, theta ? m.scores : nullptr, 8, m.out, st);
+  return launch_batch_select(m.cols, n_cols, theta ? m.scores : nullptr, 8, margin, m.out, st);
 }
 
 // Class scans that can occur: an explicit strategy fixes its column's class,
@@ -217,6 +217,8 @@ struct BatchPlan {
   uint32_t cls_mask = 0;                  // class scans a replay launches
   uint32_t kernels = 0;                   // kernels per replay
   hipGraphExec_t exec = nullptr;          // the captured replay (null: direct launches)
+  bool forked = false;                    // class scans on parallel graph branches
+  float margin = 0.0f;                    // the selector's margin when prepared
 };
 
 static void free_plan(BatchPlan* b) {
@@ -252,7 +254,7 @@ void destroy_batches(scan_ctx* ctx) {
 // joined back (ev[1..nbr]): class scans touch disjoint columns, so they may
 // run concurrently.
 static hipError_t enqueue_batch(BatchPlan* b, hipStream_t st, const hipStream_t* br, int nbr, const hipEvent_t* ev) {
-  hipError_t e = enqueue_select(b->mem, (uint32_t)b->n_items, b->selector ? b->mem.theta : nullptr, st);
+  hipError_t e = enqueue_select(b->mem, (uint32_t)b->n_items, b->selector ? b->mem.theta : nullptr, b->margin, st);
   if (e != hipSuccess || b->n_work == 0 || b->cls_mask == 0) return e;
   e = launch_batch_bin(make_args(b->mem, (uint32_t)b->n_items, b->n_work, 0), st);
   if (e != hipSuccess) return e;
@@ -278,9 +280,9 @@ static hipError_t enqueue_batch(BatchPlan* b, hipStream_t st, const hipStream_t*
 
 // Capture the replay sequence into b->exec.  Any failure leaves b->exec null
 // (replays then enqueue the launches directly) and clears the error state.
-static void capture_batch(scan_ctx* ctx, BatchPlan* b) {
+static void capture_batch(scan_ctx* ctx, BatchPlan* b, bool forked) {
   const int ncls = __builtin_popcount(b->cls_mask);
-  const int nbr = std::min(kMaxBranches, ncls);
+  const int nbr = forked ? std::min(kMaxBranches, ncls) : 0;
   hipStream_t cs = nullptr;
   hipStream_t br[kMaxBranches] = {};
   hipEvent_t ev[kMaxBranches + 1] = {};
@@ -310,6 +312,7 @@ static void capture_batch(scan_ctx* ctx, BatchPlan* b) {
   (void)hipGetLastError();
   (void)ctx;
   b->exec = ok ? x : nullptr;
+  b->forked = ok && nbr > 0;
 }
 
 static void fill_results(const BatchPlan* b, scan_result* out) {
@@ -378,7 +381,7 @@ scan_status selector_pick(scan_ctx* ctx, const scan_column* col, int32_t enc, ui
   if (e == hipSuccess) {
     BatchBuffers m = sc->mem;
     m.n_segs = (uint32_t)segs.size();
-    e = enqueue_select(m, 1, selector_theta(ctx), ctx->stream);
+    e = enqueue_select(m, 1, selector_theta(ctx), ctx->selector_margin, ctx->stream);
   }
   if (e == hipSuccess)
     e = hipMemcpyAsync(sc->mem.out_host, sc->mem.out, sizeof(BatchOut), hipMemcpyDeviceToHost, ctx->stream);
@@ -403,6 +406,7 @@ scan_status scan_batch_prepare(scan_ctx* ctx, const scan_item* items, size_t n_i
   BatchPlan* b = new BatchPlan();
   b->n_items = n_items;
   b->selector = ctx->selector_ready;
+  b->margin = ctx->selector_margin;
   b->grid = (uint32_t)ctx->cus * (uint32_t)std::clamp(t.wgs_per_cu, 1, 16);
   // dictionary classes hold the dictionary in LDS: fewer of their work-groups
   // fit on a compute unit, and their static shares are sized by the grid
@@ -444,7 +448,7 @@ scan_status scan_batch_prepare(scan_ctx* ctx, const scan_item* items, size_t n_i
   b->kernels = n_items == 0 ? 1u
                             : 2u + (b->selector ? 2u + (b->mem.n_segs ? 1u : 0u) : 0u) +
                                   (b->n_work && b->cls_mask ? 1u + (uint32_t)__builtin_popcount(b->cls_mask) : 0u);
-  if (ctx->batch_graph) capture_batch(ctx, b);
+  if (ctx->batch_graph) capture_batch(ctx, b, ctx->batch_graph == 2);
   const uint64_t h = ctx->next_batch++;
   ctx->batches[h] = b;
   *handle = h;
@@ -498,10 +502,10 @@ scan_status scan_batch_set_tune(scan_ctx* ctx, const scan_tune* t) {
   return SCAN_OK;
 }
 
-scan_status scan_batch_set_graph(scan_ctx* ctx, int32_t enabled) {
+scan_status scan_batch_set_graph(scan_ctx* ctx, int32_t mode) {
   if (!ctx) return SCAN_EINVAL;
-  if (enabled != 0 && enabled != 1) return fail(ctx, SCAN_EINVAL, "enabled must be 0 or 1");
-  ctx->batch_graph = enabled == 1;
+  if (mode < 0 || mode > 2) return fail(ctx, SCAN_EINVAL, "graph mode must be 0, 1 or 2");
+  ctx->batch_graph = mode;
   return SCAN_OK;
 }
 
@@ -511,7 +515,7 @@ scan_status scan_batch_info(scan_ctx* ctx, uint64_t handle, scan_batch_stats* ou
   auto it = ctx->batches.find(handle);
   if (it == ctx->batches.end()) return fail(ctx, SCAN_EINVAL, "unknown batch handle %llu", (unsigned long long)handle);
   const BatchPlan* b = it->second;
-  out->captured = b->exec ? 1 : 0;
+  out->captured = b->exec ? (b->forked ? 2 : 1) : 0;
   out->kernels = b->kernels;
   out->class_mask = b->cls_mask;
   out->work_items = b->n_work;

@@ -179,12 +179,15 @@ __global__ __launch_bounds__(256) void batch_feat_col_kernel(const BatchCol* col
   }
 }
 
-// Strategy per column: the requested one, else the argmin over the selector's
-// allowed classes (ties to the lowest class; class c = decoder c&1, SV (c>>1)&1,
-// zone maps (c>>2)&1), else the heuristic when no selector scores are given.
+// Strategy per column: the requested one, else the selector's choice, else
+// the heuristic when no selector scores are given.  The selector's choice is
+// the argmin over the column's allowed classes (ties to the lowest class;
+// class c = decoder c&1, SV (c>>1)&1, zone maps (c>>2)&1), except that the
+// heuristic's class is kept unless its predicted log-time exceeds the
+// argmin's by at least `margin` (margin 0: the plain argmin).
 // The choice is also recorded in the column's result slot.
 __global__ __launch_bounds__(256) void batch_select_kernel(BatchCol* cols, uint32_t n_cols, const float* scores,
-                                                           int32_t k, BatchOut* out) {
+                                                           int32_t k, float margin, BatchOut* out) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_cols) return;
   BatchCol& c = cols[i];
@@ -202,7 +205,9 @@ __global__ __launch_bounds__(256) void batch_select_kernel(BatchCol* cols, uint3
           bc = q;
         }
       }
-      if (bc >= 0) s = (bc & 1) | (((bc >> 1) & 1) << 2) | (((bc >> 2) & 1) << 3);
+      const int hc = (s & 1) | (((s >> 2) & 1) << 1) | (((s >> 3) & 1) << 2);
+      const bool keep = ((c.valid_mask >> hc) & 1u) && scores[(size_t)i * k + hc] - best < margin;
+      if (bc >= 0 && !keep) s = (bc & 1) | (((bc >> 1) & 1) << 2) | (((bc >> 2) & 1) << 3);
     }
   }
   c.strategy = s;
@@ -252,9 +257,10 @@ hipError_t launch_batch_features(const BatchCol* cols, uint32_t n_cols, const Ba
   return hipGetLastError();
 }
 
-hipError_t launch_batch_select(BatchCol* cols, uint32_t n_cols, const float* scores, int32_t k, BatchOut* out,
-                               hipStream_t st) {
-  hipLaunchKernelGGL(batch_select_kernel, dim3((n_cols + 255) / 256), dim3(256), 0, st, cols, n_cols, scores, k, out);
+hipError_t launch_batch_select(BatchCol* cols, uint32_t n_cols, const float* scores, int32_t k, float margin,
+                               BatchOut* out, hipStream_t st) {
+  hipLaunchKernelGGL(batch_select_kernel, dim3((n_cols + 255) / 256), dim3(256), 0, st, cols, n_cols, scores, k,
+                     margin, out);
   return hipGetLastError();
 }
 

@@ -30,11 +30,12 @@ struct scan_ctx {
   std::map<std::tuple<int32_t, uint32_t, int32_t>, scan_tune> tunes;
   std::map<std::pair<const void*, uint32_t>, int> occupancy;
   bool selector_ready = false;
+  float selector_margin = 0.0f;       // keep the heuristic unless the network predicts a gain above this (log time)
   SelectorState* selector = nullptr;
   std::map<uint64_t, BatchPlan*> batches;
   SelectWork* select = nullptr;       // materializing select work space
   uint64_t next_batch = 1;
-  bool batch_graph = true;            // capture prepared batches into HIP graphs
+  int batch_graph = 2;                // prepared batches: 0 direct launches, 1 graph, 2 graph with forked class scans
 };
 
 scan_status fail(scan_ctx* ctx, scan_status st, const char* fmt, ...);

@@ -89,10 +89,29 @@ scan_status scan_selector_load(scan_ctx* ctx, const char* path) {
     theta.resize(count);
     for (unsigned i = 0; i < count && ok; ++i) ok = std::fscanf(f, "%f", &theta[i]) == 1;
   }
+  // optional last line: "margin <x>" (files without it select by plain argmin)
+  float margin = 0.0f;
+  if (ok) {
+    char key[16] = {0};
+    float x = 0.0f;
+    const int got = std::fscanf(f, "%15s %f", key, &x);
+    if (got == 2 && std::strcmp(key, "margin") == 0) margin = x;
+    else if (got != EOF) ok = false;
+  }
   std::fclose(f);
-  if (!ok) return fail(ctx, SCAN_EINVAL, "%s is not a selector file ('%s %u' then %u numbers)", path, kMagic,
-                       kParamCount, kParamCount);
-  return scan_selector_set(ctx, theta.data(), theta.size());
+  if (!ok) return fail(ctx, SCAN_EINVAL, "%s is not a selector file ('%s %u', %u numbers, optionally 'margin x')",
+                       path, kMagic, kParamCount, kParamCount);
+  if (!(margin >= 0.0f && margin < 1e30f)) return fail(ctx, SCAN_EINVAL, "%s: margin must be >= 0", path);
+  const scan_status st = scan_selector_set(ctx, theta.data(), theta.size());
+  if (st == SCAN_OK) ctx->selector_margin = margin;
+  return st;
+}
+
+scan_status scan_selector_set_margin(scan_ctx* ctx, float margin) {
+  if (!ctx) return SCAN_EINVAL;
+  if (!(margin >= 0.0f && margin < 1e30f)) return fail(ctx, SCAN_EINVAL, "margin must be finite and >= 0");
+  ctx->selector_margin = margin;
+  return SCAN_OK;
 }
 
 scan_status scan_selector_save(scan_ctx* ctx, const char* path) {
@@ -106,6 +125,7 @@ scan_status scan_selector_save(scan_ctx* ctx, const char* path) {
   if (!f) return fail(ctx, SCAN_EINVAL, "cannot write %s: %s", path, std::strerror(errno));
   std::fprintf(f, "%s %u\n", kMagic, kParamCount);
   for (float x : theta) std::fprintf(f, "%.9g\n", (double)x);
+  std::fprintf(f, "margin %.9g\n", (double)ctx->selector_margin);
   const bool ok = std::fclose(f) == 0;
   return ok ? SCAN_OK : fail(ctx, SCAN_EINVAL, "write failed: %s", path);
 }

@@ -4,13 +4,17 @@
    (lengths 2^10..2^24, widths 1..24, frame-of-reference / delta /
    dictionary, log-uniform selectivity, zone maps on every column), from a
    seed of its own so that they never coincide with evaluation columns.
-2. Times each of the eight row-major strategies on each column: one scan
-   launch between two HIP events on the context stream, after a cache-evicting
-   read of a 512 MiB scratch buffer (the shipped parameters were trained when
-   the eviction overwrote it), median of `reps`.
+2. Times each of the eight row-major strategies on each column where the
+   selector is used, inside a batch (BatchTimer: the column's share of a
+   device-filling replay), or as single cold launches (Timer).
 3. Computes each column's selector features on the device (zone maps only).
 4. Fits the 6 -> 64 -> 64 -> 8 network to log-time per strategy (masked mean
-   squared error, Adam, mini-batches) with the library's device kernels.
+   squared error, Adam, mini-batches) with the library's device kernels, and
+   picks the fallback margin (keep the heuristic unless the predicted gain is
+   larger) of least total time on the training columns.
+5. Times the held-out columns (the 4096-column mixed workload itself) the
+   same way and reports the regret of the learned choice, of the heuristic
+   and of the best fixed strategy against the per-column best.
 
 Everything numeric runs in libscan; this module only orchestrates.
 """
@@ -117,15 +121,74 @@ class Timer:
         return times
 
 
-def collect(ctx: api.Context, n_cols: int = 2560, reps: int = 5, seed: int = TRAIN_SEED, log=print,
-            log2_max: float = 24.0, threads: int = 8):
-    """Time all eight strategies on n_cols fresh columns.
+class BatchTimer:
+    """Cost of one column under each strategy inside a batch, where the
+    selector works: K items of the column (the same device buffers) in one
+    prepared batch with that strategy, replayed between two HIP events after
+    a cache-evicting read, median of `reps`; minus the replay cost of a batch
+    of one single-block column with the same strategy (the launches), divided
+    by K.  K = clamp(ceil(2^30 / n), 1, 4096) fills the device with work
+    items the way a large batch does, so the figure is the column's share of
+    a saturated replay rather than its latency alone."""
 
-    Returns (X [n, 6] float32 features, T [n, 8] float64 median seconds)."""
+    FILL_VALUES = 1 << 30
+    MAX_COPIES = 4096
+
+    def __init__(self, ctx: api.Context, evict_bytes: int = 512 << 20):
+        import torch
+        self.torch = torch
+        self.ctx = ctx
+        self.evict = torch.empty(evict_bytes // 4, dtype=torch.int32, device="cuda")
+        self.evict_bytes = evict_bytes
+        self.base = {}
+
+    def _replay_time(self, items, reps):
+        torch = self.torch
+        h = self.ctx.batch_prepare(items)
+        try:
+            self.ctx.batch_replay(h, wait=False)  # first replay: code objects, graph upload
+            ev = []
+            for _ in range(reps):
+                self.ctx.cache_flush(self.evict, self.evict_bytes)
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(self.ctx.stream)
+                self.ctx.batch_replay(h, wait=False)
+                b.record(self.ctx.stream)
+                ev.append((a, b))
+            self.ctx.sync()
+            return float(np.median([a.elapsed_time(b) * 1e-3 for a, b in ev]))
+        finally:
+            self.ctx.batch_release(h)
+
+    def _base(self, col, lo, hi, s, reps):
+        key = (col.enc, s)
+        if key not in self.base:
+            one = api.Column(col.enc, col.b, min(col.n, 1024), col.layout, col.payload, refs=col.refs,
+                             bases=col.bases, dct=col.dct, zmin=col.zmin, zmax=col.zmax)
+            self.base[key] = self._replay_time([one.item(lo, hi, s)], reps)
+        return self.base[key]
+
+    def time_strategies(self, col, lo, hi, strategies, reps: int):
+        """{s: seconds per column} for every strategy s."""
+        k = int(min(self.MAX_COPIES, max(1, -(-self.FILL_VALUES // max(1, col.n)))))
+        out = {}
+        for s in strategies:
+            t = self._replay_time([col.item(lo, hi, s)] * k, reps)
+            out[s] = max(t - self._base(col, lo, hi, s, reps), 1e-9) / k
+        return out
+
+
+def collect(ctx: api.Context, n_cols: int = 2560, reps: int = 5, seed: int = TRAIN_SEED, log=print,
+            log2_max: float = 24.0, threads: int = 8, context: str = "batch"):
+    """Time all eight strategies on n_cols fresh columns, in a batch
+    (context "batch", BatchTimer) or as single cold launches ("single", Timer).
+
+    Returns (X [n, 6] float32 features, T [n, 8] float64 seconds)."""
     import torch
     from concurrent.futures import ThreadPoolExecutor
     specs = synth.config4_specs(n_cols, seed=seed, log2_max=log2_max)
-    timer = Timer(ctx)
+    timer = BatchTimer(ctx) if context == "batch" else Timer(ctx)
     X = torch.zeros(n_cols, 6, dtype=torch.float32, device="cuda")
     T = np.zeros((n_cols, K))
     t0 = time.time()
@@ -142,7 +205,7 @@ def collect(ctx: api.Context, n_cols: int = 2560, reps: int = 5, seed: int = TRA
             times = timer.time_strategies(col, lo, hi, STRATEGIES, reps)
             T[i] = [float(np.median(times[s])) for s in STRATEGIES]
             del col
-            if log and (i + 1) % 512 == 0:
+            if log and (i + 1) % 128 == 0:
                 log("selector timings: %d/%d columns, %.0f s" % (i + 1, n_cols, time.time() - t0))
     return X.cpu().numpy(), T
 
@@ -216,22 +279,64 @@ def regret(T: np.ndarray, choice: np.ndarray) -> dict:
     return {"total": float(chosen.sum() / best.sum() - 1.0), "mean": float(np.mean(chosen / best - 1.0))}
 
 
-def evaluate(ctx: api.Context, theta: np.ndarray, X: np.ndarray, T: np.ndarray) -> dict:
+HEURISTIC_CLASS = 5  # row-major direct decoder, branch-free, zone maps (every workload column has them)
+
+
+def choose(pred: np.ndarray, margin: float) -> np.ndarray:
+    """The library's rule on host predictions: the heuristic's class unless its
+    predicted log-time exceeds the argmin's by at least `margin` (every class
+    is valid for a column with zone maps; ties to the lowest class)."""
+    best = np.argmin(pred, axis=1)
+    rows = np.arange(pred.shape[0])
+    keep = pred[rows, HEURISTIC_CLASS] - pred[rows, best] < margin
+    return np.where(keep, HEURISTIC_CLASS, best)
+
+
+def pick_margin(pred: np.ndarray, T: np.ndarray, grid=(0.0, 0.02, 0.05, 0.1, 0.15, 0.2, 0.3, 0.5)) -> float:
+    """The margin of smallest total time on the training columns (the
+    smallest such margin on ties)."""
+    rows = np.arange(len(T))
+    tot = [(float(T[rows, choose(pred, m)].sum()), m) for m in grid]
+    return min(tot)[1]
+
+
+def evaluate(ctx: api.Context, theta: np.ndarray, X: np.ndarray, T: np.ndarray, margin: float = 0.0) -> dict:
     """Regret of the learned choice and of the fixed alternatives on timed columns."""
     pred = predict(ctx, theta, X)
-    learned = np.argmin(pred, axis=1)  # ties to the lowest class, as on the device
-    default = np.full(len(T), 5)       # row-major direct decoder, branch-free, zone maps on
+    rows = np.arange(len(T))
+    learned = choose(pred, margin)
+    argmin = np.argmin(pred, axis=1)   # ties to the lowest class, as on the device
+    default = np.full(len(T), HEURISTIC_CLASS)
     best_fixed = int(np.argmin(T.sum(axis=0)))
     return {
         "columns": int(len(T)),
+        "margin": margin,
         "learned": regret(T, learned),
+        "learned_plain_argmin": regret(T, argmin),
         "fixed_default": regret(T, default),
         "best_fixed_in_hindsight": {"class": best_fixed, **regret(T, np.full(len(T), best_fixed))},
-        "time_s": {"learned": float(T[np.arange(len(T)), learned].sum()), "best": float(T.min(axis=1).sum()),
-                   "fixed_default": float(T[:, 5].sum())},
+        "time_s": {"learned": float(T[rows, learned].sum()), "best": float(T.min(axis=1).sum()),
+                   "fixed_default": float(T[:, HEURISTIC_CLASS].sum())},
+        "gain_over_heuristic": float(T[:, HEURISTIC_CLASS].sum() / T[rows, learned].sum() - 1.0),
         "learned_class_counts": np.bincount(learned, minlength=K).tolist(),
         "best_class_counts": np.bincount(np.argmin(T, axis=1), minlength=K).tolist(),
     }
+
+
+def save_table(path: str, X: np.ndarray, T: np.ndarray, note: str):
+    """Timing table as text: a comment line, then per column the six features
+    and the eight per-strategy times in microseconds."""
+    with open(path, "w") as fh:
+        fh.write("# %s\n" % note)
+        fh.write("# f0 f1 f2 f3 f4 f5 | t_us class 0..7 (class c: decoder c&1, sv (c>>1)&1, zone maps (c>>2)&1)\n")
+        for x, t in zip(X, T):
+            fh.write(" ".join("%.7g" % v for v in x) + " " + " ".join("%.5g" % (v * 1e6) for v in t) + "\n")
+
+
+def load_table(path: str):
+    """(X float32 [n, 6], T float64 seconds [n, 8]) of a save_table file."""
+    a = np.loadtxt(path, comments="#", dtype=np.float64, ndmin=2)
+    return a[:, :6].astype(np.float32), a[:, 6:] * 1e-6
 
 
 def main(argv=None):
@@ -244,24 +349,49 @@ def main(argv=None):
     ap.add_argument("--eval-cols", type=int, default=4096, help="held-out columns (the mixed workload's own)")
     ap.add_argument("--eval-reps", type=int, default=3)
     ap.add_argument("--epochs", type=int, default=400)
-    ap.add_argument("--out", required=True, help="selector file to write")
+    ap.add_argument("--context", choices=("batch", "single"), default="batch",
+                    help="time strategies inside a batch (the selector's use) or as single launches")
+    ap.add_argument("--train-table", default=None, help="training timings: read if it exists, else write")
+    ap.add_argument("--eval-table", default=None, help="held-out timings: read if it exists, else write")
+    ap.add_argument("--no-eval", action="store_true", help="collect training timings only")
+    ap.add_argument("--out", default=None, help="selector file to write")
     ap.add_argument("--report", default=None, help="JSON report")
     args = ap.parse_args(argv)
+    import os
     say = lambda *a: print(*a, flush=True)  # noqa: E731
     ctx = api.Context(0)
     t0 = time.time()
-    X, T = collect(ctx, args.cols, args.reps, log=say)
+    if args.train_table and os.path.exists(args.train_table):
+        X, T = load_table(args.train_table)
+    else:
+        X, T = collect(ctx, args.cols, args.reps, log=say, context=args.context)
+        if args.train_table:
+            save_table(args.train_table, X, T, "selector training timings, %s context, %d columns, seed %d, "
+                       "median of %d" % (args.context, len(T), TRAIN_SEED, args.reps))
     say("training set: %d columns x %d strategies in %.0f s" % (len(T), K, time.time() - t0))
+    if args.no_eval:
+        ctx.close()
+        return
     theta, loss = train(ctx, X, targets(T), epochs=args.epochs, log=say)
+    margin = pick_margin(predict(ctx, theta, X), T)
     ctx.selector_set(theta)
-    ctx.selector_save(args.out)
-    train_eval = evaluate(ctx, theta, X, T)
+    ctx.selector_set_margin(margin)
+    if args.out:
+        ctx.selector_save(args.out)
+    train_eval = evaluate(ctx, theta, X, T, margin)
     t1 = time.time()
-    Xe, Te = collect(ctx, args.eval_cols, args.eval_reps, seed=synth.SEED_BASE + 3, log=say)
+    if args.eval_table and os.path.exists(args.eval_table):
+        Xe, Te = load_table(args.eval_table)
+    else:
+        Xe, Te = collect(ctx, args.eval_cols, args.eval_reps, seed=synth.SEED_BASE + 3, log=say,
+                         context=args.context)
+        if args.eval_table:
+            save_table(args.eval_table, Xe, Te, "selector held-out timings (the 4096-column mixed workload), %s "
+                       "context, seed %d, median of %d" % (args.context, synth.SEED_BASE + 3, args.eval_reps))
     say("held-out set: %d columns in %.0f s" % (len(Te), time.time() - t1))
-    held = evaluate(ctx, theta, Xe, Te)
-    report = {"train_columns": len(T), "timings": int(T.size), "reps": args.reps, "epochs": args.epochs,
-              "final_loss": loss, "train": train_eval, "held_out": held}
+    held = evaluate(ctx, theta, Xe, Te, margin)
+    report = {"context": args.context, "train_columns": len(T), "timings": int(T.size), "reps": args.reps,
+              "epochs": args.epochs, "final_loss": loss, "margin": margin, "train": train_eval, "held_out": held}
     say(json.dumps(report))
     if args.report:
         with open(args.report, "w") as fh:

@@ -174,28 +174,29 @@ def test_batch_graph_replays_equal_direct_launches(ctx, cases, with_selector):
     if with_selector:
         ctx.selector_load(os.path.join(os.path.dirname(api.__file__), "selector_mi355x.txt"))
     try:
-        ctx.batch_set_graph(False)
-        hd = ctx.batch_prepare(items)
-        ctx.batch_set_graph(True)
-        hg = ctx.batch_prepare(items)
+        handles = []
+        for mode in (0, 1, 2):
+            ctx.batch_set_graph(mode)
+            handles.append(ctx.batch_prepare(items))
         try:
-            info_d, info_g = ctx.batch_info(hd), ctx.batch_info(hg)
-            say("direct", info_d, "graph", info_g)
-            assert not info_d["captured"] and info_g["captured"]
-            assert info_g["kernels"] == info_d["kernels"] and info_g["class_mask"] == info_d["class_mask"]
-            direct = ctx.batch_replay(hd, len(items))
+            infos = [ctx.batch_info(h) for h in handles]
+            say("replay forms", infos)
+            assert [i["captured"] for i in infos] == [0, 1, 2]
+            assert len({(i["kernels"], i["class_mask"]) for i in infos}) == 1
+            direct = ctx.batch_replay(handles[0], len(items))
             x = torch.ones(1 << 20, device="cuda")
             for rep in range(4):
-                got = ctx.batch_replay(hg, len(items))
-                assert got == direct, rep
-                x.mul_(1.5)            # eager work between replays on the same stream
-                ctx.batch_replay(hd, wait=False)
+                for h in handles[1:]:
+                    got = ctx.batch_replay(h, len(items))
+                    assert got == direct, (rep, h)
+                    x.mul_(1.5)            # eager work between replays on the same stream
+                ctx.batch_replay(handles[0], wait=False)
                 torch.cuda.synchronize()
         finally:
-            ctx.batch_release(hd)
-            ctx.batch_release(hg)
+            for h in handles:
+                ctx.batch_release(h)
     finally:
-        ctx.batch_set_graph(True)
+        ctx.batch_set_graph(2)
         if with_selector:
             ctx.selector_clear()
     for (c, lo, hi, strat, zm), g in zip(meta, direct):
@@ -205,7 +206,7 @@ def test_batch_graph_replays_equal_direct_launches(ctx, cases, with_selector):
 def test_batch_info_and_graph_flag_errors(ctx, cases):
     with pytest.raises(_lib.ScanError):
         ctx.batch_info(987654321)
-    assert ctx.lib.scan_batch_set_graph(ctx.h, 2) == _lib.SCAN_EINVAL
+    assert ctx.lib.scan_batch_set_graph(ctx.h, 3) == _lib.SCAN_EINVAL
     h = ctx.batch_prepare([])
     try:
         info = ctx.batch_info(h)
@@ -345,8 +346,63 @@ def test_selector_file_round_trip(ctx, cases, tmp_path):
             check_item(c, got, c.lo, c.hi, c.spec.index)
     finally:
         ctx.selector_clear()
-    loaded = np.loadtxt(path, skiprows=1, dtype=np.float64)
+    lines = open(path).read().split("\n")
+    assert lines[0].split()[0] == "scan-mlp-v1"
+    loaded = np.array([float(x) for x in lines[1:1 + len(theta)]])
     assert np.array_equal(loaded.astype(np.float32), theta)
+    assert lines[1 + len(theta)].split() == ["margin", "0"]
+
+
+def test_selector_margin_keeps_the_heuristic_unless_the_gain_is_large(ctx, cases, tmp_path):
+    """With a fallback margin the choice is the heuristic's class unless the
+    network predicts it at least `margin` slower (log time) than its argmin,
+    in the batch and in scan_run alike; the margin survives a file round trip."""
+    theta = random_theta(13)
+    items, meta = [], []
+    for j, c in enumerate(cases):
+        lo, hi = predicates(c, j)
+        zm = j % 7 != 3
+        items.append(c.col.item(lo, hi, -1, zone_maps=zm))
+        meta.append((c, lo, hi, zm))
+    X = torch.zeros(len(items), 6, dtype=torch.float32, device="cuda")
+    margin = 0.25
+    ctx.selector_set(theta)
+    ctx.selector_set_margin(margin)
+    path = str(tmp_path / "sel_margin.txt")
+    try:
+        ctx.features(items, X)
+        single = [ctx.run(c.col, lo, hi, -1, zone_maps=zm) for c, lo, hi, zm in meta]
+        batch = ctx.batch_run(items)
+        ctx.selector_save(path)
+        ctx.selector_clear()
+        ctx.selector_set_margin(0.0)
+        ctx.selector_load(path)
+        again = [ctx.run(c.col, lo, hi, -1, zone_maps=zm)["strategy_used"] for c, lo, hi, zm in meta]
+        assert again == [r["strategy_used"] for r in single]
+    finally:
+        ctx.selector_clear()
+        ctx.selector_set_margin(0.0)
+    pred, _ = omlp.forward(theta.astype(np.float64), X.cpu().numpy().astype(np.float64), K)
+    valid = np.array([[zm or not ((q >> 2) & 1) for q in range(K)] for _, _, _, zm in meta])
+    heur = np.array([5 if zm else 1 for _, _, _, zm in meta])  # RM-direct, branch-free, zone maps when present
+    want = omlp.choose_with_margin(pred, valid, heur, margin)
+    checked = kept = 0
+    for i, ((c, lo, hi, zm), s1, sb) in enumerate(zip(meta, single, batch)):
+        check_item(c, s1, lo, hi, (c.spec.index, "margin"))
+        check_item(c, sb, lo, hi, (c.spec.index, "margin batch"))
+        assert sb["strategy_used"] & ~16 == s1["strategy_used"] & ~16, i
+        p = np.where(valid[i], pred[i], np.inf)
+        order = np.argsort(p, kind="stable")
+        gap = p[heur[i]] - p[order[0]]
+        if p[order[1]] - p[order[0]] < 1e-3 or abs(gap - margin) < 1e-3:
+            continue  # fp32 near a decision boundary
+        assert s1["strategy_used"] & ~16 == class_strategy(int(want[i])), (i, p, gap, s1)
+        checked += 1
+        kept += int(want[i] == heur[i])
+    assert checked > len(meta) // 2, (checked, kept)
+    say("margin %.2f: %d of %d clear choices kept the heuristic" % (margin, kept, checked))
+    with pytest.raises(_lib.ScanError):
+        ctx.selector_set_margin(-1.0)
 
 
 def test_selector_rejects_bad_parameters(ctx, tmp_path):

@@ -100,3 +100,22 @@ def test_features_closed_forms():
     # empty predicate
     f = mlp.features(6, n, 1, zk, zk, 14, 10)
     assert f[3] == 0.0 and np.isclose(f[2], -1.0) and np.isclose(f[5], 0.5)
+
+
+def test_choose_with_margin_limits_and_brute_force():
+    """margin 0 is the plain argmin; an unreachable margin always keeps the
+    heuristic; in between, a brute-force reading of the rule row by row."""
+    rng = np.random.default_rng(7)
+    pred = rng.normal(size=(200, 8))
+    valid = rng.random((200, 8)) < 0.8
+    heur = rng.integers(0, 8, size=200)
+    valid[np.arange(200), heur] = True
+    assert np.array_equal(mlp.choose_with_margin(pred, valid, heur, 0.0), mlp.argmin_strategy(pred, valid))
+    assert np.array_equal(mlp.choose_with_margin(pred, valid, heur, 1e9), heur)
+    for margin in (0.1, 0.5):
+        got = mlp.choose_with_margin(pred, valid, heur, margin)
+        for i in range(200):
+            vals = [(pred[i, j], j) for j in range(8) if valid[i, j]]
+            best_v, best_j = min(vals)
+            want = heur[i] if pred[i, heur[i]] - best_v < margin else best_j
+            assert got[i] == want, (i, margin)
