@@ -185,6 +185,25 @@ scan_status scan_run(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_
 scan_status scan_run_async(scan_ctx* ctx, const scan_item* item, scan_result* out_dev);
 scan_status scan_sync(scan_ctx* ctx);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): scan_run_async without a
+ * context and without any allocation.  The same kernels run with the library
+ * default launch shapes (no per-context tuning; SCAN_STRAT_AUTO resolves to
+ * the heuristic), enqueued on hip_stream (a hipStream_t, or NULL) of the
+ * current HIP device; the result (one scan_result, every field, status 0)
+ * lands in *out_dev (device memory) when the stream reaches it.  No host
+ * sync.  The work-group partials live in a static device array of the
+ * library, SCAN_STATIC_MAX_WORKGROUPS x 32 bytes per device (128 KiB, held
+ * until the process ends; set up on the first call on each device); launches
+ * are capped to that many work-groups, so any column length is accepted.
+ * Every call on a device shares that array: calls that overlap on one device
+ * (different streams, or several host threads) race and give wrong results;
+ * calls in one stream's order do not.  Errors: the argument checks of
+ * scan_run -> SCAN_EINVAL / SCAN_EUNSUPPORTED before anything is enqueued;
+ * HIP failures -> SCAN_EDEVICE.  There is no message (no context). */
+#define SCAN_STATIC_MAX_WORKGROUPS 4096u
+scan_status scan_run_static(const scan_item* item, void* hip_stream, scan_result* out_dev);
+
 /* Set / read the launch tuning used for (enc, b, strategy). */
 scan_status scan_set_tune(scan_ctx* ctx, int32_t enc, uint32_t b, int32_t strategy, const scan_tune* t);
 scan_status scan_get_tune(scan_ctx* ctx, int32_t enc, uint32_t b, int32_t strategy, scan_tune* t);

@@ -120,6 +120,7 @@ SIGNATURES = {
     "scan_run": (_i32, [_vp, _P(ScanColumn), _i32, _u32, _P(ScanPredicate), _u32, _i32, _P(ScanResult)]),
     "scan_run_async": (_i32, [_vp, _P(ScanItem), _vp]),
     "scan_sync": (_i32, [_vp]),
+    "scan_run_static": (_i32, [_P(ScanItem), _vp, _vp]),
     "scan_set_tune": (_i32, [_vp, _i32, _u32, _i32, _P(ScanTune)]),
     "scan_get_tune": (_i32, [_vp, _i32, _u32, _i32, _P(ScanTune)]),
     "scan_autotune": (_i32, [_vp, _P(ScanColumn), _i32, _u32, _P(ScanPredicate), _i32, _i32, _P(ScanTune),

@@ -213,6 +213,17 @@ def encode_rle(values, device="cuda") -> RleColumn:
                      _to_dev(br.view(np.int64), device), _to_dev(zmin, device), _to_dev(zmax, device))
 
 
+def run_static(col: Column, lo: int, hi: int, strategy: int, out_dev, stream=None, zone_maps: bool = True):
+    """scan_run_static: enqueue one scan with no context and no allocation on
+    `stream` (a torch stream; default torch's current stream) of the current
+    device; the 40-byte result lands in out_dev (a device tensor of >= 40 bytes)."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    it = col.item(lo, hi, strategy, zone_maps)
+    rc = _lib.load().scan_run_static(ctypes.byref(it), ctypes.c_void_p(s.cuda_stream), ctypes.c_void_p(_ptr(out_dev)))
+    _check(rc, "scan_run_static")
+
+
 # --------------------------------------------------------------- context
 class Context:
     """One scan_ctx bound to a device and to torch's current stream on it."""

@@ -46,4 +46,15 @@ hipError_t launch_fold(const Partial* partials, uint32_t n, Result* out, uint64_
   return hipGetLastError();
 }
 
+// A result known on the host (an empty scan) written to device memory by a
+// kernel, so that no host buffer has to outlive the call.
+__global__ void write_result_kernel(Result* out, Result r) {
+  if (threadIdx.x == 0) *out = r;
+}
+
+hipError_t launch_write_result(Result* out, const Result& r, hipStream_t st) {
+  hipLaunchKernelGGL(write_result_kernel, dim3(1), dim3(64), 0, st, out, r);
+  return hipGetLastError();
+}
+
 }  // namespace scan_dev

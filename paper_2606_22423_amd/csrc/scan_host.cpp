@@ -196,13 +196,16 @@ scan_status occupancy(scan_ctx* ctx, LaunchFn fn, uint32_t block, int* occ) {
   return SCAN_OK;
 }
 
-// Fills p and the launch geometry for one (column, strategy); returns the
-// launcher or nullptr with ctx->err set.
-scan_status prepare_scan(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b, const scan_predicate* pred,
-                         int32_t s, Result* out_dev, Params& p, LaunchFn& fn, uint32_t& grid, uint32_t& block,
-                         bool& trivially_empty) {
+// Kernel parameters of one (column, strategy) scan writing its work-group
+// partials to `partials` and its result to `out_dev`: fills p and the
+// launcher, or sets trivially_empty (n = 0, lo >= hi, or a predicate outside
+// a FOR column's u32 domain).  ctx may be null (messages are then dropped).
+scan_status scan_params(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b, const scan_predicate* pred,
+                        int32_t s, Partial* partials, Result* out_dev, Params& p, LaunchFn& fn,
+                        bool& trivially_empty) {
   const int dec = s & 3, mode = (s >> 2) & 1, zm = (s >> 3) & 1;
   std::memset(&p, 0, sizeof p);
+  fn = nullptr;
   p.payload = col->payload;
   p.refs = col->block_ref;
   p.bases = col->block_base;
@@ -219,7 +222,7 @@ scan_status prepare_scan(scan_ctx* ctx, const scan_column* col, int32_t enc, uin
   p.bsum = col->block_sum;
   p.tail = (uint32_t)(col->n - (p.nb ? (p.nb - 1) : 0) * SCAN_BLOCK_VALUES);
   p.strategy = s;
-  p.partials = ctx->partials;
+  p.partials = partials;
   p.out = out_dev;
   trivially_empty = (col->n == 0 || pred->lo >= pred->hi);
   int pf = PF_RANGE;
@@ -237,21 +240,38 @@ scan_status prepare_scan(scan_ctx* ctx, const scan_column* col, int32_t enc, uin
   if (trivially_empty) return SCAN_OK;
   fn = enc == SCAN_ENC_DELTA_FOR ? delta_fn(dec, mode, b) : code_fn(enc, dec, mode, pf, b);
   if (!fn) return fail(ctx, SCAN_EUNSUPPORTED, "no kernel for enc %d b %u strategy %d", enc, b, s);
+  return SCAN_OK;
+}
+
+// Launch geometry: p.G, p.units and the grid, from the tuning, the resident
+// work-groups per CU of the kernel (`occ`) and a cap on the grid (the number
+// of partials the caller's buffer holds).
+void scan_geometry(Params& p, const scan_tune& t, int occ, int cus, uint32_t max_grid, int dec, uint32_t b,
+                   uint32_t& grid) {
+  const uint32_t block = (uint32_t)t.wg_size;
+  const uint64_t per_cu = t.wgs_per_cu > 0 ? std::min<uint64_t>((uint64_t)t.wgs_per_cu, (uint64_t)occ) : (uint64_t)occ;
+  const uint64_t waves = block / 64u;
+  const uint32_t win = t.window_blocks > 0 ? (uint32_t)t.window_blocks : step_blocks(dec, b);
+  p.G = std::min<uint32_t>(win, 64u);
+  p.units = (p.nb + p.G - 1) / p.G;
+  const uint64_t need = (p.units + waves - 1) / waves;
+  const uint64_t cap = std::min<uint64_t>((uint64_t)cus * std::max<uint64_t>(1, per_cu), max_grid);
+  grid = (uint32_t)std::max<uint64_t>(1, std::min(need, cap));
+}
+
+// Fills p and the launch geometry for one (column, strategy) on a context.
+scan_status prepare_scan(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b, const scan_predicate* pred,
+                         int32_t s, Result* out_dev, Params& p, LaunchFn& fn, uint32_t& grid, uint32_t& block,
+                         bool& trivially_empty) {
+  scan_status st = scan_params(ctx, col, enc, b, pred, s, ctx->partials, out_dev, p, fn, trivially_empty);
+  if (st != SCAN_OK || trivially_empty) return st;
   const scan_tune t = effective_tune(ctx, enc, b, s);
   block = (uint32_t)t.wg_size;
   if (block < 64 || block > 256 || block % 64) return fail(ctx, SCAN_EINVAL, "wg_size %u invalid (64..256)", block);
   int occ = 0;
-  scan_status st = occupancy(ctx, fn, block, &occ);
+  st = occupancy(ctx, fn, block, &occ);
   if (st != SCAN_OK) return st;
-  const uint64_t per_cu = t.wgs_per_cu > 0 ? std::min<uint64_t>((uint64_t)t.wgs_per_cu, (uint64_t)occ) : (uint64_t)occ;
-  const uint64_t waves = block / 64u;
-  const uint32_t win = t.window_blocks > 0 ? (uint32_t)t.window_blocks : step_blocks(dec, b);
-  (void)step_blocks;
-  p.G = std::min<uint32_t>(win, 64u);
-  p.units = (p.nb + p.G - 1) / p.G;
-  const uint64_t need = (p.units + waves - 1) / waves;
-  const uint64_t cap = std::min<uint64_t>((uint64_t)ctx->cus * std::max<uint64_t>(1, per_cu), ctx->max_grid);
-  grid = (uint32_t)std::max<uint64_t>(1, std::min(need, cap));
+  scan_geometry(p, t, occ, ctx->cus, ctx->max_grid, s & 3, b, grid);
   return SCAN_OK;
 }
 

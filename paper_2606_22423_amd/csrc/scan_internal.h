@@ -10,6 +10,11 @@
 #include "../../include/scan.h"
 #include "device_common.h"
 
+namespace scan_dev {
+using LaunchFn = hipError_t (*)(const Params&, uint32_t grid, uint32_t block, hipStream_t stream, int* occ);
+hipError_t launch_write_result(Result* out, const Result& r, hipStream_t st);
+}  // namespace scan_dev
+
 struct SelectorState;
 struct BatchPlan;
 struct SelectWork;
@@ -44,6 +49,12 @@ scan_status validate_column(scan_ctx* ctx, const scan_column* col, int32_t enc, 
 scan_status check_strategy(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b, int32_t s);
 int32_t heuristic_strategy(const scan_column* col, int32_t enc, uint32_t b);
 scan_tune effective_tune(scan_ctx* ctx, int32_t enc, uint32_t b, int32_t s);
+scan_tune default_tune(int32_t enc, uint32_t b, int32_t s);
+scan_status scan_params(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b, const scan_predicate* pred,
+                        int32_t s, scan_dev::Partial* partials, scan_dev::Result* out_dev, scan_dev::Params& p,
+                        scan_dev::LaunchFn& fn, bool& trivially_empty);
+void scan_geometry(scan_dev::Params& p, const scan_tune& t, int occ, int cus, uint32_t max_grid, int dec, uint32_t b,
+                   uint32_t& grid);
 scan_status enqueue_scan(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b, const scan_predicate* pred,
                          int32_t strategy, scan_dev::Result* out_dev, scan_dev::Result* host_empty_out);
 namespace scan_dev {
