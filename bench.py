@@ -88,7 +88,7 @@ def measure_beta(ctx, torch, reps=7):
     return best, best_cfg, triad
 
 
-def batch_leg(ctx, torch, ncols, reps, selector_path):
+def batch_leg(ctx, torch, ncols, reps, selector_path, batch_selector_path=None, regret_sample=256):
     """Mixed-column workload: ncols columns (lengths 2^10..2^24, widths 1..24,
     FOR / delta / dictionary by index mod 3, log-uniform selectivity, zone maps
     on all).  Baseline: one launch per column with the default strategy
@@ -175,6 +175,12 @@ def batch_leg(ctx, torch, ncols, reps, selector_path):
             ctx.batch_release(h)
         return float(np.median(ts)), got
 
+    # launch shape of the class kernels for this workload (the batch autotuner),
+    # used by every batch below
+    t0 = time.time()
+    (per_cu, win), _ = ctx.batch_autotune([c.item(lo, hi, default) for c, lo, hi in cols], reps=3)
+    res["batch_tune"] = {"wgs_per_cu": per_cu, "window_blocks": win}
+    log("[bench] batch autotune: %d work-groups per CU, %d-block windows (%.0f s)" % (per_cu, win, time.time() - t0))
     # the default strategy as one replay: direct launches (0), one graph (1),
     # one graph with the class scans forked over branches (2, the library default)
     by_mode = {}
@@ -186,30 +192,51 @@ def batch_leg(ctx, torch, ncols, reps, selector_path):
     res["batched_default_ms"] = round(by_mode[2] * 1e3, 3)
     res["batched_default_ms_direct_graph_forked"] = [round(by_mode[m] * 1e3, 3) for m in (0, 1, 2)]
     if selector_path and os.path.exists(selector_path):
+        # per-column launches with the single-launch selector's choices
         ctx.selector_load(selector_path)
         learned = [ctx.run(c, lo, hi, -1)["strategy_used"] for c, lo, hi in cols]
         ctx.selector_clear()
         launch_all(learned)
         t_learn = [timed(lambda: launch_all(learned)) for _ in range(reps)]
         check("async learned")
-        counts = np.bincount([st.STRATEGIES.index(s) for s in learned], minlength=8)
-        # batched + learned: the selector runs on the device inside each replay
-        ctx.selector_load(selector_path)
+        counts = np.bincount([st.STRATEGIES.index(s & ~16) for s in learned], minlength=8)
+        res.update({"learned_async_ms": round(float(np.median(t_learn)) * 1e3, 3),
+                    "learned_class_counts": counts.tolist(),
+                    "speedup_learned_vs_default": round(float(np.median(t_async)) / float(np.median(t_learn)), 3)})
+    bsel = batch_selector_path if batch_selector_path and os.path.exists(batch_selector_path) else selector_path
+    if bsel and os.path.exists(bsel):
+        # batched + learned: the batch selector runs on the device inside each replay
+        ctx.selector_load(bsel)
+        chosen = [ctx.run(c, lo, hi, -1)["strategy_used"] & ~16 for c, lo, hi in cols]
         t_bl, got = batched([c.item(lo, hi, -1) for c, lo, hi in cols], "batched learned")
         ctx.selector_clear()
-        if [g["strategy_used"] for g in got] != learned:
+        if [g["strategy_used"] for g in got] != chosen:
             raise RuntimeError("batched selection differs from scan_run's")
         # the same choices as explicit strategies: the replay without the
         # selection kernels (features, network, argmin)
-        t_be, _ = batched([c.item(lo, hi, s) for (c, lo, hi), s in zip(cols, learned)], "batched learned explicit")
-        res.update({"learned_async_ms": round(float(np.median(t_learn)) * 1e3, 3),
-                    "learned_class_counts": counts.tolist(),
-                    "speedup_learned_vs_default": round(float(np.median(t_async)) / float(np.median(t_learn)), 3),
-                    "batched_learned_ms": round(t_bl * 1e3, 3),
+        t_be, _ = batched([c.item(lo, hi, s) for (c, lo, hi), s in zip(cols, chosen)], "batched learned explicit")
+        res.update({"batched_learned_ms": round(t_bl * 1e3, 3),
                     "batched_learned_explicit_ms": round(t_be * 1e3, 3),
                     "selection_in_replay_ms": round((t_bl - t_be) * 1e3, 3),
+                    "batched_learned_vs_default": round(res["batched_default_ms"] / (t_bl * 1e3), 4),
                     "speedup_batched_learned_vs_per_column_async": round(float(np.median(t_async)) / t_bl, 2),
                     "speedup_batched_learned_vs_per_column_sync": round(float(np.median(t_sync)) / t_bl, 2)})
+        # regret measured live on a sample of the workload's columns: every
+        # strategy timed in the batch context the selector serves
+        if regret_sample > 0:
+            t0 = time.time()
+            timer = st.BatchTimer(ctx)
+            idx = list(range(0, ncols, max(1, ncols // regret_sample)))[:regret_sample]
+            T = np.array([[timer.time_strategies(cols[i][0], cols[i][1], cols[i][2], [s], 3)[s]
+                           for s in st.STRATEGIES] for i in idx])
+            rows = np.arange(len(idx))
+            ch = np.array([st.STRATEGIES.index(chosen[i]) for i in idx])
+            best = T.min(axis=1).sum()
+            res["selector_sample"] = {"columns": len(idx),
+                                      "regret": round(float(T[rows, ch].sum() / best - 1.0), 4),
+                                      "heuristic_regret": round(float(T[:, 5].sum() / best - 1.0), 4),
+                                      "seconds": round(time.time() - t0, 1)}
+            log("[bench] selector regret on %d sampled columns: %s" % (len(idx), res["selector_sample"]))
     log("[bench] batch: %s" % {k: v for k, v in res.items() if k.endswith("_ms") or k.startswith("speedup")})
     del cols
     return res
@@ -307,7 +334,24 @@ def zonemap_leg(ctx, torch, n_log2, beta_gbs, reps=5):
     for lvl in (0, 16, 1024, 65536, "random"):
         d = [r["blocks_read_frac"] - r["sigma"] for r in rows if r["s"] == lvl and r["zone_maps"] and not r["all_match"]]
         model[str(lvl)] = round(float(np.median(d)), 6)
-    return {"read_fraction_minus_sigma": model, "rle": rle_rows,
+    # the clustering model (lawfit.read_fraction_model: blocks whose zone map
+    # meets the predicate under Gaussian displacement of s ranks) against
+    # every measured point with zone maps on
+    from paper_2606_22423_amd import lawfit
+    errs, rel = [], []
+    for r in rows:
+        if not r["zone_maps"] or r["all_match"]:
+            continue
+        lo, hi = preds[sigmas.index(r["sigma"])]
+        pred = lawfit.read_fraction_model(n, lo, hi, r["s"])
+        r["model_read_frac"] = round(pred, 7)
+        errs.append(abs(pred - r["blocks_read_frac"]) * nb)
+        rel.append(abs(pred - r["blocks_read_frac"]) / max(r["blocks_read_frac"], 1.0 / nb))
+    read_model = {"points": len(errs), "median_abs_err_blocks": round(float(np.median(errs)), 2),
+                  "max_abs_err_blocks": round(float(np.max(errs)), 2),
+                  "median_rel_err": round(float(np.median(rel)), 4), "max_rel_err": round(float(np.max(rel)), 4)}
+    log("[bench] zone-map read model: %s" % read_model)
+    return {"read_fraction_minus_sigma": model, "read_model": read_model, "rle": rle_rows,
             "workload": "N=2^%d values at b=16, sorted base displaced by s in {0,2^4,2^10,2^16} ranks or random, "
                         "[lo, lo+round(sigma 2^16)), zone maps (+ all-match) vs off, bit-packed and run-length "
                         "copies, cold cache, median of %d" % (n_log2, reps),
@@ -767,7 +811,9 @@ def main():
     ap.add_argument("--serve-rows-log2", type=int, default=28, help="serving table rows (0: skip the serving leg)")
     ap.add_argument("--serve-queries", type=int, default=10000, help="measured queries per arrival rate")
     ap.add_argument("--selector", default=os.path.join(ROOT, "paper_2606_22423_amd", "selector_mi355x.txt"),
-                    help="trained selector parameters for the batched leg")
+                    help="trained selector parameters for single launches (per-column learned leg)")
+    ap.add_argument("--batch-selector", default=os.path.join(ROOT, "paper_2606_22423_amd", "selector_batch_mi355x.txt"),
+                    help="trained selector parameters for batches (batched learned leg)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: every run here has exactly one MI355X; --gpus %d is not supported "
@@ -1065,7 +1111,7 @@ def main():
 
     batch = None
     if args.batch_cols > 0:
-        batch = batch_leg(ctx, torch, args.batch_cols, args.reps, args.selector)
+        batch = batch_leg(ctx, torch, args.batch_cols, args.reps, args.selector, args.batch_selector)
 
     zonemap = None
     if args.zonemap_log2 > 0:

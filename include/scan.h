@@ -321,6 +321,16 @@ scan_status scan_batch_release(scan_ctx* ctx, uint64_t handle);
 scan_status scan_batch_run(scan_ctx* ctx, const scan_item* items, size_t n_items, scan_result* out);
 /* Launch tuning of the batch class kernels (wgs_per_cu, window_blocks). */
 scan_status scan_batch_set_tune(scan_ctx* ctx, const scan_tune* t);
+/* Autotuner of the batch class kernels: for each of work-groups per CU
+ * {1, 2, 4, 8} x window {16, 32, 64} blocks, prepares the batch (graph mode
+ * as set), replays it once, then times `reps` replays (at most 16) with HIP
+ * events, each after the 512 MiB cache-evicting read (allocated on first
+ * use, as for scan_autotune), and keeps the median-fastest configuration as
+ * the batch tuning (scan_batch_set_tune).  *out / *ms_out (host, may be
+ * NULL) receive it and its time.  Results never depend on the tuning.  An
+ * empty batch -> SCAN_EINVAL; on failure the previous tuning is restored. */
+scan_status scan_batch_autotune(scan_ctx* ctx, const scan_item* items, size_t n_items, int32_t reps, scan_tune* out,
+                                float* ms_out);
 /* How later scan_batch_prepare calls build the replay: 0 direct launches,
  * 1 one graph with the class scans in sequence, 2 (the default) one graph with
  * the class scans forked over up to four branches.  Results are the same.

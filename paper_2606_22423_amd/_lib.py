@@ -139,6 +139,7 @@ SIGNATURES = {
     "scan_batch_run": (_i32, [_vp, _P(ScanItem), ctypes.c_size_t, _P(ScanResult)]),
     "scan_batch_set_tune": (_i32, [_vp, _P(ScanTune)]),
     "scan_batch_set_graph": (_i32, [_vp, _i32]),
+    "scan_batch_autotune": (_i32, [_vp, _P(ScanItem), ctypes.c_size_t, _i32, _P(ScanTune), _P(ctypes.c_float)]),
     "scan_batch_info": (_i32, [_vp, _u64, _P(ScanBatchStats)]),
     "scan_mlp_param_count": (ctypes.c_int, []),
     "scan_selector_set": (_i32, [_vp, _vp, ctypes.c_size_t]),

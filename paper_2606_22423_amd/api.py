@@ -416,6 +416,15 @@ class Context:
         return {"captured": int(s.captured), "kernels": int(s.kernels), "class_mask": int(s.class_mask),
                 "work_items": int(s.work_items)}
 
+    def batch_autotune(self, items, reps: int = 3):
+        """Search work-groups per CU x window for this batch; returns ((wgs_per_cu, window), best ms)."""
+        arr = self._items(items)
+        t = ScanTune()
+        ms = ctypes.c_float()
+        self.check(self.lib.scan_batch_autotune(self.h, arr, len(items), reps, ctypes.byref(t), ctypes.byref(ms)),
+                   "scan_batch_autotune")
+        return (t.wgs_per_cu, t.window_blocks), float(ms.value)
+
     def batch_set_tune(self, wgs_per_cu=0, window_blocks=0):
         t = ScanTune(0, wgs_per_cu, window_blocks, 0)
         self.check(self.lib.scan_batch_set_tune(self.h, ctypes.byref(t)), "scan_batch_set_tune")

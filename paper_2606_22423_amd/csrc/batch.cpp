@@ -502,6 +502,67 @@ scan_status scan_batch_set_tune(scan_ctx* ctx, const scan_tune* t) {
   return SCAN_OK;
 }
 
+scan_status scan_batch_autotune(scan_ctx* ctx, const scan_item* items, size_t n_items, int32_t reps, scan_tune* out,
+                               float* ms_out) {
+  if (!ctx) return SCAN_EINVAL;
+  if (n_items == 0 || !items) return fail(ctx, SCAN_EINVAL, "the autotuner needs a non-empty batch");
+  if (reps < 1) reps = 3;
+  reps = std::min(reps, 16);
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  scan_status st = ensure_evict_buffer(ctx);
+  if (st != SCAN_OK) return st;
+  const auto key = std::make_tuple((int32_t)-1, 0u, (int32_t)-1);
+  const bool had = ctx->tunes.count(key) > 0;
+  const scan_tune saved = had ? ctx->tunes[key] : scan_tune{0, 0, 0, 0};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(ctx, SCAN_EDEVICE, "events");
+  }
+  static const int kPerCu[] = {1, 2, 4, 8};
+  static const int kWin[] = {16, 32, 64};
+  float best_ms = 1e30f;
+  scan_tune best = saved;
+  for (int pc : kPerCu) {
+    for (int win : kWin) {
+      ctx->tunes[key] = scan_tune{0, pc, win, 0};
+      uint64_t h = 0;
+      st = scan_batch_prepare(ctx, items, n_items, &h);
+      if (st != SCAN_OK) break;
+      float ts[16];
+      st = scan_batch_replay(ctx, h, nullptr);  // warm: code objects, graph upload
+      for (int i = 0; i < reps && st == SCAN_OK; ++i) {
+        evict_caches(ctx);
+        hipEventRecord(e0, ctx->stream);
+        st = scan_batch_replay(ctx, h, nullptr);
+        hipEventRecord(e1, ctx->stream);
+        if (st == SCAN_OK && hipEventSynchronize(e1) == hipSuccess) hipEventElapsedTime(&ts[i], e0, e1);
+      }
+      const scan_status st2 = scan_batch_release(ctx, h);
+      if (st == SCAN_OK) st = st2;
+      if (st != SCAN_OK) break;
+      std::sort(ts, ts + reps);
+      if (ts[reps / 2] < best_ms) {
+        best_ms = ts[reps / 2];
+        best = scan_tune{0, pc, win, 0};
+      }
+    }
+    if (st != SCAN_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != SCAN_OK) {
+    if (had) ctx->tunes[key] = saved;
+    else ctx->tunes.erase(key);
+    return st;
+  }
+  ctx->tunes[key] = best;
+  if (out) *out = best;
+  if (ms_out) *ms_out = best_ms;
+  return SCAN_OK;
+}
+
 scan_status scan_batch_set_graph(scan_ctx* ctx, int32_t mode) {
   if (!ctx) return SCAN_EINVAL;
   if (mode < 0 || mode > 2) return fail(ctx, SCAN_EINVAL, "graph mode must be 0, 1 or 2");

@@ -304,6 +304,24 @@ scan_status enqueue_scan(scan_ctx* ctx, const scan_column* col, int32_t enc, uin
   return SCAN_OK;
 }
 
+// The autotuners' cache-evicting read: a 512 MiB buffer of the context,
+// allocated on first use, read in full before each timed run.
+constexpr uint64_t kEvictBytes = 512ull << 20;
+
+scan_status ensure_evict_buffer(scan_ctx* ctx) {
+  if (ctx->evict_buf) return SCAN_OK;
+  hipError_t e = hipMalloc(&ctx->evict_buf, kEvictBytes);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(evict)");
+  e = hipMemsetAsync(ctx->evict_buf, 1, kEvictBytes, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMemsetAsync(evict)");
+  return SCAN_OK;
+}
+
+void evict_caches(scan_ctx* ctx) {
+  (void)scan_dev::launch_beta_read(ctx->evict_buf, kEvictBytes, (uint32_t)ctx->cus * 8u, 1024u, 1,
+                                   reinterpret_cast<uint64_t*>(ctx->ticket) + 8, ctx->stream);
+}
+
 scan_status resolve_strategy(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b,
                              const scan_predicate* pred, int32_t strategy, bool allow_sync, int32_t* out) {
   if (strategy == SCAN_STRAT_AUTO) {
@@ -491,13 +509,8 @@ scan_status scan_autotune(scan_ctx* ctx, const scan_column* col, int32_t enc, ui
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   // A read of twice the 256 MB last-level cache between timed runs keeps the
   // column cold, as it is when a scan streams it once.
-  constexpr uint64_t kEvict = 512ull << 20;
-  if (!ctx->evict_buf) {
-    e = hipMalloc(&ctx->evict_buf, kEvict);
-    if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(evict)");
-    e = hipMemsetAsync(ctx->evict_buf, 1, kEvict, ctx->stream);
-    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemsetAsync(evict)");
-  }
+  st = ensure_evict_buffer(ctx);
+  if (st != SCAN_OK) return st;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(ctx, SCAN_EDEVICE, "events");
   const scan_tune saved = effective_tune(ctx, enc, b, strategy);
@@ -515,8 +528,7 @@ scan_status scan_autotune(scan_ctx* ctx, const scan_column* col, int32_t enc, ui
         float ts[16];
         const int r = std::min(reps, 16);
         for (int i = 0; i < r; ++i) {
-          (void)scan_dev::launch_beta_read(ctx->evict_buf, kEvict, (uint32_t)ctx->cus * 8u, 1024u, 1,
-                                           reinterpret_cast<uint64_t*>(ctx->ticket) + 8, ctx->stream);
+          evict_caches(ctx);
           hipEventRecord(e0, ctx->stream);
           st = enqueue_scan(ctx, col, enc, b, pred, strategy, ctx->out_dev, nullptr);
           hipEventRecord(e1, ctx->stream);

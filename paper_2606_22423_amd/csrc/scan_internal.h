@@ -50,6 +50,8 @@ scan_status check_strategy(scan_ctx* ctx, const scan_column* col, int32_t enc, u
 int32_t heuristic_strategy(const scan_column* col, int32_t enc, uint32_t b);
 scan_tune effective_tune(scan_ctx* ctx, int32_t enc, uint32_t b, int32_t s);
 scan_tune default_tune(int32_t enc, uint32_t b, int32_t s);
+scan_status ensure_evict_buffer(scan_ctx* ctx);
+void evict_caches(scan_ctx* ctx);
 scan_status scan_params(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b, const scan_predicate* pred,
                         int32_t s, scan_dev::Partial* partials, scan_dev::Result* out_dev, scan_dev::Params& p,
                         scan_dev::LaunchFn& fn, bool& trivially_empty);

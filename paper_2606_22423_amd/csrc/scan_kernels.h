@@ -132,6 +132,17 @@ __device__ __forceinline__ uint64_t code_value(uint32_t c, const int64_t* dict_l
   else return (uint64_t)c;
 }
 
+// Branch-free form for a code that may not pass: a failing lane reads entry 0,
+// the address every failing lane of the wavefront shares, so the LDS serves
+// them as one broadcast and only the passing lanes' scattered entries can
+// conflict in the banks (without this every lane gathers a random entry and
+// the bank conflicts, not HBM, set the dictionary scan's time).
+template <int ENC>
+__device__ __forceinline__ uint64_t code_value_if(uint32_t c, bool ok, const int64_t* dict_lds, uint32_t dict_last) {
+  if constexpr (ENC == ENC_DICT) return code_value<ENC>(ok ? c : 0u, dict_lds, dict_last);
+  else return (uint64_t)c;
+}
+
 // Selection-vector push: compact the selected lanes' entries into the ring at
 // mbcnt positions; when 64 or more are pending, every lane consumes one.
 template <int ENC, typename EntryT>
@@ -481,7 +492,7 @@ __device__ __forceinline__ void decode_pair(const Params& p, WaveState<uint32_t>
       bool ok = (PF == PF_LO0) ? (c <= cr.wm1) : ((c - cr.loc) <= cr.wm1);
       if (TAIL) ok = ok && (((DEC == DEC_RM_DIRECT) ? (32u * l + t) : (32u * t + l)) < limit);
       lc += ok ? 1u : 0u;
-      const uint64_t v = code_value<ENC>(c, dict_lds, dict_last);
+      const uint64_t v = code_value_if<ENC>(c, ok, dict_lds, dict_last);
       part += ok ? (PartT<B, ENC>)v : (PartT<B, ENC>)0;
       if ((t & 3) == 3) {
         pin(part);
@@ -607,7 +618,7 @@ __device__ __forceinline__ void decode_staged(const Params& p, WaveState<uint32_
     if constexpr (MODE == MODE_BF) {
       const bool ok = hit && valid;
       cnt += ok ? 1u : 0u;
-      const uint64_t v = code_value<ENC>(c, dict_lds, dict_last);
+      const uint64_t v = code_value_if<ENC>(c, ok, dict_lds, dict_last);
       part += ok ? (PartT<B, ENC>)v : (PartT<B, ENC>)0;
       if ((t & 3) == 3) {
         pin(part);

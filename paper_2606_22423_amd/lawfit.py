@@ -138,3 +138,77 @@ def fit_crossover(sigmas, t_bf, t_sv) -> Crossover:
     low = 1e-6 if star != star else star * 0.5
     faster = "bf" if a1 + b1 * low <= a2 + b2 * low else "sv"
     return Crossover(a1, b1, a2, b2, star, faster)
+
+
+# ------------------------------------------------- zone maps and clustering
+def _trunc_normal_pmf(s: float, clip: float):
+    """pmf of D = round(s z) for z standard normal truncated to |z| <= clip,
+    over the integers t = -T .. T (T = round(clip s)).  Returns (T, pmf)."""
+    from scipy.special import ndtr  # standard normal CDF
+    T = int(round(clip * s))
+    t = np.arange(-T, T + 1, dtype=np.float64)
+    lo = np.maximum((t - 0.5) / s, -clip)
+    hi = np.minimum((t + 0.5) / s, clip)
+    pmf = np.maximum(ndtr(hi) - ndtr(lo), 0.0)
+    return T, pmf / pmf.sum()
+
+
+def read_fraction_model(n: int, lo: int, hi: int, s, n_distinct: int = 1 << 16, L: int = 1024,
+                        clip: float = 8.0) -> float:
+    """Expected fraction of 1024-value blocks that zone maps keep for [lo, hi)
+    on the clustered column of the zone-map workload: the sorted column
+    v_r = r // P (P = n / n_distinct copies of each value) with rank r moved
+    to position ~ r + D_r, D_r = round(s z_r) independent truncated normals
+    (s = "random": a uniform permutation).
+
+    The predicate covers the ranks [A, E) = [lo P, hi P).  A block's zone map
+    misses it iff all its ranks are >= E or all are < A (disjoint events), so
+        P(read k) = 1 - P(no rank < E lands in k) - P(no rank >= A lands in k),
+    and with independent displacements, for the block's first position kL,
+        P(no rank < E lands in k)  = prod_{d >= 1} (1 - q(kL - E + d)),
+        P(no rank >= A lands in k) = prod_{d >= 0} (1 - q(kL - A - d)),
+    q(y) = P(D in [y, y + L)).  Both products are tail / prefix sums of
+    log(1 - q) over one integer grid, so every block costs O(1).  The random
+    permutation gives P(read) = 1 - (A/n)^L - ((n - E)/n)^L (values drawn
+    independently).  s = 0 is exact: the blocks overlapping [A, E).
+    This is the skipping side of the paper's two crossovers (clustering, not
+    selectivity, decides what zone maps save), made quantitative."""
+    P = n // n_distinct
+    nb = n // L
+    A, E = lo * P, hi * P
+    if A >= E:
+        return 0.0
+    if s == 0:
+        return float(-(-E // L) - A // L) / nb
+    if s == "random":
+        p = 1.0 - (A / n) ** L - ((n - E) / n) ** L
+        return float(max(p, 0.0))
+    T, pmf = _trunc_normal_pmf(float(s), clip)
+    # q(y) for y = -T - L + 1 .. T: window sums of the pmf
+    cum = np.concatenate([[0.0], np.cumsum(pmf)])            # cum[i] = P(D < -T + i)
+    y = np.arange(-T - L + 1, T + 1)
+    a = np.clip(y + T, 0, 2 * T + 1)
+    b = np.clip(y + L + T, 0, 2 * T + 1)
+    q = np.clip(cum[b] - cum[a], 0.0, 1.0)
+    with np.errstate(divide="ignore"):
+        g = np.log1p(-q)
+    g = np.where(q >= 1.0, -np.inf, g)
+    y0 = int(y[0])
+    # prefix and suffix sums kept apart (log(1 - q) is -inf where a window
+    # holds the whole support, and -inf - -inf would be undefined)
+    pre = np.concatenate([[0.0], np.cumsum(g)])              # pre[i] = sum g(y0 .. y0 + i - 1)
+    suf = np.concatenate([np.cumsum(g[::-1])[::-1], [0.0]])  # suf[i] = sum g(y0 + i ..)
+
+    def prefix(w):   # sum_{y <= w} g(y)
+        return pre[np.clip(w - y0 + 1, 0, len(g))]
+
+    def tail(v):     # sum_{y >= v} g(y)
+        return suf[np.clip(v - y0, 0, len(g))]
+
+    k0 = max(0, (A - T - 2 * L) // L)
+    k1 = min(nb, (E + T + 2 * L) // L + 1)
+    k = np.arange(k0, k1, dtype=np.int64)
+    f_up = np.exp(tail(k * L - E + 1))
+    f_dn = np.exp(prefix(k * L - A))
+    p = np.clip(1.0 - f_up - f_dn, 0.0, 1.0)
+    return float(p.sum()) / nb

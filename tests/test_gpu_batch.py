@@ -216,6 +216,22 @@ def test_batch_info_and_graph_flag_errors(ctx, cases):
         ctx.batch_release(h)
 
 
+def test_batch_autotune_keeps_results(ctx, cases):
+    """The batch autotuner returns a configuration of its grid, installs it,
+    and the tuned batch gives the same results."""
+    items, meta = build_items(cases[:40])
+    base = ctx.batch_run(items)
+    try:
+        (per_cu, win), ms = ctx.batch_autotune(items, reps=2)
+        say("batch autotune:", per_cu, win, ms)
+        assert per_cu in (1, 2, 4, 8) and win in (16, 32, 64) and ms > 0
+        assert ctx.batch_run(items) == base
+        with pytest.raises(_lib.ScanError):
+            ctx.batch_autotune([], reps=1)
+    finally:
+        ctx.batch_set_tune(0, 0)
+
+
 def test_batch_window_and_occupancy_do_not_change_results(ctx, cases):
     items, meta = build_items(cases[:30])
     base = ctx.batch_run(items)

@@ -85,3 +85,39 @@ def test_crossover_absent_when_one_mode_always_wins():
     assert c.faster_below == "bf"
     with pytest.raises(ValueError):
         lawfit.fit_crossover([0.1], [1.0], [2.0])
+
+
+@pytest.mark.parametrize("s", [0, 16, 1024, 65536, "random"])
+def test_read_fraction_model_matches_generated_columns(s):
+    """The clustering model of the zone-map workload (expected share of blocks
+    the zone maps keep) against exact counts on columns drawn by the
+    workload's own generator at 2^22 values (each value fills 64 ranks): within
+    3 blocks + 3 % of the count for every (selectivity, predicate draw)."""
+    import oracle
+    import synth
+    n = 1 << 22
+    v = synth.config3_column(n, s=s).numpy().view(np.uint32)
+    zmin, zmax = oracle.zonemap_u32(v)
+    for sg in (1e-4, 1e-3, 1e-2, 0.1, 0.5):
+        for draw in range(2):
+            lo, hi = synth.config3_predicate(sg, draw=draw)
+            meas = int(np.sum(~((zmax < lo) | (zmin >= hi))))
+            model = lawfit.read_fraction_model(n, lo, hi, s) * (n // 1024)
+            assert abs(meas - model) <= 3 + 0.03 * model, (s, sg, draw, meas, model)
+            if s == 0:
+                assert meas == round(model)
+
+
+def test_read_fraction_model_limits():
+    """Closed limits: an empty predicate reads nothing; the sorted column reads
+    exactly the blocks its value range covers; the random permutation follows
+    1 - (lo/V)^L - ((V-hi)/V)^L; a small displacement (s << L) adds at most
+    one block per predicate edge."""
+    n, V = 1 << 30, 1 << 16
+    assert lawfit.read_fraction_model(n, 10, 10, 1024) == 0.0
+    assert lawfit.read_fraction_model(n, 100, 107, 0) * (n // 1024) == 7 * 16
+    lo, hi = 1000, 1007
+    want = 1 - (lo / V) ** 1024 - ((V - hi) / V) ** 1024
+    assert abs(lawfit.read_fraction_model(n, lo, hi, "random") - want) < 1e-12
+    extra = lawfit.read_fraction_model(n, lo, hi, 4) * (n // 1024) - 7 * 16
+    assert 0.0 <= extra <= 2.0 + 1e-9
