@@ -299,9 +299,8 @@ scan_status scan_gather(scan_ctx* ctx, const scan_column* col, int32_t enc, uint
  *
  * scan_batch_prepare validates the items, uploads their descriptors, windows
  * and zone-map segments once, and captures the replay sequence into a HIP
- * graph (by default the class kernels forked over up to four branches; see
- * scan_batch_set_graph; if capture fails, replays enqueue the kernels one by
- * one: same results).  Baked in at that moment: the selector
+ * graph (see scan_batch_set_graph; if capture fails, replays enqueue the
+ * kernels one by one: same results).  Baked in at that moment: the selector
  * (its parameters are copied), and the tuning stored for (enc -1, b 0,
  * strategy -1) (work-groups per CU of the class kernels, default 4, at most
  * the number that fit, and the window, default and at most 64 blocks).  An
@@ -332,8 +331,9 @@ scan_status scan_batch_set_tune(scan_ctx* ctx, const scan_tune* t);
 scan_status scan_batch_autotune(scan_ctx* ctx, const scan_item* items, size_t n_items, int32_t reps, scan_tune* out,
                                 float* ms_out);
 /* How later scan_batch_prepare calls build the replay: 0 direct launches,
- * 1 one graph with the class scans in sequence, 2 (the default) one graph with
- * the class scans forked over up to four branches.  Results are the same.
+ * 1 (the default) one graph with the class scans in sequence, 2 one graph
+ * with the class scans forked over up to four branches (measured slower on
+ * MI355X: the concurrent class scans contend).  Results are the same.
  * Other values -> SCAN_EINVAL. */
 scan_status scan_batch_set_graph(scan_ctx* ctx, int32_t mode);
 typedef struct {

@@ -406,8 +406,8 @@ class Context:
         return [out[i].as_dict() for i in range(len(items))]
 
     def batch_set_graph(self, mode: int):
-        """Replay form of later prepared batches: 0 direct launches, 1 one graph,
-        2 one graph with the class scans forked over branches (the default)."""
+        """Replay form of later prepared batches: 0 direct launches, 1 one graph
+        (the default), 2 one graph with the class scans forked over branches."""
         self.check(self.lib.scan_batch_set_graph(self.h, int(mode)), "scan_batch_set_graph")
 
     def batch_info(self, handle: int) -> dict:

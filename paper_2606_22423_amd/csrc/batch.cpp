@@ -6,7 +6,8 @@
 //   -> select (strategy per column, written on the device)
 //   -> bin (items into twelve class lists)
 //   -> the persistent class scans that can occur (static schedule over each
-//      list), forked over up to four graph branches
+//      list), in sequence (forking them over graph branches is an option;
+//      running concurrently they contend and measured slower)
 // so a replay is one hipGraphLaunch whatever the number of columns; the
 // 32-byte result slots come back with one copy.  If capture or instantiation
 // fails the same sequence is enqueued launch by launch.  The same column

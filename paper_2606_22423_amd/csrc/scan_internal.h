@@ -40,7 +40,7 @@ struct scan_ctx {
   std::map<uint64_t, BatchPlan*> batches;
   SelectWork* select = nullptr;       // materializing select work space
   uint64_t next_batch = 1;
-  int batch_graph = 2;                // prepared batches: 0 direct launches, 1 graph, 2 graph with forked class scans
+  int batch_graph = 1;                // prepared batches: 0 direct launches, 1 graph, 2 graph with forked class scans
 };
 
 scan_status fail(scan_ctx* ctx, scan_status st, const char* fmt, ...);

@@ -134,6 +134,116 @@ def select_section(trace_path, bench_line, command):
     return lines
 
 
+def _dispatches(path, counter=None):
+    """[(dispatch id, raw kernel name, value)] of a kernel trace (value: the
+    duration in ns) or of one counter of a counter-collection CSV."""
+    rows = []
+    with open(path) as fh:
+        for row in csv.DictReader(fh):
+            if counter is None:
+                rows.append((int(row["Dispatch_Id"]), row["Kernel_Name"],
+                             int(row["End_Timestamp"]) - int(row["Start_Timestamp"])))
+            elif row["Counter_Name"] == counter:
+                rows.append((int(row["Dispatch_Id"]), row["Kernel_Name"], float(row["Counter_Value"])))
+    rows.sort()
+    return rows
+
+
+def _assign(cases, rows):
+    """Per case, the values of its dispatches: cases run in order, so each
+    takes the next `launches` dispatches whose name matches its regular
+    expression (the first of a case with a warm-up launch is dropped by the
+    caller through `launches`)."""
+    cursor = {}
+    out = []
+    for c in cases:
+        rx = re.compile(c["kernel"])
+        pos = cursor.get(c["kernel"], 0)
+        got = []
+        while pos < len(rows) and len(got) < c["launches"]:
+            if rx.search(rows[pos][1]):
+                got.append(rows[pos][2])
+            pos += 1
+        cursor[c["kernel"]] = pos
+        out.append(got)
+    return out
+
+
+def _med(v):
+    v = sorted(v)
+    return v[len(v) // 2] if v else None
+
+
+def paths_summary(run, trace, fetch, write, sq, command):
+    """Markdown table of the profile_paths.py cases (trace, HBM bytes, SQ counters)."""
+    cases = run["cases"]
+    dur = _assign(cases, _dispatches(trace))
+    lines = ["# rocprofv3 summary: dictionary, delta, batch, serving, run-length and select kernels on one MI355X",
+             "", "Commands (repository root):", ""]
+    lines += ["    " + c for c in command.split(" ;; ")]
+    lines += ["", "Workload (`paper_2606_22423_amd/profile_paths.py`): 2^%d-value columns (the sweep's length) for the "
+              "dictionary (2^b sorted int64 entries, 10 %% of the codes selected), delta (cumulative sums of b-bit "
+              "draws, 10 %% selected) and select (b = 16) cases, the 4096-column mixed workload for the batch class "
+              "kernels (default strategy: row-major direct, branch-free, zone maps), a 64-query batch on the 16-column "
+              "serving table, and the zone-map workload's column displaced by 2^16 ranks, run-length encoded.  Cold "
+              "cache before every launch (512 MiB read of scratch).  Algorithmic bytes: the payload bytes of the "
+              "blocks the kernel must decode (after zone maps where used), plus zone maps, bases, dictionaries, "
+              "ballots and positions as each kernel's notes say; GB/s and the fraction of the 8 TB/s peak are on the "
+              "kernel-trace duration." % (run["n"].bit_length() - 1), ""]
+    lines += ["| case | launches | avg us | algorithmic bytes | algorithmic GB/s | fraction of 8 TB/s |",
+              "|---|---|---|---|---|---|"]
+    for c, d in zip(cases, dur):
+        d = d[c.get("warmup", 0):]  # a case's first launch may be an untimed warm-up
+        if not d:
+            lines.append("| %s | 0 | - | %d | - | - |" % (c["name"], c["algorithmic_bytes"]))
+            continue
+        avg = sum(d) / len(d)
+        lines.append("| %s | %d | %.1f | %d | %.0f | %.3f |" % (c["name"], len(d), avg / 1e3, c["algorithmic_bytes"],
+                                                                c["algorithmic_bytes"] / avg,
+                                                                c["algorithmic_bytes"] / avg / 8000.0))
+    if fetch and write:
+        frows, wrows = _dispatches(fetch, "FETCH_SIZE"), _dispatches(write, "WRITE_SIZE")
+        f_cal = sorted(v for _, k, v in frows if "beta_read" in k)
+        w_cal = sorted(v for _, k, v in wrows if "beta_triad" in k)
+        sf = _med(f_cal) * 1024 / run["cal_read_bytes"] if f_cal else None
+        sw = _med(w_cal) * 1024 / (run["cal_triad_floats"] * 4) if w_cal else None
+        fv, wv = _assign(cases, frows), _assign(cases, wrows)
+        lines += ["", "HBM traffic: FETCH_SIZE and WRITE_SIZE (KiB per dispatch, medians over the case's launches), each "
+                  "scaled by the same counter's reading for a kernel of known traffic run first (FETCH factor %.4f: "
+                  "streaming read of %d bytes; WRITE factor %.4f: triad, 4 B written per float)."
+                  % (sf or 0, run["cal_read_bytes"], sw or 0), "",
+                  "| case | FETCH KiB | WRITE KiB | scaled bytes | algorithmic bytes | ratio |", "|---|---|---|---|---|---|"]
+        for c, f, w in zip(cases, fv, wv):
+            fm, wm = _med(f), _med(w)
+            if fm is None or wm is None or not sf or not sw:
+                continue
+            tb = fm * 1024 / sf + wm * 1024 / sw
+            lines.append("| %s | %.0f | %.1f | %.0f | %d | %.3f |" % (c["name"], fm, wm, tb, c["algorithmic_bytes"],
+                                                                       tb / c["algorithmic_bytes"]))
+    if sq:
+        names = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT",
+                 "SQ_ACTIVE_INST_VALU", "SQ_WAVE_CYCLES", "SQ_INSTS_VMEM")
+        got = {nm: _assign(cases, _dispatches(sq, nm)) for nm in names}
+        lines += ["", "SQ counters (medians over the case's launches; instruction counts are per wavefront, shown per "
+                  "decoded value as count x 64 / values): VALU, SALU, LDS and vector-memory instructions per value, "
+                  "LDS bank-conflict cycles per LDS instruction, and the share of wavefront cycles with a VALU "
+                  "instruction issued.", "",
+                  "| case | waves | VALU / value | SALU / value | LDS / value | VMEM / value | bank-conflict cycles / LDS instr. | VALU-active cycles |",
+                  "|---|---|---|---|---|---|---|---|"]
+        for i, c in enumerate(cases):
+            v = {nm: _med(got[nm][i]) for nm in names}
+            if v["SQ_INSTS_VALU"] is None or not c.get("values"):
+                continue
+            nv = c["values"]
+            lines.append("| %s | %d | %.2f | %.2f | %.3f | %.3f | %s | %s |" % (
+                c["name"], v["SQ_WAVES"] or 0, v["SQ_INSTS_VALU"] * 64 / nv, (v["SQ_INSTS_SALU"] or 0) * 64 / nv,
+                (v["SQ_INSTS_LDS"] or 0) * 64 / nv, (v["SQ_INSTS_VMEM"] or 0) * 64 / nv,
+                "%.2f" % (v["SQ_LDS_BANK_CONFLICT"] / v["SQ_INSTS_LDS"]) if v["SQ_LDS_BANK_CONFLICT"] is not None and
+                v["SQ_INSTS_LDS"] else "-",
+                "%.3f" % (v["SQ_ACTIVE_INST_VALU"] / v["SQ_WAVE_CYCLES"]) if v["SQ_WAVE_CYCLES"] else "-"))
+    return lines
+
+
 def load_bench_record(path):
     """The full bench record: bench.py's detail file (its "line" object), or
     an older stdout holding the whole record as its last JSON line."""
@@ -159,7 +269,17 @@ def main(argv=None):
     ap.add_argument("--traffic-json")
     ap.add_argument("--sq", help="counter_collection.csv of an SQ_* pass")
     ap.add_argument("--select-out", help="with --bench-json: also write the select leg's kernel table here")
+    ap.add_argument("--paths-json", help="stdout of profile_paths.py: summarise its cases instead")
     args = ap.parse_args(argv)
+
+    if args.paths_json:
+        with open(args.paths_json) as fh:
+            run = json.loads([ln for ln in fh if ln.startswith("{")][-1])
+        lines = paths_summary(run, args.trace, args.fetch, args.write, args.sq, args.command)
+        with open(args.out, "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+        print("\n".join(lines))
+        return 0
 
     if args.bench_json:
         line = load_bench_record(args.bench_json)

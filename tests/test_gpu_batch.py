@@ -196,7 +196,7 @@ def test_batch_graph_replays_equal_direct_launches(ctx, cases, with_selector):
             for h in handles:
                 ctx.batch_release(h)
     finally:
-        ctx.batch_set_graph(2)
+        ctx.batch_set_graph(1)
         if with_selector:
             ctx.selector_clear()
     for (c, lo, hi, strat, zm), g in zip(meta, direct):
