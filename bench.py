@@ -620,15 +620,23 @@ def serve_leg(ctx, torch, rows_log2, nq, lambdas=(0.25, 0.5, 0.8, 0.95), warm=50
             srv.close()
         return res, sub, stats
 
-    # saturation: flood the server
+    # saturation: flood the server, with the per-query kernel and then with
+    # the shared-decode kernel (the default, used for the arrival rates below)
     flood = synth.config5_queries(2000, spec, 1.0, dicts, seed_stream=11)
-    t1 = time.perf_counter()
-    res, sub, _ = drive(flood, None)
-    sat = len(flood) / (time.perf_counter() - t1)
-    log("[bench] serving saturation %.0f queries/s" % sat)
+    sat_by_kernel = {}
+    for kern in (serve.PER_QUERY, serve.SHARED):
+        cfg = serve.config(hbm_budget_bytes=2 << 30, max_inflight=256, n_streams=2, max_batch=64,
+                           batch_window_us=200, kernel=kern)
+        t1 = time.perf_counter()
+        res, sub, _ = drive(flood, None)
+        sat_by_kernel[kern] = len(flood) / (time.perf_counter() - t1)
+    sat = sat_by_kernel[serve.SHARED]
+    log("[bench] serving saturation %.0f queries/s (per-query kernel %.0f)" % (sat, sat_by_kernel[serve.PER_QUERY]))
     out = {"workload": "16 columns x 2^%d rows, b in {4,8,12,16,20}, FOR/dict alternating, half clustered; "
                        "1..3 conjuncts + SUM, sigma log-uniform [1e-5, 0.5]; 2 streams, batches <= 64, 200 us window"
-                       % rows_log2, "saturation_qps": round(sat, 1), "payload_bytes": int(payload), "rates": []}
+                       % rows_log2, "saturation_qps": round(sat, 1),
+           "saturation_qps_per_query_kernel": round(sat_by_kernel[serve.PER_QUERY], 1),
+           "payload_bytes": int(payload), "rates": []}
     for k, lam in enumerate(lambdas):
         qs = synth.config5_queries(nq + warm, spec, lam * sat, dicts, seed_stream=20 + k)
         t1 = time.perf_counter()
@@ -787,7 +795,9 @@ def compact_line(full: dict, detail_path: str) -> dict:
                                                     (ctl.get("byte_aligned_vs_generic") or {}).items()}}
     sv = full.get("serving")
     if sv:
-        line["serving"] = {"saturation_qps": sv["saturation_qps"], "isolation_checked": sv.get("isolation_checked"),
+        line["serving"] = {"saturation_qps": sv["saturation_qps"],
+                           "saturation_qps_per_query_kernel": sv.get("saturation_qps_per_query_kernel"),
+                           "isolation_checked": sv.get("isolation_checked"),
                            "p50_p99_us": {str(r["lambda"]): [r["p50_us"], r["p99_us"]] for r in sv["rates"]}}
     line["detail_file"] = os.path.basename(detail_path)
     return line
@@ -920,6 +930,29 @@ def main():
     for b in widths:
         best[b] = min((sweep[(SIGMA, s)][b], s) for s in all_strats if b in sweep[(SIGMA, s)])[1]
 
+    # --- fixed cost of one scan (scan kernel + fold kernel) apart from decoding:
+    # a one-block column (the first block of each width's column) with the
+    # width's strategy, launched back to back (before the timed region, so
+    # that a kernel trace's last launches of each kernel are the timed ones);
+    # the law is refitted below on the timed region's times minus this cost
+    out1 = torch.zeros(5, dtype=torch.int64, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fixed = {}
+    for b in widths:
+        s = best[b]
+        src_col = col_for(b, s)
+        one = api.Column(src_col.enc, b, 1024, src_col.layout, src_col.payload[: 32 * b])
+        burst = []
+        for _ in range(3):
+            ctx.run_async(one, 0, bounds[b], s, out1)
+            e0.record()
+            for _ in range(50):
+                ctx.run_async(one, 0, bounds[b], s, out1)
+            e1.record()
+            e1.synchronize()
+            burst.append(e0.elapsed_time(e1) * 1e-3 / 50)
+        fixed[b] = float(np.median(burst))
+
     # --- timed region: K steps of the whole workload
     hi_head = lambda b: bounds[b]  # noqa: E731
     for _ in range(args.warmup):
@@ -978,42 +1011,20 @@ def main():
                 sigma_fits["%s@%g" % (strategy_name(s), sg)] = {"T_dec_gvalues_per_s": round(ft.t_dec / 1e9, 1),
                                                                "b_star": round(ft.b_star, 2)}
 
-    # --- fixed cost of one scan (scan kernel + fold kernel) apart from decoding:
-    # a one-block column (the first block of each width's column) with the
-    # width's timed strategy, launched back to back; the law refitted on the
-    # times with that cost taken out
-    launch_cost = None
-    if True:
-        out1 = torch.zeros(5, dtype=torch.int64, device="cuda")
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        fixed = {}
-        for b in widths:
-            s = best[b]
-            src_col = col_for(b, s)
-            one = api.Column(src_col.enc, b, 1024, src_col.layout, src_col.payload[: 32 * b])
-            burst = []
-            for _ in range(3):
-                ctx.run_async(one, 0, bounds[b], s, out1)
-                e0.record()
-                for _ in range(50):
-                    ctx.run_async(one, 0, bounds[b], s, out1)
-                e1.record()
-                e1.synchronize()
-                burst.append(e0.elapsed_time(e1) * 1e-3 / 50)
-            fixed[b] = float(np.median(burst))
-        net = {b: max(float(np.median(per_kernel[b])) - fixed[b], 1e-9) for b in widths}
-        f_net = [lawfit.bandwidth_fraction(N, b, net[b], beta) for b in widths]
-        ft_net = lawfit.fit_tdec(widths, f_net, beta)
-        launch_cost = {"fixed_us_median": round(float(np.median(list(fixed.values()))) * 1e6, 2),
-                       "fixed_us_b1_b32": [round(fixed[1] * 1e6, 2), round(fixed[32] * 1e6, 2)],
-                       "share_of_time_b1": round(fixed[1] / float(np.median(per_kernel[1])), 3),
-                       "law_fit_without_fixed_cost": {"T_dec_gvalues_per_s": round(ft_net.t_dec / 1e9, 1),
-                                                      "b_star": round(ft_net.b_star, 2),
-                                                      "median_abs_err": round(ft_net.median_err, 4)},
-                       "median_abs_err_with_fixed_cost": round(ft_best.median_err, 4)}
-        log("[bench] fixed launch cost %.1f us (b=1: %.0f%% of its time); law without it: T_dec %.3g, b* %.1f, "
-            "median err %.3f" % (launch_cost["fixed_us_median"], 100 * launch_cost["share_of_time_b1"],
-                                 ft_net.t_dec, ft_net.b_star, ft_net.median_err))
+    # law without the fixed launch cost
+    net = {b: max(float(np.median(per_kernel[b])) - fixed[b], 1e-9) for b in widths}
+    f_net = [lawfit.bandwidth_fraction(N, b, net[b], beta) for b in widths]
+    ft_net = lawfit.fit_tdec(widths, f_net, beta)
+    launch_cost = {"fixed_us_median": round(float(np.median(list(fixed.values()))) * 1e6, 2),
+                   "fixed_us_b1_b32": [round(fixed[1] * 1e6, 2), round(fixed[32] * 1e6, 2)],
+                   "share_of_time_b1": round(fixed[1] / float(np.median(per_kernel[1])), 3),
+                   "law_fit_without_fixed_cost": {"T_dec_gvalues_per_s": round(ft_net.t_dec / 1e9, 1),
+                                                  "b_star": round(ft_net.b_star, 2),
+                                                  "median_abs_err": round(ft_net.median_err, 4)},
+                   "median_abs_err_with_fixed_cost": round(ft_best.median_err, 4)}
+    log("[bench] fixed launch cost %.1f us (b=1: %.0f%% of its time); law without it: T_dec %.3g, b* %.1f, "
+        "median err %.3f" % (launch_cost["fixed_us_median"], 100 * launch_cost["share_of_time_b1"],
+                             ft_net.t_dec, ft_net.b_star, ft_net.median_err))
 
     # --- materializing select (positions to HBM) on the same resident columns
     select_rows = []

@@ -448,6 +448,8 @@ typedef struct {
   uint32_t batch_window_us;
   uint32_t window_blocks;
   uint32_t wgs_per_cu;
+  uint32_t kernel;            /* SCAN_QUERY_SHARED (0, default) or SCAN_QUERY_PER_QUERY (1) */
+  uint32_t reserved;
 } scan_server_config;
 
 /* Validate the columns and upload their descriptors.  Errors: different row
@@ -459,9 +461,20 @@ void scan_table_destroy(scan_table* t);
  * n results.  Bad filter or sum column indices -> SCAN_EINVAL. */
 scan_status scan_query_run(scan_ctx* ctx, const scan_table* t, const scan_query* queries, size_t n,
                            scan_query_result* out);
-/* Launch shape of scan_query_run (0 = default: 64-block windows, as many
- * work-groups per CU as fit). */
+/* Launch shape of scan_query_run (0 = default: 64-block windows for the
+ * per-query kernel, 8 for the shared one; as many work-groups per CU as fit). */
 scan_status scan_query_set_tune(scan_ctx* ctx, int32_t wgs_per_cu, int32_t window_blocks);
+/* Which query kernel scan_query_run uses (the server takes it from its config):
+ *  SCAN_QUERY_SHARED (default): a work item is a window of blocks for every
+ *    query of the batch; each column block that any query still needs is
+ *    decoded once into LDS and evaluated for all of them (tables of at most
+ *    64 columns; batches run 64 queries per launch);
+ *  SCAN_QUERY_PER_QUERY: a work item is (window, query); each query decodes
+ *    the blocks it needs itself.
+ * Same results.  Other values -> SCAN_EINVAL.  A table of more than 64
+ * columns always runs the per-query kernel. */
+enum { SCAN_QUERY_SHARED = 0, SCAN_QUERY_PER_QUERY = 1 };
+scan_status scan_query_set_kernel(scan_ctx* ctx, int32_t kernel);
 
 /* Start a server on the context's device (its own host thread and streams;
  * the context itself is not used by the thread).  The table must outlive it. */

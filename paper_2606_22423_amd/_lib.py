@@ -104,7 +104,8 @@ class ScanQueryResult(ctypes.Structure):
 class ScanServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_uint32),
                 ("n_streams", ctypes.c_uint32), ("max_batch", ctypes.c_uint32), ("batch_window_us", ctypes.c_uint32),
-                ("window_blocks", ctypes.c_uint32), ("wgs_per_cu", ctypes.c_uint32)]
+                ("window_blocks", ctypes.c_uint32), ("wgs_per_cu", ctypes.c_uint32),
+                ("kernel", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 _vp, _u64, _u32, _i32, _i64, _f32 = (ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32,
@@ -156,6 +157,7 @@ SIGNATURES = {
     "scan_table_destroy": (None, [_vp]),
     "scan_query_run": (_i32, [_vp, _vp, _P(ScanQuery), ctypes.c_size_t, _P(ScanQueryResult)]),
     "scan_query_set_tune": (_i32, [_vp, _i32, _i32]),
+    "scan_query_set_kernel": (_i32, [_vp, _i32]),
     "scan_server_create": (_i32, [_vp, _vp, _P(ScanServerConfig), _P(_vp)]),
     "scan_server_submit": (_i32, [_vp, _P(ScanQuery), _P(_u64)]),
     "scan_server_poll": (_i32, [_vp, _P(ScanQueryResult), ctypes.c_size_t, _P(ctypes.c_size_t), _u32]),

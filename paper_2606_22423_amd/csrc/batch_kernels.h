@@ -209,7 +209,9 @@ __device__ __forceinline__ void batch_dict_share(const BatchArgs& a, const uint3
       __syncthreads();  // every wavefront is done with the previous dictionary
       const int64_t* src = a.cols[col].dict;
       const uint32_t len = a.cols[col].dict_len < kMaxDict ? a.cols[col].dict_len : kMaxDict;
-      for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) dict[i] = src[i];
+      const uint32_t clo = a.cols[col].clo, chi = a.cols[col].chi;
+      // entries outside the column's code range are 0 (see mask_dictionary)
+      for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) dict[i] = (i >= clo && i < chi) ? src[i] : 0;
       __syncthreads();
       cur = col;
       dlast = len ? len - 1u : 0u;

@@ -132,16 +132,16 @@ __device__ __forceinline__ uint64_t code_value(uint32_t c, const int64_t* dict_l
   else return (uint64_t)c;
 }
 
-// Branch-free form for a code that may not pass: a failing lane reads entry 0,
-// the address every failing lane of the wavefront shares, so the LDS serves
-// them as one broadcast and only the passing lanes' scattered entries can
-// conflict in the banks (without this every lane gathers a random entry and
-// the bank conflicts, not HBM, set the dictionary scan's time).
-template <int ENC>
-__device__ __forceinline__ uint64_t code_value_if(uint32_t c, bool ok, const int64_t* dict_lds, uint32_t dict_last) {
-  if constexpr (ENC == ENC_DICT) return code_value<ENC>(ok ? c : 0u, dict_lds, dict_last);
-  else return (uint64_t)c;
+// Zero the LDS dictionary's entries outside the code range [clo, chi): a
+// branch-free scan then adds every code's entry (0 for a code that fails the
+// predicate) and a compacted one only ever reads entries inside the range.
+// Ends with a barrier.
+__device__ __forceinline__ void mask_dictionary(int64_t* dict_lds, uint32_t len, uint32_t clo, uint32_t chi) {
+  for (uint32_t i = threadIdx.x; i < len; i += blockDim.x)
+    if (i < clo || i >= chi) dict_lds[i] = 0;
+  __syncthreads();
 }
+
 
 // Selection-vector push: compact the selected lanes' entries into the ring at
 // mbcnt positions; when 64 or more are pending, every lane consumes one.
@@ -482,6 +482,34 @@ __device__ __forceinline__ void decode_pair(const Params& p, WaveState<uint32_t>
       s.lsum += (uint64_t)sp;
       if constexpr (PF == PF_REFS) s.lsum += (uint64_t)lc * ref;
     }
+  } else if constexpr (MODE == MODE_BF && ENC == ENC_DICT) {
+    // Branch-free dictionary: the LDS dictionary holds 0 outside the code
+    // range [clo, chi) (see mask_dictionary), so the sum gathers every
+    // code's entry with no compare and no select; COUNT comes from packed
+    // fields (b <= 15, full blocks) or one compare per code.  Only a partial
+    // last block masks its padding slots.
+    uint32_t lc = 0;
+    if constexpr (!TAIL && B <= 15) {
+      uint32_t unused = 0;
+      swar_count_sum<B, PF>(w, cr.loc, cr.wm1, lc, unused);
+    }
+#pragma unroll
+    for (int t = 0; t < 32; ++t) {
+      const uint32_t c = run_code<B, B>(w, t);
+      bool valid = true;
+      if (TAIL) valid = (((DEC == DEC_RM_DIRECT) ? (32u * l + t) : (32u * t + l)) < limit);
+      if constexpr (TAIL || B > 15) lc += (valid && (c - cr.loc) <= cr.wm1) ? 1u : 0u;
+      const uint64_t v = code_value<ENC>(c, dict_lds, dict_last);
+      part += TAIL ? (valid ? v : 0ull) : v;
+      if ((t & 3) == 3) {
+        pin(part);
+        pin(lc);
+      }
+    }
+    if (act) {
+      s.lcount += lc;
+      s.lsum += (uint64_t)part;
+    }
   } else if constexpr (MODE == MODE_BF) {
     // Branch-free: per-lane count and masked add; the compare's mask stays in
     // VCC and feeds a select and a carry-add (no ballot, no scalar work).
@@ -492,7 +520,7 @@ __device__ __forceinline__ void decode_pair(const Params& p, WaveState<uint32_t>
       bool ok = (PF == PF_LO0) ? (c <= cr.wm1) : ((c - cr.loc) <= cr.wm1);
       if (TAIL) ok = ok && (((DEC == DEC_RM_DIRECT) ? (32u * l + t) : (32u * t + l)) < limit);
       lc += ok ? 1u : 0u;
-      const uint64_t v = code_value_if<ENC>(c, ok, dict_lds, dict_last);
+      const uint64_t v = code_value<ENC>(c, dict_lds, dict_last);
       part += ok ? (PartT<B, ENC>)v : (PartT<B, ENC>)0;
       if ((t & 3) == 3) {
         pin(part);
@@ -615,10 +643,19 @@ __device__ __forceinline__ void decode_staged(const Params& p, WaveState<uint32_
     else c = funnel(sp[2 * B * t + 1], sp[2 * B * t], sh) & width_mask<B>();
     const bool hit = (PF == PF_LO0) ? (c <= cr.wm1) : ((c - cr.loc) <= cr.wm1);
     const bool valid = !TAIL || (lane + 64u * t < limit);
-    if constexpr (MODE == MODE_BF) {
+    if constexpr (MODE == MODE_BF && ENC == ENC_DICT) {
+      // masked dictionary (0 outside [clo, chi)): gather every valid code's entry
+      cnt += (hit && valid) ? 1u : 0u;
+      const uint64_t v = code_value<ENC>(c, dict_lds, dict_last);
+      part += valid ? v : 0ull;
+      if ((t & 3) == 3) {
+        pin(part);
+        pin(cnt);
+      }
+    } else if constexpr (MODE == MODE_BF) {
       const bool ok = hit && valid;
       cnt += ok ? 1u : 0u;
-      const uint64_t v = code_value_if<ENC>(c, ok, dict_lds, dict_last);
+      const uint64_t v = code_value<ENC>(c, dict_lds, dict_last);
       part += ok ? (PartT<B, ENC>)v : (PartT<B, ENC>)0;
       if ((t & 3) == 3) {
         pin(part);
@@ -913,6 +950,8 @@ __global__ __launch_bounds__(256) void code_scan(const Params p) {
     clo = lower_bound_lds(dict_lds, p.dict_len, p.lo);
     chi = lower_bound_lds(dict_lds, p.dict_len, p.hi);
     dict_last = p.dict_len - 1u;
+    __syncthreads();  // every thread has its code range before the entries change
+    mask_dictionary(dict_lds, p.dict_len, clo, chi);
   }
   // Grid-strided windows of p.G blocks: at any moment the wavefronts read one
   // compact region of the column (DRAM row locality), like a streaming copy.

@@ -33,6 +33,7 @@ struct scan_table {
   int device = 0;
   uint64_t n = 0, nb = 0;
   uint32_t n_cols = 0;
+  uint32_t stage_words = 0;  // LDS words holding one block of every column (shared-decode kernel)
   std::vector<QCol> cols;
   QCol* cols_dev = nullptr;
 };
@@ -44,10 +45,17 @@ namespace {
 // so every resident wavefront helps).
 constexpr uint32_t kDefaultWindow = 64;
 
-uint32_t default_wgs_per_cu() {
+uint32_t default_wgs_per_cu(const scan_table* t, bool shared) {
   int occ = 0;
-  if (query_scan_occupancy(&occ) != hipSuccess || occ < 1) return 2u;
+  const hipError_t e = shared ? query_shared_occupancy(&occ, t->stage_words) : query_scan_occupancy(&occ);
+  if (e != hipSuccess || occ < 1) return 2u;
   return (uint32_t)std::min(occ, 16);
+}
+
+// The shared-decode kernel keeps a bit per table column and one block of
+// every column in LDS: tables of at most 64 columns whose blocks fit 64 KiB.
+bool use_shared(const scan_table* t, uint32_t kernel) {
+  return kernel == SCAN_QUERY_SHARED && t->n_cols <= kSharedMaxCols && t->stage_words <= kSharedMaxStageWords;
 }
 
 double now_us() {
@@ -82,6 +90,8 @@ scan_status check_config(scan_ctx* ctx, const scan_server_config* c) {
   if (c->max_batch > (1u << 20)) return fail(ctx, SCAN_EINVAL, "max_batch is at most 2^20");
   if (c->window_blocks > 64) return fail(ctx, SCAN_EINVAL, "window_blocks is at most 64");
   if (c->wgs_per_cu > 16) return fail(ctx, SCAN_EINVAL, "wgs_per_cu is at most 16");
+  if (c->kernel != SCAN_QUERY_SHARED && c->kernel != SCAN_QUERY_PER_QUERY)
+    return fail(ctx, SCAN_EINVAL, "kernel must be SCAN_QUERY_SHARED or SCAN_QUERY_PER_QUERY");
   return SCAN_OK;
 }
 
@@ -134,8 +144,11 @@ struct BatchSlot {
   }
 };
 
-// Enqueue setup + scan + result copy of slot.q_host[0..nq) on `st`.
-hipError_t enqueue_queries(const scan_table* t, BatchSlot& s, uint32_t nq, uint32_t G, uint32_t grid, hipStream_t st) {
+// Enqueue setup + scan + result copy of slot.q_host[0..nq) on `st`.  The
+// shared-decode kernel runs the queries in launches of at most 64; its grid
+// is capped by the number of windows.
+hipError_t enqueue_queries(const scan_table* t, BatchSlot& s, uint32_t nq, uint32_t G, uint32_t grid, bool shared,
+                           hipStream_t st) {
   hipError_t e = hipMemcpyAsync(s.q_dev, s.q_host, sizeof(QDesc) * nq, hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return e;
   QArgs a;
@@ -148,8 +161,24 @@ hipError_t enqueue_queries(const scan_table* t, BatchSlot& s, uint32_t nq, uint3
   a.n = t->n;
   a.nb = t->nb;
   a.items = ((t->nb + G - 1) / G) * (uint64_t)nq;
+  a.stage_words = t->stage_words;
+  a.pad = 0;
   if ((e = launch_query_setup(a, st)) != hipSuccess) return e;
-  if ((e = launch_query_scan(a, grid, st)) != hipSuccess) return e;
+  if (shared) {
+    const uint64_t windows = (t->nb + G - 1) / G;
+    const uint32_t g = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(grid, windows));
+    for (uint32_t off = 0; off < nq && e == hipSuccess; off += kSharedMaxQueries) {
+      QArgs c = a;
+      c.q = s.q_dev + off;
+      c.out = s.out_dev + off;
+      c.nq = std::min(kSharedMaxQueries, nq - off);
+      c.items = windows;
+      e = launch_query_shared(c, g, st);
+    }
+  } else {
+    e = launch_query_scan(a, grid, st);
+  }
+  if (e != hipSuccess) return e;
   return hipMemcpyAsync(s.out_host, s.out_dev, sizeof(QOut) * nq, hipMemcpyDeviceToHost, st);
 }
 
@@ -168,6 +197,7 @@ struct scan_server {
   const scan_table* table = nullptr;
   Policy pol;
   uint32_t grid = 0, G = 16;
+  bool shared = true;
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> done_ev;
   std::vector<BatchSlot> slots;
@@ -232,7 +262,7 @@ void scan_server::loop() {
           pending.pop_front();
           sl.q_host[i] = make_desc(running[s].back().q);
         }
-        hipError_t e = enqueue_queries(table, sl, n, G, grid, streams[s]);
+        hipError_t e = enqueue_queries(table, sl, n, G, grid, shared, streams[s]);
         if (e == hipSuccess) e = hipEventRecord(done_ev[s], streams[s]);
         if (e != hipSuccess && dev_err == hipSuccess) dev_err = e;
         ++batches;
@@ -275,7 +305,15 @@ scan_status scan_table_create(scan_ctx* ctx, const scan_table_column* cols, uint
     q.enc = (uint32_t)c.enc;
     q.dict_len = c.col.dict_len;
   }
+  // staging slots of the shared-decode kernel: 32 b words then a spill word,
+  // rounded to 16 bytes, one slot per column
+  uint64_t off = 0;
+  for (uint32_t i = 0; i < n_cols; ++i) {
+    qc[i].stage_off = (uint32_t)std::min<uint64_t>(off, 0xFFFFFFFFu);
+    off += 32u * (uint64_t)qc[i].b + 4u;
+  }
   scan_table* t = new scan_table();
+  t->stage_words = (uint32_t)std::min<uint64_t>(off, 0xFFFFFFFFu);
   t->device = ctx->device;
   t->n = n;
   t->nb = (n + SCAN_BLOCK_VALUES - 1) / SCAN_BLOCK_VALUES;
@@ -311,7 +349,9 @@ scan_status scan_query_run(scan_ctx* ctx, const scan_table* t, const scan_query*
   }
   const auto tit = ctx->tunes.find(std::make_tuple((int32_t)-2, 0u, (int32_t)-1));
   const scan_tune tn = tit != ctx->tunes.end() ? tit->second : scan_tune{0, 0, 0, 0};
-  const uint32_t G = tn.window_blocks > 0 ? (uint32_t)std::min(tn.window_blocks, 64) : kDefaultWindow;
+  const bool shared = use_shared(t, (uint32_t)tn.reserved);
+  const uint32_t G = tn.window_blocks > 0 ? (uint32_t)std::min(tn.window_blocks, shared ? 32 : 64)
+                                          : (shared ? kSharedWindow : kDefaultWindow);
   if (((t->nb + G - 1) / G) * (uint64_t)n >= (1ull << 31)) return fail(ctx, SCAN_EINVAL, "too many work items");
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
@@ -324,8 +364,8 @@ scan_status scan_query_run(scan_ctx* ctx, const scan_table* t, const scan_query*
   for (size_t i = 0; i < n; ++i) s.q_host[i] = make_desc(queries[i]);
   const double t0 = now_us();
   const uint32_t grid = (uint32_t)ctx->cus * (tn.wgs_per_cu > 0 ? (uint32_t)std::min(tn.wgs_per_cu, 16)
-                                                                   : default_wgs_per_cu());
-  e = enqueue_queries(t, s, (uint32_t)n, G, grid, ctx->stream);
+                                                                   : default_wgs_per_cu(t, shared));
+  e = enqueue_queries(t, s, (uint32_t)n, G, grid, shared, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   const double t1 = now_us();
   if (e == hipSuccess)
@@ -345,11 +385,24 @@ scan_status scan_query_run(scan_ctx* ctx, const scan_table* t, const scan_query*
   return e == hipSuccess ? SCAN_OK : hip_fail(ctx, e, "query scan");
 }
 
+// The query kernel's tuning is kept under (enc -2, b 0, strategy -1); its
+// `reserved` field holds the kernel choice.
 scan_status scan_query_set_tune(scan_ctx* ctx, int32_t wgs_per_cu, int32_t window_blocks) {
   if (!ctx) return SCAN_EINVAL;
   if (wgs_per_cu < 0 || wgs_per_cu > 16 || window_blocks < 0 || window_blocks > 64)
     return fail(ctx, SCAN_EINVAL, "wgs_per_cu in 0..16, window_blocks in 0..64");
-  ctx->tunes[std::make_tuple((int32_t)-2, 0u, (int32_t)-1)] = scan_tune{0, wgs_per_cu, window_blocks, 0};
+  scan_tune& t = ctx->tunes[std::make_tuple((int32_t)-2, 0u, (int32_t)-1)];
+  t.wg_size = 0;
+  t.wgs_per_cu = wgs_per_cu;
+  t.window_blocks = window_blocks;
+  return SCAN_OK;
+}
+
+scan_status scan_query_set_kernel(scan_ctx* ctx, int32_t kernel) {
+  if (!ctx) return SCAN_EINVAL;
+  if (kernel != SCAN_QUERY_SHARED && kernel != SCAN_QUERY_PER_QUERY)
+    return fail(ctx, SCAN_EINVAL, "kernel must be SCAN_QUERY_SHARED or SCAN_QUERY_PER_QUERY");
+  ctx->tunes[std::make_tuple((int32_t)-2, 0u, (int32_t)-1)].reserved = kernel;
   return SCAN_OK;
 }
 
@@ -359,7 +412,9 @@ scan_status scan_server_create(scan_ctx* ctx, const scan_table* t, const scan_se
   if (!t || !out) return fail(ctx, SCAN_EINVAL, "table and out must not be NULL");
   scan_status st = check_config(ctx, cfg);
   if (st != SCAN_OK) return st;
-  const uint32_t G = cfg->window_blocks ? cfg->window_blocks : kDefaultWindow;
+  const bool shared = use_shared(t, cfg->kernel);
+  const uint32_t G = cfg->window_blocks ? std::min(cfg->window_blocks, shared ? 32u : 64u)
+                                        : (shared ? kSharedWindow : kDefaultWindow);
   if (((t->nb + G - 1) / G) * (uint64_t)cfg->max_batch >= (1ull << 31))
     return fail(ctx, SCAN_EINVAL, "max_batch x windows exceeds 2^31 work items");
   *out = nullptr;
@@ -370,7 +425,8 @@ scan_status scan_server_create(scan_ctx* ctx, const scan_table* t, const scan_se
   s->table = t;
   s->pol.cfg = *cfg;
   s->G = G;
-  s->grid = (uint32_t)ctx->cus * (cfg->wgs_per_cu ? cfg->wgs_per_cu : default_wgs_per_cu());
+  s->shared = shared;
+  s->grid = (uint32_t)ctx->cus * (cfg->wgs_per_cu ? cfg->wgs_per_cu : default_wgs_per_cu(t, shared));
   const uint32_t ns = cfg->n_streams;
   s->streams.assign(ns, nullptr);
   s->done_ev.assign(ns, nullptr);

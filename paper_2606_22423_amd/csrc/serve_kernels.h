@@ -35,7 +35,8 @@ struct QCol {
   const int64_t* dict;   // dictionary entries
   const uint32_t* zmin;  // per-block min / max (values for FOR, codes for dictionary)
   const uint32_t* zmax;
-  uint32_t b, enc, dict_len, pad;
+  uint32_t b, enc, dict_len;
+  uint32_t stage_off;    // shared-decode kernel: word offset of this column's block in the LDS staging area
 };
 
 struct QDesc {
@@ -61,11 +62,38 @@ struct QArgs {
   uint32_t nq;
   uint32_t G;        // blocks per window (1..64)
   uint64_t n, nb;    // rows and blocks of the table
-  uint64_t items;    // windows x queries
+  uint64_t items;    // windows x queries (shared-decode kernel: windows)
+  uint32_t stage_words;  // shared-decode kernel: LDS words of the staging area (every column's block)
+  uint32_t pad;
 };
 
 hipError_t launch_query_setup(const QArgs& a, hipStream_t st);
 hipError_t launch_query_scan(const QArgs& a, uint32_t grid, hipStream_t st);
 hipError_t query_scan_occupancy(int* wgs_per_cu);
+
+// Shared-decode form: work item = a window of G blocks for every query of
+// the launch (at most kSharedMaxQueries; tables of at most kSharedMaxCols
+// columns whose blocks fit the staging area together).  Per block, a
+// work-group reads each column block that any surviving query needs once and
+// evaluates every query on it:
+//  1. zone maps: lane q of every wavefront tests its query's conjuncts on the
+//     window's blocks (a bit per block), so each block starts with a ballot of
+//     the queries that survive it (the same in every wavefront);
+//  2. the union of those queries' filter and SUM columns is staged in LDS,
+//     packed, at each column's fixed offset: one round of loads (eight
+//     columns' loads in flight at a time) and one barrier per block;
+//  3. the i-th surviving query runs on wavefront i mod 4, entirely: its
+//     conjuncts in order on the staged blocks (funnel-shift extraction, a
+//     16-bit row mask per lane, early out when no row is left), then its SUM
+//     column under the mask, into the work-group's accumulator of the query;
+//  4. at the end the work-group adds its accumulators to the result slots.
+// Every column block a batch needs is read from memory once per work-group
+// item instead of once per query; results are identical (integer sums).
+constexpr uint32_t kSharedMaxQueries = 64;
+constexpr uint32_t kSharedMaxCols = 64;
+constexpr uint32_t kSharedWindow = 8;
+constexpr uint32_t kSharedMaxStageWords = 16384;  // 64 KiB of LDS
+hipError_t launch_query_shared(const QArgs& a, uint32_t grid, hipStream_t st);
+hipError_t query_shared_occupancy(int* wgs_per_cu, uint32_t stage_words);
 
 }  // namespace scan_dev

@@ -33,6 +33,26 @@ __global__ __launch_bounds__(256) void query_setup_kernel(QArgs a) {
   d.empty = empty;
 }
 
+// Sum of the dictionary entries of a lane's selected rows (bit t of rows:
+// row lane + 64 t).  Every one of the 16 entries is loaded, an unselected row
+// reading entry 0, before any is added: the loads are in flight together
+// instead of one memory latency per selected row (codes index the dictionary,
+// clamped to its last entry).
+__device__ __forceinline__ uint64_t dict_sum_masked(const int64_t* dict, uint32_t dict_len, const Extract& ex,
+                                                    uint32_t rows) {
+  const uint32_t last = dict_len - 1u;
+  int64_t e[16];
+#pragma unroll
+  for (uint32_t t = 0; t < 16u; ++t) {
+    const uint32_t code = ((rows >> t) & 1u) ? ex(t) : 0u;
+    e[t] = dict[code < last ? code : last];
+  }
+  uint64_t sum = 0;
+#pragma unroll
+  for (uint32_t t = 0; t < 16u; ++t) sum += ((rows >> t) & 1u) ? (uint64_t)e[t] : 0ull;
+  return sum;
+}
+
 // At most 64 VGPRs (the occupancy hint), so that eight work-groups (32
 // wavefronts, the most a CU holds) are resident: the kernel waits on
 // dependent loads and every resident wavefront hides latency.
@@ -98,12 +118,7 @@ __global__ __launch_bounds__(256, 8) void query_scan_kernel(const QArgs a) {
       const uint32_t nsel = (uint32_t)__builtin_popcount(rows);
       lcount += nsel;
       if (s.enc == ENC_DICT) {
-        const uint32_t last = s.dict_len - 1u;  // codes index the dictionary (clamped)
-        for (uint32_t t = 0; t < 16u; ++t)
-          if ((rows >> t) & 1u) {
-            const uint32_t code = ex(t);
-            lsum += (uint64_t)s.dict[code < last ? code : last];
-          }
+        lsum += dict_sum_masked(s.dict, s.dict_len, ex, rows);
       } else {
         uint64_t part = 0;
 #pragma unroll
@@ -121,6 +136,183 @@ __global__ __launch_bounds__(256, 8) void query_scan_kernel(const QArgs a) {
       atomicAdd(reinterpret_cast<unsigned long long*>(&o->blocks), (unsigned long long)blocks);
     }
   }
+}
+
+__device__ __forceinline__ uint64_t wave_or_u64(uint64_t x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const uint32_t lo = __shfl_xor((uint32_t)x, o, 64);
+    const uint32_t hi = __shfl_xor((uint32_t)(x >> 32), o, 64);
+    x |= ((uint64_t)hi << 32) | lo;
+  }
+  return x;
+}
+
+// Stage block k of every column in `need` into its slot of the LDS staging
+// area (32 b words at cols[c].stage_off, then a zero spill word for the
+// funnel shift of the block's last code), and each staged FOR column's block
+// reference into col_ref.  Columns go in groups of eight: the group's loads
+// are all issued before any store, so eight loads are in flight per thread.
+__device__ __forceinline__ void stage_columns(uint32_t* stage, uint32_t* col_ref, const QCol* cols, uint64_t need,
+                                              uint64_t k) {
+  const uint32_t tid = threadIdx.x;
+  while (need) {
+    uint32_t cs[8];
+    bool on[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      on[i] = need != 0ull;
+      cs[i] = on[i] ? (uint32_t)__builtin_ctzll(need) : 0u;
+      need &= need - (on[i] ? 1ull : 0ull);
+    }
+    uint4 r[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      r[i] = make_uint4(0u, 0u, 0u, 0u);
+      if (on[i]) {
+        const QCol& c = cols[cs[i]];
+        if (tid < 8u * c.b) r[i] = reinterpret_cast<const uint4*>(c.payload + k * (32u * c.b))[tid];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (on[i]) {
+        const QCol& c = cols[cs[i]];
+        if (tid < 8u * c.b) reinterpret_cast<uint4*>(stage + c.stage_off)[tid] = r[i];
+        if (tid == 0) {
+          stage[c.stage_off + 32u * c.b] = 0u;
+          col_ref[cs[i]] = (c.enc != ENC_DICT && c.refs) ? c.refs[k] : 0u;
+        }
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void query_shared_kernel(const QArgs a) {
+  extern __shared__ __align__(16) uint32_t stage[];
+  __shared__ uint64_t acc_count[kSharedMaxQueries], acc_sum[kSharedMaxQueries];
+  __shared__ uint32_t col_ref[kSharedMaxCols];
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  // lane q of every wavefront holds query q
+  const uint32_t ql = lane < a.nq ? lane : 0u;
+  const QDesc& dq = a.q[ql];
+  const bool has_q = lane < a.nq && !dq.empty;
+  const uint32_t nf = has_q ? dq.nf : 0u;
+  uint32_t fcol[kQueryMaxFilters];
+  int64_t flo[kQueryMaxFilters], fhi[kQueryMaxFilters];
+  uint64_t need_bits = 0;
+#pragma unroll
+  for (int f = 0; f < kQueryMaxFilters; ++f) {
+    fcol[f] = (uint32_t)f < nf ? dq.col[f] : 0u;
+    flo[f] = dq.zlo[f];
+    fhi[f] = dq.zhi[f];
+    if ((uint32_t)f < nf) need_bits |= 1ull << fcol[f];
+  }
+  const uint32_t scol = dq.sum_col;
+  if (has_q) need_bits |= 1ull << scol;
+  for (uint32_t i = threadIdx.x; i < kSharedMaxQueries; i += blockDim.x) {
+    acc_count[i] = 0;
+    acc_sum[i] = 0;
+  }
+  uint64_t blocks_acc = 0;  // wavefront 0, lane q: blocks that survive query q's zone maps
+  for (uint64_t w = blockIdx.x; w < a.items; w += gridDim.x) {
+    const uint64_t k0 = w * a.G;
+    const uint32_t cnt = (uint32_t)((a.nb - k0) < a.G ? (a.nb - k0) : a.G);
+    // 1. zone maps: bit j of live = block k0 + j meets every conjunct
+    uint32_t live = has_q ? (cnt >= 32u ? ~0u : ((1u << cnt) - 1u)) : 0u;
+#pragma unroll
+    for (int f = 0; f < kQueryMaxFilters; ++f) {
+      if ((uint32_t)f >= nf) continue;
+      const QCol& c = a.cols[fcol[f]];
+      for (uint32_t j = 0; j < cnt; ++j) {
+        const int64_t mn = c.zmin[k0 + j], mx = c.zmax[k0 + j];
+        if (mx < flo[f] || mn >= fhi[f]) live &= ~(1u << j);
+      }
+    }
+    if (wave == 0) blocks_acc += (uint64_t)__builtin_popcount(live);
+    for (uint32_t j = 0; j < cnt; ++j) {
+      const uint64_t qmask = ballot((live >> j) & 1u);
+      if (qmask == 0) continue;  // uniform: every wavefront holds the same masks
+      const uint64_t k = k0 + j;
+      const uint32_t valid = (k == a.nb - 1) ? (uint32_t)(a.n - k * kBlockValues) : kBlockValues;
+      uint32_t vrows = 0;
+      for (uint32_t t = 0; t < 16u; ++t) vrows |= (lane + 64u * t < valid) ? (1u << t) : 0u;
+      const bool lq = (qmask >> lane) & 1ull;
+      const uint64_t need = wave_or_u64(lq ? need_bits : 0ull);
+      // 2. stage the block of every column a surviving query needs
+      __syncthreads();  // every wavefront is done with the previous block's staging
+      stage_columns(stage, col_ref, a.cols, need, k);
+      __syncthreads();
+      // 3. the i-th surviving query on wavefront i mod nw, conjuncts then SUM
+      uint32_t idx = 0;
+      for (uint64_t m = qmask; m; m &= m - 1, ++idx) {
+        if (idx % nw != wave) continue;
+        const int q = (int)__builtin_ctzll(m);
+        const uint32_t nfq = readlane(nf, q);
+        uint32_t rows = vrows;
+#pragma unroll
+        for (int f = 0; f < kQueryMaxFilters; ++f) {
+          if ((uint32_t)f >= nfq) break;
+          const uint32_t ci = readlane(fcol[f], q);
+          const QCol& c = a.cols[ci];
+          int64_t clo = (int64_t)readlane64((uint64_t)flo[f], q), chi = (int64_t)readlane64((uint64_t)fhi[f], q);
+          if (c.enc != ENC_DICT) {
+            const int64_t ref = (int64_t)col_ref[ci];
+            const int64_t top = int64_t(1) << c.b;
+            clo = clo - ref > 0 ? clo - ref : 0;
+            chi = chi - ref < top ? chi - ref : top;
+          }
+          if (clo >= chi) {
+            rows = 0u;
+            break;
+          }
+          const Extract ex(stage + c.stage_off, lane, c.b);
+          const uint32_t lo32 = (uint32_t)clo, wm1 = (uint32_t)(chi - clo - 1);
+          uint32_t keep = 0;
+#pragma unroll
+          for (uint32_t t = 0; t < 16u; ++t) keep |= ((ex(t) - lo32) <= wm1) ? (1u << t) : 0u;
+          rows &= keep;
+          if (!ballot(rows != 0u)) break;
+        }
+        if (!ballot(rows != 0u)) continue;
+        const uint32_t si = readlane(scol, q);
+        const QCol& s = a.cols[si];
+        const Extract ex(stage + s.stage_off, lane, s.b);
+        const uint32_t nsel = (uint32_t)__builtin_popcount(rows);
+        uint64_t lsum = 0;
+        if (s.enc == ENC_DICT) {
+          lsum += dict_sum_masked(s.dict, s.dict_len, ex, rows);
+        } else {
+#pragma unroll
+          for (uint32_t t = 0; t < 16u; ++t) lsum += ((rows >> t) & 1u) ? (uint64_t)ex(t) : 0ull;
+          lsum += (uint64_t)col_ref[si] * nsel;
+        }
+        const uint64_t tc = wave_sum_u64(nsel), ts = wave_sum_u64(lsum);
+        if (lane == 0) {
+          acc_count[q] += tc;
+          acc_sum[q] += ts;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (wave == 0 && has_q && blocks_acc)
+    atomicAdd(reinterpret_cast<unsigned long long*>(&a.out[lane].blocks), (unsigned long long)blocks_acc);
+  for (uint32_t i = threadIdx.x; i < a.nq; i += blockDim.x) {
+    if (acc_count[i]) atomicAdd(reinterpret_cast<unsigned long long*>(&a.out[i].count), (unsigned long long)acc_count[i]);
+    if (acc_sum[i]) atomicAdd(reinterpret_cast<unsigned long long*>(&a.out[i].sum), (unsigned long long)acc_sum[i]);
+  }
+}
+
+hipError_t query_shared_occupancy(int* wgs_per_cu, uint32_t stage_words) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(wgs_per_cu, query_shared_kernel, 256, stage_words * 4u);
+}
+
+hipError_t launch_query_shared(const QArgs& a, uint32_t grid, hipStream_t st) {
+  if (a.items == 0 || a.nq == 0) return hipSuccess;
+  if (a.stage_words > kSharedMaxStageWords) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(query_shared_kernel, dim3(grid), dim3(256), a.stage_words * 4u, st, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_query_setup(const QArgs& a, hipStream_t st) {

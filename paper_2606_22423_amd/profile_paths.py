@@ -152,16 +152,22 @@ def main(argv=None):
             del vals
         table = serve.Table(ctx, tcols)
         qs = synth.config5_queries(64, spec, 1.0, dicts, seed_stream=11)
-        res = table.run([(q.filters, q.sum_col) for q in qs])
-        ms = timed(lambda: table.run([(q.filters, q.sum_col) for q in qs]))
-        byt = 0
-        for q, r in zip(qs, res):
-            touched = {f[0] for f in q.filters} | {q.sum_col}
-            byt += r["blocks_read"] * sum(128 * spec[j].b for j in touched)
-            byt += 8 * (n // 1024) * len(q.filters)
-        cases.append({"name": "serving query batch (64 queries, 16 x 2^%d rows)" % args.n_log2,
-                      "kernel": r"query_scan_kernel", "launches": args.launches + 1, "warmup": 1, "algorithmic_bytes": int(byt),
-                      "values": int(sum(r["blocks_read"] for r in res) * 1024), "event_ms": ms})
+        for kern, kname, rx in ((serve.PER_QUERY, "per-query", r"query_scan_kernel"),
+                                (serve.SHARED, "shared-decode", r"query_shared_kernel")):
+            ctx.lib.scan_query_set_kernel(ctx.h, kern)
+            res = table.run([(q.filters, q.sum_col) for q in qs])
+            ms = timed(lambda: table.run([(q.filters, q.sum_col) for q in qs]))
+            # per query: the blocks of every column it touches that no conjunct's
+            # zone map excludes, plus its conjuncts' zone maps (no sharing counted)
+            byt = 0
+            for q, r in zip(qs, res):
+                touched = {f[0] for f in q.filters} | {q.sum_col}
+                byt += r["blocks_read"] * sum(128 * spec[j].b for j in touched)
+                byt += 8 * (n // 1024) * len(q.filters)
+            cases.append({"name": "serving query batch, %s kernel (64 queries, 16 x 2^%d rows)" % (kname, args.n_log2),
+                          "kernel": rx, "launches": args.launches + 1, "warmup": 1, "algorithmic_bytes": int(byt),
+                          "values": int(sum(r["blocks_read"] for r in res) * 1024), "event_ms": ms})
+        ctx.lib.scan_query_set_kernel(ctx.h, serve.SHARED)
         table.close()
         del tcols
         say("serving done")

@@ -433,3 +433,33 @@ def test_selector_rejects_bad_parameters(ctx, tmp_path):
     with pytest.raises(_lib.ScanError):
         ctx.selector_load(str(p))
     assert not ctx.selector_loaded
+
+
+def test_batch_1024_columns_up_to_2p22_matches_oracle(ctx):
+    """A 1024-column batch shaped like the mixed workload, lengths log-uniform
+    in [2^10, 2^22] (work items of many windows, dictionary columns spanning
+    many items), every item against the oracle, with the selector's
+    batch parameters choosing on the device and with the default strategy."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    specs = synth.config4_specs(1024, seed=synth.SEED_BASE + 60, log2_min=10.0, log2_max=22.0)
+    with ThreadPoolExecutor(16) as ex:
+        cases = list(ex.map(Case, specs))
+    say("1024-column batch: %d values" % sum(s.n for s in specs))
+    default = strategy(DEC_RM_DIRECT, 0, 1)
+    for sel in (None, os.path.join(os.path.dirname(api.__file__), "selector_batch_mi355x.txt")):
+        items = [c.col.item(c.lo, c.hi, -1 if sel else default) for c in cases]
+        if sel:
+            ctx.selector_load(sel)
+        try:
+            res = ctx.batch_run(items)
+        finally:
+            ctx.selector_clear()
+
+        def verify(pair):
+            c, got = pair
+            check_item(c, got, c.lo, c.hi, (c.spec.index, c.spec.enc, c.spec.b, c.spec.n, sel is not None))
+            return True
+
+        with ThreadPoolExecutor(16) as ex:
+            assert all(ex.map(verify, zip(cases, res)))

@@ -96,30 +96,74 @@ def check(w, q, got):
     assert got["blocks_read"] == blocks_read(w, filters), (q, got)
 
 
-def test_batch_of_queries_matches_oracle(world):
-    say("queries:", len(world["queries"]))
+KERNELS = [serve.SHARED, serve.PER_QUERY]
+
+
+@pytest.fixture(params=KERNELS, ids=["shared", "per_query"])
+def kernel(ctx, request):
+    assert ctx.lib.scan_query_set_kernel(ctx.h, request.param) == 0
+    yield request.param
+    ctx.lib.scan_query_set_kernel(ctx.h, serve.SHARED)
+
+
+def test_batch_of_queries_matches_oracle(world, kernel):
+    say("queries:", len(world["queries"]), "kernel", kernel)
     res = world["table"].run(world["queries"])
     for q, got in zip(world["queries"], res):
         check(world, q, got)
 
 
-def test_each_result_is_the_same_alone_and_in_the_mix(world):
+def test_each_result_is_the_same_alone_and_in_the_mix(world, kernel):
     mix = world["table"].run(world["queries"])
     for q, m in zip(world["queries"][:40], mix[:40]):
         alone = world["table"].run([q])[0]
         assert (alone["count"], alone["sum"], alone["blocks_read"]) == (m["count"], m["sum"], m["blocks_read"])
 
 
-def test_launch_shape_does_not_change_results(ctx, world):
-    base = world["table"].run(world["queries"][:30])
+def test_launch_shape_does_not_change_results(ctx, world, kernel):
+    base = world["table"].run(world["queries"][:70])
     try:
-        for per_cu, win in ((1, 1), (4, 7), (8, 64)):
+        for per_cu, win in ((1, 1), (4, 7), (8, 32)):
             ctx.lib.scan_query_set_tune(ctx.h, per_cu, win)
-            got = world["table"].run(world["queries"][:30])
+            got = world["table"].run(world["queries"][:70])
             assert [(g["count"], g["sum"], g["blocks_read"]) for g in got] == \
                 [(b["count"], b["sum"], b["blocks_read"]) for b in base]
     finally:
         ctx.lib.scan_query_set_tune(ctx.h, 0, 0)
+
+
+def test_kernel_choice_errors(ctx):
+    assert ctx.lib.scan_query_set_kernel(ctx.h, 2) == _lib.SCAN_EINVAL
+    assert ctx.lib.scan_query_set_kernel(ctx.h, -1) == _lib.SCAN_EINVAL
+
+
+def test_queries_at_2p22_rows_match_oracle(ctx):
+    """The serving workload's table and queries at 2^22 rows (16 columns,
+    widths 4..20, FOR and dictionary, half clustered): every result of a
+    64-query batch equals the oracle, with both kernels."""
+    n = 1 << 22
+    spec = synth.config5_table(16)
+    cols, ocols, dicts = [], [], {}
+    for tc in spec:
+        vals, dct = synth.config5_column(tc, n)
+        cols.append(api.encode_for(vals, tc.b) if tc.enc == 0 else api.encode_dict(vals, tc.b, dct))
+        if tc.enc != 0:
+            dicts[tc.index] = dct
+        ocols.append({"enc": tc.enc, "b": tc.b, "payload": oracle.pack_rm(vals, tc.b), "refs": None, "dict": dct})
+    table = serve.Table(ctx, cols)
+    try:
+        qs = synth.config5_queries(64, spec, 1000.0, dicts, seed_stream=31)
+        queries = [(q.filters, q.sum_col) for q in qs]
+        wants = [oracle.query(ocols, n, f, s) for f, s in queries]
+        for k in KERNELS:
+            assert ctx.lib.scan_query_set_kernel(ctx.h, k) == 0
+            say("2^22-row table, kernel", k)
+            got = table.run(queries)
+            for q, g, r in zip(queries, got, wants):
+                assert (g["count"], g["sum"]) == (r.count, r.sum), (k, q, g, r)
+    finally:
+        ctx.lib.scan_query_set_kernel(ctx.h, serve.SHARED)
+        table.close()
 
 
 def test_invalid_queries_are_rejected(world):
@@ -129,9 +173,10 @@ def test_invalid_queries_are_rejected(world):
         world["table"].run([([], 0)])
 
 
-def test_server_results_match_oracle(ctx, world):
+@pytest.mark.parametrize("kern", KERNELS, ids=["shared", "per_query"])
+def test_server_results_match_oracle(ctx, world, kern):
     srv = serve.Server(ctx, world["table"], serve.config(max_inflight=16, n_streams=2, max_batch=8,
-                                                         batch_window_us=100))
+                                                         batch_window_us=100, kernel=kern))
     try:
         tickets, results, busy = {}, {}, 0
         t0 = time.time()
