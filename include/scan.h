@@ -140,15 +140,20 @@ typedef struct {
 } scan_item;
 
 /* Launch tuning of one (encoding, width, strategy): work-group size (64, 128,
- * 192 or 256), work-groups per compute unit (0 = as many as fit), and the
+ * 192 or 256), work-groups per compute unit (0 = as many as fit), the
  * window: wavefronts take grid-strided windows of this many consecutive
- * blocks (1..64; 0 = one pipelined decode step).  Zero fields mean "library
+ * blocks (1..64; 0 = one pipelined decode step), and the step depth (values
+ * each wavefront has in flight per pipelined step): 0 the default, 1 the
+ * alternative depth of the branch-free frame-of-reference kernels of the
+ * register decoders (SCAN_DEC_RM_DIRECT, SCAN_DEC_LI) without block
+ * references: half as many block pairs per step below b = 16, one pair more
+ * from b = 16 on; other kernels ignore it.  Zero fields mean "library
  * default". */
 typedef struct {
   int32_t wg_size;
   int32_t wgs_per_cu;
   int32_t window_blocks;
-  int32_t reserved;
+  int32_t depth;
 } scan_tune;
 
 /* ---------------------------------------------------------------- context */
@@ -210,7 +215,8 @@ scan_status scan_get_tune(scan_ctx* ctx, int32_t enc, uint32_t b, int32_t strate
 
 /* Autotuner: times every launch configuration of a small grid (work-group
  * size {64,128,256} x work-groups per CU {1,2,4,8} x window {2,4,8,16,64}
- * blocks) for one column and strategy, median of `reps` runs each with HIP events on
+ * blocks x step depth {0, 1} where the kernel has the alternative depth) for
+ * one column and strategy, median of `reps` runs each with HIP events on
  * the context stream (a 512 MiB read before each run keeps the column out of
  * the 256 MB last-level cache), and keeps the fastest with scan_set_tune.
  * *out (host, may be NULL) receives it, *ms_out (may be NULL) its time in ms.
@@ -448,7 +454,7 @@ typedef struct {
   uint32_t batch_window_us;
   uint32_t window_blocks;
   uint32_t wgs_per_cu;
-  uint32_t kernel;            /* SCAN_QUERY_SHARED (0, default) or SCAN_QUERY_PER_QUERY (1) */
+  uint32_t kernel;            /* SCAN_QUERY_PER_QUERY (0, default) or SCAN_QUERY_SHARED (1) */
   uint32_t reserved;
 } scan_server_config;
 
@@ -465,15 +471,19 @@ scan_status scan_query_run(scan_ctx* ctx, const scan_table* t, const scan_query*
  * per-query kernel, 8 for the shared one; as many work-groups per CU as fit). */
 scan_status scan_query_set_tune(scan_ctx* ctx, int32_t wgs_per_cu, int32_t window_blocks);
 /* Which query kernel scan_query_run uses (the server takes it from its config):
- *  SCAN_QUERY_SHARED (default): a work item is a window of blocks for every
- *    query of the batch; each column block that any query still needs is
- *    decoded once into LDS and evaluated for all of them (tables of at most
- *    64 columns; batches run 64 queries per launch);
- *  SCAN_QUERY_PER_QUERY: a work item is (window, query); each query decodes
- *    the blocks it needs itself.
- * Same results.  Other values -> SCAN_EINVAL.  A table of more than 64
- * columns always runs the per-query kernel. */
-enum { SCAN_QUERY_SHARED = 0, SCAN_QUERY_PER_QUERY = 1 };
+ *  SCAN_QUERY_PER_QUERY (default): a work item is (window, query); each query
+ *    stages the blocks it needs itself, and the window-major item order lets
+ *    the queries of a batch share column reads through the caches;
+ *  SCAN_QUERY_SHARED: a work item is a window of blocks for every query of
+ *    the batch; per block, every column block that any surviving query needs
+ *    is read once into LDS and all of them are evaluated on it (tables of at
+ *    most 64 columns whose blocks fit 64 KiB together; 64 queries per
+ *    launch).  It reads 3.3x fewer bytes but measured slower on MI355X
+ *    (10.9 against 6.0 ms for 64 queries on 16 x 2^28 rows): each wavefront
+ *    runs its share of the queries one after another between two barriers.
+ * Same results.  Other values -> SCAN_EINVAL.  A table the shared kernel
+ * cannot hold always runs the per-query kernel. */
+enum { SCAN_QUERY_PER_QUERY = 0, SCAN_QUERY_SHARED = 1 };
 scan_status scan_query_set_kernel(scan_ctx* ctx, int32_t kernel);
 
 /* Start a server on the context's device (its own host thread and streams;

@@ -68,7 +68,7 @@ class ScanItem(ctypes.Structure):
 
 class ScanTune(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
-                ("window_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("window_blocks", ctypes.c_int32), ("depth", ctypes.c_int32)]
 
 
 class ScanBatchStats(ctypes.Structure):

@@ -278,24 +278,25 @@ class Context:
     def sync(self):
         self.check(self.lib.scan_sync(self.h), "scan_sync")
 
-    def set_tune(self, enc: int, b: int, strategy: int, wg_size=0, wgs_per_cu=0, window_blocks=0):
-        t = ScanTune(wg_size, wgs_per_cu, window_blocks, 0)
+    def set_tune(self, enc: int, b: int, strategy: int, wg_size=0, wgs_per_cu=0, window_blocks=0, depth=0):
+        t = ScanTune(wg_size, wgs_per_cu, window_blocks, depth)
         self.check(self.lib.scan_set_tune(self.h, enc, b, strategy, ctypes.byref(t)), "scan_set_tune")
 
     def get_tune(self, enc: int, b: int, strategy: int) -> tuple:
+        """(wg_size, wgs_per_cu, window_blocks, depth) as the scan will use it."""
         t = ScanTune()
         self.check(self.lib.scan_get_tune(self.h, enc, b, strategy, ctypes.byref(t)), "scan_get_tune")
-        return (t.wg_size, t.wgs_per_cu, t.window_blocks)
+        return (t.wg_size, t.wgs_per_cu, t.window_blocks, t.depth)
 
     def autotune(self, col: Column, lo: int, hi: int, strategy: int, reps: int = 3, zone_maps: bool = True):
-        """Exhaustive launch-configuration search; returns ((wg, per_cu, window), best ms)."""
+        """Exhaustive launch-configuration search; returns ((wg, per_cu, window, depth), best ms)."""
         c = col.struct(zone_maps)
         t = ScanTune()
         ms = ctypes.c_float()
         pred = ScanPredicate(int(lo), int(hi))
         self.check(self.lib.scan_autotune(self.h, ctypes.byref(c), col.enc, col.b, ctypes.byref(pred), strategy,
                                           reps, ctypes.byref(t), ctypes.byref(ms)), "scan_autotune")
-        return (t.wg_size, t.wgs_per_cu, t.window_blocks), float(ms.value)
+        return (t.wg_size, t.wgs_per_cu, t.window_blocks, t.depth), float(ms.value)
 
     def tune_save(self, path: str):
         self.check(self.lib.scan_tune_save(self.h, path.encode()), "scan_tune_save")

@@ -133,9 +133,9 @@ __device__ __forceinline__ void batch_item(const Params& p, const BatchCol& c, u
     s.ring = st + 32u * 32u + 4u;
     const uint32_t dlast = c.dict_len ? c.dict_len - 1u : 0u;
     if (ENC == ENC_FOR && c.refs)
-      scan_range<B, DEC, MODE, ENC, PF_REFS, true>(p, s, lane, list, st, k0, k1, 64, 64, c.dict, dlast, c.clo, c.chi);
+      scan_range<B, DEC, MODE, ENC, PF_REFS, STEP_SMALL>(p, s, lane, list, st, k0, k1, 64, 64, c.dict, dlast, c.clo, c.chi);
     else
-      scan_range<B, DEC, MODE, ENC, PF_RANGE, true>(p, s, lane, list, st, k0, k1, 64, 64, c.dict, dlast, c.clo,
+      scan_range<B, DEC, MODE, ENC, PF_RANGE, STEP_SMALL>(p, s, lane, list, st, k0, k1, 64, 64, c.dict, dlast, c.clo,
                                                     c.chi);
     if constexpr (MODE == MODE_SV) sv_drain_rest<ENC, uint32_t>(s, lane, c.dict, dlast);
     count = s.count + wave_sum_u64(s.lcount);
@@ -184,7 +184,7 @@ __device__ __forceinline__ void dict_flush(WaveState<uint32_t>& s, uint32_t lane
 
 #define BATCH_DICT_CASE(B)                                                                                    \
   case B:                                                                                                     \
-    scan_range<B, DEC, MODE, ENC_DICT, PF_RANGE, true>(p, s, lane, list, st, w.k0 + b0, w.k0 + b1, 64, 64, dict, \
+    scan_range<B, DEC, MODE, ENC_DICT, PF_RANGE, STEP_SMALL>(p, s, lane, list, st, w.k0 + b0, w.k0 + b1, 64, 64, dict, \
                                                        dlast, c.clo, c.chi);                                  \
     break;
 

@@ -24,11 +24,24 @@ inline hipError_t launch_kernel(K kern, bool& attr_done, const Params& p, uint32
   return hipLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid), dim3(block), args, lds, st);
 }
 
-template <int B, int DEC, int MODE, int ENC, int PF>
+template <int B, int DEC, int MODE, int ENC, int PF, int STEP = STEP_DEFAULT>
 hipError_t launch_code(const Params& p, uint32_t grid, uint32_t block, hipStream_t st, int* occ) {
   static bool attr = false;
-  return launch_kernel(code_scan<B, DEC, MODE, ENC, PF>, attr, p, grid, block,
+  return launch_kernel(code_scan<B, DEC, MODE, ENC, PF, STEP>, attr, p, grid, block,
                        code_scan_lds<B, DEC, MODE, ENC>(block / 64u), st, occ);
+}
+
+// The alternative step depth exists for the register decoders' branch-free
+// frame-of-reference kernels without block references.
+template <int B, int DEC>
+LaunchFn pick_code_alt(int enc, int mode, int pf) {
+  if constexpr (DEC == DEC_RM_DIRECT || DEC == DEC_LI) {
+    if (enc == ENC_FOR && mode == MODE_BF) {
+      if (pf == PF_LO0) return &launch_code<B, DEC, MODE_BF, ENC_FOR, PF_LO0, STEP_ALT>;
+      if (pf == PF_RANGE) return &launch_code<B, DEC, MODE_BF, ENC_FOR, PF_RANGE, STEP_ALT>;
+    }
+  }
+  return nullptr;
 }
 
 template <int B, int DEC, int MODE>
@@ -83,6 +96,14 @@ LaunchFn code_fn_li_b(int enc, int mode, int pf, int b);
 LaunchFn code_fn_li_c(int enc, int mode, int pf, int b);
 LaunchFn code_fn_li_d(int enc, int mode, int pf, int b);
 LaunchFn code_fn_bytes(int enc, int mode, int pf, int b);
+LaunchFn code_fn_alt_rm_direct_a(int enc, int mode, int pf, int b);
+LaunchFn code_fn_alt_rm_direct_b(int enc, int mode, int pf, int b);
+LaunchFn code_fn_alt_rm_direct_c(int enc, int mode, int pf, int b);
+LaunchFn code_fn_alt_rm_direct_d(int enc, int mode, int pf, int b);
+LaunchFn code_fn_alt_li_a(int enc, int mode, int pf, int b);
+LaunchFn code_fn_alt_li_b(int enc, int mode, int pf, int b);
+LaunchFn code_fn_alt_li_c(int enc, int mode, int pf, int b);
+LaunchFn code_fn_alt_li_d(int enc, int mode, int pf, int b);
 LaunchFn delta_fn_rm_lds_a(int mode, int b);
 LaunchFn delta_fn_rm_lds_b(int mode, int b);
 LaunchFn delta_fn_rm_lds_c(int mode, int b);

@@ -46,6 +46,18 @@ namespace {
 // Width group of the instantiation units: 1-4, 5-8, 9-16, 17-32.
 int width_group(uint32_t b) { return b <= 4 ? 0 : b <= 8 ? 1 : b <= 16 ? 2 : 3; }
 
+// The alternative step depth's kernel, or nullptr where it does not exist.
+LaunchFn code_fn_alt(int enc, int dec, int mode, int pf, uint32_t b) {
+  static LaunchFn (*const direct[4])(int, int, int, int) = {code_fn_alt_rm_direct_a, code_fn_alt_rm_direct_b,
+                                                            code_fn_alt_rm_direct_c, code_fn_alt_rm_direct_d};
+  static LaunchFn (*const li[4])(int, int, int, int) = {code_fn_alt_li_a, code_fn_alt_li_b, code_fn_alt_li_c,
+                                                        code_fn_alt_li_d};
+  const int g = width_group(b);
+  if (dec == DEC_RM_DIRECT) return direct[g](enc, mode, pf, (int)b);
+  if (dec == DEC_LI) return li[g](enc, mode, pf, (int)b);
+  return nullptr;
+}
+
 LaunchFn code_fn(int enc, int dec, int mode, int pf, uint32_t b) {
   static LaunchFn (*const lds[4])(int, int, int, int) = {code_fn_rm_lds_a, code_fn_rm_lds_b, code_fn_rm_lds_c,
                                                          code_fn_rm_lds_d};
@@ -138,7 +150,7 @@ scan_tune default_tune(int32_t enc, uint32_t b, int32_t s) {
     t.wg_size = 256;
     t.wgs_per_cu = 4;
     t.window_blocks = 64;
-    t.reserved = 0;
+    t.depth = 0;
     return t;
   }
   // From the autotuner on MI355X (2^28-value columns, cold, branch-free):
@@ -155,7 +167,7 @@ scan_tune default_tune(int32_t enc, uint32_t b, int32_t s) {
   // With zone maps every window costs one dependent zone-map load and ballot
   // per wavefront: 64-block windows test 64 blocks per step.
   if (s >= 0 && ((s >> 3) & 1)) t.window_blocks = 64;
-  t.reserved = 0;
+  t.depth = 0;
   return t;
 }
 
@@ -166,6 +178,7 @@ scan_tune effective_tune(scan_ctx* ctx, int32_t enc, uint32_t b, int32_t s) {
     if (it->second.wg_size) t.wg_size = it->second.wg_size;
     if (it->second.wgs_per_cu) t.wgs_per_cu = it->second.wgs_per_cu;
     if (it->second.window_blocks) t.window_blocks = it->second.window_blocks;
+    if (it->second.depth) t.depth = it->second.depth;
   }
   return t;
 }
@@ -201,7 +214,7 @@ scan_status occupancy(scan_ctx* ctx, LaunchFn fn, uint32_t block, int* occ) {
 // launcher, or sets trivially_empty (n = 0, lo >= hi, or a predicate outside
 // a FOR column's u32 domain).  ctx may be null (messages are then dropped).
 scan_status scan_params(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b, const scan_predicate* pred,
-                        int32_t s, Partial* partials, Result* out_dev, Params& p, LaunchFn& fn,
+                        int32_t s, int32_t depth, Partial* partials, Result* out_dev, Params& p, LaunchFn& fn,
                         bool& trivially_empty) {
   const int dec = s & 3, mode = (s >> 2) & 1, zm = (s >> 3) & 1;
   std::memset(&p, 0, sizeof p);
@@ -238,9 +251,20 @@ scan_status scan_params(scan_ctx* ctx, const scan_column* col, int32_t enc, uint
     }
   }
   if (trivially_empty) return SCAN_OK;
-  fn = enc == SCAN_ENC_DELTA_FOR ? delta_fn(dec, mode, b) : code_fn(enc, dec, mode, pf, b);
+  fn = nullptr;
+  if (depth == 1 && enc != SCAN_ENC_DELTA_FOR) fn = code_fn_alt(enc, dec, mode, pf, b);
+  if (!fn) fn = enc == SCAN_ENC_DELTA_FOR ? delta_fn(dec, mode, b) : code_fn(enc, dec, mode, pf, b);
   if (!fn) return fail(ctx, SCAN_EUNSUPPORTED, "no kernel for enc %d b %u strategy %d", enc, b, s);
   return SCAN_OK;
+}
+
+// Whether the alternative step depth exists for this scan (its predicate
+// form included).
+bool has_alt_depth(const scan_column* col, int32_t enc, uint32_t b, const scan_predicate* pred, int32_t s) {
+  if (enc != SCAN_ENC_FOR || col->block_ref) return false;
+  const int64_t lo = std::max<int64_t>(pred->lo, 0);
+  const int pf = lo == 0 ? PF_LO0 : PF_RANGE;
+  return code_fn_alt(enc, s & 3, (s >> 2) & 1, pf, b) != nullptr;
 }
 
 // Launch geometry: p.G, p.units and the grid, from the tuning, the resident
@@ -263,9 +287,9 @@ void scan_geometry(Params& p, const scan_tune& t, int occ, int cus, uint32_t max
 scan_status prepare_scan(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b, const scan_predicate* pred,
                          int32_t s, Result* out_dev, Params& p, LaunchFn& fn, uint32_t& grid, uint32_t& block,
                          bool& trivially_empty) {
-  scan_status st = scan_params(ctx, col, enc, b, pred, s, ctx->partials, out_dev, p, fn, trivially_empty);
-  if (st != SCAN_OK || trivially_empty) return st;
   const scan_tune t = effective_tune(ctx, enc, b, s);
+  scan_status st = scan_params(ctx, col, enc, b, pred, s, t.depth, ctx->partials, out_dev, p, fn, trivially_empty);
+  if (st != SCAN_OK || trivially_empty) return st;
   block = (uint32_t)t.wg_size;
   if (block < 64 || block > 256 || block % 64) return fail(ctx, SCAN_EINVAL, "wg_size %u invalid (64..256)", block);
   int occ = 0;
@@ -485,6 +509,7 @@ scan_status scan_set_tune(scan_ctx* ctx, int32_t enc, uint32_t b, int32_t strate
   if (t->wgs_per_cu < 0 || t->wgs_per_cu > 64) return fail(ctx, SCAN_EINVAL, "wgs_per_cu must be in 0..64");
   if (t->wg_size > 256) return fail(ctx, SCAN_EINVAL, "wg_size above 256 is not supported");
   if (t->window_blocks < 0 || t->window_blocks > 64) return fail(ctx, SCAN_EINVAL, "window_blocks must be in 0..64");
+  if (t->depth < 0 || t->depth > 1) return fail(ctx, SCAN_EINVAL, "depth must be 0 or 1");
   ctx->tunes[std::make_tuple(enc, b, strategy)] = *t;
   return SCAN_OK;
 }
@@ -518,31 +543,32 @@ scan_status scan_autotune(scan_ctx* ctx, const scan_column* col, int32_t enc, ui
   static const int kWg[] = {64, 128, 256};
   static const int kPerCu[] = {1, 2, 4, 8};
   static const int kWin[] = {2, 4, 8, 16, 64};
+  const int depths = has_alt_depth(col, enc, b, pred, strategy) ? 2 : 1;
   float best_ms = 1e30f;
   scan_tune best = saved;
-  for (int wg : kWg)
-    for (int pc : kPerCu)
-      for (int win : kWin) {
-        scan_tune t{wg, pc, win, 0};
-        ctx->tunes[std::make_tuple(enc, b, strategy)] = t;
-        float ts[16];
-        const int r = std::min(reps, 16);
-        for (int i = 0; i < r; ++i) {
-          evict_caches(ctx);
-          hipEventRecord(e0, ctx->stream);
-          st = enqueue_scan(ctx, col, enc, b, pred, strategy, ctx->out_dev, nullptr);
-          hipEventRecord(e1, ctx->stream);
-          if (st != SCAN_OK) break;
-          hipEventSynchronize(e1);
-          hipEventElapsedTime(&ts[i], e0, e1);
-        }
-        if (st != SCAN_OK) break;
-        std::sort(ts, ts + r);
-        if (ts[r / 2] < best_ms) {
-          best_ms = ts[r / 2];
-          best = t;
-        }
-      }
+  constexpr int kShapes = 3 * 4 * 5;
+  for (int k = 0; k < depths * kShapes && st == SCAN_OK; ++k) {
+    const int shape = k % kShapes;
+    const scan_tune t{kWg[shape / 20], kPerCu[(shape / 5) % 4], kWin[shape % 5], k / kShapes};
+    ctx->tunes[std::make_tuple(enc, b, strategy)] = t;
+    float ts[16];
+    const int r = std::min(reps, 16);
+    for (int i = 0; i < r && st == SCAN_OK; ++i) {
+      evict_caches(ctx);
+      hipEventRecord(e0, ctx->stream);
+      st = enqueue_scan(ctx, col, enc, b, pred, strategy, ctx->out_dev, nullptr);
+      hipEventRecord(e1, ctx->stream);
+      if (st != SCAN_OK) break;
+      hipEventSynchronize(e1);
+      hipEventElapsedTime(&ts[i], e0, e1);
+    }
+    if (st != SCAN_OK) break;
+    std::sort(ts, ts + r);
+    if (ts[r / 2] < best_ms) {
+      best_ms = ts[r / 2];
+      best = t;
+    }
+  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (st != SCAN_OK) {
@@ -565,9 +591,9 @@ scan_status scan_tune_save(scan_ctx* ctx, const char* path) {
   size_t i = 0;
   for (const auto& kv : ctx->tunes) {
     std::fprintf(f, "  {\"enc\": %d, \"b\": %u, \"strategy\": %d, \"wg_size\": %d, \"wgs_per_cu\": %d, "
-                    "\"window_blocks\": %d}%s\n",
+                    "\"window_blocks\": %d, \"depth\": %d}%s\n",
                  std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), kv.second.wg_size,
-                 kv.second.wgs_per_cu, kv.second.window_blocks, ++i < ctx->tunes.size() ? "," : "");
+                 kv.second.wgs_per_cu, kv.second.window_blocks, kv.second.depth, ++i < ctx->tunes.size() ? "," : "");
   }
   std::fprintf(f, "]}\n");
   std::fclose(f);
@@ -588,18 +614,19 @@ scan_status scan_tune_load(scan_ctx* ctx, const char* path) {
   while (std::fgets(line, sizeof line, f)) {
     ++lineno;
     if (!std::strstr(line, "\"enc\"")) continue;  // the header and the closing bracket
-    int enc, strat, wg, pc, win;
+    int enc, strat, wg, pc, win, depth = 0;
     unsigned b;
-    if (std::sscanf(line,
-                    " {\"enc\": %d, \"b\": %u, \"strategy\": %d, \"wg_size\": %d, \"wgs_per_cu\": %d, "
-                    "\"window_blocks\": %d}",
-                    &enc, &b, &strat, &wg, &pc, &win) != 6) {
+    const int fields = std::sscanf(line,
+                                   " {\"enc\": %d, \"b\": %u, \"strategy\": %d, \"wg_size\": %d, \"wgs_per_cu\": %d, "
+                                   "\"window_blocks\": %d, \"depth\": %d}",
+                                   &enc, &b, &strat, &wg, &pc, &win, &depth);
+    if (fields != 7 && !(fields == 6 && std::strstr(line, "\"depth\"") == nullptr)) {  // no depth field: 0
       if (!bad) bad = lineno;
       continue;
     }
-    const scan_tune t{wg, pc, win, 0};
+    const scan_tune t{wg, pc, win, depth};
     const bool ok = (wg == 0 || (wg >= 64 && wg <= 256 && wg % 64 == 0)) && pc >= 0 && pc <= 64 && win >= 0 &&
-                    win <= 64;
+                    win <= 64 && depth >= 0 && depth <= 1;
     if (!ok) {
       if (!bad) bad = lineno;
       continue;

@@ -40,6 +40,7 @@ struct scan_ctx {
   std::map<uint64_t, BatchPlan*> batches;
   SelectWork* select = nullptr;       // materializing select work space
   uint64_t next_batch = 1;
+  int32_t query_kernel = 0;           // SCAN_QUERY_PER_QUERY or SCAN_QUERY_SHARED (scan_query_run)
   int batch_graph = 1;                // prepared batches: 0 direct launches, 1 graph, 2 graph with forked class scans
 };
 
@@ -53,8 +54,8 @@ scan_tune default_tune(int32_t enc, uint32_t b, int32_t s);
 scan_status ensure_evict_buffer(scan_ctx* ctx);
 void evict_caches(scan_ctx* ctx);
 scan_status scan_params(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b, const scan_predicate* pred,
-                        int32_t s, scan_dev::Partial* partials, scan_dev::Result* out_dev, scan_dev::Params& p,
-                        scan_dev::LaunchFn& fn, bool& trivially_empty);
+                        int32_t s, int32_t depth, scan_dev::Partial* partials, scan_dev::Result* out_dev,
+                        scan_dev::Params& p, scan_dev::LaunchFn& fn, bool& trivially_empty);
 void scan_geometry(scan_dev::Params& p, const scan_tune& t, int occ, int cus, uint32_t max_grid, int dec, uint32_t b,
                    uint32_t& grid);
 scan_status enqueue_scan(scan_ctx* ctx, const scan_column* col, int32_t enc, uint32_t b, const scan_predicate* pred,

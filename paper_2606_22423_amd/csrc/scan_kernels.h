@@ -49,6 +49,10 @@ struct Geo {
   // 18 %).  Compaction keeps about 4 KiB (its ring and masks need the
   // registers; deeper steps spill).
   static constexpr int kPairs = B >= 24 ? 2 : B >= 16 ? 1 : (32 / B > 8 ? 8 : 32 / B);
+  // the alternative step depth the autotuner may pick instead (branch-free
+  // frame-of-reference, register decoders): half as deep below b = 16, one
+  // pair deeper from b = 16 on
+  static constexpr int kPairsAlt = B >= 16 ? kPairs + 1 : (kPairs / 2 > 1 ? kPairs / 2 : 1);
   static constexpr int kPairsSV = B >= 16 ? 1 : (16 / B > 4 ? 4 : 16 / B);
   // the delta decoders (prefix scan per pair) keep one pair per step from b = 16
   static constexpr int kDeltaPairs = B >= 16 ? 1 : (16 / B > 4 ? 4 : 16 / B);
@@ -879,12 +883,17 @@ __host__ __device__ constexpr uint32_t code_scan_lds(uint32_t waves) {
   return (ENC == ENC_DICT ? kMaxDict * 8u : 0u) + waves * wave_lds_words<B, DEC, MODE>() * 4u;
 }
 
-// Scan blocks [ka, ke) of a FOR/DICT column into the wavefront state.  SMALL
-// selects one block pair (or one staged block) per pipelined step instead of
-// ~4 KiB steps (the batched kernels use it to bound code size).  The partial
+// Step depth of scan_range: the default pipelined steps, the alternative
+// depth of the register decoders' branch-free frame-of-reference kernels
+// (Geo<B>::kPairsAlt; a tuning choice), or one block pair / staged block per
+// step (the batched kernels, to bound code size).
+enum StepForm { STEP_DEFAULT = 0, STEP_ALT = 1, STEP_SMALL = 2 };
+
+// Scan blocks [ka, ke) of a FOR/DICT column into the wavefront state, with
+// steps of the given form.  The partial
 // last block, when it lies in the range, is decoded here with per-value
 // validity after the pipelined loop.
-template <int B, int DEC, int MODE, int ENC, int PF, bool SMALL>
+template <int B, int DEC, int MODE, int ENC, int PF, int STEP>
 __device__ __forceinline__ void scan_range(const Params& p, WaveState<uint32_t>& s, uint32_t lane, uint32_t* list,
                                            uint32_t* st, uint64_t ka, uint64_t ke, uint64_t stride, uint32_t win,
                                            const int64_t* dict_lds, uint32_t dict_last, uint32_t clo, uint32_t chi) {
@@ -892,13 +901,15 @@ __device__ __forceinline__ void scan_range(const Params& p, WaveState<uint32_t>&
   const bool tail_partial = p.tail != kBlockValues;
   const uint64_t excl = tail_partial ? last : ~0ull;
   if constexpr (DEC == DEC_RM_DIRECT || DEC == DEC_LI) {
-    constexpr int P = SMALL ? 1 : (MODE == MODE_BF ? Geo<B>::kPairs : Geo<B>::kPairsSV);
+    constexpr int P = STEP == STEP_SMALL ? 1
+                      : MODE == MODE_SV ? Geo<B>::kPairsSV
+                      : STEP == STEP_ALT ? Geo<B>::kPairsAlt : Geo<B>::kPairs;
     run_pairs<B, DEC, MODE, ENC, PF, P>(p, s, lane, list, ka, ke, stride, win, excl, dict_lds, dict_last, clo, chi);
   } else if constexpr (DEC == DEC_RM_LDS) {
-    run_staged<B, MODE, ENC, PF, SMALL ? 1 : Geo<B>::kLdsBlocks>(p, s, lane, st, ka, ke, stride, win, excl, dict_lds,
+    run_staged<B, MODE, ENC, PF, STEP == STEP_SMALL ? 1 : Geo<B>::kLdsBlocks>(p, s, lane, st, ka, ke, stride, win, excl, dict_lds,
                                                                  dict_last, clo, chi);
   } else {
-    run_bytes<B, MODE, ENC, PF, SMALL ? 1 : Geo<B>::kByteBlocks>(p, s, lane, ka, ke, stride, win, excl);
+    run_bytes<B, MODE, ENC, PF, STEP == STEP_SMALL ? 1 : Geo<B>::kByteBlocks>(p, s, lane, ka, ke, stride, win, excl);
   }
   if (tail_partial && owns_block(last, ka, ke, stride, win) && block_survives<ENC>(p, last, clo, chi)) {
     if (block_inside<ENC>(p, last, clo, chi)) {
@@ -931,7 +942,7 @@ __device__ __forceinline__ void scan_range(const Params& p, WaveState<uint32_t>&
   }
 }
 
-template <int B, int DEC, int MODE, int ENC, int PF>
+template <int B, int DEC, int MODE, int ENC, int PF, int STEP = STEP_DEFAULT>
 __global__ __launch_bounds__(256) void code_scan(const Params p) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -956,7 +967,7 @@ __global__ __launch_bounds__(256) void code_scan(const Params p) {
   // Grid-strided windows of p.G blocks: at any moment the wavefronts read one
   // compact region of the column (DRAM row locality), like a streaming copy.
   const uint64_t gw = (uint64_t)blockIdx.x * nw + wave, tw = (uint64_t)gridDim.x * nw;
-  scan_range<B, DEC, MODE, ENC, PF, false>(p, s, lane, list, st, gw * p.G, p.nb, tw * p.G, p.G, dict_lds, dict_last,
+  scan_range<B, DEC, MODE, ENC, PF, STEP>(p, s, lane, list, st, gw * p.G, p.nb, tw * p.G, p.G, dict_lds, dict_last,
                                            clo, chi);
   if constexpr (MODE == MODE_SV) sv_drain_rest<ENC, uint32_t>(s, lane, dict_lds, dict_last);
   finish_scan(p, s.count + wave_sum_u64(s.lcount), s.lsum + (lane == 0 ? s.refsum : 0ull), s.blocks);

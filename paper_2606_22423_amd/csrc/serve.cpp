@@ -349,7 +349,7 @@ scan_status scan_query_run(scan_ctx* ctx, const scan_table* t, const scan_query*
   }
   const auto tit = ctx->tunes.find(std::make_tuple((int32_t)-2, 0u, (int32_t)-1));
   const scan_tune tn = tit != ctx->tunes.end() ? tit->second : scan_tune{0, 0, 0, 0};
-  const bool shared = use_shared(t, (uint32_t)tn.reserved);
+  const bool shared = use_shared(t, (uint32_t)ctx->query_kernel);
   const uint32_t G = tn.window_blocks > 0 ? (uint32_t)std::min(tn.window_blocks, shared ? 32 : 64)
                                           : (shared ? kSharedWindow : kDefaultWindow);
   if (((t->nb + G - 1) / G) * (uint64_t)n >= (1ull << 31)) return fail(ctx, SCAN_EINVAL, "too many work items");
@@ -385,8 +385,7 @@ scan_status scan_query_run(scan_ctx* ctx, const scan_table* t, const scan_query*
   return e == hipSuccess ? SCAN_OK : hip_fail(ctx, e, "query scan");
 }
 
-// The query kernel's tuning is kept under (enc -2, b 0, strategy -1); its
-// `reserved` field holds the kernel choice.
+// The query kernel's tuning is kept under (enc -2, b 0, strategy -1).
 scan_status scan_query_set_tune(scan_ctx* ctx, int32_t wgs_per_cu, int32_t window_blocks) {
   if (!ctx) return SCAN_EINVAL;
   if (wgs_per_cu < 0 || wgs_per_cu > 16 || window_blocks < 0 || window_blocks > 64)
@@ -402,7 +401,7 @@ scan_status scan_query_set_kernel(scan_ctx* ctx, int32_t kernel) {
   if (!ctx) return SCAN_EINVAL;
   if (kernel != SCAN_QUERY_SHARED && kernel != SCAN_QUERY_PER_QUERY)
     return fail(ctx, SCAN_EINVAL, "kernel must be SCAN_QUERY_SHARED or SCAN_QUERY_PER_QUERY");
-  ctx->tunes[std::make_tuple((int32_t)-2, 0u, (int32_t)-1)].reserved = kernel;
+  ctx->query_kernel = kernel;
   return SCAN_OK;
 }
 

@@ -77,7 +77,8 @@ extern "C" scan_status scan_run_static(const scan_item* item, void* hip_stream, 
   Params p;
   LaunchFn fn = nullptr;
   bool empty = false;
-  st = scan_params(nullptr, &item->col, item->enc, item->b, &item->pred, s, slot->scratch, out, p, fn, empty);
+  const scan_tune t = default_tune(item->enc, item->b, s);
+  st = scan_params(nullptr, &item->col, item->enc, item->b, &item->pred, s, t.depth, slot->scratch, out, p, fn, empty);
   if (st != SCAN_OK) return st;
   if (empty) {
     Result r;
@@ -87,7 +88,6 @@ extern "C" scan_status scan_run_static(const scan_item* item, void* hip_stream, 
     r.strategy_used = s;
     return launch_write_result(out, r, stream) == hipSuccess ? SCAN_OK : SCAN_EDEVICE;
   }
-  const scan_tune t = default_tune(item->enc, item->b, s);
   int occ = 0;
   if (fn(p, 0, (uint32_t)t.wg_size, stream, &occ) != hipSuccess) return SCAN_EDEVICE;
   uint32_t grid = 0;

@@ -22,11 +22,11 @@ def make_query(filters, sum_col: int) -> ScanQuery:
     return q
 
 
-SHARED, PER_QUERY = 0, 1  # query kernels (scan_query_set_kernel)
+PER_QUERY, SHARED = 0, 1  # query kernels (scan_query_set_kernel)
 
 
 def config(hbm_budget_bytes=2 << 30, max_inflight=256, n_streams=2, max_batch=64, batch_window_us=200,
-           window_blocks=0, wgs_per_cu=0, kernel=SHARED) -> ScanServerConfig:
+           window_blocks=0, wgs_per_cu=0, kernel=PER_QUERY) -> ScanServerConfig:
     return ScanServerConfig(int(hbm_budget_bytes), max_inflight, n_streams, max_batch, batch_window_us,
                             window_blocks, wgs_per_cu, kernel, 0)
 

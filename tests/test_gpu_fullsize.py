@@ -210,9 +210,10 @@ def test_oracle_packed_random_columns(ctx, b):
         for lo, hi in ((0, max(1, p // 10)), (p // 4, p // 4 + max(1, p // 3)), (int(raw[77]), int(raw[77]) + 1)):
             want = oracle.scan_for(words, N24, b, lo, hi, layout=layout, zone_maps=True)
             for s in strategies_for(b, layout):
-                for shape in ((0, 0, 0), (64, 1, 4)):
-                    if shape[0]:
-                        # 256 wavefronts of 4-block windows: every wavefront walks 16 windows
+                for shape in ((0, 0, 0, 0), (64, 1, 4, 0), (0, 0, 0, 1)):
+                    if any(shape):
+                        # (64, 1, 4): 256 wavefronts of 4-block windows, every wavefront walks
+                        # 16 windows; (0, 0, 0, 1): the alternative step depth
                         ctx.set_tune(ENC_FOR, b, s, *shape)
                     say("oracle-packed n=2^24 b=%d layout=%d strategy=%d shape=%s pred=[%d,%d)" %
                         (b, layout, s, shape, lo, hi))

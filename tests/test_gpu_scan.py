@@ -272,21 +272,26 @@ def test_async_results_and_repeat_launches(ctx):
 
 
 def test_launch_tuning_does_not_change_results(ctx):
-    """Work-group size, work-groups per CU and the window size are speed knobs only."""
+    """Work-group size, work-groups per CU, the window size and the step depth
+    are speed knobs only."""
     n = 300 * 1024 + 999
-    for b in (3, 13, 32):
+    for b in (3, 13, 16, 32):
         v = synth.width_values(synth.pcg32(44, b, n), b)
-        col = api.encode_for(v, b)
-        lo, hi = (1 << b) // 5, (1 << b) // 2
-        want = oracle.scan_for(oracle.pack_rm(v, b), n, b, lo, hi, zone_maps=True)
-        for s in (strategy(DEC_RM_DIRECT, 0, 1), strategy(DEC_RM_LDS, 1, 0)):
-            for wg, per_cu, win in ((64, 1, 1), (128, 3, 5), (256, 0, 64), (192, 2, 0)):
-                ctx.set_tune(ENC_FOR, b, s, wg, per_cu, win)
-                got = ctx.run(col, lo, hi, s)
-                assert (got["count"], got["sum"]) == (want.count, want.sum), (b, s, wg, per_cu, win)
-                if (s >> 3) & 1:
-                    assert got["blocks_read"] == want.blocks_read
-            ctx.set_tune(ENC_FOR, b, s, 0, 0, 0)
+        for layout, pack in ((LAYOUT_RM, oracle.pack_rm), (LAYOUT_LI, oracle.pack_li)):
+            col = api.encode_for(v, b, layout=layout)
+            for lo, hi in (((1 << b) // 5, (1 << b) // 2), (0, (1 << b) // 3)):
+                want = oracle.scan_for(pack(v, b), n, b, lo, hi, layout=layout, zone_maps=True)
+                decs = (DEC_LI,) if layout == LAYOUT_LI else (DEC_RM_DIRECT, DEC_RM_LDS)
+                for s in [strategy(d, m, z) for d in decs for m, z in ((0, 1), (1, 0), (0, 0))]:
+                    for wg, per_cu, win, depth in ((64, 1, 1, 1), (128, 3, 5, 0), (256, 0, 64, 1), (192, 2, 0, 1),
+                                                   (0, 0, 0, 1)):
+                        ctx.set_tune(ENC_FOR, b, s, wg, per_cu, win, depth)
+                        got = ctx.run(col, lo, hi, s)
+                        case = (b, layout, s, wg, per_cu, win, depth, lo, hi)
+                        assert (got["count"], got["sum"]) == (want.count, want.sum), case
+                        if (s >> 3) & 1:
+                            assert got["blocks_read"] == want.blocks_read, case
+                    ctx.set_tune(ENC_FOR, b, s, 0, 0, 0, 0)
 
 
 def test_tune_file_round_trip_and_errors(ctx, tmp_path):
@@ -294,12 +299,18 @@ def test_tune_file_round_trip_and_errors(ctx, tmp_path):
     file without entries or with a malformed or invalid entry is refused
     (SCAN_EINVAL) and installs nothing."""
     s = strategy(DEC_RM_DIRECT, 0, 0)
-    ctx.set_tune(ENC_FOR, 7, s, 128, 2, 8)
+    ctx.set_tune(ENC_FOR, 7, s, 128, 2, 8, 1)
     good = str(tmp_path / "good.json")
     ctx.tune_save(good)
     ctx.set_tune(ENC_FOR, 7, s, 0, 0, 0)
     ctx.tune_load(good)
-    assert ctx.get_tune(ENC_FOR, 7, s) == (128, 2, 8)
+    assert ctx.get_tune(ENC_FOR, 7, s) == (128, 2, 8, 1)
+    # a file written before the depth field existed loads with depth 0
+    old = tmp_path / "old.json"
+    old.write_text('{"format": "scan-autotune-1", "entries": [\n'
+                   '  {"enc": 0, "b": 7, "strategy": %d, "wg_size": 64, "wgs_per_cu": 4, "window_blocks": 2}\n]}\n' % s)
+    ctx.tune_load(str(old))
+    assert ctx.get_tune(ENC_FOR, 7, s) == (64, 4, 2, 0)
     ctx.set_tune(ENC_FOR, 7, s, 0, 0, 0)
     before = ctx.get_tune(ENC_FOR, 7, s)
     cases = {
@@ -309,6 +320,9 @@ def test_tune_file_round_trip_and_errors(ctx, tmp_path):
                         '  {"enc": 0, "b": 9, "strategy": oops}\n]}\n',
         "invalid.json": '{"format": "scan-autotune-1", "entries": [\n'
                         '  {"enc": 0, "b": 7, "strategy": 1, "wg_size": 100, "wgs_per_cu": 2, "window_blocks": 8}\n]}\n',
+        "bad_depth.json": '{"format": "scan-autotune-1", "entries": [\n'
+                          '  {"enc": 0, "b": 7, "strategy": 1, "wg_size": 64, "wgs_per_cu": 2, "window_blocks": 8, '
+                          '"depth": 2}\n]}\n',
     }
     for name, text in cases.items():
         path = tmp_path / name

@@ -103,7 +103,7 @@ KERNELS = [serve.SHARED, serve.PER_QUERY]
 def kernel(ctx, request):
     assert ctx.lib.scan_query_set_kernel(ctx.h, request.param) == 0
     yield request.param
-    ctx.lib.scan_query_set_kernel(ctx.h, serve.SHARED)
+    ctx.lib.scan_query_set_kernel(ctx.h, serve.PER_QUERY)
 
 
 def test_batch_of_queries_matches_oracle(world, kernel):
@@ -133,7 +133,7 @@ def test_launch_shape_does_not_change_results(ctx, world, kernel):
 
 
 def test_kernel_choice_errors(ctx):
-    assert ctx.lib.scan_query_set_kernel(ctx.h, 2) == _lib.SCAN_EINVAL
+    assert ctx.lib.scan_query_set_kernel(ctx.h, 2) == _lib.SCAN_EINVAL  # neither kernel
     assert ctx.lib.scan_query_set_kernel(ctx.h, -1) == _lib.SCAN_EINVAL
 
 
@@ -162,7 +162,7 @@ def test_queries_at_2p22_rows_match_oracle(ctx):
             for q, g, r in zip(queries, got, wants):
                 assert (g["count"], g["sum"]) == (r.count, r.sum), (k, q, g, r)
     finally:
-        ctx.lib.scan_query_set_kernel(ctx.h, serve.SHARED)
+        ctx.lib.scan_query_set_kernel(ctx.h, serve.PER_QUERY)
         table.close()
 
 

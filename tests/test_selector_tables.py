@@ -33,11 +33,15 @@ def read_table(path):
     return a[:, :6].astype(np.float32), a[:, 6:] * 1e-6
 
 
-CASES = [("selector_batch_mi355x.txt", "selector_heldout_batch_mi355x.txt")]
+# (parameters, held-out table, least gain over the heuristic's total time):
+# timed one launch per column, the heuristic's fixed choice loses about 28 %
+# against the per-column best; in a batch of scans it is near the best already
+CASES = [("selector_mi355x.txt", "selector_heldout_single_mi355x.txt", 0.20),
+         ("selector_batch_mi355x.txt", "selector_heldout_batch_mi355x.txt", 0.0)]
 
 
-@pytest.mark.parametrize("sel,table", CASES)
-def test_selector_regret_and_gain_on_heldout_table(sel, table):
+@pytest.mark.parametrize("sel,table,min_gain", CASES)
+def test_selector_regret_and_gain_on_heldout_table(sel, table, min_gain):
     theta, margin = read_selector(os.path.join(HERE, sel))
     X, T = read_table(os.path.join(HERE, table))
     assert T.shape == (4096, K) and np.all(T > 0)
@@ -51,7 +55,7 @@ def test_selector_regret_and_gain_on_heldout_table(sel, table):
     t_heur = T[:, HEURISTIC].sum()
     regret = t_learned / t_best - 1.0
     assert 0.0 <= regret <= 0.10, regret
-    assert t_learned <= t_heur, (t_learned, t_heur)
+    assert t_learned <= t_heur * (1.0 - min_gain), (t_learned, t_heur)
     # the fallback is what keeps the network from losing: the plain argmin's
     # regret is reported beside it (not bounded)
     plain = T[rows, omlp.argmin_strategy(pred, valid)].sum() / t_best - 1.0
