@@ -96,10 +96,11 @@ def batch_leg(ctx, torch, ncols, reps, selector_path, batch_selector_path=None, 
     (ii) asynchronous launches on one stream and one final sync.  Learned: the
     same launches with the strategy the trained selector picks per column (the
     device time of feature extraction and the network for all columns is
-    reported beside it).  Batched: one prepared batch (a fixed sequence of
-    launches for all columns), replays timed, with the default strategy and
-    with the selector choosing on the device inside each replay.  Results of
-    every column must agree."""
+    reported beside it).  Batched: one prepared batch (planned once, replayed
+    as one graph launch), replays timed, with the default strategy and with
+    the batch selector's choices (made on the device when the batch is
+    planned; the planning time is reported beside).  Results of every column
+    must agree."""
     import numpy as np
 
     import synth
@@ -164,16 +165,20 @@ def batch_leg(ctx, torch, ncols, reps, selector_path, batch_selector_path=None, 
                 raise RuntimeError("%s: column %d differs: %s vs %s" % (what, i, got[i], r))
 
     def batched(items, what):
-        """Plan once, then time replays (each a fixed sequence of launches)."""
+        """Plan once (host clock), then time replays (one graph launch each)."""
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
         h = ctx.batch_prepare(items)
+        t_prep = time.perf_counter() - t1
         try:
+            info = ctx.batch_info(h)
             got = ctx.batch_replay(h, len(items))
             check_batch(got, what)
             ts = [timed(lambda: ctx.batch_replay(h, wait=False)) for _ in range(reps)]
             check_batch(ctx.batch_replay(h, len(items)), what)
         finally:
             ctx.batch_release(h)
-        return float(np.median(ts)), got
+        return float(np.median(ts)), got, t_prep, info
 
     # launch shape of the class kernels for this workload (the batch autotuner),
     # used by every batch below
@@ -184,12 +189,18 @@ def batch_leg(ctx, torch, ncols, reps, selector_path, batch_selector_path=None, 
     # the default strategy as one replay: direct launches (0), one graph (1,
     # the library default), one graph with the class scans forked over branches (2)
     by_mode = {}
+    prep_default = None
     for mode in (0, 1, 2):
         ctx.batch_set_graph(mode)
-        t_m, _ = batched([c.item(lo, hi, default) for c, lo, hi in cols], "batched default (mode %d)" % mode)
+        t_m, _, t_p, info_d = batched([c.item(lo, hi, default) for c, lo, hi in cols],
+                                      "batched default (mode %d)" % mode)
         by_mode[mode] = t_m
+        if mode == 1:
+            prep_default = t_p
+            res["class_scans_default"] = bin(info_d["class_mask"]).count("1")
     ctx.batch_set_graph(1)
     res["batched_default_ms"] = round(by_mode[1] * 1e3, 3)
+    res["prepare_default_ms"] = round(prep_default * 1e3, 1)
     res["batched_default_ms_direct_graph_forked"] = [round(by_mode[m] * 1e3, 3) for m in (0, 1, 2)]
     if selector_path and os.path.exists(selector_path):
         # per-column launches with the single-launch selector's choices
@@ -205,19 +216,22 @@ def batch_leg(ctx, torch, ncols, reps, selector_path, batch_selector_path=None, 
                     "speedup_learned_vs_default": round(float(np.median(t_async)) / float(np.median(t_learn)), 3)})
     bsel = batch_selector_path if batch_selector_path and os.path.exists(batch_selector_path) else selector_path
     if bsel and os.path.exists(bsel):
-        # batched + learned: the batch selector runs on the device inside each replay
+        # batched + learned: the batch selector chooses on the device when the
+        # batch is planned (features, network, argmin with the fallback
+        # margin, then the class-scan cost); replays reuse the plan
         ctx.selector_load(bsel)
         chosen = [ctx.run(c, lo, hi, -1)["strategy_used"] & ~16 for c, lo, hi in cols]
-        t_bl, got = batched([c.item(lo, hi, -1) for c, lo, hi in cols], "batched learned")
+        t_bl, got, t_prep, info_l = batched([c.item(lo, hi, -1) for c, lo, hi in cols], "batched learned")
         ctx.selector_clear()
-        if [g["strategy_used"] for g in got] != chosen:
-            raise RuntimeError("batched selection differs from scan_run's")
-        # the same choices as explicit strategies: the replay without the
-        # selection kernels (features, network, argmin)
-        t_be, _ = batched([c.item(lo, hi, s) for (c, lo, hi), s in zip(cols, chosen)], "batched learned explicit")
+        used = [g["strategy_used"] for g in got]
+        heur = strategy(DEC_RM_DIRECT, 0, 1)
+        if any(u != s and u != heur for u, s in zip(used, chosen)):
+            raise RuntimeError("batched selection is neither scan_run's choice nor the heuristic")
         res.update({"batched_learned_ms": round(t_bl * 1e3, 3),
-                    "batched_learned_explicit_ms": round(t_be * 1e3, 3),
-                    "selection_in_replay_ms": round((t_bl - t_be) * 1e3, 3),
+                    "prepare_learned_ms": round(t_prep * 1e3, 1),
+                    "learned_differs_from_heuristic": int(sum(u != heur for u in used)),
+                    "learned_taken_back_for_class_cost": info_l["pruned"],
+                    "class_scans_learned": bin(info_l["class_mask"]).count("1"),
                     "batched_learned_vs_default": round(res["batched_default_ms"] / (t_bl * 1e3), 4),
                     "speedup_batched_learned_vs_per_column_async": round(float(np.median(t_async)) / t_bl, 2),
                     "speedup_batched_learned_vs_per_column_sync": round(float(np.median(t_sync)) / t_bl, 2)})
@@ -765,10 +779,19 @@ def compact_line(full: dict, detail_path: str) -> dict:
                                    for dec, rows in cr.items()}
     sel = full.get("select")
     if sel:
-        line["select"] = [[r["b"], r["sigma"], r["ms"], r["f"]] for r in sel]
+        # f of the materializing select per width, at each selectivity
+        line["select_f"] = {"sigma": sorted({r["sigma"] for r in sel})}
+        for r in sel:
+            line["select_f"].setdefault(str(r["b"]), []).append(r["f"])
     bt = full.get("batch")
     if bt:
-        line["batch"] = {k: v for k, v in bt.items() if k not in ("workload", "learned_class_counts")}
+        keys = ("baseline_sync_ms", "baseline_async_ms", "learned_async_ms", "batched_default_ms",
+                "batched_learned_ms", "batched_learned_vs_default", "prepare_default_ms", "prepare_learned_ms",
+                "class_scans_default", "class_scans_learned", "learned_differs_from_heuristic",
+                "learned_taken_back_for_class_cost", "speedup_batched_learned_vs_per_column_sync")
+        line["batch"] = {k: bt[k] for k in keys if k in bt}
+        if bt.get("selector_sample"):
+            line["batch"]["selector_sample"] = bt["selector_sample"]
     zm = full.get("zonemap")
     if zm:
         pts = zm["points"]

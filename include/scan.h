@@ -304,16 +304,27 @@ scan_status scan_gather(scan_ctx* ctx, const scan_column* col, int32_t enc, uint
  * decoder.  Results equal scan_run's for every item, bit for bit.
  *
  * scan_batch_prepare validates the items, uploads their descriptors, windows
- * and zone-map segments once, and captures the replay sequence into a HIP
- * graph (see scan_batch_set_graph; if capture fails, replays enqueue the
- * kernels one by one: same results).  Baked in at that moment: the selector
- * (its parameters are copied), and the tuning stored for (enc -1, b 0,
- * strategy -1) (work-groups per CU of the class kernels, default 4, at most
- * the number that fit, and the window, default and at most 64 blocks).  An
- * invalid item does not fail the call: its result carries the error in
- * `status`.  `items` (host) may be freed after the call; the columns' device
- * buffers must stay alive until the handle is released.  *handle (host)
- * receives an id.  Up to 2^24 items; more -> SCAN_EINVAL. */
+ * and zone-map segments once, and plans the batch on the device once: every
+ * SCAN_STRAT_AUTO item's strategy (the selector's choice, from the columns'
+ * zone maps as they are now, else the heuristic) and the per-class work
+ * lists.  A selector choice that would add a class scan (decoder x mode of
+ * the encoding) that no other column of the batch needs is taken back to the
+ * heuristic when the network's predicted gains of all the columns it moves
+ * into that class add up to less than the class-scan cost
+ * (scan_batch_set_class_cost); so a batch's AUTO strategy can differ from
+ * scan_run's for the same item.  It then captures the replay sequence (reset
+ * of the result slots, then one persistent kernel per class with items) into
+ * a HIP graph (see scan_batch_set_graph; if capture fails, replays enqueue
+ * the kernels one by one: same results).  Baked in at that moment: the
+ * strategies, and the tuning stored for (enc -1, b 0, strategy -1)
+ * (work-groups per CU of the class kernels, default 4, at most the number
+ * that fit, and the window, default and at most 64 blocks).  The columns'
+ * contents and zone maps must not change while the batch lives.  An invalid
+ * item does not fail the call: its result carries the error in `status`.
+ * `items` (host) may be freed after the call; the columns' device buffers
+ * must stay alive until the handle is released.  Synchronizes the context
+ * stream.  *handle (host) receives an id.  Up to 2^24 items; more ->
+ * SCAN_EINVAL. */
 scan_status scan_batch_prepare(scan_ctx* ctx, const scan_item* items, size_t n_items, uint64_t* handle);
 /* Enqueue the batch on the context stream (one graph launch).  With out
  * (host, n_items results) non-NULL, also copies the results back, waits and
@@ -342,11 +353,19 @@ scan_status scan_batch_autotune(scan_ctx* ctx, const scan_item* items, size_t n_
  * MI355X: the concurrent class scans contend).  Results are the same.
  * Other values -> SCAN_EINVAL. */
 scan_status scan_batch_set_graph(scan_ctx* ctx, int32_t mode);
+/* Cost in microseconds of one more class scan in a replay (its launch and
+ * drain; default 10, measured on MI355X with 4096-column batches), used by
+ * later scan_batch_prepare calls to take back selector choices that would
+ * need a class scan of their own (see scan_batch_prepare).  0 keeps every
+ * choice.  Negative or not finite -> SCAN_EINVAL. */
+scan_status scan_batch_set_class_cost(scan_ctx* ctx, float us);
 typedef struct {
   int32_t captured;           /* 0: direct launches; 1: one graph launch; 2: one graph, forked class scans */
-  uint32_t kernels;           /* kernels in one replay */
+  uint32_t kernels;           /* kernels in one replay (0 for an empty batch) */
   uint32_t class_mask;        /* class scans launched (bit enc*4 + decoder*2 + mode) */
   uint32_t work_items;        /* work items of the batch's columns */
+  uint32_t pruned;            /* selector choices taken back to the heuristic (class-scan cost) */
+  uint32_t reserved;
 } scan_batch_stats;
 /* Plan facts of a prepared batch into *out (host).  Unknown handle -> SCAN_EINVAL. */
 scan_status scan_batch_info(scan_ctx* ctx, uint64_t handle, scan_batch_stats* out);

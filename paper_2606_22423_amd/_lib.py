@@ -73,7 +73,7 @@ class ScanTune(ctypes.Structure):
 
 class ScanBatchStats(ctypes.Structure):
     _fields_ = [("captured", ctypes.c_int32), ("kernels", ctypes.c_uint32), ("class_mask", ctypes.c_uint32),
-                ("work_items", ctypes.c_uint32)]
+                ("work_items", ctypes.c_uint32), ("pruned", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class ScanRleColumn(ctypes.Structure):
@@ -142,6 +142,7 @@ SIGNATURES = {
     "scan_batch_set_graph": (_i32, [_vp, _i32]),
     "scan_batch_autotune": (_i32, [_vp, _P(ScanItem), ctypes.c_size_t, _i32, _P(ScanTune), _P(ctypes.c_float)]),
     "scan_batch_info": (_i32, [_vp, _u64, _P(ScanBatchStats)]),
+    "scan_batch_set_class_cost": (_i32, [_vp, _f32]),
     "scan_mlp_param_count": (ctypes.c_int, []),
     "scan_selector_set": (_i32, [_vp, _vp, ctypes.c_size_t]),
     "scan_selector_clear": (_i32, [_vp]),

@@ -415,7 +415,10 @@ class Context:
         s = _lib.ScanBatchStats()
         self.check(self.lib.scan_batch_info(self.h, handle, ctypes.byref(s)), "scan_batch_info")
         return {"captured": int(s.captured), "kernels": int(s.kernels), "class_mask": int(s.class_mask),
-                "work_items": int(s.work_items)}
+                "work_items": int(s.work_items), "pruned": int(s.pruned)}
+
+    def batch_set_class_cost(self, us: float):
+        self.check(self.lib.scan_batch_set_class_cost(self.h, float(us)), "scan_batch_set_class_cost")
 
     def batch_autotune(self, items, reps: int = 3):
         """Search work-groups per CU x window for this batch; returns ((wgs_per_cu, window), best ms)."""

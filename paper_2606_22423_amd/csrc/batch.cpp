@@ -1,21 +1,27 @@
-// Batched scans: host side.  A batch is planned once (validation, column
-// descriptors, work items, zone-map segments, device buffers) and its replay
-// sequence is captured into a HIP graph:
-//   setup (clear slots and class counts, dictionary code ranges)
+// Batched scans: host side.  A batch is planned once: validation, column
+// descriptors, work items, zone-map segments and device buffers, then one
+// planning pass on the device
+//   setup (class counts, dictionary code ranges)
 //   -> [zone-map features -> selector MLP]  (when a selector is loaded)
 //   -> select (strategy per column, written on the device)
+//   -> [class pruning on the host, see prune_classes]
 //   -> bin (items into twelve class lists)
-//   -> the persistent class scans that can occur (static schedule over each
-//      list), in sequence (forking them over graph branches is an option;
-//      running concurrently they contend and measured slower)
-// so a replay is one hipGraphLaunch whatever the number of columns; the
-// 32-byte result slots come back with one copy.  If capture or instantiation
-// fails the same sequence is enqueued launch by launch.  The same column
-// descriptors serve the single-column selector (scan_run with
-// SCAN_STRAT_AUTO) and the feature export.
+// whose strategies and class lists every replay reuses (the items, the
+// selector and the zone maps are fixed for the life of the batch).  The
+// replay sequence
+//   reset (result slots) -> the class scans that have items (persistent,
+//   static schedule over each list), in sequence (forking them over graph
+//   branches is an option; running concurrently they contend and measured
+//   slower)
+// is captured into a HIP graph, so a replay is one hipGraphLaunch whatever
+// the number of columns; the 32-byte result slots come back with one copy.
+// If capture or instantiation fails the same sequence is enqueued launch by
+// launch.  The same column descriptors serve the single-column selector
+// (scan_run with SCAN_STRAT_AUTO) and the feature export.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -31,6 +37,7 @@ hipError_t launch_batch_features(const BatchCol* cols, uint32_t n_cols, const Ba
 hipError_t launch_batch_select(BatchCol* cols, uint32_t n_cols, const float* scores, int32_t k, float margin,
                                BatchOut* out, hipStream_t st);
 hipError_t launch_batch_bin(const BatchArgs& a, hipStream_t st);
+hipError_t launch_batch_reset(const BatchCol* cols, uint32_t n_cols, BatchOut* out, hipStream_t st);
 hipError_t launch_mlp_forward(const float* theta, const float* X, uint32_t rows, float* out, hipStream_t st);
 }  // namespace scan_dev
 
@@ -38,7 +45,6 @@ namespace {
 
 constexpr uint32_t kMaxWindow = 64;  // a wavefront's block-survivor list holds 64 entries
 constexpr int kMaxBranches = 4;      // graph branches the class scans are forked over
-constexpr uint32_t kThetaFloats = 64 * 6 + 64 + 64 * 64 + 64 + 8 * 64 + 8;
 
 // Device buffers of a batch (or of the one-column selector scratch).
 struct BatchBuffers {
@@ -52,18 +58,17 @@ struct BatchBuffers {
   float* scores = nullptr;
   BatchWork* segs = nullptr;     // zone-map segments (selector features)
   FeatPart* fparts = nullptr;    // their sums
-  float* theta = nullptr;        // the batch's own copy of the selector parameters
   uint32_t n_segs = 0;
 
   void release() {
     for (void* p : {(void*)cols, (void*)work, (void*)lists, (void*)counters, (void*)out, (void*)feats, (void*)scores,
-                    (void*)segs, (void*)fparts, (void*)theta})
+                    (void*)segs, (void*)fparts})
       if (p) (void)hipFree(p);
     if (out_host) (void)hipHostFree(out_host);
     *this = BatchBuffers();
   }
 
-  hipError_t allocate(size_t n_cols, size_t n_work, size_t n_seg, bool with_theta) {
+  hipError_t allocate(size_t n_cols, size_t n_work, size_t n_seg) {
     const size_t nc = std::max<size_t>(1, n_cols), nw = std::max<size_t>(1, n_work), ns = std::max<size_t>(1, n_seg);
     hipError_t e;
     if ((e = hipMalloc(&cols, sizeof(BatchCol) * nc)) != hipSuccess) return e;
@@ -75,7 +80,6 @@ struct BatchBuffers {
     if ((e = hipMalloc(&scores, sizeof(float) * 8 * nc)) != hipSuccess) return e;
     if ((e = hipMalloc(&segs, sizeof(BatchWork) * ns)) != hipSuccess) return e;
     if ((e = hipMalloc(&fparts, sizeof(FeatPart) * ns)) != hipSuccess) return e;
-    if (with_theta && (e = hipMalloc(&theta, sizeof(float) * kThetaFloats)) != hipSuccess) return e;
     n_segs = (uint32_t)n_seg;
     return hipHostMalloc(&out_host, sizeof(BatchOut) * nc, hipHostMallocDefault);
   }
@@ -190,17 +194,44 @@ hipError_t enqueue_select(const BatchBuffers& m, uint32_t n_cols, const float* t
   return launch_batch_select(m.cols, n_cols, theta ? m.scores : nullptr, 8, margin, m.out, st);
 }
 
-// Class scans that can occur: an explicit strategy fixes its column's class,
-// the selector may pick any decoder and mode of the column's encoding, the
-// heuristic fixes one.
-uint32_t possible_classes(const std::vector<BatchCol>& cols, bool selector) {
-  uint32_t mask = 0;
-  for (const BatchCol& c : cols) {
+// Selector class of a row-major strategy: decoder bit, mode, zone maps.
+int selector_class(int32_t s) { return (s & 1) | (((s >> 2) & 1) << 1) | (((s >> 3) & 1) << 2); }
+
+// The network predicts each column's time alone; a class scan costs a launch
+// and a drain on top of its columns' times (scan_batch_set_class_cost).
+// Columns the network moves away from their heuristic strategy into a class
+// that no heuristic or explicit column uses are moved back when the
+// predicted gains (exp of the predicted log-times, microseconds) of all the
+// class's columns add up to less than `class_us`.
+void prune_classes(std::vector<BatchCol>& cols, const std::vector<float>& scores, double class_us) {
+  uint32_t base = 0;
+  double gain[kBatchClasses] = {};
+  auto learned = [](const BatchCol& c) {
+    return !(c.flags & (kColEmpty | kColSkip)) && c.requested < 0 && c.strategy != c.heuristic;
+  };
+  for (size_t i = 0; i < cols.size(); ++i) {
+    const BatchCol& c = cols[i];
     if (c.flags & (kColEmpty | kColSkip)) continue;
-    if (c.requested >= 0) mask |= 1u << batch_class(c.enc, c.requested);
-    else if (selector) mask |= 0xFu << (4 * c.enc);
-    else mask |= 1u << batch_class(c.enc, c.heuristic);
+    const int k = batch_class(c.enc, c.strategy);
+    if (!learned(c)) {
+      base |= 1u << k;
+      continue;
+    }
+    const float* sc = &scores[i * 8];
+    gain[k] += std::exp((double)sc[selector_class(c.heuristic)]) - std::exp((double)sc[selector_class(c.strategy)]);
   }
+  for (BatchCol& c : cols) {
+    if (!learned(c)) continue;
+    const int k = batch_class(c.enc, c.strategy);
+    if (!((base >> k) & 1u) && gain[k] < class_us) c.strategy = c.heuristic;
+  }
+}
+
+// Class scans with items, from the planned strategies.
+uint32_t used_classes(const std::vector<BatchCol>& cols) {
+  uint32_t mask = 0;
+  for (const BatchCol& c : cols)
+    if (!(c.flags & (kColEmpty | kColSkip))) mask |= 1u << batch_class(c.enc, c.strategy);
   return mask;
 }
 
@@ -220,6 +251,7 @@ struct BatchPlan {
   hipGraphExec_t exec = nullptr;          // the captured replay (null: direct launches)
   bool forked = false;                    // class scans on parallel graph branches
   float margin = 0.0f;                    // the selector's margin when prepared
+  uint32_t pruned = 0;                    // columns moved back to the heuristic (prune_classes)
 };
 
 static void free_plan(BatchPlan* b) {
@@ -251,14 +283,13 @@ void destroy_batches(scan_ctx* ctx) {
 }
 
 // The replay sequence on `st`.  With nbr > 0 branch streams (graph capture)
-// the class scans are forked over them after the binning kernel (ev[0]) and
+// the class scans are forked over them after the reset kernel (ev[0]) and
 // joined back (ev[1..nbr]): class scans touch disjoint columns, so they may
 // run concurrently.
 static hipError_t enqueue_batch(BatchPlan* b, hipStream_t st, const hipStream_t* br, int nbr, const hipEvent_t* ev) {
-  hipError_t e = enqueue_select(b->mem, (uint32_t)b->n_items, b->selector ? b->mem.theta : nullptr, b->margin, st);
+  if (b->n_items == 0) return hipSuccess;
+  hipError_t e = launch_batch_reset(b->mem.cols, (uint32_t)b->n_items, b->mem.out, st);
   if (e != hipSuccess || b->n_work == 0 || b->cls_mask == 0) return e;
-  e = launch_batch_bin(make_args(b->mem, (uint32_t)b->n_items, b->n_work, 0), st);
-  if (e != hipSuccess) return e;
   if (nbr > 0) {
     e = hipEventRecord(ev[0], st);
     for (int i = 0; i < nbr && e == hipSuccess; ++i) e = hipStreamWaitEvent(br[i], ev[0], 0);
@@ -367,7 +398,7 @@ scan_status selector_pick(scan_ctx* ctx, const scan_column* col, int32_t enc, ui
   }
   if (!sc) {
     sc = new PickScratch();
-    const hipError_t e = sc->mem.allocate(1, 1, std::max<size_t>(segs.size(), 64), false);
+    const hipError_t e = sc->mem.allocate(1, 1, std::max<size_t>(segs.size(), 64));
     if (e != hipSuccess) {
       sc->mem.release();
       delete sc;
@@ -424,8 +455,7 @@ scan_status scan_batch_prepare(scan_ctx* ctx, const scan_item* items, size_t n_i
     return fail(ctx, SCAN_EINVAL, "too many work items");
   }
   b->n_work = (uint32_t)work.size();
-  b->cls_mask = possible_classes(b->cols, b->selector);
-  e = b->mem.allocate(n_items, work.size(), b->selector ? segs.size() : 0, b->selector);
+  e = b->mem.allocate(n_items, work.size(), b->selector ? segs.size() : 0);
   if (e != hipSuccess) {
     free_plan(b);
     return fail(ctx, SCAN_ENOMEM, "batch buffers: %s", hipGetErrorString(e));
@@ -435,21 +465,36 @@ scan_status scan_batch_prepare(scan_ctx* ctx, const scan_item* items, size_t n_i
     e = hipMemcpy(b->mem.work, work.data(), sizeof(BatchWork) * work.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess && b->selector && !segs.empty())
     e = hipMemcpy(b->mem.segs, segs.data(), sizeof(BatchWork) * segs.size(), hipMemcpyHostToDevice);
-  // the selector as it is now is part of the batch: a later change of the
-  // context's selector does not reach replays of this one
-  if (e == hipSuccess && b->selector) {
-    e = hipStreamSynchronize(ctx->stream);
-    if (e == hipSuccess)
-      e = hipMemcpy(b->mem.theta, selector_theta(ctx), sizeof(float) * kThetaFloats, hipMemcpyDeviceToDevice);
+  // The planning pass.  The selector as it is now decides the strategies:
+  // a later change of the context's selector does not reach this batch.
+  const uint32_t n = (uint32_t)n_items;
+  if (e == hipSuccess && n)
+    e = enqueue_select(b->mem, n, b->selector ? selector_theta(ctx) : nullptr, b->margin, ctx->stream);
+  if (e == hipSuccess && n)
+    e = hipMemcpyAsync(b->cols.data(), b->mem.cols, sizeof(BatchCol) * n, hipMemcpyDeviceToHost, ctx->stream);
+  std::vector<float> scores;
+  if (e == hipSuccess && n && b->selector) {
+    scores.resize((size_t)n * 8);
+    e = hipMemcpyAsync(scores.data(), b->mem.scores, sizeof(float) * scores.size(), hipMemcpyDeviceToHost,
+                       ctx->stream);
   }
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess && n && b->selector) {
+    std::vector<int32_t> before(n);
+    for (uint32_t i = 0; i < n; ++i) before[i] = b->cols[i].strategy;
+    prune_classes(b->cols, scores, ctx->class_scan_us);
+    for (uint32_t i = 0; i < n; ++i) b->pruned += b->cols[i].strategy != before[i] ? 1u : 0u;
+    e = hipMemcpy(b->mem.cols, b->cols.data(), sizeof(BatchCol) * n, hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess && b->n_work) e = launch_batch_bin(make_args(b->mem, n, b->n_work, 0), ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
     free_plan(b);
-    return hip_fail(ctx, e, "batch upload");
+    return hip_fail(ctx, e, "batch planning");
   }
-  b->kernels = n_items == 0 ? 1u
-                            : 2u + (b->selector ? 2u + (b->mem.n_segs ? 1u : 0u) : 0u) +
-                                  (b->n_work && b->cls_mask ? 1u + (uint32_t)__builtin_popcount(b->cls_mask) : 0u);
-  if (ctx->batch_graph) capture_batch(ctx, b, ctx->batch_graph == 2);
+  b->cls_mask = b->n_work ? used_classes(b->cols) : 0u;
+  b->kernels = n == 0 ? 0u : 1u + (uint32_t)__builtin_popcount(b->cls_mask);
+  if (ctx->batch_graph && b->kernels) capture_batch(ctx, b, ctx->batch_graph == 2);
   const uint64_t h = ctx->next_batch++;
   ctx->batches[h] = b;
   *handle = h;
@@ -564,6 +609,13 @@ scan_status scan_batch_autotune(scan_ctx* ctx, const scan_item* items, size_t n_
   return SCAN_OK;
 }
 
+scan_status scan_batch_set_class_cost(scan_ctx* ctx, float us) {
+  if (!ctx) return SCAN_EINVAL;
+  if (!(us >= 0.0f) || !std::isfinite(us)) return fail(ctx, SCAN_EINVAL, "class cost must be finite and >= 0");
+  ctx->class_scan_us = us;
+  return SCAN_OK;
+}
+
 scan_status scan_batch_set_graph(scan_ctx* ctx, int32_t mode) {
   if (!ctx) return SCAN_EINVAL;
   if (mode < 0 || mode > 2) return fail(ctx, SCAN_EINVAL, "graph mode must be 0, 1 or 2");
@@ -581,6 +633,8 @@ scan_status scan_batch_info(scan_ctx* ctx, uint64_t handle, scan_batch_stats* ou
   out->kernels = b->kernels;
   out->class_mask = b->cls_mask;
   out->work_items = b->n_work;
+  out->pruned = b->pruned;
+  out->reserved = 0;
   return SCAN_OK;
 }
 
@@ -596,7 +650,7 @@ scan_status scan_features(scan_ctx* ctx, const scan_item* items, size_t n_items,
   for (size_t i = 0; i < n_items; ++i)
     if (status[i] != SCAN_OK) return (scan_status)status[i];
   BatchBuffers m;
-  hipError_t e = m.allocate(n_items, 1, segs.size(), false);
+  hipError_t e = m.allocate(n_items, 1, segs.size());
   if (e == hipSuccess)
     e = hipMemcpyAsync(m.cols, cols.data(), sizeof(BatchCol) * n_items, hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess && !segs.empty())

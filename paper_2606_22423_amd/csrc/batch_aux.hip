@@ -264,6 +264,18 @@ hipError_t launch_batch_select(BatchCol* cols, uint32_t n_cols, const float* sco
   return hipGetLastError();
 }
 
+// Start of a replay of a planned batch: every result slot cleared, carrying
+// the strategy its column uses (fixed when the batch was planned).
+__global__ __launch_bounds__(256) void batch_reset_kernel(const BatchCol* cols, uint32_t n_cols, BatchOut* out) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_cols) out[i] = BatchOut{0, 0, 0, (uint64_t)(uint32_t)cols[i].strategy};
+}
+
+hipError_t launch_batch_reset(const BatchCol* cols, uint32_t n_cols, BatchOut* out, hipStream_t st) {
+  hipLaunchKernelGGL(batch_reset_kernel, dim3((n_cols + 255) / 256), dim3(256), 0, st, cols, n_cols, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_batch_bin(const BatchArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(batch_bin_kernel, dim3((a.n_work + 255) / 256), dim3(256), 0, st, a);
   return hipGetLastError();

@@ -188,7 +188,7 @@ __device__ __forceinline__ void dict_flush(WaveState<uint32_t>& s, uint32_t lane
                                                        dlast, c.clo, c.chi);                                  \
     break;
 
-constexpr uint32_t kBatchDictBytes = kMaxDict * 8u;
+constexpr uint32_t kBatchDictBytes = kDictLdsBytes;
 
 template <int DEC, int MODE>
 __device__ __forceinline__ void batch_dict_share(const BatchArgs& a, const uint32_t* items, uint32_t n,
@@ -210,8 +210,18 @@ __device__ __forceinline__ void batch_dict_share(const BatchArgs& a, const uint3
       const int64_t* src = a.cols[col].dict;
       const uint32_t len = a.cols[col].dict_len < kMaxDict ? a.cols[col].dict_len : kMaxDict;
       const uint32_t clo = a.cols[col].clo, chi = a.cols[col].chi;
-      // entries outside the column's code range are 0 (see mask_dictionary)
-      for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) dict[i] = (i >= clo && i < chi) ? src[i] : 0;
+      // staged as code_scan stages it: packed (branch-free classes, when the
+      // window's range allows) or masked, 0 outside [clo, chi) up to the zero slot
+      uint64_t base = clo < chi ? (uint64_t)src[clo] : 0ull;
+      const bool packed = MODE == MODE_BF && (clo >= chi || (uint64_t)src[chi - 1u] - base < kDictMaxRange);
+      for (uint32_t i = threadIdx.x; i <= kDictZeroSlot; i += blockDim.x) {
+        int64_t e = 0;
+        if (i >= clo && i < chi)
+          e = packed ? (int64_t)(((uint64_t)src[i] - base) | (1ull << kDictCountShift)) : src[i];
+        dict[i] = e;
+      }
+      s.dict_packed = packed;
+      s.dict_base = base;
       __syncthreads();
       cur = col;
       dlast = len ? len - 1u : 0u;

@@ -12,6 +12,11 @@ namespace scan_dev {
 
 constexpr uint32_t kBlockValues = 1024;  // values per block (zone map / layout unit)
 constexpr uint32_t kMaxDict = 4096;      // dictionary entries staged in LDS
+// The LDS dictionary area: kMaxDict entries, then one zero entry (read for a
+// partial last block's padding slots and for codes past the area), padded to
+// 16 bytes.
+constexpr uint32_t kDictZeroSlot = kMaxDict;
+constexpr uint32_t kDictLdsBytes = kMaxDict * 8u + 16u;
 constexpr uint32_t kRingEntries = 128;   // per-wavefront selection-vector ring (u32 or u64 entries)
 
 enum Dec { DEC_RM_LDS = 0, DEC_RM_DIRECT = 1, DEC_LI = 2, DEC_BYTES = 3 };

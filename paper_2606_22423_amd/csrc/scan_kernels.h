@@ -69,13 +69,8 @@ struct Geo {
 // every fourth value, so the scheduler still interleaves four values.
 template <typename T>
 __device__ __forceinline__ void pin(T& x) {
-  if constexpr (sizeof(T) == 4) {
-    asm volatile("" : "+v"(x));
-  } else {
-    uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
-    asm volatile("" : "+v"(lo), "+v"(hi));
-    x = ((T)hi << 32) | lo;
-  }
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "one VGPR or an aligned VGPR pair");
+  asm volatile("" : "+v"(x));
 }
 
 // ------------------------------------------------------------------ loads
@@ -126,6 +121,10 @@ struct WaveState {
   uint64_t lcount = 0;  // per lane (branch-free mode counts per lane, no ballot)
   uint32_t head = 0, tail = 0;  // selection-vector ring counters (uniform)
   EntryT* ring = nullptr;
+  // branch-free dictionary scans: the LDS dictionary holds packed entries
+  // (see pack_dictionary) relative to dict_base (uniform)
+  bool dict_packed = false;
+  uint64_t dict_base = 0;
 };
 
 // Value of a selected code: FOR adds the code (references are added through
@@ -136,14 +135,48 @@ __device__ __forceinline__ uint64_t code_value(uint32_t c, const int64_t* dict_l
   else return (uint64_t)c;
 }
 
-// Zero the LDS dictionary's entries outside the code range [clo, chi): a
-// branch-free scan then adds every code's entry (0 for a code that fails the
-// predicate) and a compacted one only ever reads entries inside the range.
-// Ends with a barrier.
-__device__ __forceinline__ void mask_dictionary(int64_t* dict_lds, uint32_t len, uint32_t clo, uint32_t chi) {
-  for (uint32_t i = threadIdx.x; i < len; i += blockDim.x)
+// Zero the LDS dictionary area outside the code window [clo, chi), up to and
+// including the zero slot: a branch-free scan then adds every code's entry
+// (0 for a code that fails) with no compare and no select, and a compacted
+// one only reads entries inside the window.  Ends with a barrier.
+__device__ __forceinline__ void mask_dictionary(int64_t* dict_lds, uint32_t clo, uint32_t chi) {
+  for (uint32_t i = threadIdx.x; i <= kDictZeroSlot; i += blockDim.x)
     if (i < clo || i >= chi) dict_lds[i] = 0;
   __syncthreads();
+}
+
+// Packed dictionary for branch-free scans: an entry inside the code window
+// [clo, chi) becomes (entry - base) + 2^58 with base the window's first
+// entry, every other slot 0.  One 64-bit add per code then accumulates both
+// results: over one block (at most 32 codes per lane) the high six bits hold
+// the matches and the low 58 bits the sum of (entry - base), which cannot
+// carry into them while the window's range (last - first entry) is below
+// 2^53.  SUM = that sum + base x COUNT (mod 2^64).  Returns whether the
+// window qualifies (uniform); if not, the dictionary is only masked
+// (mask_dictionary).  Reads the staged entries, ends with a barrier.
+constexpr int kDictCountShift = 58;
+constexpr uint64_t kDictSumMask = (1ull << kDictCountShift) - 1ull;
+constexpr uint64_t kDictMaxRange = 1ull << 53;
+__device__ __forceinline__ bool pack_dictionary(int64_t* dict_lds, uint32_t clo, uint32_t chi, uint64_t& base) {
+  base = clo < chi ? (uint64_t)dict_lds[clo] : 0ull;
+  const bool packed = clo >= chi || (uint64_t)dict_lds[chi - 1u] - base < kDictMaxRange;
+  __syncthreads();  // every thread has read the window's ends before the entries change
+  for (uint32_t i = threadIdx.x; i <= kDictZeroSlot; i += blockDim.x) {
+    int64_t e = 0;
+    if (i >= clo && i < chi) e = packed ? (int64_t)(((uint64_t)dict_lds[i] - base) | (1ull << kDictCountShift))
+                                        : dict_lds[i];
+    dict_lds[i] = e;
+  }
+  __syncthreads();
+  return packed;
+}
+
+// Index of a code's entry in the masked LDS dictionary: codes of b <= 12 bits
+// stay inside the area; wider codes at or past the zero slot read it.
+template <int B>
+__device__ __forceinline__ uint32_t dict_index(uint32_t c) {
+  if constexpr (B > 12) return c < kDictZeroSlot ? c : kDictZeroSlot;
+  else return c;
 }
 
 
@@ -487,29 +520,51 @@ __device__ __forceinline__ void decode_pair(const Params& p, WaveState<uint32_t>
       if constexpr (PF == PF_REFS) s.lsum += (uint64_t)lc * ref;
     }
   } else if constexpr (MODE == MODE_BF && ENC == ENC_DICT) {
-    // Branch-free dictionary: the LDS dictionary holds 0 outside the code
-    // range [clo, chi) (see mask_dictionary), so the sum gathers every
-    // code's entry with no compare and no select; COUNT comes from packed
-    // fields (b <= 15, full blocks) or one compare per code.  Only a partial
-    // last block masks its padding slots.
-    uint32_t lc = 0;
-    if constexpr (!TAIL && B <= 15) {
+    // Branch-free dictionary: SUM adds every code's entry from the masked
+    // LDS dictionary (no compare, no select; a partial last block's padding
+    // slots read the zero slot).  COUNT: packed fields for b <= 8 on full
+    // blocks, else one compare per code and a scalar popcount of the
+    // wavefront's mask; a lane whose block is absent or cannot match compares
+    // against an empty window (a dictionary's code window is at most kMaxDict
+    // wide, so its width does not overflow).
+    if (s.dict_packed) {
+      // packed entries: one 64-bit add per code (see pack_dictionary)
+#pragma unroll
+      for (int t = 0; t < 32; ++t) {
+        const uint32_t c = run_code<B, B>(w, t);
+        uint32_t idx = dict_index<B>(c);
+        if (TAIL) idx = (((DEC == DEC_RM_DIRECT) ? (32u * l + t) : (32u * t + l)) < limit) ? idx : kDictZeroSlot;
+        part += (uint64_t)dict_lds[idx];
+        if ((t & 7) == 7) pin(part);
+      }
+      if (act) {
+        const uint32_t lc = (uint32_t)(part >> kDictCountShift);
+        s.lcount += lc;
+        s.lsum += (part & kDictSumMask) + s.dict_base * lc;
+      }
+      return;
+    }
+    constexpr bool kFields = !TAIL && B <= 8;
+    uint32_t lc = 0;   // per lane (packed fields)
+    uint32_t cnt = 0;  // uniform (compares)
+    if constexpr (kFields) {
       uint32_t unused = 0;
       swar_count_sum<B, PF>(w, cr.loc, cr.wm1, lc, unused);
     }
+    uint32_t width = act ? cr.wm1 + 1u : 0u;
+    pin(width);  // a per-lane bound: keeps the compiler from splitting it back into act && compare
 #pragma unroll
     for (int t = 0; t < 32; ++t) {
       const uint32_t c = run_code<B, B>(w, t);
       bool valid = true;
       if (TAIL) valid = (((DEC == DEC_RM_DIRECT) ? (32u * l + t) : (32u * t + l)) < limit);
-      if constexpr (TAIL || B > 15) lc += (valid && (c - cr.loc) <= cr.wm1) ? 1u : 0u;
-      const uint64_t v = code_value<ENC>(c, dict_lds, dict_last);
-      part += TAIL ? (valid ? v : 0ull) : v;
-      if ((t & 3) == 3) {
-        pin(part);
-        pin(lc);
-      }
+      if constexpr (!kFields) cnt += (uint32_t)__builtin_popcountll(ballot(valid && (c - cr.loc) < width));
+      uint32_t idx = dict_index<B>(c);
+      if (TAIL) idx = valid ? idx : kDictZeroSlot;
+      part += (uint64_t)dict_lds[idx];
+      if ((t & 7) == 7) pin(part);
     }
+    s.count += cnt;
     if (act) {
       s.lcount += lc;
       s.lsum += (uint64_t)part;
@@ -639,7 +694,27 @@ __device__ __forceinline__ void decode_staged(const Params& p, WaveState<uint32_
   const uint32_t* sp = st + (bit0 >> 5);
   const uint32_t sh = bit0 & 31u;
   uint32_t cnt = 0;
+  uint32_t ucnt = 0;  // branch-free dictionary: uniform count
   PartT<B, ENC> part = 0;
+  if constexpr (MODE == MODE_BF && ENC == ENC_DICT) {
+    if (s.dict_packed) {
+      // packed entries: one 64-bit add per code (see pack_dictionary)
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        uint32_t c;
+        if (B == 32) c = sp[64 * t];
+        else c = funnel(sp[2 * B * t + 1], sp[2 * B * t], sh) & width_mask<B>();
+        uint32_t idx = dict_index<B>(c);
+        if (TAIL) idx = (lane + 64u * t < limit) ? idx : kDictZeroSlot;
+        part += (uint64_t)dict_lds[idx];
+        if ((t & 3) == 3) pin(part);
+      }
+      const uint32_t lc = (uint32_t)(part >> kDictCountShift);
+      s.lcount += lc;
+      s.lsum += (part & kDictSumMask) + s.dict_base * lc;
+      return;
+    }
+  }
 #pragma unroll
   for (int t = 0; t < 16; ++t) {
     uint32_t c;
@@ -648,14 +723,13 @@ __device__ __forceinline__ void decode_staged(const Params& p, WaveState<uint32_
     const bool hit = (PF == PF_LO0) ? (c <= cr.wm1) : ((c - cr.loc) <= cr.wm1);
     const bool valid = !TAIL || (lane + 64u * t < limit);
     if constexpr (MODE == MODE_BF && ENC == ENC_DICT) {
-      // masked dictionary (0 outside [clo, chi)): gather every valid code's entry
-      cnt += (hit && valid) ? 1u : 0u;
-      const uint64_t v = code_value<ENC>(c, dict_lds, dict_last);
-      part += valid ? v : 0ull;
-      if ((t & 3) == 3) {
-        pin(part);
-        pin(cnt);
-      }
+      // a window too wide to pack: scalar popcount of the compare mask and
+      // the masked entry (padding slots read the zero slot)
+      ucnt += (uint32_t)__builtin_popcountll(ballot(hit && valid));
+      uint32_t idx = dict_index<B>(c);
+      if (TAIL) idx = valid ? idx : kDictZeroSlot;
+      part += (uint64_t)dict_lds[idx];
+      if ((t & 3) == 3) pin(part);
     } else if constexpr (MODE == MODE_BF) {
       const bool ok = hit && valid;
       cnt += ok ? 1u : 0u;
@@ -672,7 +746,10 @@ __device__ __forceinline__ void decode_staged(const Params& p, WaveState<uint32_
       sv_push<ENC, uint32_t>(s, c, hit && valid, m, lane, dict_lds, dict_last);
     }
   }
-  if constexpr (MODE == MODE_BF) {
+  if constexpr (MODE == MODE_BF && ENC == ENC_DICT) {
+    s.count += ucnt;
+    s.lsum += (uint64_t)part;
+  } else if constexpr (MODE == MODE_BF) {
     s.lcount += cnt;  // per lane
     s.lsum += (uint64_t)part + (uint64_t)cnt * ref;
   } else {
@@ -880,7 +957,7 @@ __host__ __device__ constexpr uint32_t wave_lds_words() {
 // Dynamic LDS bytes of code_scan for a work-group of `waves` wavefronts.
 template <int B, int DEC, int MODE, int ENC>
 __host__ __device__ constexpr uint32_t code_scan_lds(uint32_t waves) {
-  return (ENC == ENC_DICT ? kMaxDict * 8u : 0u) + waves * wave_lds_words<B, DEC, MODE>() * 4u;
+  return (ENC == ENC_DICT ? kDictLdsBytes : 0u) + waves * wave_lds_words<B, DEC, MODE>() * 4u;
 }
 
 // Step depth of scan_range: the default pipelined steps, the alternative
@@ -947,7 +1024,7 @@ __global__ __launch_bounds__(256) void code_scan(const Params p) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   int64_t* dict_lds = reinterpret_cast<int64_t*>(smem);
-  uint32_t* wave_area = reinterpret_cast<uint32_t*>(smem + (ENC == ENC_DICT ? kMaxDict * 8u : 0u)) +
+  uint32_t* wave_area = reinterpret_cast<uint32_t*>(smem + (ENC == ENC_DICT ? kDictLdsBytes : 0u)) +
                         wave * wave_lds_words<B, DEC, MODE>();
   uint32_t* list = wave_area;
   uint32_t* st = wave_area + kListWords;  // 16-byte aligned: the list is 256 bytes
@@ -962,7 +1039,8 @@ __global__ __launch_bounds__(256) void code_scan(const Params p) {
     chi = lower_bound_lds(dict_lds, p.dict_len, p.hi);
     dict_last = p.dict_len - 1u;
     __syncthreads();  // every thread has its code range before the entries change
-    mask_dictionary(dict_lds, p.dict_len, clo, chi);
+    if constexpr (MODE == MODE_BF) s.dict_packed = pack_dictionary(dict_lds, clo, chi, s.dict_base);
+    else mask_dictionary(dict_lds, clo, chi);
   }
   // Grid-strided windows of p.G blocks: at any moment the wavefronts read one
   // compact region of the column (DRAM row locality), like a streaming copy.

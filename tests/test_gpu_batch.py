@@ -384,6 +384,7 @@ def test_selector_margin_keeps_the_heuristic_unless_the_gain_is_large(ctx, cases
     margin = 0.25
     ctx.selector_set(theta)
     ctx.selector_set_margin(margin)
+    ctx.batch_set_class_cost(0.0)  # the batch keeps every choice: compared with scan_run's below
     path = str(tmp_path / "sel_margin.txt")
     try:
         ctx.features(items, X)
@@ -398,6 +399,7 @@ def test_selector_margin_keeps_the_heuristic_unless_the_gain_is_large(ctx, cases
     finally:
         ctx.selector_clear()
         ctx.selector_set_margin(0.0)
+        ctx.batch_set_class_cost(10.0)
     pred, _ = omlp.forward(theta.astype(np.float64), X.cpu().numpy().astype(np.float64), K)
     valid = np.array([[zm or not ((q >> 2) & 1) for q in range(K)] for _, _, _, zm in meta])
     heur = np.array([5 if zm else 1 for _, _, _, zm in meta])  # RM-direct, branch-free, zone maps when present
@@ -463,3 +465,62 @@ def test_batch_1024_columns_up_to_2p22_matches_oracle(ctx):
 
         with ThreadPoolExecutor(16) as ex:
             assert all(ex.map(verify, zip(cases, res)))
+
+
+def test_batch_class_cost_takes_back_choices_needing_their_own_class_scan(ctx, cases):
+    """A prepared batch keeps the network's choice for a column unless the
+    choice needs a class scan (encoding x decoder x mode) that no heuristic or
+    explicit column of the batch uses and the predicted gains of the class's
+    columns do not pay for its launch: cost 0 keeps every choice scan_run
+    makes; an unbounded cost takes back exactly the choices whose class scan
+    only learned choices would use.  Results stay exact either way."""
+    theta = random_theta(14)
+    items, meta = [], []
+    for j, c in enumerate(cases):
+        lo, hi = predicates(c, j)
+        zm = j % 7 != 3
+        items.append(c.col.item(lo, hi, -1, zone_maps=zm))
+        meta.append((c, lo, hi, zm))
+
+    def prepared(cost):
+        ctx.batch_set_class_cost(cost)
+        h = ctx.batch_prepare(items)
+        try:
+            return ctx.batch_replay(h, len(items)), ctx.batch_info(h)
+        finally:
+            ctx.batch_release(h)
+
+    ctx.selector_set(theta)
+    try:
+        single = [ctx.run(c.col, lo, hi, -1, zone_maps=zm)["strategy_used"] & ~16 for c, lo, hi, zm in meta]
+        keep, info0 = prepared(0.0)
+        taken, info1 = prepared(1e30)
+    finally:
+        ctx.selector_clear()
+        ctx.batch_set_class_cost(10.0)
+    assert [g["strategy_used"] & ~16 for g in keep] == single
+    assert info0["pruned"] == 0
+
+    def class_of(c, s):
+        return c.spec.enc * 4 + (s & 1) * 2 + ((s >> 2) & 1)
+
+    def live(c, lo, hi):
+        if c.spec.n == 0 or lo >= hi:
+            return False
+        return c.spec.enc != ENC_FOR or max(lo, 0) < min(hi, 1 << 32)
+
+    heur = [strategy(DEC_RM_DIRECT, 0, 1 if zm else 0) for _, _, _, zm in meta]
+    alive = [live(c, lo, hi) for c, lo, hi, _ in meta]
+    base = {class_of(m[0], s) for m, s, h, a in zip(meta, single, heur, alive) if a and s == h}
+    want = [s if (not a or s == h or class_of(m[0], s) in base) else h
+            for m, s, h, a in zip(meta, single, heur, alive)]
+    assert [g["strategy_used"] & ~16 for g in taken] == want
+    assert info1["pruned"] == sum(w != s for w, s in zip(want, single)) > 0
+    assert bin(info1["class_mask"]).count("1") <= bin(info0["class_mask"]).count("1")
+    say("class cost: %d of %d choices taken back, class scans %d -> %d" %
+        (info1["pruned"], len(items), bin(info0["class_mask"]).count("1"), bin(info1["class_mask"]).count("1")))
+    for (c, lo, hi, _), g0, g1 in zip(meta, keep, taken):
+        check_item(c, g0, lo, hi, (c.spec.index, "cost 0"))
+        check_item(c, g1, lo, hi, (c.spec.index, "cost inf"))
+    for bad in (-1.0, float("nan"), float("inf")):
+        assert ctx.lib.scan_batch_set_class_cost(ctx.h, bad) == _lib.SCAN_EINVAL

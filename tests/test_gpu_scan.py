@@ -205,6 +205,44 @@ def test_dict_every_strategy(ctx, b):
                 check(ctx.run(col, lo, hi, s), want, (s >> 3) & 1, (b, n, lo, hi, _lib.strategy_name(s)), want_off)
 
 
+def wide_dictionary(b):
+    """Sorted entries over [-2^62, 2^62): for b = 3 a hand-made one with
+    windows of range 2^53 - 1 and 2^53 exactly, else stratified draws."""
+    if b == 3:
+        e = [-(1 << 62), -(1 << 62) + 1, -(1 << 62) + (1 << 53) - 1, -(1 << 62) + (1 << 53), 0, 5,
+             (1 << 62) - 3, (1 << 62) - 1]
+        return np.array(e, dtype=np.int64)
+    return synth.dict_entries(min(1 << b, 4096), 17, b, 62)
+
+
+@pytest.mark.parametrize("b", [3, 8, 12])
+def test_dict_packed_and_wide_code_windows(ctx, b):
+    """Branch-free dictionary scans carry the match count inside packed
+    entries when the selected entries span less than 2^53 and compare per
+    code otherwise.  Windows on both sides of that bound (for b = 3: ranges
+    2^53 - 1 and 2^53 exactly), negative entries and sums that wrap mod 2^64
+    match the oracle in every strategy, single scans and a batch."""
+    dct = wide_dictionary(b)
+    m = len(dct)
+    windows = [(0, 2), (0, 3), (1, 3), (0, m - 1), (4, 5), (m // 2, m // 2)] if b == 3 else \
+        [(0, 0), (5, 7), (m // 3, m // 3 + 3), (m // 3, m // 3 + 5), (0, m - 1), (m - 9, m - 1)]
+    for n in (5 * 1024 + 3, 300 * 1024 + 7):
+        codes = synth.bounded(31, b, n, m)
+        w = oracle.pack_rm(codes, b)
+        col = api.encode_dict(codes, b, dct)
+        items, wants = [], []
+        for i, j in windows:
+            lo, hi = int(dct[i]), int(dct[j]) + 1
+            want = oracle.scan_dict(w, dct, n, b, lo, hi, zone_maps=True)
+            want_off = oracle.scan_dict(w, dct, n, b, lo, hi, zone_maps=False)
+            for s in rm_strategies(b, ENC_DICT):
+                check(ctx.run(col, lo, hi, s), want, (s >> 3) & 1, (b, n, i, j, _lib.strategy_name(s)), want_off)
+                items.append(col.item(lo, hi, s))
+                wants.append((want, want_off, s, (b, n, i, j)))
+        for got, (want, want_off, s, what) in zip(ctx.batch_run(items), wants):
+            check(got, want, (s >> 3) & 1, what + ("batch", _lib.strategy_name(s)), want_off)
+
+
 def test_sorted_column_zone_maps_read_exact_blocks(ctx):
     n, nd = 1 << 22, 1 << 8  # 2^14 copies per value: 16 whole blocks each
     v = synth.config3_column(n, nd, 0).numpy().astype(np.uint32)
