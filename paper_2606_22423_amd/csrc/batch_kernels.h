@@ -210,7 +210,7 @@ __device__ __forceinline__ void batch_dict_share(const BatchArgs& a, const uint3
       const int64_t* src = a.cols[col].dict;
       const uint32_t len = a.cols[col].dict_len < kMaxDict ? a.cols[col].dict_len : kMaxDict;
       const uint32_t clo = a.cols[col].clo, chi = a.cols[col].chi;
-      // staged as code_scan stages it: packed (branch-free classes, when the
+      // the form stage_dictionary writes: packed (branch-free classes, when the
       // window's range allows) or masked, 0 outside [clo, chi) up to the zero slot
       uint64_t base = clo < chi ? (uint64_t)src[clo] : 0ull;
       const bool packed = MODE == MODE_BF && (clo >= chi || (uint64_t)src[chi - 1u] - base < kDictMaxRange);
@@ -282,6 +282,16 @@ using BatchLaunchFn = hipError_t (*)(const BatchArgs&, uint32_t grid, uint32_t b
 
 template <int ENC, int DEC, int MODE>
 hipError_t launch_batch_class(const BatchArgs& a, uint32_t grid, uint32_t block, hipStream_t st, int* occ) {
+  if constexpr (ENC == ENC_DICT) {
+    // the dictionary is addressed from LDS address 0 (see dict_at)
+    static const hipError_t lds0 = [] {
+      hipFuncAttributes fa;
+      const hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(batch_scan<ENC, DEC, MODE>));
+      if (e != hipSuccess) return e;
+      return fa.sharedSizeBytes == 0 ? hipSuccess : hipErrorInvalidConfiguration;
+    }();
+    if (lds0 != hipSuccess) return lds0;
+  }
   const uint32_t lds = (ENC == ENC_DICT ? kBatchDictBytes : 0u) + (block / 64u) * kBatchWaveWords * 4u;
   if (occ) return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, batch_scan<ENC, DEC, MODE>, (int)block, lds);
   hipLaunchKernelGGL((batch_scan<ENC, DEC, MODE>), dim3(grid), dim3(block), lds, st, a);

@@ -177,9 +177,13 @@ hipError_t launch_fold(const Partial* partials, uint32_t n, Result* out, uint64_
 // last-work-group ticket instead needs an agent-scope release per
 // work-group, i.e. an L2 write-back on this multi-XCD part, and cost 5-11 us
 // per launch; stream order makes the partials visible to the fold for free.
-// `count` and `blocks` are wave-uniform, `lane_sum` per lane.
-__device__ __forceinline__ void write_partial(Partial* partials, uint64_t count, uint64_t lane_sum, uint64_t blocks) {
-  __shared__ uint64_t red[16][3];
+// `count` and `blocks` are wave-uniform, `lane_sum` per lane.  `red`: LDS
+// for 16 x 3 values (kRedBytes); the scan kernels place it at the end of their
+// dynamic LDS, which leaves their own LDS data at address 0 (no base add in
+// the dictionary gathers' addresses).
+constexpr uint32_t kRedBytes = 16u * 3u * 8u;
+__device__ __forceinline__ void write_partial(Partial* partials, uint64_t count, uint64_t lane_sum, uint64_t blocks,
+                                              uint64_t (*red)[3]) {
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const uint64_t s = wave_sum_u64(lane_sum);
   if (lane == 0) {
@@ -202,9 +206,14 @@ __device__ __forceinline__ void write_partial(Partial* partials, uint64_t count,
   }
 }
 
-__device__ __forceinline__ void finish_scan(const Params& p, uint64_t count, uint64_t lane_sum,
-                                            uint64_t blocks) {
-  write_partial(p.partials, count, lane_sum, blocks);
+__device__ __forceinline__ void write_partial(Partial* partials, uint64_t count, uint64_t lane_sum, uint64_t blocks) {
+  __shared__ uint64_t red[16][3];
+  write_partial(partials, count, lane_sum, blocks, red);
+}
+
+__device__ __forceinline__ void finish_scan(const Params& p, uint64_t count, uint64_t lane_sum, uint64_t blocks,
+                                            uint64_t (*red)[3]) {
+  write_partial(p.partials, count, lane_sum, blocks, red);
 }
 
 }  // namespace scan_dev

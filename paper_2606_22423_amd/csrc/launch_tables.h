@@ -10,6 +10,17 @@ namespace scan_dev {
 // work-groups of `block` threads fit on one compute unit.
 using LaunchFn = hipError_t (*)(const Params&, uint32_t grid, uint32_t block, hipStream_t stream, int* occ);
 
+// Whether a kernel holds no static LDS, so that its dynamic LDS starts at
+// address 0 (the dictionary kernels address their entries from 0, see
+// dict_at).  Checked once per kernel.
+template <typename K>
+inline hipError_t lds_starts_at_zero(K kern) {
+  hipFuncAttributes fa;
+  const hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kern));
+  if (e != hipSuccess) return e;
+  return fa.sharedSizeBytes == 0 ? hipSuccess : hipErrorInvalidConfiguration;
+}
+
 template <typename K>
 inline hipError_t launch_kernel(K kern, bool& attr_done, const Params& p, uint32_t grid, uint32_t block,
                                 uint32_t lds, hipStream_t st, int* occ) {
@@ -27,6 +38,10 @@ inline hipError_t launch_kernel(K kern, bool& attr_done, const Params& p, uint32
 template <int B, int DEC, int MODE, int ENC, int PF, int STEP = STEP_DEFAULT>
 hipError_t launch_code(const Params& p, uint32_t grid, uint32_t block, hipStream_t st, int* occ) {
   static bool attr = false;
+  if constexpr (ENC == ENC_DICT) {
+    static const hipError_t lds0 = lds_starts_at_zero(code_scan<B, DEC, MODE, ENC, PF, STEP>);
+    if (lds0 != hipSuccess) return lds0;
+  }
   return launch_kernel(code_scan<B, DEC, MODE, ENC, PF, STEP>, attr, p, grid, block,
                        code_scan_lds<B, DEC, MODE, ENC>(block / 64u), st, occ);
 }

@@ -164,6 +164,13 @@ scan_tune default_tune(int32_t enc, uint32_t b, int32_t s) {
   if (b <= 12) t.window_blocks = 64;
   else if (b <= 16 || (s >= 0 && (s & 3) == SCAN_DEC_LI)) t.window_blocks = 16;
   else t.window_blocks = 4;
+  // Dictionary scans wait on LDS gathers: the autotuner on MI355X picks four
+  // work-groups per CU (as many as the LDS dictionary lets fit), 64-block
+  // windows up to b = 8 and short ones above.
+  if (enc == SCAN_ENC_DICT) {
+    t.wgs_per_cu = 4;
+    t.window_blocks = b <= 8 ? 64 : 8;
+  }
   // With zone maps every window costs one dependent zone-map load and ballot
   // per wavefront: 64-block windows test 64 blocks per step.
   if (s >= 0 && ((s >> 3) & 1)) t.window_blocks = 64;

@@ -122,7 +122,7 @@ struct WaveState {
   uint32_t head = 0, tail = 0;  // selection-vector ring counters (uniform)
   EntryT* ring = nullptr;
   // branch-free dictionary scans: the LDS dictionary holds packed entries
-  // (see pack_dictionary) relative to dict_base (uniform)
+  // (see stage_dictionary) relative to dict_base (uniform)
   bool dict_packed = false;
   uint64_t dict_base = 0;
 };
@@ -135,40 +135,88 @@ __device__ __forceinline__ uint64_t code_value(uint32_t c, const int64_t* dict_l
   else return (uint64_t)c;
 }
 
-// Zero the LDS dictionary area outside the code window [clo, chi), up to and
-// including the zero slot: a branch-free scan then adds every code's entry
-// (0 for a code that fails) with no compare and no select, and a compacted
-// one only reads entries inside the window.  Ends with a barrier.
-__device__ __forceinline__ void mask_dictionary(int64_t* dict_lds, uint32_t clo, uint32_t chi) {
-  for (uint32_t i = threadIdx.x; i <= kDictZeroSlot; i += blockDim.x)
-    if (i < clo || i >= chi) dict_lds[i] = 0;
-  __syncthreads();
-}
-
 // Packed dictionary for branch-free scans: an entry inside the code window
 // [clo, chi) becomes (entry - base) + 2^58 with base the window's first
 // entry, every other slot 0.  One 64-bit add per code then accumulates both
 // results: over one block (at most 32 codes per lane) the high six bits hold
 // the matches and the low 58 bits the sum of (entry - base), which cannot
 // carry into them while the window's range (last - first entry) is below
-// 2^53.  SUM = that sum + base x COUNT (mod 2^64).  Returns whether the
-// window qualifies (uniform); if not, the dictionary is only masked
-// (mask_dictionary).  Reads the staged entries, ends with a barrier.
+// 2^53.  SUM = that sum + base x COUNT (mod 2^64).  A window of larger range
+// is only masked: its entries as they are, every other slot 0.
 constexpr int kDictCountShift = 58;
 constexpr uint64_t kDictSumMask = (1ull << kDictCountShift) - 1ull;
 constexpr uint64_t kDictMaxRange = 1ull << 53;
-__device__ __forceinline__ bool pack_dictionary(int64_t* dict_lds, uint32_t clo, uint32_t chi, uint64_t& base) {
-  base = clo < chi ? (uint64_t)dict_lds[clo] : 0ull;
-  const bool packed = clo >= chi || (uint64_t)dict_lds[chi - 1u] - base < kDictMaxRange;
-  __syncthreads();  // every thread has read the window's ends before the entries change
-  for (uint32_t i = threadIdx.x; i <= kDictZeroSlot; i += blockDim.x) {
-    int64_t e = 0;
-    if (i >= clo && i < chi) e = packed ? (int64_t)(((uint64_t)dict_lds[i] - base) | (1ull << kDictCountShift))
-                                        : dict_lds[i];
-    dict_lds[i] = e;
+
+// Stage a dictionary in LDS, in the form the scan reads (packed when PACK and
+// the window qualifies, else masked, up to and including the zero slot), for
+// the code window [clo, chi) of the predicate [lo, hi).  The entries are
+// sorted and distinct, so clo and chi are the numbers of entries below lo and
+// below hi: counted while the entries arrive, with each thread's loads in
+// flight together, instead of two binary searches after them.  `scratch`:
+// 32 words of LDS.  Ends with a barrier.
+template <bool PACK>
+__device__ __forceinline__ void stage_dictionary(const int64_t* __restrict__ src, uint32_t len, int64_t lo, int64_t hi,
+                                                 int64_t* dict_lds, uint32_t* scratch, uint32_t& clo, uint32_t& chi,
+                                                 bool& packed, uint64_t& base) {
+  constexpr uint32_t kPer = 8;
+  const uint32_t bd = blockDim.x, lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nw = bd >> 6;
+  uint32_t nlo = 0, nhi = 0;
+  for (uint32_t c0 = 0; c0 < len; c0 += bd * kPer) {
+    int64_t e[kPer];
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j) {
+      const uint32_t i = c0 + threadIdx.x + j * bd;
+      e[j] = i < len ? src[i] : 0;
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j) {
+      const uint32_t i = c0 + threadIdx.x + j * bd;
+      if (i < len) {
+        nlo += e[j] < lo ? 1u : 0u;
+        nhi += e[j] < hi ? 1u : 0u;
+        dict_lds[i] = e[j];
+      }
+    }
+  }
+  nlo = (uint32_t)wave_sum_u64(nlo);
+  nhi = (uint32_t)wave_sum_u64(nhi);
+  if (lane == 0) {
+    scratch[wave] = nlo;
+    scratch[16u + wave] = nhi;
   }
   __syncthreads();
-  return packed;
+  clo = 0;
+  chi = 0;
+  for (uint32_t w = 0; w < nw; ++w) {
+    clo += scratch[w];
+    chi += scratch[16u + w];
+  }
+  base = clo < chi ? (uint64_t)dict_lds[clo] : 0ull;
+  packed = PACK && (clo >= chi || (uint64_t)dict_lds[chi - 1u] - base < kDictMaxRange);
+  __syncthreads();  // every thread has read the window's ends before the entries change
+  for (uint32_t c0 = 0; c0 <= kDictZeroSlot; c0 += bd * kPer) {
+    int64_t e[kPer];
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j) {
+      const uint32_t i = c0 + threadIdx.x + j * bd;
+      e[j] = (i >= clo && i < chi) ? dict_lds[i] : 0;
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j) {
+      const uint32_t i = c0 + threadIdx.x + j * bd;
+      if (i <= kDictZeroSlot) {
+        int64_t v = e[j];
+        if (packed && i >= clo && i < chi) v = (int64_t)(((uint64_t)v - base) | (1ull << kDictCountShift));
+        dict_lds[i] = v;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+typedef __attribute__((address_space(3))) const int64_t LdsI64;
+__device__ __forceinline__ uint64_t dict_at(uint32_t idx) {
+  return (uint64_t)*reinterpret_cast<LdsI64*>((uintptr_t)(idx * 8u));
 }
 
 // Index of a code's entry in the masked LDS dictionary: codes of b <= 12 bits
@@ -528,14 +576,21 @@ __device__ __forceinline__ void decode_pair(const Params& p, WaveState<uint32_t>
     // against an empty window (a dictionary's code window is at most kMaxDict
     // wide, so its width does not overflow).
     if (s.dict_packed) {
-      // packed entries: one 64-bit add per code (see pack_dictionary)
+      // packed entries: one 64-bit add per code (see stage_dictionary); the
+      // reads go out in groups of eight before their adds
 #pragma unroll
-      for (int t = 0; t < 32; ++t) {
-        const uint32_t c = run_code<B, B>(w, t);
-        uint32_t idx = dict_index<B>(c);
-        if (TAIL) idx = (((DEC == DEC_RM_DIRECT) ? (32u * l + t) : (32u * t + l)) < limit) ? idx : kDictZeroSlot;
-        part += (uint64_t)dict_lds[idx];
-        if ((t & 7) == 7) pin(part);
+      for (int g = 0; g < 32; g += 8) {
+        uint64_t e[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int t = g + k;
+          const uint32_t c = run_code<B, B>(w, t);
+          uint32_t idx = dict_index<B>(c);
+          if (TAIL) idx = (((DEC == DEC_RM_DIRECT) ? (32u * l + t) : (32u * t + l)) < limit) ? idx : kDictZeroSlot;
+          e[k] = dict_at(idx);
+        }
+        part += ((e[0] + e[1]) + (e[2] + e[3])) + ((e[4] + e[5]) + (e[6] + e[7]));
+        pin(part);
       }
       if (act) {
         const uint32_t lc = (uint32_t)(part >> kDictCountShift);
@@ -698,16 +753,23 @@ __device__ __forceinline__ void decode_staged(const Params& p, WaveState<uint32_
   PartT<B, ENC> part = 0;
   if constexpr (MODE == MODE_BF && ENC == ENC_DICT) {
     if (s.dict_packed) {
-      // packed entries: one 64-bit add per code (see pack_dictionary)
+      // packed entries: one 64-bit add per code (see stage_dictionary); the
+      // reads go out in groups of eight before their adds
 #pragma unroll
-      for (int t = 0; t < 16; ++t) {
-        uint32_t c;
-        if (B == 32) c = sp[64 * t];
-        else c = funnel(sp[2 * B * t + 1], sp[2 * B * t], sh) & width_mask<B>();
-        uint32_t idx = dict_index<B>(c);
-        if (TAIL) idx = (lane + 64u * t < limit) ? idx : kDictZeroSlot;
-        part += (uint64_t)dict_lds[idx];
-        if ((t & 3) == 3) pin(part);
+      for (int g = 0; g < 16; g += 8) {
+        uint64_t e[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int t = g + k;
+          uint32_t c;
+          if (B == 32) c = sp[64 * t];
+          else c = funnel(sp[2 * B * t + 1], sp[2 * B * t], sh) & width_mask<B>();
+          uint32_t idx = dict_index<B>(c);
+          if (TAIL) idx = (lane + 64u * t < limit) ? idx : kDictZeroSlot;
+          e[k] = dict_at(idx);
+        }
+        part += ((e[0] + e[1]) + (e[2] + e[3])) + ((e[4] + e[5]) + (e[6] + e[7]));
+        pin(part);
       }
       const uint32_t lc = (uint32_t)(part >> kDictCountShift);
       s.lcount += lc;
@@ -936,16 +998,6 @@ __device__ __forceinline__ void run_bytes(const Params& p, WaveState<uint32_t>& 
 
 // ------------------------------------------------------------ FOR / DICT
 
-__device__ __forceinline__ uint32_t lower_bound_lds(const int64_t* d, uint32_t m, int64_t x) {
-  uint32_t a = 0, e = m;
-  while (a < e) {
-    const uint32_t mid = (a + e) >> 1;
-    if (d[mid] < x) a = mid + 1u;
-    else e = mid;
-  }
-  return a;
-}
-
 constexpr uint32_t kListWords = 64;  // per-wavefront survivor list
 
 template <int B, int DEC, int MODE>
@@ -957,7 +1009,7 @@ __host__ __device__ constexpr uint32_t wave_lds_words() {
 // Dynamic LDS bytes of code_scan for a work-group of `waves` wavefronts.
 template <int B, int DEC, int MODE, int ENC>
 __host__ __device__ constexpr uint32_t code_scan_lds(uint32_t waves) {
-  return (ENC == ENC_DICT ? kDictLdsBytes : 0u) + waves * wave_lds_words<B, DEC, MODE>() * 4u;
+  return (ENC == ENC_DICT ? kDictLdsBytes : 0u) + waves * wave_lds_words<B, DEC, MODE>() * 4u + kRedBytes;
 }
 
 // Step depth of scan_range: the default pipelined steps, the alternative
@@ -1031,16 +1083,15 @@ __global__ __launch_bounds__(256) void code_scan(const Params p) {
   WaveState<uint32_t> s;
   s.ring = st + (DEC == DEC_RM_LDS ? Geo<B>::kLdsBlocks * Geo<B>::kStageWords : 0u);
 
+  // LDS after the wavefront areas: the work-group reduction of the result
+  // (and, before the scan, the dictionary staging's counts)
+  auto* red = reinterpret_cast<uint64_t(*)[3]>(smem + (ENC == ENC_DICT ? kDictLdsBytes : 0u) +
+                                               nw * wave_lds_words<B, DEC, MODE>() * 4u);
   uint32_t clo = 0, chi = 0, dict_last = 0;
   if constexpr (ENC == ENC_DICT) {
-    for (uint32_t i = threadIdx.x; i < p.dict_len; i += blockDim.x) dict_lds[i] = p.dict[i];
-    __syncthreads();
-    clo = lower_bound_lds(dict_lds, p.dict_len, p.lo);
-    chi = lower_bound_lds(dict_lds, p.dict_len, p.hi);
+    stage_dictionary<MODE == MODE_BF>(p.dict, p.dict_len, p.lo, p.hi, dict_lds, reinterpret_cast<uint32_t*>(red), clo,
+                                      chi, s.dict_packed, s.dict_base);
     dict_last = p.dict_len - 1u;
-    __syncthreads();  // every thread has its code range before the entries change
-    if constexpr (MODE == MODE_BF) s.dict_packed = pack_dictionary(dict_lds, clo, chi, s.dict_base);
-    else mask_dictionary(dict_lds, clo, chi);
   }
   // Grid-strided windows of p.G blocks: at any moment the wavefronts read one
   // compact region of the column (DRAM row locality), like a streaming copy.
@@ -1048,7 +1099,7 @@ __global__ __launch_bounds__(256) void code_scan(const Params p) {
   scan_range<B, DEC, MODE, ENC, PF, STEP>(p, s, lane, list, st, gw * p.G, p.nb, tw * p.G, p.G, dict_lds, dict_last,
                                            clo, chi);
   if constexpr (MODE == MODE_SV) sv_drain_rest<ENC, uint32_t>(s, lane, dict_lds, dict_last);
-  finish_scan(p, s.count + wave_sum_u64(s.lcount), s.lsum + (lane == 0 ? s.refsum : 0ull), s.blocks);
+  finish_scan(p, s.count + wave_sum_u64(s.lcount), s.lsum + (lane == 0 ? s.refsum : 0ull), s.blocks, red);
 }
 
 // ------------------------------------------------------------- delta scan
@@ -1229,7 +1280,7 @@ __host__ __device__ constexpr uint32_t delta_wave_words() {
 
 template <int B, int DEC, int MODE>
 __host__ __device__ constexpr uint32_t delta_scan_lds(uint32_t waves) {
-  return waves * delta_wave_words<B, DEC, MODE>() * 4u;
+  return waves * delta_wave_words<B, DEC, MODE>() * 4u + kRedBytes;
 }
 
 // Scan blocks [ka, ke) of a delta column into the wavefront state (see
@@ -1345,7 +1396,8 @@ __global__ __launch_bounds__(256) void delta_scan(const Params p) {
   const uint64_t gw = (uint64_t)blockIdx.x * nw + wave, tw = (uint64_t)gridDim.x * nw;
   delta_range<B, DEC, MODE, false>(p, s, lane, list, st, gw * p.G, p.nb, tw * p.G, p.G);
   if constexpr (MODE == MODE_SV) sv_drain_rest<ENC_DELTA, R>(s, lane, nullptr, 0);
-  finish_scan(p, s.count + wave_sum_u64(s.lcount), s.lsum + (lane == 0 ? s.refsum : 0ull), s.blocks);
+  auto* red = reinterpret_cast<uint64_t(*)[3]>(smem + nw * delta_wave_words<B, DEC, MODE>() * 4u);
+  finish_scan(p, s.count + wave_sum_u64(s.lcount), s.lsum + (lane == 0 ? s.refsum : 0ull), s.blocks, red);
 }
 
 }  // namespace scan_dev
