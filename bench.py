@@ -99,8 +99,8 @@ def batch_leg(ctx, torch, ncols, reps, selector_path, batch_selector_path=None, 
     reported beside it).  Batched: one prepared batch (planned once, replayed
     as one graph launch), replays timed, with the default strategy and with
     the batch selector's choices (made on the device when the batch is
-    planned; the planning time is reported beside).  Results of every column
-    must agree."""
+    planned; the planning time is reported beside), the two batches' replays
+    alternating.  Results of every column must agree."""
     import numpy as np
 
     import synth
@@ -221,8 +221,29 @@ def batch_leg(ctx, torch, ncols, reps, selector_path, batch_selector_path=None, 
         # margin, then the class-scan cost); replays reuse the plan
         ctx.selector_load(bsel)
         chosen = [ctx.run(c, lo, hi, -1)["strategy_used"] & ~16 for c, lo, hi in cols]
-        t_bl, got, t_prep, info_l = batched([c.item(lo, hi, -1) for c, lo, hi in cols], "batched learned")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        h_l = ctx.batch_prepare([c.item(lo, hi, -1) for c, lo, hi in cols])
+        t_prep = time.perf_counter() - t1
         ctx.selector_clear()
+        h_d = ctx.batch_prepare([c.item(lo, hi, default) for c, lo, hi in cols])
+        try:
+            info_l = ctx.batch_info(h_l)
+            got = ctx.batch_replay(h_l, ncols)
+            check_batch(got, "batched learned")
+            check_batch(ctx.batch_replay(h_d, ncols), "batched default")
+            # default and learned replays alternate, so that clock and
+            # thermal drift over the leg reach both alike
+            td, tl = [], []
+            for _ in range(2 * reps):
+                td.append(timed(lambda: ctx.batch_replay(h_d, wait=False)))
+                tl.append(timed(lambda: ctx.batch_replay(h_l, wait=False)))
+            check_batch(ctx.batch_replay(h_l, ncols), "batched learned")
+        finally:
+            ctx.batch_release(h_l)
+            ctx.batch_release(h_d)
+        t_bl = float(np.median(tl))
+        res["batched_default_ms"] = round(float(np.median(td)) * 1e3, 3)
         used = [g["strategy_used"] for g in got]
         heur = strategy(DEC_RM_DIRECT, 0, 1)
         if any(u != s and u != heur for u, s in zip(used, chosen)):

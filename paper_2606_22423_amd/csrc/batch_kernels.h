@@ -214,12 +214,27 @@ __device__ __forceinline__ void batch_dict_share(const BatchArgs& a, const uint3
       // window's range allows) or masked, 0 outside [clo, chi) up to the zero slot
       uint64_t base = clo < chi ? (uint64_t)src[clo] : 0ull;
       const bool packed = MODE == MODE_BF && (clo >= chi || (uint64_t)src[chi - 1u] - base < kDictMaxRange);
-      for (uint32_t i = threadIdx.x; i <= kDictZeroSlot; i += blockDim.x) {
-        int64_t e = 0;
-        if (i >= clo && i < chi)
-          e = packed ? (int64_t)(((uint64_t)src[i] - base) | (1ull << kDictCountShift)) : src[i];
-        dict[i] = e;
+      // slots a code can reach: the entries, and up to 2^b (at most kMaxDict)
+      const uint32_t b = a.cols[col].b;
+      const uint32_t reach = b <= 12u ? (1u << b) : kMaxDict;
+      const uint32_t top = len > reach ? len : reach;
+      // eight loads in flight per thread, then their slots
+      for (uint32_t c0 = 0; c0 < top; c0 += blockDim.x * 8u) {
+        int64_t e[8];
+#pragma unroll
+        for (uint32_t j = 0; j < 8u; ++j) {
+          const uint32_t i = c0 + threadIdx.x + j * blockDim.x;
+          e[j] = (i >= clo && i < chi) ? src[i] : 0;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < 8u; ++j) {
+          const uint32_t i = c0 + threadIdx.x + j * blockDim.x;
+          if (i < top)
+            dict[i] = (packed && i >= clo && i < chi)
+                          ? (int64_t)(((uint64_t)e[j] - base) | (1ull << kDictCountShift)) : e[j];
+        }
       }
+      if (threadIdx.x == 0) dict[kDictZeroSlot] = 0;
       s.dict_packed = packed;
       s.dict_base = base;
       __syncthreads();
@@ -243,7 +258,8 @@ __device__ __forceinline__ void batch_dict_share(const BatchArgs& a, const uint3
 }
 
 template <int ENC, int DEC, int MODE>
-__global__ __launch_bounds__(256) void batch_scan(const BatchArgs a) {
+// At least two wavefronts per SIMD (two work-groups per CU): at most 256 VGPRs.
+__global__ __launch_bounds__(256, 2) void batch_scan(const BatchArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
   constexpr uint32_t kDictBytes = ENC == ENC_DICT ? kBatchDictBytes : 0u;

@@ -152,12 +152,13 @@ constexpr uint64_t kDictMaxRange = 1ull << 53;
 // the code window [clo, chi) of the predicate [lo, hi).  The entries are
 // sorted and distinct, so clo and chi are the numbers of entries below lo and
 // below hi: counted while the entries arrive, with each thread's loads in
-// flight together, instead of two binary searches after them.  `scratch`:
-// 32 words of LDS.  Ends with a barrier.
+// flight together, instead of two binary searches after them.  Slots from
+// len up to `reach` (the codes' range, at most kMaxDict) and the zero slot
+// are 0.  `scratch`: 32 words of LDS.  Ends with a barrier.
 template <bool PACK>
-__device__ __forceinline__ void stage_dictionary(const int64_t* __restrict__ src, uint32_t len, int64_t lo, int64_t hi,
-                                                 int64_t* dict_lds, uint32_t* scratch, uint32_t& clo, uint32_t& chi,
-                                                 bool& packed, uint64_t& base) {
+__device__ __forceinline__ void stage_dictionary(const int64_t* __restrict__ src, uint32_t len, uint32_t reach,
+                                                 int64_t lo, int64_t hi, int64_t* dict_lds, uint32_t* scratch,
+                                                 uint32_t& clo, uint32_t& chi, bool& packed, uint64_t& base) {
   constexpr uint32_t kPer = 8;
   const uint32_t bd = blockDim.x, lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nw = bd >> 6;
   uint32_t nlo = 0, nhi = 0;
@@ -194,7 +195,8 @@ __device__ __forceinline__ void stage_dictionary(const int64_t* __restrict__ src
   base = clo < chi ? (uint64_t)dict_lds[clo] : 0ull;
   packed = PACK && (clo >= chi || (uint64_t)dict_lds[chi - 1u] - base < kDictMaxRange);
   __syncthreads();  // every thread has read the window's ends before the entries change
-  for (uint32_t c0 = 0; c0 <= kDictZeroSlot; c0 += bd * kPer) {
+  const uint32_t top = len > reach ? len : reach;
+  for (uint32_t c0 = 0; c0 < top; c0 += bd * kPer) {
     int64_t e[kPer];
 #pragma unroll
     for (uint32_t j = 0; j < kPer; ++j) {
@@ -204,13 +206,14 @@ __device__ __forceinline__ void stage_dictionary(const int64_t* __restrict__ src
 #pragma unroll
     for (uint32_t j = 0; j < kPer; ++j) {
       const uint32_t i = c0 + threadIdx.x + j * bd;
-      if (i <= kDictZeroSlot) {
+      if (i < top) {
         int64_t v = e[j];
         if (packed && i >= clo && i < chi) v = (int64_t)(((uint64_t)v - base) | (1ull << kDictCountShift));
         dict_lds[i] = v;
       }
     }
   }
+  if (threadIdx.x == 0) dict_lds[kDictZeroSlot] = 0;
   __syncthreads();
 }
 
@@ -1089,8 +1092,8 @@ __global__ __launch_bounds__(256) void code_scan(const Params p) {
                                                nw * wave_lds_words<B, DEC, MODE>() * 4u);
   uint32_t clo = 0, chi = 0, dict_last = 0;
   if constexpr (ENC == ENC_DICT) {
-    stage_dictionary<MODE == MODE_BF>(p.dict, p.dict_len, p.lo, p.hi, dict_lds, reinterpret_cast<uint32_t*>(red), clo,
-                                      chi, s.dict_packed, s.dict_base);
+    stage_dictionary<MODE == MODE_BF>(p.dict, p.dict_len, B <= 12 ? (1u << B) : kMaxDict, p.lo, p.hi, dict_lds,
+                                      reinterpret_cast<uint32_t*>(red), clo, chi, s.dict_packed, s.dict_base);
     dict_last = p.dict_len - 1u;
   }
   // Grid-strided windows of p.G blocks: at any moment the wavefronts read one

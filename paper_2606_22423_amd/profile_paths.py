@@ -91,7 +91,7 @@ def main(argv=None):
                 s = strategy(dec, 0, 0)
                 ms = timed(lambda: ctx.run_async(col, lo, hi, s, out))
                 cases.append({"name": "dictionary b=%d %s/bf/nozm" % (b, dec_names[dec]),
-                              "kernel": r"code_scan<%d, %d, 0, 2, \d+>" % (b, dec), "launches": args.launches,
+                              "kernel": r"code_scan<%d, %d, 0, 2, \d+(, \d+)?>" % (b, dec), "launches": args.launches,
                               "algorithmic_bytes": n * b // 8, "values": n, "event_ms": ms})
             del col
             say("dictionary b=%d done" % b)
@@ -194,7 +194,7 @@ def main(argv=None):
             hi = synth.lt_bound(sg, b)
             cnt = int(ctx.select(col, 0, hi, zone_maps=False, out=pos).numel())
             ms = timed(lambda: ctx.select(col, 0, hi, zone_maps=False, out=pos))
-            cases.append({"name": "select mark pass b=16 sigma=%g" % sg, "kernel": r"select_mark_kernel<16>",
+            cases.append({"name": "select mark pass b=16 sigma=%g" % sg, "kernel": r"select_mark_kernel<16u?>",
                           "launches": args.launches + 1, "warmup": 1, "algorithmic_bytes": n * b // 8 + n // 8 + (n // 1024) * 4,
                           "values": n, "event_ms": ms, "group": sg})
             cases.append({"name": "select write pass b=16 sigma=%g (%d positions)" % (sg, cnt),

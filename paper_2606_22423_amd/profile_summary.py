@@ -32,8 +32,9 @@ def kernel_source_hash() -> str:
 
 
 def short_name(name: str) -> str:
-    """'void scan_dev::code_scan<31, 2, 0, 0, 2>(scan_dev::Params)' -> 'code_scan<B=31,li/bf/nozm>'."""
-    m = re.search(r"code_scan<(\d+), (\d+), (\d+), (\d+), (\d+)>", name)
+    """'void scan_dev::code_scan<31, 2, 0, 0, 2, 0>(scan_dev::Params)' -> 'code_scan<B=31,li/bf/nozm>'
+    (either step depth: the timed region runs the one the autotuner chose)."""
+    m = re.search(r"code_scan<(\d+), (\d+), (\d+), (\d+), (\d+)(?:, \d+)?>", name)
     if m:
         b, dec, mode = int(m.group(1)), int(m.group(2)), int(m.group(3))
         return "code_scan<B=%d,%s/%s/nozm>" % (b, DEC[dec], "sv" if mode else "bf")
