@@ -183,9 +183,10 @@ def batch_leg(ctx, torch, ncols, reps, selector_path, batch_selector_path=None, 
     # launch shape of the class kernels for this workload (the batch autotuner),
     # used by every batch below
     t0 = time.time()
-    (per_cu, win), _ = ctx.batch_autotune([c.item(lo, hi, default) for c, lo, hi in cols], reps=3)
-    res["batch_tune"] = {"wgs_per_cu": per_cu, "window_blocks": win}
-    log("[bench] batch autotune: %d work-groups per CU, %d-block windows (%.0f s)" % (per_cu, win, time.time() - t0))
+    (per_cu, win, order), _ = ctx.batch_autotune([c.item(lo, hi, default) for c, lo, hi in cols], reps=3)
+    res["batch_tune"] = {"wgs_per_cu": per_cu, "window_blocks": win, "list_order": order}
+    log("[bench] batch autotune: %d work-groups per CU, %d-block windows, list order %d (%.0f s)" %
+        (per_cu, win, order, time.time() - t0))
     # the default strategy as one replay: direct launches (0), one graph (1,
     # the library default), one graph with the class scans forked over branches (2)
     by_mode = {}

@@ -291,14 +291,14 @@ scan_status scan_gather(scan_ctx* ctx, const scan_column* col, int32_t enc, uint
 /* ---------------------------------------------------------------- batches */
 /* Not in the paper (the workload's mixed-column batch).
  * Many columns (mixed length, width, encoding, strategy) scanned by one fixed
- * sequence of kernels, whatever the number of columns: per-column setup,
- * strategy selection on the device (the loaded selector for SCAN_STRAT_AUTO
- * items: zone-map features, the network, the argmin; else the heuristic),
- * binning of the columns' work items (four windows of blocks each) by
- * (encoding, decoder, predicate mode), then one persistent kernel per class
- * that can occur, walking its items on a static schedule (a work-group per
- * item, one window per wavefront; dictionary classes hold the column's
- * dictionary in LDS).
+ * sequence of kernels, whatever the number of columns.  Planned once:
+ * per-column setup, strategy selection on the device (the loaded selector for
+ * SCAN_STRAT_AUTO items: zone-map features, the network, the argmin; else the
+ * heuristic), and lists of the columns' work items (four windows of blocks
+ * each) per class (encoding, decoder, predicate mode), in item order.  A
+ * replay: one persistent kernel per class with items, walking its list on a
+ * static schedule (a work-group per item, one window per wavefront;
+ * dictionary classes hold the column's dictionary in LDS).
  * Columns must be row-major;
  * explicit strategies must use the SCAN_DEC_RM_LDS or SCAN_DEC_RM_DIRECT
  * decoder.  Results equal scan_run's for every item, bit for bit.
@@ -337,13 +337,14 @@ scan_status scan_batch_release(scan_ctx* ctx, uint64_t handle);
 scan_status scan_batch_run(scan_ctx* ctx, const scan_item* items, size_t n_items, scan_result* out);
 /* Launch tuning of the batch class kernels (wgs_per_cu, window_blocks). */
 scan_status scan_batch_set_tune(scan_ctx* ctx, const scan_tune* t);
-/* Autotuner of the batch class kernels: for each of work-groups per CU
- * {1, 2, 4, 8} x window {16, 32, 64} blocks, prepares the batch (graph mode
- * as set), replays it once, then times `reps` replays (at most 16) with HIP
- * events, each after the 512 MiB cache-evicting read (allocated on first
- * use, as for scan_autotune), and keeps the median-fastest configuration as
- * the batch tuning (scan_batch_set_tune).  *out / *ms_out (host, may be
- * NULL) receive it and its time.  Results never depend on the tuning.  An
+/* Autotuner of the batch class kernels: for each of class-list order {0, 1}
+ * x work-groups per CU {1, 2, 4, 8} x window {16, 32, 64} blocks, prepares
+ * the batch (graph mode as set), replays it once, then times `reps` replays
+ * (at most 16) with HIP events, each after the 512 MiB cache-evicting read
+ * (allocated on first use, as for scan_autotune), and keeps the
+ * median-fastest configuration as the batch tuning (scan_batch_set_tune)
+ * and list order (scan_batch_set_order).  *out / *ms_out (host, may be
+ * NULL) receive it (out->depth: the list order) and its time.  Results never depend on the tuning.  An
  * empty batch -> SCAN_EINVAL; on failure the previous tuning is restored. */
 scan_status scan_batch_autotune(scan_ctx* ctx, const scan_item* items, size_t n_items, int32_t reps, scan_tune* out,
                                 float* ms_out);
@@ -353,6 +354,14 @@ scan_status scan_batch_autotune(scan_ctx* ctx, const scan_item* items, size_t n_
  * MI355X: the concurrent class scans contend).  Results are the same.
  * Other values -> SCAN_EINVAL. */
 scan_status scan_batch_set_graph(scan_ctx* ctx, int32_t mode);
+/* Order of the class lists of later scan_batch_prepare calls: 0 item order
+ * (columns in the batch's order, each column's work items in block order),
+ * 1 (the default) that order walked with a stride: list position j takes
+ * item (j * (2^31 - 1)) mod L of the L items, which spreads every column's
+ * items over the static schedule.  Deterministic either way; results are the
+ * same, the speed differs with the mix (the batch autotuner tries both).
+ * Other values -> SCAN_EINVAL. */
+scan_status scan_batch_set_order(scan_ctx* ctx, int32_t order);
 /* Cost in microseconds of one more class scan in a replay (its launch and
  * drain; default 10, measured on MI355X with 4096-column batches), used by
  * later scan_batch_prepare calls to take back selector choices that would

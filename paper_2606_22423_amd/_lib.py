@@ -143,6 +143,7 @@ SIGNATURES = {
     "scan_batch_autotune": (_i32, [_vp, _P(ScanItem), ctypes.c_size_t, _i32, _P(ScanTune), _P(ctypes.c_float)]),
     "scan_batch_info": (_i32, [_vp, _u64, _P(ScanBatchStats)]),
     "scan_batch_set_class_cost": (_i32, [_vp, _f32]),
+    "scan_batch_set_order": (_i32, [_vp, _i32]),
     "scan_mlp_param_count": (ctypes.c_int, []),
     "scan_selector_set": (_i32, [_vp, _vp, ctypes.c_size_t]),
     "scan_selector_clear": (_i32, [_vp]),

@@ -417,17 +417,21 @@ class Context:
         return {"captured": int(s.captured), "kernels": int(s.kernels), "class_mask": int(s.class_mask),
                 "work_items": int(s.work_items), "pruned": int(s.pruned)}
 
+    def batch_set_order(self, order: int):
+        self.check(self.lib.scan_batch_set_order(self.h, int(order)), "scan_batch_set_order")
+
     def batch_set_class_cost(self, us: float):
         self.check(self.lib.scan_batch_set_class_cost(self.h, float(us)), "scan_batch_set_class_cost")
 
     def batch_autotune(self, items, reps: int = 3):
-        """Search work-groups per CU x window for this batch; returns ((wgs_per_cu, window), best ms)."""
+        """Search list order x work-groups per CU x window for this batch;
+        returns ((wgs_per_cu, window, order), best ms)."""
         arr = self._items(items)
         t = ScanTune()
         ms = ctypes.c_float()
         self.check(self.lib.scan_batch_autotune(self.h, arr, len(items), reps, ctypes.byref(t), ctypes.byref(ms)),
                    "scan_batch_autotune")
-        return (t.wgs_per_cu, t.window_blocks), float(ms.value)
+        return (t.wgs_per_cu, t.window_blocks, t.depth), float(ms.value)
 
     def batch_set_tune(self, wgs_per_cu=0, window_blocks=0):
         t = ScanTune(0, wgs_per_cu, window_blocks, 0)

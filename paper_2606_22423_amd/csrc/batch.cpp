@@ -5,8 +5,9 @@
 //   -> [zone-map features -> selector MLP]  (when a selector is loaded)
 //   -> select (strategy per column, written on the device)
 //   -> [class pruning on the host, see prune_classes]
-//   -> bin (items into twelve class lists)
-// whose strategies and class lists every replay reuses (the items, the
+// then the class lists, built on the host in item order (so that a plan, and
+// the static schedule the class scans follow over it, is the same however
+// the device ran), whose strategies and lists every replay reuses (the items, the
 // selector and the zone maps are fixed for the life of the batch).  The
 // replay sequence
 //   reset (result slots) -> the class scans that have items (persistent,
@@ -36,7 +37,6 @@ hipError_t launch_batch_features(const BatchCol* cols, uint32_t n_cols, const Ba
                                  FeatPart* parts, float* X, hipStream_t st);
 hipError_t launch_batch_select(BatchCol* cols, uint32_t n_cols, const float* scores, int32_t k, float margin,
                                BatchOut* out, hipStream_t st);
-hipError_t launch_batch_bin(const BatchArgs& a, hipStream_t st);
 hipError_t launch_batch_reset(const BatchCol* cols, uint32_t n_cols, BatchOut* out, hipStream_t st);
 hipError_t launch_mlp_forward(const float* theta, const float* X, uint32_t rows, float* out, hipStream_t st);
 }  // namespace scan_dev
@@ -252,6 +252,7 @@ struct BatchPlan {
   bool forked = false;                    // class scans on parallel graph branches
   float margin = 0.0f;                    // the selector's margin when prepared
   uint32_t pruned = 0;                    // columns moved back to the heuristic (prune_classes)
+  int order = 0;                          // class-list order (scan_batch_set_order)
 };
 
 static void free_plan(BatchPlan* b) {
@@ -439,6 +440,7 @@ scan_status scan_batch_prepare(scan_ctx* ctx, const scan_item* items, size_t n_i
   b->n_items = n_items;
   b->selector = ctx->selector_ready;
   b->margin = ctx->selector_margin;
+  b->order = ctx->batch_order;
   b->grid = (uint32_t)ctx->cus * (uint32_t)std::clamp(t.wgs_per_cu, 1, 16);
   // dictionary classes hold the dictionary in LDS: fewer of their work-groups
   // fit on a compute unit, and their static shares are sized by the grid
@@ -486,7 +488,35 @@ scan_status scan_batch_prepare(scan_ctx* ctx, const scan_item* items, size_t n_i
     for (uint32_t i = 0; i < n; ++i) b->pruned += b->cols[i].strategy != before[i] ? 1u : 0u;
     e = hipMemcpy(b->mem.cols, b->cols.data(), sizeof(BatchCol) * n, hipMemcpyHostToDevice);
   }
-  if (e == hipSuccess && b->n_work) e = launch_batch_bin(make_args(b->mem, n, b->n_work, 0), ctx->stream);
+  // class lists: in item order (items are in column order, then block
+  // order), or that order walked with a stride (scan_batch_set_order)
+  if (e == hipSuccess && b->n_work) {
+    std::vector<uint32_t> lists((size_t)b->n_work * kBatchClasses);
+    uint32_t counts[kBatchClasses] = {};
+    for (uint32_t i = 0; i < b->n_work; ++i) {
+      const BatchCol& c = b->cols[work[i].col];
+      if (c.flags & (kColEmpty | kColSkip)) continue;
+      const int k = batch_class(c.enc, c.strategy);
+      lists[(size_t)k * b->n_work + counts[k]++] = i;
+    }
+    if (b->order == 1) {
+      // position j takes item (j * P) mod L, P = 2^31 - 1 (a prime above any
+      // list length L, so the walk is a permutation)
+      std::vector<uint32_t> tmp;
+      for (int k = 0; k < kBatchClasses; ++k) {
+        const uint64_t L = counts[k];
+        if (L < 2) continue;
+        uint32_t* l = &lists[(size_t)k * b->n_work];
+        tmp.assign(l, l + L);
+        for (uint64_t j = 0; j < L; ++j) l[j] = tmp[(j * 2147483647ull) % L];
+      }
+    }
+    e = hipMemcpyAsync(b->mem.lists, lists.data(), sizeof(uint32_t) * lists.size(), hipMemcpyHostToDevice,
+                       ctx->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b->mem.counters, counts, sizeof(counts), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);  // the host arrays outlive the copies
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
     free_plan(b);
@@ -568,11 +598,15 @@ scan_status scan_batch_autotune(scan_ctx* ctx, const scan_item* items, size_t n_
   }
   static const int kPerCu[] = {1, 2, 4, 8};
   static const int kWin[] = {16, 32, 64};
+  const int saved_order = ctx->batch_order;
   float best_ms = 1e30f;
   scan_tune best = saved;
+  int best_order = saved_order;
+  for (int order = 0; order < 2 && st == SCAN_OK; ++order)
   for (int pc : kPerCu) {
     for (int win : kWin) {
       ctx->tunes[key] = scan_tune{0, pc, win, 0};
+      ctx->batch_order = order;
       uint64_t h = 0;
       st = scan_batch_prepare(ctx, items, n_items, &h);
       if (st != SCAN_OK) break;
@@ -592,6 +626,7 @@ scan_status scan_batch_autotune(scan_ctx* ctx, const scan_item* items, size_t n_
       if (ts[reps / 2] < best_ms) {
         best_ms = ts[reps / 2];
         best = scan_tune{0, pc, win, 0};
+        best_order = order;
       }
     }
     if (st != SCAN_OK) break;
@@ -601,11 +636,23 @@ scan_status scan_batch_autotune(scan_ctx* ctx, const scan_item* items, size_t n_
   if (st != SCAN_OK) {
     if (had) ctx->tunes[key] = saved;
     else ctx->tunes.erase(key);
+    ctx->batch_order = saved_order;
     return st;
   }
   ctx->tunes[key] = best;
-  if (out) *out = best;
+  ctx->batch_order = best_order;
+  if (out) {
+    *out = best;
+    out->depth = best_order;  // for batches: the class-list order chosen
+  }
   if (ms_out) *ms_out = best_ms;
+  return SCAN_OK;
+}
+
+scan_status scan_batch_set_order(scan_ctx* ctx, int32_t order) {
+  if (!ctx) return SCAN_EINVAL;
+  if (order != 0 && order != 1) return fail(ctx, SCAN_EINVAL, "order must be 0 or 1");
+  ctx->batch_order = order;
   return SCAN_OK;
 }
 

@@ -214,32 +214,6 @@ __global__ __launch_bounds__(256) void batch_select_kernel(BatchCol* cols, uint3
   out[i].pad = (uint64_t)(uint32_t)s;
 }
 
-// Items into per-class lists with one atomic per class present in a
-// wavefront (atomics on one address serialize: one per item cost 0.28 ms for
-// the 27k items of a 4096-column batch).  The lanes of a class take
-// consecutive slots in lane order.  Every lane takes part in the atomic (the
-// class's first lane adds the class's lane count, the others 0; the compiler
-// folds it into one atomic) and that lane's old value is read into a scalar
-// register: the loop's control depends on ballots only and stays uniform.
-__global__ __launch_bounds__(256) void batch_bin_kernel(BatchArgs a) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t lane = threadIdx.x & 63u;
-  int cls = -1;
-  if (i < a.n_work) {
-    const BatchCol& c = a.cols[a.work[i].col];
-    if (!(c.flags & (kColEmpty | kColSkip))) cls = batch_class(c.enc, c.strategy);
-  }
-  for (uint64_t todo = ballot(cls >= 0); todo;) {
-    const uint32_t first = (uint32_t)__builtin_ctzll(todo);
-    const int k = (int)readlane((uint32_t)cls, first);
-    const uint64_t m = ballot(cls == k);
-    const uint32_t old = atomicAdd(&a.counts[k], lane == first ? (uint32_t)__builtin_popcountll(m) : 0u);
-    const uint32_t base = readlane(old, first);
-    if (cls == k) a.lists[(size_t)k * a.n_work + base + mbcnt(m)] = i;
-    todo &= ~m;
-  }
-}
-
 hipError_t launch_batch_setup(const BatchArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(batch_setup_kernel, dim3((a.n_cols + 255) / 256 + 1), dim3(256), 0, st, a);
   return hipGetLastError();
@@ -276,9 +250,5 @@ hipError_t launch_batch_reset(const BatchCol* cols, uint32_t n_cols, BatchOut* o
   return hipGetLastError();
 }
 
-hipError_t launch_batch_bin(const BatchArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(batch_bin_kernel, dim3((a.n_work + 255) / 256), dim3(256), 0, st, a);
-  return hipGetLastError();
-}
 
 }  // namespace scan_dev

@@ -164,6 +164,16 @@ scan_tune default_tune(int32_t enc, uint32_t b, int32_t s) {
   if (b <= 12) t.window_blocks = 64;
   else if (b <= 16 || (s >= 0 && (s & 3) == SCAN_DEC_LI)) t.window_blocks = 16;
   else t.window_blocks = 4;
+  // Delta scans wait on their per-block prefix sums: the autotuner on MI355X
+  // picks 4-8 work-groups per CU and short windows (2-16 blocks), with zone
+  // maps too.
+  if (enc == SCAN_ENC_DELTA_FOR) {
+    const bool zm = s >= 0 && ((s >> 3) & 1);
+    t.wgs_per_cu = zm || b <= 12 ? 8 : 4;
+    t.window_blocks = zm || b <= 8 ? 16 : b <= 12 ? 8 : 4;
+    t.depth = 0;
+    return t;
+  }
   // Dictionary scans wait on LDS gathers: the autotuner on MI355X picks four
   // work-groups per CU (as many as the LDS dictionary lets fit), 64-block
   // windows up to b = 8 and short ones above.

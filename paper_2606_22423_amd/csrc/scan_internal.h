@@ -43,6 +43,7 @@ struct scan_ctx {
   int32_t query_kernel = 0;           // SCAN_QUERY_PER_QUERY or SCAN_QUERY_SHARED (scan_query_run)
   int batch_graph = 1;                // prepared batches: 0 direct launches, 1 graph, 2 graph with forked class scans
   float class_scan_us = 10.0f;        // cost of one more class scan in a batch replay (scan_batch_set_class_cost)
+  int batch_order = 1;                // class-list order of prepared batches (scan_batch_set_order)
 };
 
 scan_status fail(scan_ctx* ctx, scan_status st, const char* fmt, ...);

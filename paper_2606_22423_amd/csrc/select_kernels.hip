@@ -151,12 +151,6 @@ struct GroupRegs {
   }
 };
 
-__device__ __forceinline__ uint64_t readlane64(uint64_t x, uint32_t l) {
-  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, l);
-  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(x >> 32), l);
-  return ((uint64_t)hi << 32) | lo;
-}
-
 }  // namespace
 
 template <uint32_t B>
@@ -289,10 +283,24 @@ __global__ __launch_bounds__(256) void scan_add_kernel(uint32_t* out, uint64_t m
 // Write pass: wavefront step = kWriteGroup consecutive blocks.  Lane j < 16
 // holds block g + j's count, offset and class; the ballots of the blocks that
 // have matches and no all-match shortcut arrive in four 8-byte loads per lane
-// (load i, lane l: block 4 i + l / 16, step l % 16).
+// (load i, lane l: block 4 i + l / 16, step l % 16).  The offsets are an
+// exclusive scan of the counts in block order, so the positions of four
+// consecutive blocks fill one contiguous range of the output: each quarter
+// (four blocks) is expanded into the wavefront's LDS buffer (every lane
+// writes the set bits of its own ballot word, whole blocks are filled with
+// their consecutive positions) and then copied out with coalesced stores.
+// Only the wavefront itself touches its buffer: no work-group barrier.
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 __global__ __launch_bounds__(256) void select_write_kernel(const SelParams p, uint32_t* positions) {
+  __shared__ uint32_t stage_all[kSelWaves][4u * kBlockValues];
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint32_t* stage = stage_all[wave];
   const ZRange zr = load_range(p);
   const uint64_t ngroups = (p.nb + kWriteGroup - 1) / kWriteGroup;
   const uint64_t tw = (uint64_t)gridDim.x * kSelWaves;
@@ -311,19 +319,20 @@ __global__ __launch_bounds__(256) void select_write_kernel(const SelParams p, ui
       const uint32_t blk = 4u * i + (lane >> 4);
       mk[i] = ((read >> blk) & 1ull) ? p.marks[(k0 + blk) * 16u + (lane & 15u)] : 0ull;
     }
-    // all-match blocks: their position ranges, unread
-    for (uint64_t rest = has & ~read; rest; rest &= rest - 1) {
-      const uint32_t j = (uint32_t)__builtin_ctzll(rest);
-      const uint32_t c = __builtin_amdgcn_readlane(cnt, j);
-      const uint32_t o = __builtin_amdgcn_readlane(off, j);
-      const uint32_t first = (uint32_t)((k0 + j) * kBlockValues);
-      for (uint32_t q = lane; q < c; q += 64u) positions[o + q] = first + q;
-    }
-    // blocks with ballots: each nonzero ballot at its block's offset plus the
-    // matches of the block's earlier steps (prefix sum over 16 lanes)
 #pragma unroll
     for (uint32_t i = 0; i < 4u; ++i) {
-      const uint64_t w = mk[i];
+      const uint32_t q0 = 4u * i;
+      if (!((has >> q0) & 0xFull)) continue;  // uniform: no match in the quarter
+      // the quarter's output range: from the offset of its first block with
+      // matches, as many positions as its blocks hold
+      const uint32_t first_blk = q0 + (uint32_t)__builtin_ctzll((has >> q0) & 0xFull);
+      const uint32_t base = __builtin_amdgcn_readlane(off, first_blk);
+      uint32_t span = 0;
+#pragma unroll
+      for (uint32_t j = 0; j < 4u; ++j) span += __builtin_amdgcn_readlane(cnt, q0 + j);
+      // ballot words: each lane places its word's positions after the
+      // matches of its block's earlier steps (prefix sum over 16 lanes)
+      uint64_t w = mk[i];
       const uint32_t pc = (uint32_t)__builtin_popcountll(w);
       uint32_t incl = pc;
 #pragma unroll
@@ -331,14 +340,23 @@ __global__ __launch_bounds__(256) void select_write_kernel(const SelParams p, ui
         const uint32_t y = __shfl_up(incl, d, 16);
         if ((lane & 15u) >= d) incl += y;
       }
-      const uint32_t wo = __shfl(off, 4u * i + (lane >> 4), 64) + incl - pc;
-      for (uint64_t nz = ballot(w != 0ull); nz; nz &= nz - 1) {
-        const uint32_t l = (uint32_t)__builtin_ctzll(nz);
-        const uint64_t m = readlane64(w, l);
-        const uint32_t o = __builtin_amdgcn_readlane(wo, l);
-        const uint32_t first = (uint32_t)((k0 + 4u * i + (l >> 4)) * kBlockValues) + 64u * (l & 15u);
-        if ((m >> lane) & 1ull) positions[o + mbcnt(m)] = first + lane;
+      uint32_t at = __shfl(off, q0 + (lane >> 4), 64) - base + incl - pc;
+      const uint32_t first = (uint32_t)((k0 + q0 + (lane >> 4)) * kBlockValues) + 64u * (lane & 15u);
+      while (w) {
+        stage[at++] = first + (uint32_t)__builtin_ctzll(w);
+        w &= w - 1ull;
       }
+      // whole blocks of the quarter: their positions are consecutive
+      for (uint64_t rest = (has & ~read) & (0xFull << q0); rest; rest &= rest - 1) {
+        const uint32_t j = (uint32_t)__builtin_ctzll(rest);
+        const uint32_t c = __builtin_amdgcn_readlane(cnt, j);
+        const uint32_t o = __builtin_amdgcn_readlane(off, j) - base;
+        const uint32_t pos0 = (uint32_t)((k0 + j) * kBlockValues);
+        for (uint32_t q = lane; q < c; q += 64u) stage[o + q] = pos0 + q;
+      }
+      wave_lds_order();
+      for (uint32_t q = lane; q < span; q += 64u) positions[base + q] = stage[q];
+      wave_lds_order();  // the copy has read the buffer before the next quarter fills it
     }
   }
 }

@@ -222,14 +222,32 @@ def test_batch_autotune_keeps_results(ctx, cases):
     items, meta = build_items(cases[:40])
     base = ctx.batch_run(items)
     try:
-        (per_cu, win), ms = ctx.batch_autotune(items, reps=2)
-        say("batch autotune:", per_cu, win, ms)
-        assert per_cu in (1, 2, 4, 8) and win in (16, 32, 64) and ms > 0
+        (per_cu, win, order), ms = ctx.batch_autotune(items, reps=2)
+        say("batch autotune:", per_cu, win, order, ms)
+        assert per_cu in (1, 2, 4, 8) and win in (16, 32, 64) and order in (0, 1) and ms > 0
         assert ctx.batch_run(items) == base
         with pytest.raises(_lib.ScanError):
             ctx.batch_autotune([], reps=1)
     finally:
         ctx.batch_set_tune(0, 0)
+        ctx.batch_set_order(1)
+
+
+def test_batch_list_order_does_not_change_results(ctx, cases):
+    """Both class-list orders plan the same work: equal results, and a plan
+    is the same on every prepare (the lists are built on the host)."""
+    items, meta = build_items(cases[:50])
+    try:
+        got = []
+        for order in (0, 1, 0):
+            ctx.batch_set_order(order)
+            got.append(ctx.batch_run(items))
+        assert got[0] == got[1] == got[2]
+        assert ctx.lib.scan_batch_set_order(ctx.h, 2) == _lib.SCAN_EINVAL
+    finally:
+        ctx.batch_set_order(1)
+    for (c, lo, hi, strat, zm), g in zip(meta, got[0]):
+        check_item(c, g, lo, hi, (c.spec.index, strat))
 
 
 def test_batch_window_and_occupancy_do_not_change_results(ctx, cases):
@@ -524,3 +542,55 @@ def test_batch_class_cost_takes_back_choices_needing_their_own_class_scan(ctx, c
         check_item(c, g1, lo, hi, (c.spec.index, "cost inf"))
     for bad in (-1.0, float("nan"), float("inf")):
         assert ctx.lib.scan_batch_set_class_cost(ctx.h, bad) == _lib.SCAN_EINVAL
+
+
+def test_learned_batch_is_not_slower_than_default(ctx):
+    """With the committed batch selector, a prepared batch of the mixed-column
+    workload (1024 columns, a seed of its own) replays no slower than the
+    same batch with the default strategy: the two batches' replays alternate
+    (21 each, HIP events on the context stream) and the learned batch's
+    median is within 5 % of the default's (the class-scan cost keeps the
+    learned batch to the class scans that pay; the tolerance covers
+    replay-to-replay noise).  Both give the same results."""
+    import os
+
+    import torch
+
+    from paper_2606_22423_amd import selector_train as st
+
+    specs = synth.config4_specs(1024, seed=synth.SEED_BASE + 77)
+    cols = st.build_columns(specs)
+    default = strategy(DEC_RM_DIRECT, 0, 1)
+    ctx.selector_load(os.path.join(os.path.dirname(api.__file__), "selector_batch_mi355x.txt"))
+    try:
+        h_l = ctx.batch_prepare([c.item(lo, hi, -1) for c, lo, hi in cols])
+    finally:
+        ctx.selector_clear()
+    h_d = ctx.batch_prepare([c.item(lo, hi, default) for c, lo, hi in cols])
+    try:
+        got_l = ctx.batch_replay(h_l, len(cols))
+        got_d = ctx.batch_replay(h_d, len(cols))
+        assert [(g["count"], g["sum"]) for g in got_l] == [(g["count"], g["sum"]) for g in got_d]
+        stream = torch.cuda.current_stream()
+
+        def timed(h):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            ctx.batch_replay(h, wait=False)
+            b.record(stream)
+            b.synchronize()
+            return a.elapsed_time(b)
+
+        for h in (h_d, h_l):
+            timed(h)
+        td, tl = [], []
+        for _ in range(21):
+            td.append(timed(h_d))
+            tl.append(timed(h_l))
+        info = ctx.batch_info(h_l)
+    finally:
+        ctx.batch_release(h_l)
+        ctx.batch_release(h_d)
+    md, ml = float(np.median(td)), float(np.median(tl))
+    say("learned batch %.3f ms, default %.3f ms, %d choices taken back" % (ml, md, info["pruned"]))
+    assert ml <= 1.05 * md, (ml, md)
