@@ -4,15 +4,30 @@
 
 namespace scan_dev {
 
+// Each thread keeps eight partials' loads in flight (two 16-byte loads per
+// partial) before it adds them: the partials come from the L2s of every XCD,
+// and one load round trip per 256 partials made the fold take ~4 us.
 __global__ __launch_bounds__(256) void fold_partials_kernel(const Partial* __restrict__ partials, uint32_t n,
                                                             Result* out, uint64_t blocks_total, int32_t strategy) {
   __shared__ uint64_t red[4][3];
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  constexpr uint32_t kPer = 8;
+  const uint4* q4 = reinterpret_cast<const uint4*>(partials);
   uint64_t c = 0, t = 0, b = 0;
-  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-    c += partials[i].count;
-    t += partials[i].sum;
-    b += partials[i].blocks;
+  for (uint32_t i0 = 0; i0 < n; i0 += blockDim.x * kPer) {
+    uint4 x[kPer], y[kPer];
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j) {
+      const uint32_t i = i0 + threadIdx.x + j * blockDim.x;
+      x[j] = i < n ? q4[2u * i] : make_uint4(0u, 0u, 0u, 0u);       // count, sum
+      y[j] = i < n ? q4[2u * i + 1u] : make_uint4(0u, 0u, 0u, 0u);  // blocks, pad
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j) {
+      c += ((uint64_t)x[j].y << 32) | x[j].x;
+      t += ((uint64_t)x[j].w << 32) | x[j].z;
+      b += ((uint64_t)y[j].y << 32) | y[j].x;
+    }
   }
   c = wave_sum_u64(c);
   t = wave_sum_u64(t);
