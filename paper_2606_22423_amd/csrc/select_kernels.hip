@@ -289,6 +289,9 @@ __global__ __launch_bounds__(256) void scan_add_kernel(uint32_t* out, uint64_t m
 // (four blocks) is expanded into the wavefront's LDS buffer (every lane
 // writes the set bits of its own ballot word, whole blocks are filled with
 // their consecutive positions) and then copied out with coalesced stores.
+// The buffer holds each position's offset from the quarter's first row (12
+// bits, in 16-bit slots).  A quarter with at most 64 positions skips the
+// buffer: each nonzero ballot word's positions go straight to the output.
 // Only the wavefront itself touches its buffer: no work-group barrier.
 __device__ __forceinline__ void wave_lds_order() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -296,11 +299,17 @@ __device__ __forceinline__ void wave_lds_order() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, uint32_t l) {
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, l);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(x >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 __global__ __launch_bounds__(256) void select_write_kernel(const SelParams p, uint32_t* positions) {
-  __shared__ uint32_t stage_all[kSelWaves][4u * kBlockValues];
+  __shared__ uint16_t stage_all[kSelWaves][4u * kBlockValues];
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  uint32_t* stage = stage_all[wave];
+  uint16_t* stage = stage_all[wave];
   const ZRange zr = load_range(p);
   const uint64_t ngroups = (p.nb + kWriteGroup - 1) / kWriteGroup;
   const uint64_t tw = (uint64_t)gridDim.x * kSelWaves;
@@ -340,22 +349,43 @@ __global__ __launch_bounds__(256) void select_write_kernel(const SelParams p, ui
         const uint32_t y = __shfl_up(incl, d, 16);
         if ((lane & 15u) >= d) incl += y;
       }
-      uint32_t at = __shfl(off, q0 + (lane >> 4), 64) - base + incl - pc;
-      const uint32_t first = (uint32_t)((k0 + q0 + (lane >> 4)) * kBlockValues) + 64u * (lane & 15u);
+      const uint32_t wo = __shfl(off, q0 + (lane >> 4), 64) + incl - pc;  // this word's first output slot
+      const uint32_t qrow = (uint32_t)((k0 + q0) * kBlockValues);         // the quarter's first row
+      const uint32_t wrow = 1024u * (lane >> 4) + 64u * (lane & 15u);      // this word's first row, from qrow
+      const uint64_t whole_q = (has & ~read) & (0xFull << q0);
+      if (span <= 64u) {
+        // few positions: straight to the output, one nonzero word at a time
+        for (uint64_t nz = ballot(w != 0ull); nz; nz &= nz - 1) {
+          const uint32_t l = (uint32_t)__builtin_ctzll(nz);
+          const uint64_t m = readlane64(w, l);
+          const uint32_t o = __builtin_amdgcn_readlane(wo, l);
+          const uint32_t r = qrow + __builtin_amdgcn_readlane(wrow, l);
+          if ((m >> lane) & 1ull) positions[o + mbcnt(m)] = r + lane;
+        }
+        for (uint64_t rest = whole_q; rest; rest &= rest - 1) {
+          const uint32_t j = (uint32_t)__builtin_ctzll(rest);
+          const uint32_t c = __builtin_amdgcn_readlane(cnt, j);
+          const uint32_t o = __builtin_amdgcn_readlane(off, j);
+          const uint32_t r = (uint32_t)((k0 + j) * kBlockValues);
+          for (uint32_t q = lane; q < c; q += 64u) positions[o + q] = r + q;
+        }
+        continue;
+      }
+      uint32_t at = wo - base;
       while (w) {
-        stage[at++] = first + (uint32_t)__builtin_ctzll(w);
+        stage[at++] = (uint16_t)(wrow + (uint32_t)__builtin_ctzll(w));
         w &= w - 1ull;
       }
-      // whole blocks of the quarter: their positions are consecutive
-      for (uint64_t rest = (has & ~read) & (0xFull << q0); rest; rest &= rest - 1) {
+      // whole blocks of the quarter: their rows are consecutive
+      for (uint64_t rest = whole_q; rest; rest &= rest - 1) {
         const uint32_t j = (uint32_t)__builtin_ctzll(rest);
         const uint32_t c = __builtin_amdgcn_readlane(cnt, j);
         const uint32_t o = __builtin_amdgcn_readlane(off, j) - base;
-        const uint32_t pos0 = (uint32_t)((k0 + j) * kBlockValues);
-        for (uint32_t q = lane; q < c; q += 64u) stage[o + q] = pos0 + q;
+        const uint32_t r = 1024u * (j - q0);
+        for (uint32_t q = lane; q < c; q += 64u) stage[o + q] = (uint16_t)(r + q);
       }
       wave_lds_order();
-      for (uint32_t q = lane; q < span; q += 64u) positions[base + q] = stage[q];
+      for (uint32_t q = lane; q < span; q += 64u) positions[base + q] = qrow + stage[q];
       wave_lds_order();  // the copy has read the buffer before the next quarter fills it
     }
   }
@@ -480,6 +510,20 @@ hipError_t launch_exclusive_scan(const uint32_t* in, uint64_t m, uint32_t* out, 
 }
 
 hipError_t launch_select_write(const SelParams& p, uint32_t* positions, uint32_t grid, hipStream_t st) {
+  // no more work-groups than fit at once (the LDS buffers limit them): the
+  // grid-strided loop then has no late second wave
+  static int fit = 0;
+  if (fit == 0) {
+    int dev = 0, cus = 0, occ = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, select_write_kernel, 64 * kSelWaves, 0) == hipSuccess &&
+        occ > 0 && cus > 0)
+      fit = cus * occ;
+    else
+      fit = -1;
+  }
+  if (fit > 0 && grid > (uint32_t)fit) grid = (uint32_t)fit;
   hipLaunchKernelGGL(select_write_kernel, dim3(grid), dim3(64 * kSelWaves), 0, st, p, positions);
   return hipGetLastError();
 }
