@@ -290,19 +290,13 @@ __global__ __launch_bounds__(256) void scan_add_kernel(uint32_t* out, uint64_t m
 // writes the set bits of its own ballot word, whole blocks are filled with
 // their consecutive positions) and then copied out with coalesced stores.
 // The buffer holds each position's offset from the quarter's first row (12
-// bits, in 16-bit slots).  A quarter with at most 64 positions skips the
-// buffer: each nonzero ballot word's positions go straight to the output.
-// Only the wavefront itself touches its buffer: no work-group barrier.
+// bits, in 16-bit slots; sparse quarters writing their few positions
+// straight to the output measured slower).  Only the wavefront itself
+// touches its buffer: no work-group barrier.
 __device__ __forceinline__ void wave_lds_order() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
-__device__ __forceinline__ uint64_t readlane64(uint64_t x, uint32_t l) {
-  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, l);
-  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(x >> 32), l);
-  return ((uint64_t)hi << 32) | lo;
 }
 
 __global__ __launch_bounds__(256) void select_write_kernel(const SelParams p, uint32_t* positions) {
@@ -353,24 +347,6 @@ __global__ __launch_bounds__(256) void select_write_kernel(const SelParams p, ui
       const uint32_t qrow = (uint32_t)((k0 + q0) * kBlockValues);         // the quarter's first row
       const uint32_t wrow = 1024u * (lane >> 4) + 64u * (lane & 15u);      // this word's first row, from qrow
       const uint64_t whole_q = (has & ~read) & (0xFull << q0);
-      if (span <= 64u) {
-        // few positions: straight to the output, one nonzero word at a time
-        for (uint64_t nz = ballot(w != 0ull); nz; nz &= nz - 1) {
-          const uint32_t l = (uint32_t)__builtin_ctzll(nz);
-          const uint64_t m = readlane64(w, l);
-          const uint32_t o = __builtin_amdgcn_readlane(wo, l);
-          const uint32_t r = qrow + __builtin_amdgcn_readlane(wrow, l);
-          if ((m >> lane) & 1ull) positions[o + mbcnt(m)] = r + lane;
-        }
-        for (uint64_t rest = whole_q; rest; rest &= rest - 1) {
-          const uint32_t j = (uint32_t)__builtin_ctzll(rest);
-          const uint32_t c = __builtin_amdgcn_readlane(cnt, j);
-          const uint32_t o = __builtin_amdgcn_readlane(off, j);
-          const uint32_t r = (uint32_t)((k0 + j) * kBlockValues);
-          for (uint32_t q = lane; q < c; q += 64u) positions[o + q] = r + q;
-        }
-        continue;
-      }
       uint32_t at = wo - base;
       while (w) {
         stage[at++] = (uint16_t)(wrow + (uint32_t)__builtin_ctzll(w));
