@@ -5,8 +5,7 @@
 namespace scan_dev {
 
 // Each thread keeps eight partials' loads in flight (two 16-byte loads per
-// partial) before it adds them: the partials come from the L2s of every XCD,
-// and one load round trip per 256 partials made the fold take ~4 us.
+// partial) before it adds them (one round trip for up to 2048 partials).
 __global__ __launch_bounds__(256) void fold_partials_kernel(const Partial* __restrict__ partials, uint32_t n,
                                                             Result* out, uint64_t blocks_total, int32_t strategy) {
   __shared__ uint64_t red[4][3];
