@@ -401,7 +401,9 @@ def controls_leg(ctx, torch, beta_gbs, cols_rm, reps=7, burst=50):
     at b = 8) through the 256 MiB last-level cache to 1 GiB, predicate
     v < round(0.1 2^b), branch-free row-major direct decoder, launch shape
     autotuned per column.  Warm: one launch, then `burst` launches back to back
-    between two events, time per launch = total / burst; cold: the cache flushed
+    between two events, queued behind a spin kernel that touches no memory (so
+    that the events time the GPU, not the host's submission), time per launch
+    = total / burst; cold: the cache flushed
     before each single launch, median of reps.  f = payload bytes / time / beta.
     Results are checked against a numpy count and sum of the host values."""
     import numpy as np
@@ -412,6 +414,13 @@ def controls_leg(ctx, torch, beta_gbs, cols_rm, reps=7, burst=50):
 
     s = strategy(DEC_RM_DIRECT, 0, 0)
     saved = {b: ctx.get_tune(ENC_FOR, b, s) for b in (8, 32)}
+    # spin cycles for ~1 ms of GPU time (longer than submitting a burst)
+    a, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    torch.cuda._sleep(1 << 20)
+    b_.record()
+    b_.synchronize()
+    spin_cycles = int((1 << 20) * min(64.0, max(1.0, 1.0 / max(a.elapsed_time(b_), 1e-3))))
     evict = torch.empty(256 << 20, dtype=torch.int32, device="cuda")
     out = torch.zeros(5, dtype=torch.int64, device="cuda")
     draws = synth.config2_draws(1 << 26)
@@ -440,6 +449,10 @@ def controls_leg(ctx, torch, beta_gbs, cols_rm, reps=7, burst=50):
         warm = []
         for _ in range(3):
             ctx.run_async(col, lo, hi, s, out)
+            # a spin kernel that touches no memory holds the GPU while the
+            # burst is submitted: the events time the GPU, and the cache keeps
+            # the column
+            torch.cuda._sleep(spin_cycles)
             e0.record()
             for _ in range(burst):
                 ctx.run_async(col, lo, hi, s, out)
@@ -497,6 +510,7 @@ def controls_leg(ctx, torch, beta_gbs, cols_rm, reps=7, burst=50):
         warm = []
         for _ in range(3):
             ctx.beta_read(buf, nbytes, sink)
+            torch.cuda._sleep(spin_cycles)
             e0.record()
             for _ in range(burst):
                 ctx.beta_read(buf, nbytes, sink)
@@ -509,7 +523,8 @@ def controls_leg(ctx, torch, beta_gbs, cols_rm, reps=7, burst=50):
     in_cache = [r["f_warm"] for r in rows if r["payload_mib"] <= 128 and r["f_cold"] <= 1.0]
     return {"workload": "FOR b=8 (N=2^20 workload 1, 2^24, 2^26, 2^27) and b=32 (N=2^20..2^26, 2^28), "
                         "v < round(0.1 2^b) (v < 26 for workload 1), rm-direct branch-free, autotuned per column; "
-                        "warm = %d back-to-back launches, cold = flushed single launch, median of %d" % (burst, reps),
+                        "warm = %d back-to-back launches queued behind a spin kernel (GPU time, cache kept), "
+                        "cold = flushed single launch, median of %d" % (burst, reps),
             "max_f_warm_in_cache": max(in_cache) if in_cache else None, "points": rows,
             "read_probe": read_rows}
 
