@@ -143,11 +143,14 @@ typedef struct {
  * 192 or 256), work-groups per compute unit (0 = as many as fit), the
  * window: wavefronts take grid-strided windows of this many consecutive
  * blocks (1..64; 0 = one pipelined decode step), and the step depth (values
- * each wavefront has in flight per pipelined step): 0 the default, 1 the
- * alternative depth of the branch-free frame-of-reference kernels of the
- * register decoders (SCAN_DEC_RM_DIRECT, SCAN_DEC_LI) without block
- * references: half as many block pairs per step below b = 16, one pair more
- * from b = 16 on; other kernels ignore it.  Zero fields mean "library
+ * each wavefront has in flight per pipelined step): 0 the kernel's default,
+ * 1 its alternative.  The alternative exists for the branch-free
+ * frame-of-reference kernels of the register decoders (SCAN_DEC_RM_DIRECT,
+ * SCAN_DEC_LI) without block references (half as many block pairs per step
+ * below b = 16, one pair more from b = 16 on) and for the branch-free
+ * dictionary kernels of SCAN_DEC_RM_DIRECT (below b = 16 their default is
+ * the shallower step and the alternative twice as deep; from b = 16 on one
+ * pair more); other kernels ignore it.  Zero fields mean "library
  * default". */
 typedef struct {
   int32_t wg_size;

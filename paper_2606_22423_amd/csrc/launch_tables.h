@@ -47,7 +47,8 @@ hipError_t launch_code(const Params& p, uint32_t grid, uint32_t block, hipStream
 }
 
 // The alternative step depth exists for the register decoders' branch-free
-// frame-of-reference kernels without block references.
+// frame-of-reference kernels without block references, and for the
+// row-major direct branch-free dictionary kernels.
 template <int B, int DEC>
 LaunchFn pick_code_alt(int enc, int mode, int pf) {
   if constexpr (DEC == DEC_RM_DIRECT || DEC == DEC_LI) {
@@ -55,6 +56,10 @@ LaunchFn pick_code_alt(int enc, int mode, int pf) {
       if (pf == PF_LO0) return &launch_code<B, DEC, MODE_BF, ENC_FOR, PF_LO0, STEP_ALT>;
       if (pf == PF_RANGE) return &launch_code<B, DEC, MODE_BF, ENC_FOR, PF_RANGE, STEP_ALT>;
     }
+  }
+  if constexpr (DEC == DEC_RM_DIRECT) {
+    if (enc == ENC_DICT && mode == MODE_BF && pf == PF_RANGE)
+      return &launch_code<B, DEC, MODE_BF, ENC_DICT, PF_RANGE, STEP_ALT>;
   }
   return nullptr;
 }

@@ -174,12 +174,13 @@ scan_tune default_tune(int32_t enc, uint32_t b, int32_t s) {
     t.depth = 0;
     return t;
   }
-  // Dictionary scans wait on LDS gathers: the autotuner on MI355X picks four
-  // work-groups per CU (as many as the LDS dictionary lets fit), 64-block
-  // windows up to b = 8 and short ones above.
+  // Dictionary scans wait on LDS gathers: the autotuner on MI355X (2^28
+  // codes, 10 % selected, cold, branch-free) picks as many work-groups per CU
+  // as the LDS dictionary lets fit up to b = 8 and two above, and 64-, 16-
+  // and 4-block windows at b = 4, 8 and 12.
   if (enc == SCAN_ENC_DICT) {
-    t.wgs_per_cu = 4;
-    t.window_blocks = b <= 8 ? 64 : 8;
+    t.wgs_per_cu = b <= 8 ? 8 : 2;
+    t.window_blocks = b <= 4 ? 64 : b <= 8 ? 16 : 4;
   }
   // With zone maps every window costs one dependent zone-map load and ballot
   // per wavefront: 64-block windows test 64 blocks per step.
@@ -278,9 +279,9 @@ scan_status scan_params(scan_ctx* ctx, const scan_column* col, int32_t enc, uint
 // Whether the alternative step depth exists for this scan (its predicate
 // form included).
 bool has_alt_depth(const scan_column* col, int32_t enc, uint32_t b, const scan_predicate* pred, int32_t s) {
-  if (enc != SCAN_ENC_FOR || col->block_ref) return false;
+  if (enc == SCAN_ENC_DELTA_FOR || (enc == SCAN_ENC_FOR && col->block_ref)) return false;
   const int64_t lo = std::max<int64_t>(pred->lo, 0);
-  const int pf = lo == 0 ? PF_LO0 : PF_RANGE;
+  const int pf = enc == SCAN_ENC_FOR && lo == 0 ? PF_LO0 : PF_RANGE;
   return code_fn_alt(enc, s & 3, (s >> 2) & 1, pf, b) != nullptr;
 }
 

@@ -51,7 +51,10 @@ struct Geo {
   static constexpr int kPairs = B >= 24 ? 2 : B >= 16 ? 1 : (32 / B > 8 ? 8 : 32 / B);
   // the alternative step depth the autotuner may pick instead (branch-free
   // frame-of-reference, register decoders): half as deep below b = 16, one
-  // pair deeper from b = 16 on
+  // pair deeper from b = 16 on.  Branch-free dictionary scans (row-major
+  // direct) swap the two below b = 16: the shallower step is their default
+  // (its LDS gathers measured 1-2 us faster at b = 4 and 8, 10 % at b = 12)
+  // and kPairs their alternative.
   static constexpr int kPairsAlt = B >= 16 ? kPairs + 1 : (kPairs / 2 > 1 ? kPairs / 2 : 1);
   static constexpr int kPairsSV = B >= 16 ? 1 : (16 / B > 4 ? 4 : 16 / B);
   // the delta decoders (prefix scan per pair) keep one pair per step from b = 16
@@ -147,73 +150,102 @@ constexpr int kDictCountShift = 58;
 constexpr uint64_t kDictSumMask = (1ull << kDictCountShift) - 1ull;
 constexpr uint64_t kDictMaxRange = 1ull << 53;
 
+// Smallest and largest of a value over the wavefront.
+__device__ __forceinline__ void wave_min_max_i64(int64_t& mn, int64_t& mx) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const uint64_t a = (uint64_t)mn, b = (uint64_t)mx;
+    const int64_t pa = (int64_t)(((uint64_t)__shfl_xor((uint32_t)(a >> 32), o, 64) << 32) | __shfl_xor((uint32_t)a, o, 64));
+    const int64_t pb = (int64_t)(((uint64_t)__shfl_xor((uint32_t)(b >> 32), o, 64) << 32) | __shfl_xor((uint32_t)b, o, 64));
+    mn = pa < mn ? pa : mn;
+    mx = pb > mx ? pb : mx;
+  }
+}
+
 // Stage a dictionary in LDS, in the form the scan reads (packed when PACK and
 // the window qualifies, else masked, up to and including the zero slot), for
 // the code window [clo, chi) of the predicate [lo, hi).  The entries are
 // sorted and distinct, so clo and chi are the numbers of entries below lo and
-// below hi: counted while the entries arrive, with each thread's loads in
-// flight together, instead of two binary searches after them.  Slots from
-// len up to `reach` (the codes' range, at most kMaxDict) and the zero slot
-// are 0.  `scratch`: 32 words of LDS.  Ends with a barrier.
+// below hi, and the window's first and last entries are the smallest and
+// largest entries inside [lo, hi): all four come out of one reduction over the
+// entries as they arrive (a thread's loads in flight together), with no
+// binary search.  Each thread stores its entries as they are and rewrites the
+// same slots after the reduction, so there are two barriers.  Slots from len
+// up to `reach` (the codes' range, at most kMaxDict) and the zero slot are 0.
+// `red`: the work-group reduction area (16 x 3 words of 64 bits).  Every
+// thread of the work-group must call it.
 template <bool PACK>
 __device__ __forceinline__ void stage_dictionary(const int64_t* __restrict__ src, uint32_t len, uint32_t reach,
-                                                 int64_t lo, int64_t hi, int64_t* dict_lds, uint32_t* scratch,
+                                                 int64_t lo, int64_t hi, int64_t* dict_lds, uint64_t (*red)[3],
                                                  uint32_t& clo, uint32_t& chi, bool& packed, uint64_t& base) {
-  constexpr uint32_t kPer = 8;
-  const uint32_t bd = blockDim.x, lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nw = bd >> 6;
-  uint32_t nlo = 0, nhi = 0;
-  for (uint32_t c0 = 0; c0 < len; c0 += bd * kPer) {
-    int64_t e[kPer];
+  constexpr uint32_t kPer = 16;  // a 4096-entry dictionary in one round at 256 threads
+  const uint32_t bd = blockDim.x, tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6, nw = bd >> 6;
+  const uint32_t span = bd * kPer;
+  // entries below lo (bits 0-15) and below hi (bits 16-31): at most kMaxDict each
+  uint32_t n = 0;
+  int64_t mn = INT64_MAX, mx = INT64_MIN;
+  // Rounds of kPer entries per thread (slots c0 + tid + j*bd), every load of
+  // a round in flight together; each entry is tallied and stored in its slot
+  // as it is, to be rewritten after the reduction by the same thread.
+  for (uint32_t c0 = 0; c0 < len; c0 += span) {
+    const uint32_t rem = len - c0;
+    const uint32_t nv0 = tid < rem ? (rem - tid - 1u) / bd + 1u : 0u;
+    const uint32_t nv = nv0 < kPer ? nv0 : kPer;  // this thread's real entries of the round
+    int64_t x[kPer];
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j) x[j] = j < nv ? src[c0 + tid + j * bd] : 0;
 #pragma unroll
     for (uint32_t j = 0; j < kPer; ++j) {
-      const uint32_t i = c0 + threadIdx.x + j * bd;
-      e[j] = i < len ? src[i] : 0;
-    }
-#pragma unroll
-    for (uint32_t j = 0; j < kPer; ++j) {
-      const uint32_t i = c0 + threadIdx.x + j * bd;
-      if (i < len) {
-        nlo += e[j] < lo ? 1u : 0u;
-        nhi += e[j] < hi ? 1u : 0u;
-        dict_lds[i] = e[j];
+      if (j < nv) {
+        const int64_t v = x[j];
+        n += (v < lo ? 1u : 0u) + (v < hi ? 0x10000u : 0u);
+        const bool in = v >= lo && v < hi;
+        mn = in && v < mn ? v : mn;
+        mx = in && v > mx ? v : mx;
+        dict_lds[c0 + tid + j * bd] = v;
       }
     }
   }
-  nlo = (uint32_t)wave_sum_u64(nlo);
-  nhi = (uint32_t)wave_sum_u64(nhi);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) n += __shfl_xor(n, o, 64);
+  wave_min_max_i64(mn, mx);
   if (lane == 0) {
-    scratch[wave] = nlo;
-    scratch[16u + wave] = nhi;
+    red[wave][0] = n;
+    red[wave][1] = (uint64_t)mn;
+    red[wave][2] = (uint64_t)mx;
   }
   __syncthreads();
-  clo = 0;
-  chi = 0;
-  for (uint32_t w = 0; w < nw; ++w) {
-    clo += scratch[w];
-    chi += scratch[16u + w];
+  uint32_t tot = 0;
+  // work-groups of at most 256 threads: four wavefronts
+#pragma unroll
+  for (uint32_t w = 0; w < 4u; ++w) {
+    if (w >= nw) break;
+    tot += (uint32_t)red[w][0];
+    const int64_t a = (int64_t)red[w][1], b = (int64_t)red[w][2];
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
   }
-  base = clo < chi ? (uint64_t)dict_lds[clo] : 0ull;
-  packed = PACK && (clo >= chi || (uint64_t)dict_lds[chi - 1u] - base < kDictMaxRange);
-  __syncthreads();  // every thread has read the window's ends before the entries change
+  clo = tot & 0xFFFFu;
+  chi = tot >> 16;
+  base = clo < chi ? (uint64_t)mn : 0ull;
+  packed = PACK && (clo >= chi || (uint64_t)mx - base < kDictMaxRange);
+  // Every slot below top in the form the scan reads: an entry inside
+  // [lo, hi) is inside the code window (sorted, distinct entries).
   const uint32_t top = len > reach ? len : reach;
-  for (uint32_t c0 = 0; c0 < top; c0 += bd * kPer) {
-    int64_t e[kPer];
+  for (uint32_t c0 = 0; c0 < top; c0 += span) {
 #pragma unroll
     for (uint32_t j = 0; j < kPer; ++j) {
-      const uint32_t i = c0 + threadIdx.x + j * bd;
-      e[j] = (i >= clo && i < chi) ? dict_lds[i] : 0;
-    }
-#pragma unroll
-    for (uint32_t j = 0; j < kPer; ++j) {
-      const uint32_t i = c0 + threadIdx.x + j * bd;
+      const uint32_t i = c0 + tid + j * bd;
       if (i < top) {
-        int64_t v = e[j];
-        if (packed && i >= clo && i < chi) v = (int64_t)(((uint64_t)v - base) | (1ull << kDictCountShift));
-        dict_lds[i] = v;
+        const int64_t v = i < len ? dict_lds[i] : 0;
+        int64_t o = 0;
+        if (i < len && v >= lo && v < hi)
+          o = packed ? (int64_t)(((uint64_t)v - base) | (1ull << kDictCountShift)) : v;
+        dict_lds[i] = o;
       }
     }
   }
-  if (threadIdx.x == 0) dict_lds[kDictZeroSlot] = 0;
+  if (tid == 0) dict_lds[kDictZeroSlot] = 0;
   __syncthreads();
 }
 
@@ -1033,9 +1065,10 @@ __device__ __forceinline__ void scan_range(const Params& p, WaveState<uint32_t>&
   const bool tail_partial = p.tail != kBlockValues;
   const uint64_t excl = tail_partial ? last : ~0ull;
   if constexpr (DEC == DEC_RM_DIRECT || DEC == DEC_LI) {
+    constexpr bool kSwap = ENC == ENC_DICT && MODE == MODE_BF && B < 16;
     constexpr int P = STEP == STEP_SMALL ? 1
                       : MODE == MODE_SV ? Geo<B>::kPairsSV
-                      : STEP == STEP_ALT ? Geo<B>::kPairsAlt : Geo<B>::kPairs;
+                      : (STEP == STEP_ALT) != kSwap ? Geo<B>::kPairsAlt : Geo<B>::kPairs;
     run_pairs<B, DEC, MODE, ENC, PF, P>(p, s, lane, list, ka, ke, stride, win, excl, dict_lds, dict_last, clo, chi);
   } else if constexpr (DEC == DEC_RM_LDS) {
     run_staged<B, MODE, ENC, PF, STEP == STEP_SMALL ? 1 : Geo<B>::kLdsBlocks>(p, s, lane, st, ka, ke, stride, win, excl, dict_lds,
@@ -1092,8 +1125,8 @@ __global__ __launch_bounds__(256) void code_scan(const Params p) {
                                                nw * wave_lds_words<B, DEC, MODE>() * 4u);
   uint32_t clo = 0, chi = 0, dict_last = 0;
   if constexpr (ENC == ENC_DICT) {
-    stage_dictionary<MODE == MODE_BF>(p.dict, p.dict_len, B <= 12 ? (1u << B) : kMaxDict, p.lo, p.hi, dict_lds,
-                                      reinterpret_cast<uint32_t*>(red), clo, chi, s.dict_packed, s.dict_base);
+    stage_dictionary<MODE == MODE_BF>(p.dict, p.dict_len, B <= 12 ? (1u << B) : kMaxDict, p.lo, p.hi, dict_lds, red,
+                                      clo, chi, s.dict_packed, s.dict_base);
     dict_last = p.dict_len - 1u;
   }
   // Grid-strided windows of p.G blocks: at any moment the wavefronts read one

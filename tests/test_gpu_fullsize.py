@@ -32,7 +32,7 @@ if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
 from paper_2606_22423_amd import api  # noqa: E402
-from paper_2606_22423_amd._lib import (DEC_BYTES, DEC_LI, DEC_RM_DIRECT, DEC_RM_LDS, ENC_FOR,  # noqa: E402
+from paper_2606_22423_amd._lib import (DEC_BYTES, DEC_LI, DEC_RM_DIRECT, DEC_RM_LDS, ENC_DICT, ENC_FOR,  # noqa: E402
                                        LAYOUT_LI, LAYOUT_RM, strategy)
 
 N28 = 1 << 28
@@ -223,6 +223,39 @@ def test_oracle_packed_random_columns(ctx, b):
                     if (s >> 3) & 1:
                         assert got["blocks_read"] == want.blocks_read, (b, layout, s, shape, lo, hi)
         del col
+
+
+@pytest.mark.parametrize("b", [4, 8, 12])
+def test_oracle_packed_dictionary_columns(ctx, b):
+    """2^24 codes packed by the oracle over 2^b sorted entries spanning 2^39
+    (the dictionary workload's shape), windows of 10 % and of one code, every
+    row-major strategy at the default launch shape (the one the bench starts
+    from) and at both step depths of the branch-free direct kernel."""
+    m = 1 << b
+    codes = synth.bounded(613, b, N24, m)
+    dct = synth.dict_entries(m, 614, b, 38)
+    words = oracle.pack_rm(codes, b)
+    zmin, zmax = oracle.zonemap_u32(codes)
+    col = api.Column(ENC_DICT, b, N24, LAYOUT_RM, torch.from_numpy(words.view(np.int32)).cuda(),
+                     zmin=torch.from_numpy(zmin.view(np.int32)).cuda(),
+                     zmax=torch.from_numpy(zmax.view(np.int32)).cuda(),
+                     dct=torch.from_numpy(dct).cuda())
+    cw = max(1, round(0.1 * m))
+    c0 = (m - cw) // 2
+    for i, j in ((c0, c0 + cw), (int(codes[77]), int(codes[77]) + 1)):
+        lo, hi = int(dct[i]), int(dct[j]) if j < m else int(dct[m - 1]) + 1
+        want = oracle.scan_dict(words, dct, N24, b, lo, hi, zone_maps=True)
+        for s in [strategy(d, sv, zm) for d in (DEC_RM_DIRECT, DEC_RM_LDS) for sv in (0, 1) for zm in (0, 1)]:
+            for depth in (0, 1):
+                if depth:
+                    ctx.set_tune(ENC_DICT, b, s, 0, 0, 0, 1)
+                say("dictionary n=2^24 b=%d strategy=%d depth=%d pred=[%d,%d)" % (b, s, depth, lo, hi))
+                got = ctx.run(col, lo, hi, s)
+                ctx.set_tune(ENC_DICT, b, s, 0, 0, 0, 0)
+                assert (got["count"], got["sum"]) == (want.count, want.sum), (b, s, depth, i, j)
+                if (s >> 3) & 1:
+                    assert got["blocks_read"] == want.blocks_read, (b, s, depth, i, j)
+    del col
 
 
 @pytest.mark.parametrize("b", [8, 21])

@@ -332,6 +332,32 @@ def test_launch_tuning_does_not_change_results(ctx):
                     ctx.set_tune(ENC_FOR, b, s, 0, 0, 0, 0)
 
 
+@pytest.mark.parametrize("b", [3, 8, 12, 17])
+def test_dict_launch_tuning_does_not_change_results(ctx, b):
+    """Launch shape and both step depths of the branch-free dictionary kernels
+    are speed knobs only: packed windows (entries over 2^39) and, on the wide
+    dictionary, windows spanning 2^53 or more, on a ragged column."""
+    n = 300 * 1024 + 999
+    for dct in (synth.dict_entries(min(1 << b, 4096), 23, b, 38), wide_dictionary(b)):
+        m = len(dct)
+        codes = synth.bounded(29, b, n, m)
+        w = oracle.pack_rm(codes, b)
+        col = api.encode_dict(codes, b, dct)
+        for i, j in ((0, m - 1), (m // 3, m // 3 + max(1, m // 10)), (m // 2, m // 2)):
+            lo, hi = int(dct[i]), int(dct[j]) + 1
+            want = oracle.scan_dict(w, dct, n, b, lo, hi, zone_maps=True)
+            for s in (strategy(DEC_RM_DIRECT, 0, 0), strategy(DEC_RM_DIRECT, 0, 1), strategy(DEC_RM_LDS, 0, 0)):
+                for wg, per_cu, win, depth in ((64, 1, 1, 1), (128, 3, 5, 0), (256, 0, 64, 1), (192, 2, 0, 0),
+                                               (0, 0, 0, 1)):
+                    ctx.set_tune(ENC_DICT, b, s, wg, per_cu, win, depth)
+                    got = ctx.run(col, lo, hi, s)
+                    case = (b, m, s, wg, per_cu, win, depth, i, j)
+                    assert (got["count"], got["sum"]) == (want.count, want.sum), case
+                    if (s >> 3) & 1:
+                        assert got["blocks_read"] == want.blocks_read, case
+                ctx.set_tune(ENC_DICT, b, s, 0, 0, 0, 0)
+
+
 def test_tune_file_round_trip_and_errors(ctx, tmp_path):
     """scan_tune_save / scan_tune_load: a saved file restores every entry; a
     file without entries or with a malformed or invalid entry is refused
