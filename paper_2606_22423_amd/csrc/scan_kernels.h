@@ -581,13 +581,12 @@ __device__ __forceinline__ void swar_count_sum(const uint32_t (&w)[B], uint32_t 
 
 // Decode the 32 codes each lane holds for one block (lanes 0-31: one block,
 // lanes 32-63: another).  `act`: this lane's block is real and may match.
+// `ref`: the block's reference (PF_REFS; loaded with its words, a step ahead).
 template <int B, int DEC, int MODE, int ENC, int PF, bool TAIL>
 __device__ __forceinline__ void decode_pair(const Params& p, WaveState<uint32_t>& s, uint32_t lane,
-                                            const uint32_t (&w)[B], uint64_t kb, bool act, const int64_t* dict_lds,
-                                            uint32_t dict_last, uint32_t clo, uint32_t chi) {
+                                            const uint32_t (&w)[B], uint64_t kb, bool act, uint32_t ref,
+                                            const int64_t* dict_lds, uint32_t dict_last, uint32_t clo, uint32_t chi) {
   const uint32_t l = lane & 31u;
-  uint32_t ref = 0;
-  if constexpr (PF == PF_REFS) ref = p.refs[kb];
   const CodeRange cr = block_range<B, ENC, PF>(p, ref, clo, chi);
   act = act && cr.nonempty;
   const uint64_t act_m = ballot(act);
@@ -743,26 +742,30 @@ __device__ __forceinline__ void run_pairs(const Params& p, WaveState<uint32_t>& 
   uint64_t k0b[P], k1b[P];
   uint32_t a0 = 0, a1 = 0;
   uint32_t w0[P][B], w1[P][B];
-  auto load = [&](const uint64_t (&kb)[P], uint32_t (&w)[P][B]) {
+  uint32_t r0[P], r1[P];  // block references (PF_REFS), in flight with the words
+  auto load = [&](const uint64_t (&kb)[P], uint32_t (&w)[P][B], uint32_t (&r)[P]) {
 #pragma unroll
-    for (int q = 0; q < P; ++q) load_pair_words<B, DEC>(p, kb[q], l, w[q]);
+    for (int q = 0; q < P; ++q) {
+      load_pair_words<B, DEC>(p, kb[q], l, w[q]);
+      r[q] = PF == PF_REFS ? p.refs[kb[q]] : 0u;
+    }
   };
-  auto decode = [&](const uint32_t (&w)[P][B], const uint64_t (&kb)[P], uint32_t ab) {
+  auto decode = [&](const uint32_t (&w)[P][B], const uint64_t (&kb)[P], uint32_t ab, const uint32_t (&r)[P]) {
 #pragma unroll
     for (int q = 0; q < P; ++q)
-      decode_pair<B, DEC, MODE, ENC, PF, false>(p, s, lane, w[q], kb[q], (ab >> q) & 1u, dict_lds, dict_last, clo,
-                                                chi);
+      decode_pair<B, DEC, MODE, ENC, PF, false>(p, s, lane, w[q], kb[q], (ab >> q) & 1u, r[q], dict_lds, dict_last,
+                                                clo, chi);
   };
   if (!cur.fetch(k0b, a0, s.blocks, live_fn, lane)) return;
-  load(k0b, w0);
+  load(k0b, w0, r0);
   while (true) {
     const bool more1 = cur.fetch(k1b, a1, s.blocks, live_fn, lane);
-    load(k1b, w1);
-    decode(w0, k0b, a0);
+    load(k1b, w1, r1);
+    decode(w0, k0b, a0, r0);
     if (!more1) break;
     const bool more0 = cur.fetch(k0b, a0, s.blocks, live_fn, lane);
-    load(k0b, w0);
-    decode(w1, k1b, a1);
+    load(k0b, w0, r0);
+    decode(w1, k1b, a1, r1);
     if (!more0) break;
   }
 }
@@ -773,10 +776,8 @@ __device__ __forceinline__ void run_pairs(const Params& p, WaveState<uint32_t>& 
 // which share the shift (l*B mod 32) and sit 2*B*t words apart.
 template <int B, int MODE, int ENC, int PF, bool TAIL>
 __device__ __forceinline__ void decode_staged(const Params& p, WaveState<uint32_t>& s, uint32_t lane,
-                                              const uint32_t* st, uint64_t k, const int64_t* dict_lds,
+                                              const uint32_t* st, uint64_t k, uint32_t ref, const int64_t* dict_lds,
                                               uint32_t dict_last, uint32_t clo, uint32_t chi) {
-  uint32_t ref = 0;
-  if constexpr (PF == PF_REFS) ref = p.refs[k];
   const CodeRange cr = block_range<B, ENC, PF>(p, ref, clo, chi);
   if (!cr.nonempty) return;
   const uint32_t limit = TAIL ? p.tail : kBlockValues;
@@ -858,9 +859,7 @@ __device__ __forceinline__ void decode_staged(const Params& p, WaveState<uint32_
 // Byte-aligned: one 16-byte load per lane per KiB of the block.
 template <int B, int MODE, int ENC, int PF, bool TAIL>
 __device__ __forceinline__ void decode_bytes(const Params& p, WaveState<uint32_t>& s, uint32_t lane,
-                                             const uint4 (&x)[B / 8], uint64_t k) {
-  uint32_t ref = 0;
-  if constexpr (PF == PF_REFS) ref = p.refs[k];
+                                             const uint4 (&x)[B / 8], uint64_t k, uint32_t ref) {
   const CodeRange cr = block_range<B, ENC, PF>(p, ref, 0, 0);
   if (!cr.nonempty) return;
   const uint32_t limit = TAIL ? p.tail : kBlockValues;
@@ -951,11 +950,16 @@ __device__ __forceinline__ void run_staged(const Params& p, WaveState<uint32_t>&
   BlockCursor<NB, decltype(live_fn)> cur{ka, ke, 0, 0, stride, win};
   uint64_t k0 = 0, m0 = 0, k1 = 0, m1 = 0;
   uint32_t r0[NB][NL], r1[NB][NL];
-  auto load = [&](uint64_t base, uint64_t mask, uint32_t (&dst)[NB][NL]) {
+  uint32_t f0[NB], f1[NB];  // block references (PF_REFS), in flight with the words
+  auto load = [&](uint64_t base, uint64_t mask, uint32_t (&dst)[NB][NL], uint32_t (&f)[NB]) {
 #pragma unroll
-    for (int j = 0; j < NB; ++j) stage_load<B>(p.payload + step_block(base, mask, j) * (32u * B), lane, dst[j]);
+    for (int j = 0; j < NB; ++j) {
+      const uint64_t k = step_block(base, mask, j);
+      stage_load<B>(p.payload + k * (32u * B), lane, dst[j]);
+      f[j] = PF == PF_REFS ? p.refs[k] : 0u;
+    }
   };
-  auto decode = [&](uint64_t base, uint64_t mask, const uint32_t (&src)[NB][NL]) {
+  auto decode = [&](uint64_t base, uint64_t mask, const uint32_t (&src)[NB][NL], const uint32_t (&f)[NB]) {
     const int n = __builtin_popcountll(mask);
 #pragma unroll
     for (int j = 0; j < NB; ++j)
@@ -966,23 +970,23 @@ __device__ __forceinline__ void run_staged(const Params& p, WaveState<uint32_t>&
       if (mask) {
         const uint64_t k = base + (uint64_t)__builtin_ctzll(mask);
         mask &= mask - 1ull;
-        decode_staged<B, MODE, ENC, PF, false>(p, s, lane, st + j * SW, k, dict_lds, dict_last, clo, chi);
+        decode_staged<B, MODE, ENC, PF, false>(p, s, lane, st + j * SW, k, f[j], dict_lds, dict_last, clo, chi);
       }
     }
     __builtin_amdgcn_wave_barrier();
   };
   if (!cur.fetch(k0, m0, s.blocks, live_fn)) return;
-  load(k0, m0, r0);
+  load(k0, m0, r0, f0);
   while (true) {
     const bool more1 = cur.fetch(k1, m1, s.blocks, live_fn);
     if (!more1) { k1 = k0; m1 = m0; }
-    load(k1, m1, r1);
-    decode(k0, m0, r0);
+    load(k1, m1, r1, f1);
+    decode(k0, m0, r0, f0);
     if (!more1) break;
     const bool more0 = cur.fetch(k0, m0, s.blocks, live_fn);
     if (!more0) { k0 = k1; m0 = m1; }
-    load(k0, m0, r0);
-    decode(k1, m1, r1);
+    load(k0, m0, r0, f0);
+    decode(k1, m1, r1, f1);
     if (!more0) break;
   }
 }
@@ -997,36 +1001,39 @@ __device__ __forceinline__ void run_bytes(const Params& p, WaveState<uint32_t>& 
   BlockCursor<NB, decltype(live_fn)> cur{ka, ke, 0, 0, stride, win};
   uint64_t k0 = 0, m0 = 0, k1 = 0, m1 = 0;
   uint4 x0[NB][Q], x1[NB][Q];
-  auto load = [&](uint64_t base, uint64_t mask, uint4 (&dst)[NB][Q]) {
+  uint32_t f0[NB], f1[NB];  // block references (PF_REFS), in flight with the words
+  auto load = [&](uint64_t base, uint64_t mask, uint4 (&dst)[NB][Q], uint32_t (&f)[NB]) {
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      const uint4* blk = reinterpret_cast<const uint4*>(p.payload + step_block(base, mask, j) * (32u * B));
+      const uint64_t k = step_block(base, mask, j);
+      const uint4* blk = reinterpret_cast<const uint4*>(p.payload + k * (32u * B));
 #pragma unroll
       for (int q = 0; q < Q; ++q) dst[j][q] = load_stream16(blk + 64 * q + lane);
+      f[j] = PF == PF_REFS ? p.refs[k] : 0u;
     }
   };
-  auto decode = [&](uint64_t base, uint64_t mask, const uint4 (&src)[NB][Q]) {
+  auto decode = [&](uint64_t base, uint64_t mask, const uint4 (&src)[NB][Q], const uint32_t (&f)[NB]) {
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       if (mask) {
         const uint64_t k = base + (uint64_t)__builtin_ctzll(mask);
         mask &= mask - 1ull;
-        decode_bytes<B, MODE, ENC, PF, false>(p, s, lane, src[j], k);
+        decode_bytes<B, MODE, ENC, PF, false>(p, s, lane, src[j], k, f[j]);
       }
     }
   };
   if (!cur.fetch(k0, m0, s.blocks, live_fn)) return;
-  load(k0, m0, x0);
+  load(k0, m0, x0, f0);
   while (true) {
     const bool more1 = cur.fetch(k1, m1, s.blocks, live_fn);
     if (!more1) { k1 = k0; m1 = m0; }
-    load(k1, m1, x1);
-    decode(k0, m0, x0);
+    load(k1, m1, x1, f1);
+    decode(k0, m0, x0, f0);
     if (!more1) break;
     const bool more0 = cur.fetch(k0, m0, s.blocks, live_fn);
     if (!more0) { k0 = k1; m0 = m1; }
-    load(k0, m0, x0);
-    decode(k1, m1, x1);
+    load(k0, m0, x0, f0);
+    decode(k1, m1, x1, f1);
     if (!more0) break;
   }
 }
@@ -1086,7 +1093,8 @@ __device__ __forceinline__ void scan_range(const Params& p, WaveState<uint32_t>&
       s.blocks += 1;
       uint32_t w[B];
       load_pair_words<B, DEC>(p, last, lane & 31u, w);
-      decode_pair<B, DEC, MODE, ENC, PF, true>(p, s, lane, w, last, lane < 32u, dict_lds, dict_last, clo, chi);
+      decode_pair<B, DEC, MODE, ENC, PF, true>(p, s, lane, w, last, lane < 32u, PF == PF_REFS ? p.refs[last] : 0u,
+                                               dict_lds, dict_last, clo, chi);
     } else if constexpr (DEC == DEC_RM_LDS) {
       s.blocks += 1;
       uint32_t r[Geo<B>::kStageLoads];
@@ -1094,7 +1102,8 @@ __device__ __forceinline__ void scan_range(const Params& p, WaveState<uint32_t>&
       __builtin_amdgcn_wave_barrier();
       stage_store<B>(st, lane, r);
       __builtin_amdgcn_wave_barrier();
-      decode_staged<B, MODE, ENC, PF, true>(p, s, lane, st, last, dict_lds, dict_last, clo, chi);
+      decode_staged<B, MODE, ENC, PF, true>(p, s, lane, st, last, PF == PF_REFS ? p.refs[last] : 0u, dict_lds,
+                                            dict_last, clo, chi);
       __builtin_amdgcn_wave_barrier();
     } else {
       s.blocks += 1;
@@ -1102,7 +1111,7 @@ __device__ __forceinline__ void scan_range(const Params& p, WaveState<uint32_t>&
       const uint4* blk = reinterpret_cast<const uint4*>(p.payload + last * (32u * B));
 #pragma unroll
       for (int q = 0; q < B / 8; ++q) x[q] = blk[64 * q + lane];
-      decode_bytes<B, MODE, ENC, PF, true>(p, s, lane, x, last);
+      decode_bytes<B, MODE, ENC, PF, true>(p, s, lane, x, last, PF == PF_REFS ? p.refs[last] : 0u);
     }
   }
 }
@@ -1188,13 +1197,13 @@ __device__ __forceinline__ T seg_inclusive_scan(T x, uint32_t lane) {
 
 // Delta, half-wavefront per block: lane l holds deltas 32 l .. 32 l + 31,
 // forms its local inclusive prefix, the half-wavefront scans the slice totals,
-// rel = exclusive + local prefix.
+// rel = exclusive + local prefix.  `base`: the block's base, loaded with its
+// words (a step ahead of the decode).
 template <int B, int MODE, bool TAIL>
 __device__ __forceinline__ void decode_delta_pair(const Params& p, WaveState<RelT<B>>& s, uint32_t lane,
-                                                  const uint32_t (&w)[B], uint64_t kb, bool act) {
+                                                  const uint32_t (&w)[B], uint64_t kb, bool act, int64_t base) {
   using R = RelT<B>;
   const uint32_t l = lane & 31u;
-  const int64_t base = p.bases[kb];
   const RelRange<B> rr = rel_range<B>(base, p.lo, p.hi);
   act = act && rr.nonempty;
   const uint64_t act_m = ballot(act);
@@ -1254,9 +1263,8 @@ __device__ __forceinline__ void decode_delta_pair(const Params& p, WaveState<Rel
 // sits at a compile-time offset, and the wavefront scans the run totals.
 template <int B, int MODE, bool TAIL>
 __device__ __forceinline__ void decode_delta_staged(const Params& p, WaveState<RelT<B>>& s, uint32_t lane,
-                                                    const uint32_t* st, uint64_t k) {
+                                                    const uint32_t* st, int64_t base) {
   using R = RelT<B>;
-  const int64_t base = p.bases[k];
   const RelRange<B> rr = rel_range<B>(base, p.lo, p.hi);
   if (!rr.nonempty) return;
   constexpr int NY = (16 * B + 31) / 32;
@@ -1335,24 +1343,29 @@ __device__ __forceinline__ void delta_range(const Params& p, WaveState<RelT<B>>&
     uint64_t k0b[P], k1b[P];
     uint32_t a0 = 0, a1 = 0;
     uint32_t w0[P][B], w1[P][B];
-    auto load = [&](const uint64_t (&kb)[P], uint32_t (&w)[P][B]) {
+    int64_t b0[P], b1[P];  // block bases, in flight with the words
+    auto load = [&](const uint64_t (&kb)[P], uint32_t (&w)[P][B], int64_t (&bb)[P]) {
 #pragma unroll
-      for (int q = 0; q < P; ++q) load_pair_words<B, DEC_RM_DIRECT>(p, kb[q], l, w[q]);
+      for (int q = 0; q < P; ++q) {
+        load_pair_words<B, DEC_RM_DIRECT>(p, kb[q], l, w[q]);
+        bb[q] = p.bases[kb[q]];
+      }
     };
-    auto decode = [&](const uint32_t (&w)[P][B], const uint64_t (&kb)[P], uint32_t ab) {
+    auto decode = [&](const uint32_t (&w)[P][B], const uint64_t (&kb)[P], uint32_t ab, const int64_t (&bb)[P]) {
 #pragma unroll
-      for (int q = 0; q < P; ++q) decode_delta_pair<B, MODE, false>(p, s, lane, w[q], kb[q], (ab >> q) & 1u);
+      for (int q = 0; q < P; ++q)
+        decode_delta_pair<B, MODE, false>(p, s, lane, w[q], kb[q], (ab >> q) & 1u, bb[q]);
     };
     if (cur.fetch(k0b, a0, s.blocks, live_fn, lane)) {
-      load(k0b, w0);
+      load(k0b, w0, b0);
       while (true) {
         const bool more1 = cur.fetch(k1b, a1, s.blocks, live_fn, lane);
-        load(k1b, w1);
-        decode(w0, k0b, a0);
+        load(k1b, w1, b1);
+        decode(w0, k0b, a0, b0);
         if (!more1) break;
         const bool more0 = cur.fetch(k0b, a0, s.blocks, live_fn, lane);
-        load(k0b, w0);
-        decode(w1, k1b, a1);
+        load(k0b, w0, b0);
+        decode(w1, k1b, a1, b1);
         if (!more0) break;
       }
     }
@@ -1361,38 +1374,38 @@ __device__ __forceinline__ void delta_range(const Params& p, WaveState<RelT<B>>&
     BlockCursor<NB, decltype(live_fn)> cur{ka, ke, 0, 0, stride, win};
     uint64_t k0 = 0, m0 = 0, k1 = 0, m1 = 0;
     uint32_t r0[NB][NL], r1[NB][NL];
-    auto load = [&](uint64_t base, uint64_t mask, uint32_t (&dst)[NB][NL]) {
+    int64_t b0[NB], b1[NB];  // block bases, in flight with the words (step_block j: the j-th decoded block)
+    auto load = [&](uint64_t base, uint64_t mask, uint32_t (&dst)[NB][NL], int64_t (&bb)[NB]) {
 #pragma unroll
-      for (int j = 0; j < NB; ++j) stage_load<B>(p.payload + step_block(base, mask, j) * (32u * B), lane, dst[j]);
+      for (int j = 0; j < NB; ++j) {
+        const uint64_t k = step_block(base, mask, j);
+        stage_load<B>(p.payload + k * (32u * B), lane, dst[j]);
+        bb[j] = p.bases[k];
+      }
     };
-    auto decode = [&](uint64_t base, uint64_t mask, const uint32_t (&src)[NB][NL]) {
+    auto decode = [&](uint64_t mask, const uint32_t (&src)[NB][NL], const int64_t (&bb)[NB]) {
       const int n = __builtin_popcountll(mask);
 #pragma unroll
       for (int j = 0; j < NB; ++j)
         if (j < n) stage_store<B>(st + j * SW, lane, src[j]);
       __builtin_amdgcn_wave_barrier();
 #pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        if (mask) {
-          const uint64_t k = base + (uint64_t)__builtin_ctzll(mask);
-          mask &= mask - 1ull;
-          decode_delta_staged<B, MODE, false>(p, s, lane, st + j * SW, k);
-        }
-      }
+      for (int j = 0; j < NB; ++j)
+        if (j < n) decode_delta_staged<B, MODE, false>(p, s, lane, st + j * SW, bb[j]);
       __builtin_amdgcn_wave_barrier();
     };
     if (cur.fetch(k0, m0, s.blocks, live_fn)) {
-      load(k0, m0, r0);
+      load(k0, m0, r0, b0);
       while (true) {
         const bool more1 = cur.fetch(k1, m1, s.blocks, live_fn);
         if (!more1) { k1 = k0; m1 = m0; }
-        load(k1, m1, r1);
-        decode(k0, m0, r0);
+        load(k1, m1, r1, b1);
+        decode(m0, r0, b0);
         if (!more1) break;
         const bool more0 = cur.fetch(k0, m0, s.blocks, live_fn);
         if (!more0) { k0 = k1; m0 = m1; }
-        load(k0, m0, r0);
-        decode(k1, m1, r1);
+        load(k0, m0, r0, b0);
+        decode(m1, r1, b1);
         if (!more0) break;
       }
     }
@@ -1407,14 +1420,14 @@ __device__ __forceinline__ void delta_range(const Params& p, WaveState<RelT<B>>&
       s.blocks += 1;
       uint32_t w[B];
       load_pair_words<B, DEC_RM_DIRECT>(p, last, lane & 31u, w);
-      decode_delta_pair<B, MODE, true>(p, s, lane, w, last, lane < 32u);
+      decode_delta_pair<B, MODE, true>(p, s, lane, w, last, lane < 32u, p.bases[last]);
     } else {
       s.blocks += 1;
       uint32_t r[Geo<B>::kStageLoads];
       stage_load<B>(p.payload + last * (32u * B), lane, r);
       stage_store<B>(st, lane, r);
       __builtin_amdgcn_wave_barrier();
-      decode_delta_staged<B, MODE, true>(p, s, lane, st, last);
+      decode_delta_staged<B, MODE, true>(p, s, lane, st, p.bases[last]);
     }
   }
 }
