@@ -21,15 +21,26 @@ __device__ __forceinline__ uint32_t lower_bound_global(const int64_t* d, uint32_
   return lo;
 }
 
-// Block k (32 b words) of a row-major payload into the wavefront's LDS slot.
+// Block k (32 b words) of a row-major payload into the wavefront's LDS slot
+// `st` with direct global-to-LDS loads: 8 b pieces of 16 bytes, at most four
+// per lane, piece i = lane + 64 j landing at byte 1024 j + 16 lane of the slot
+// (the load's lane layout), all in flight together and none through
+// registers; the wait after them makes the block visible to the wavefront.
 __device__ __forceinline__ void stage_rt_block(uint32_t* st, const uint32_t* payload, uint32_t b, uint64_t k,
                                                uint32_t lane) {
-  const uint32_t words = 32u * b;
-  const uint4* src = reinterpret_cast<const uint4*>(payload + k * words);
-  uint4* dst = reinterpret_cast<uint4*>(st);
-  __builtin_amdgcn_wave_barrier();
-  for (uint32_t i = lane; i < words / 4u; i += 64u) dst[i] = src[i];
+  typedef __attribute__((address_space(1))) const void GlobalV;
+  typedef __attribute__((address_space(3))) void LdsV;
+  const uint32_t words = 32u * b, pieces = words / 4u;
+  const uint32_t* src = payload + k * words;
+  __builtin_amdgcn_s_waitcnt(0);  // the slot's earlier reads have returned
+#pragma unroll
+  for (uint32_t j = 0; j < 4u; ++j) {
+    if (64u * j >= pieces) break;  // uniform
+    if (lane + 64u * j < pieces)
+      __builtin_amdgcn_global_load_lds((GlobalV*)(src + 4u * (lane + 64u * j)), (LdsV*)(st + 256u * j), 16u, 0, 0);
+  }
   st[words] = 0u;  // every lane writes the same pad word
+  __builtin_amdgcn_s_waitcnt(0);  // every piece is in LDS
   __builtin_amdgcn_wave_barrier();
 }
 
