@@ -147,10 +147,10 @@ typedef struct {
  * 1 its alternative.  The alternative exists for the branch-free
  * frame-of-reference kernels of the register decoders (SCAN_DEC_RM_DIRECT,
  * SCAN_DEC_LI) without block references (half as many block pairs per step
- * below b = 16, one pair more from b = 16 on) and for the branch-free
- * dictionary kernels of SCAN_DEC_RM_DIRECT (below b = 16 their default is
- * the shallower step and the alternative twice as deep; from b = 16 on one
- * pair more); other kernels ignore it.  Zero fields mean "library
+ * below b = 16, one pair more at b = 16-23, one pair instead of two from
+ * b = 24 on) and for the branch-free dictionary kernels of SCAN_DEC_RM_DIRECT
+ * (below b = 16 their default is the shallower step and the alternative
+ * twice as deep; above, as for frame of reference); other kernels ignore it.  Zero fields mean "library
  * default". */
 typedef struct {
   int32_t wg_size;

@@ -51,11 +51,11 @@ struct Geo {
   static constexpr int kPairs = B >= 24 ? 2 : B >= 16 ? 1 : (32 / B > 8 ? 8 : 32 / B);
   // the alternative step depth the autotuner may pick instead (branch-free
   // frame-of-reference, register decoders): half as deep below b = 16, one
-  // pair deeper from b = 16 on.  Branch-free dictionary scans (row-major
-  // direct) swap the two below b = 16: the shallower step is their default
-  // (its LDS gathers measured 1-2 us faster at b = 4 and 8, 10 % at b = 12)
-  // and kPairs their alternative.
-  static constexpr int kPairsAlt = B >= 16 ? kPairs + 1 : (kPairs / 2 > 1 ? kPairs / 2 : 1);
+  // pair deeper at b = 16-23, one pair from b = 24 on.  Branch-free dictionary
+  // scans (row-major direct) swap the two below b = 16: the shallower step is
+  // their default (its LDS gathers measured 1-2 us faster at b = 4 and 8,
+  // 10 % at b = 12) and kPairs their alternative.
+  static constexpr int kPairsAlt = B >= 24 ? 1 : B >= 16 ? kPairs + 1 : (kPairs / 2 > 1 ? kPairs / 2 : 1);
   static constexpr int kPairsSV = B >= 16 ? 1 : (16 / B > 4 ? 4 : 16 / B);
   // the delta decoders (prefix scan per pair) keep one pair per step from b = 16
   static constexpr int kDeltaPairs = B >= 16 ? 1 : (16 / B > 4 ? 4 : 16 / B);
