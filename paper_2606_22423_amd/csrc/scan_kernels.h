@@ -490,9 +490,10 @@ struct BlockCursor {
 // Branch-free COUNT and SUM of the 32 codes a lane holds, for B <= 15 (frame
 // of reference, full blocks): SIMD within a register.  The codes are spread
 // into fields with spare bits above each code (B = 2, 4, 8: fields of 2B
-// bits, odd and even codes apart; B = 3, 5, 6, 7: four consecutive codes
-// shifted into the four bytes of a register; B = 9-15: two consecutive codes
-// into the two halves), so one subtraction tests all fields of a register
+// bits, odd and even codes apart; B = 3: eight consecutive codes into the
+// eight nibbles of a register; B = 5, 6, 7: four consecutive codes shifted
+// into the four bytes of a register; B = 9-15: two consecutive codes into the
+// two halves), so one subtraction tests all fields of a register
 // against the code window with no borrow between fields, and the top bit of
 // each field is its pass flag.  v_bcnt counts the flags; an unsigned dot
 // product of the fields with the 0/1 flags (dot8 of nibbles, dot4 of bytes,
@@ -507,7 +508,27 @@ __device__ __forceinline__ void swar_count_sum(const uint32_t (&w)[B], uint32_t 
     const bool p1 = loc <= 1u && loc + wm1 >= 1u;      // code 1 in the window
     lc += (p0 ? 32u - pc : 0u) + (p1 ? pc : 0u);
     part += p1 ? pc : 0u;
-  } else if constexpr (B == 3 || B == 5 || B == 6 || B == 7) {
+  } else if constexpr (B == 3) {
+    // eight codes (24 stream bits) into the eight nibbles of a register, bit 3
+    // of each the spare: 12 + 12 bits to the two halves, 6 + 6 to the bytes
+    // of each half, 3 + 3 to the nibbles of each byte
+    constexpr uint32_t hm = 0x88888888u;
+    const uint32_t locr = loc * 0x11111111u;
+    const uint32_t wr = (0x8u + wm1) * 0x11111111u;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int bit = 24 * g, wi = bit >> 5, sh = bit & 31;
+      const int wn = wi + 1 < B ? wi + 1 : wi;  // only read when the group straddles a word
+      const uint32_t chunk = sh + 24 <= 32 ? (w[wi] >> sh) : funnel(w[wn], w[wi], sh);
+      uint32_t x = (chunk & 0xFFFu) | ((chunk & 0xFFF000u) << 4);
+      x = (x & 0x003F003Fu) | ((x & 0x0FC00FC0u) << 2);
+      x = (x & 0x07070707u) | ((x & 0x38383838u) << 1);
+      const uint32_t g4 = PF == PF_LO0 ? x : (((x | hm) - locr) & ~hm);
+      const uint32_t flags = (wr - g4) & hm;
+      lc += (uint32_t)__builtin_popcount(flags);
+      part = __builtin_amdgcn_udot8(x, flags >> 3, part, false);
+    }
+  } else if constexpr (B == 5 || B == 6 || B == 7) {
     constexpr uint32_t m0 = (1u << B) - 1u;
     constexpr uint32_t hm = 0x80808080u;
     const uint32_t locr = loc * 0x01010101u;
