@@ -128,6 +128,9 @@ struct WaveState {
   // (see stage_dictionary) relative to dict_base (uniform)
   bool dict_packed = false;
   uint64_t dict_base = 0;
+  // packed dictionaries of b <= kDictPairMaxB: a table of code pairs staged
+  // beside the entries (see stage_dictionary_pairs)
+  bool dict_pairs = false;
 };
 
 // Value of a selected code: FOR adds the code (references are added through
@@ -252,6 +255,25 @@ __device__ __forceinline__ void stage_dictionary(const int64_t* __restrict__ src
 typedef __attribute__((address_space(3))) const int64_t LdsI64;
 __device__ __forceinline__ uint64_t dict_at(uint32_t idx) {
   return (uint64_t)*reinterpret_cast<LdsI64*>((uintptr_t)(idx * 8u));
+}
+
+// Code pairs of a packed dictionary of b <= kDictPairMaxB: slot
+// kDictPairBase + (c0 | c1 << b) holds entry c0 + entry c1 (both packed, so
+// the match counts add too; 16 pairs per lane and block keep the count field
+// at most 32), so one gather serves two codes.  The table sits between the
+// entries (at most 2^b <= kDictPairBase slots) and the zero slot.
+constexpr int kDictPairMaxB = 5;
+constexpr uint32_t kDictPairBase = 64;
+static_assert(kDictPairBase + (1u << (2 * kDictPairMaxB)) <= kDictZeroSlot, "pair table overlaps the zero slot");
+
+// Build the pair table from the staged (packed) entries; every thread of the
+// work-group calls it after stage_dictionary.  Ends with a barrier.
+template <int B>
+__device__ __forceinline__ void stage_dictionary_pairs(int64_t* dict_lds) {
+  constexpr uint32_t kMask = (1u << B) - 1u;
+  for (uint32_t q = threadIdx.x; q < (1u << (2 * B)); q += blockDim.x)
+    dict_lds[kDictPairBase + q] = (int64_t)((uint64_t)dict_lds[q & kMask] + (uint64_t)dict_lds[q >> B]);
+  __syncthreads();
 }
 
 // Index of a code's entry in the masked LDS dictionary: codes of b <= 12 bits
@@ -630,6 +652,25 @@ __device__ __forceinline__ void decode_pair(const Params& p, WaveState<uint32_t>
     // wavefront's mask; a lane whose block is absent or cannot match compares
     // against an empty window (a dictionary's code window is at most kMaxDict
     // wide, so its width does not overflow).
+    if constexpr (!TAIL && B <= kDictPairMaxB) {
+      if (s.dict_pairs) {
+        // one gather per two consecutive codes (see stage_dictionary_pairs)
+#pragma unroll
+        for (int g = 0; g < 16; g += 8) {
+          uint64_t e[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) e[k] = dict_at(kDictPairBase + run_code<2 * B, B>(w, g + k));
+          part += ((e[0] + e[1]) + (e[2] + e[3])) + ((e[4] + e[5]) + (e[6] + e[7]));
+          pin(part);
+        }
+        if (act) {
+          const uint32_t lc = (uint32_t)(part >> kDictCountShift);
+          s.lcount += lc;
+          s.lsum += (part & kDictSumMask) + s.dict_base * lc;
+        }
+        return;
+      }
+    }
     if (s.dict_packed) {
       // packed entries: one 64-bit add per code (see stage_dictionary); the
       // reads go out in groups of eight before their adds
@@ -1158,6 +1199,12 @@ __global__ __launch_bounds__(256) void code_scan(const Params p) {
     stage_dictionary<MODE == MODE_BF>(p.dict, p.dict_len, B <= 12 ? (1u << B) : kMaxDict, p.lo, p.hi, dict_lds, red,
                                       clo, chi, s.dict_packed, s.dict_base);
     dict_last = p.dict_len - 1u;
+    if constexpr (MODE == MODE_BF && DEC == DEC_RM_DIRECT && B <= kDictPairMaxB) {
+      if (s.dict_packed) {  // uniform: the same window in every work-group
+        stage_dictionary_pairs<B>(dict_lds);
+        s.dict_pairs = true;
+      }
+    }
   }
   // Grid-strided windows of p.G blocks: at any moment the wavefronts read one
   // compact region of the column (DRAM row locality), like a streaming copy.
