@@ -151,41 +151,32 @@ __device__ __forceinline__ uint64_t wave_or_u64(uint64_t x) {
 // Stage block k of every column in `need` into its slot of the LDS staging
 // area (32 b words at cols[c].stage_off, then a zero spill word for the
 // funnel shift of the block's last code), and each staged FOR column's block
-// reference into col_ref.  Columns go in groups of eight: the group's loads
-// are all issued before any store, so eight loads are in flight per thread.
+// reference into col_ref.  Direct global-to-LDS loads: thread t takes the
+// block's 16-byte piece t (a block has at most 256), which lands at byte
+// 1024 w + 16 lane of the slot for thread t = 64 w + lane (the load's lane
+// layout); every column's loads are in flight together and none goes through
+// registers.  Ends with this wavefront's loads complete; the caller's
+// barrier then makes the whole stage visible.
 __device__ __forceinline__ void stage_columns(uint32_t* stage, uint32_t* col_ref, const QCol* cols, uint64_t need,
                                               uint64_t k) {
-  const uint32_t tid = threadIdx.x;
+  typedef __attribute__((address_space(1))) const void GlobalV;
+  typedef __attribute__((address_space(3))) void LdsV;
+  const uint32_t tid = threadIdx.x, wave = tid >> 6;
   while (need) {
-    uint32_t cs[8];
-    bool on[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      on[i] = need != 0ull;
-      cs[i] = on[i] ? (uint32_t)__builtin_ctzll(need) : 0u;
-      need &= need - (on[i] ? 1ull : 0ull);
-    }
-    uint4 r[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      r[i] = make_uint4(0u, 0u, 0u, 0u);
-      if (on[i]) {
-        const QCol& c = cols[cs[i]];
-        if (tid < 8u * c.b) r[i] = reinterpret_cast<const uint4*>(c.payload + k * (32u * c.b))[tid];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      if (on[i]) {
-        const QCol& c = cols[cs[i]];
-        if (tid < 8u * c.b) reinterpret_cast<uint4*>(stage + c.stage_off)[tid] = r[i];
-        if (tid == 0) {
-          stage[c.stage_off + 32u * c.b] = 0u;
-          col_ref[cs[i]] = (c.enc != ENC_DICT && c.refs) ? c.refs[k] : 0u;
-        }
-      }
+    const uint32_t c = (uint32_t)__builtin_ctzll(need);
+    need &= need - 1ull;
+    const QCol& col = cols[c];
+    const uint32_t words = 32u * col.b;
+    uint32_t* slot = stage + col.stage_off;
+    if (tid < words / 4u)
+      __builtin_amdgcn_global_load_lds((GlobalV*)(col.payload + k * words + 4u * tid), (LdsV*)(slot + 256u * wave),
+                                       16u, 0, 0);
+    if (tid == 0) {
+      slot[words] = 0u;
+      col_ref[c] = (col.enc != ENC_DICT && col.refs) ? col.refs[k] : 0u;
     }
   }
+  __builtin_amdgcn_s_waitcnt(0);
 }
 
 __global__ __launch_bounds__(256) void query_shared_kernel(const QArgs a) {
