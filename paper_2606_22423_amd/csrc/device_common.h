@@ -14,7 +14,8 @@ constexpr uint32_t kBlockValues = 1024;  // values per block (zone map / layout 
 constexpr uint32_t kMaxDict = 4096;      // dictionary entries staged in LDS
 // The LDS dictionary area: kMaxDict entries, then one zero entry (read for a
 // partial last block's padding slots and for codes past the area), padded to
-// 16 bytes.
+// 16 bytes.  Branch-free scans of dictionaries of b <= 5 also keep a table of
+// code pairs in it, between the entries and the zero slot.
 constexpr uint32_t kDictZeroSlot = kMaxDict;
 constexpr uint32_t kDictLdsBytes = kMaxDict * 8u + 16u;
 constexpr uint32_t kRingEntries = 128;   // per-wavefront selection-vector ring (u32 or u64 entries)

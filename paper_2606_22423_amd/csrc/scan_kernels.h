@@ -645,13 +645,16 @@ __device__ __forceinline__ void decode_pair(const Params& p, WaveState<uint32_t>
       if constexpr (PF == PF_REFS) s.lsum += (uint64_t)lc * ref;
     }
   } else if constexpr (MODE == MODE_BF && ENC == ENC_DICT) {
-    // Branch-free dictionary: SUM adds every code's entry from the masked
-    // LDS dictionary (no compare, no select; a partial last block's padding
-    // slots read the zero slot).  COUNT: packed fields for b <= 8 on full
-    // blocks, else one compare per code and a scalar popcount of the
-    // wavefront's mask; a lane whose block is absent or cannot match compares
-    // against an empty window (a dictionary's code window is at most kMaxDict
-    // wide, so its width does not overflow).
+    // Branch-free dictionary, in three forms: (1) b <= kDictPairMaxB with a
+    // pair table on full blocks, one gather per two codes; (2) packed entries,
+    // one gather and one 64-bit add per code giving COUNT and SUM; (3) masked
+    // entries (windows spanning 2^53 or more): SUM adds every code's entry (no
+    // compare, no select; a partial last block's padding slots read the zero
+    // slot) and COUNT comes from packed fields for b <= 8 on full blocks, else
+    // one compare per code and a scalar popcount of the wavefront's mask; a
+    // lane whose block is absent or cannot match compares against an empty
+    // window (a dictionary's code window is at most kMaxDict wide, so its
+    // width does not overflow).
     if constexpr (!TAIL && B <= kDictPairMaxB) {
       if (s.dict_pairs) {
         // one gather per two consecutive codes (see stage_dictionary_pairs)
