@@ -57,157 +57,183 @@ __device__ __forceinline__ int block_class(const SelParams& p, const ZRange& zr,
   return 1;
 }
 
-// Pass ballots of a staged block (b = B, `valid` values) for the code window
-// [clo, chi): lane t < 16 receives the ballot of step t (bit l: value l + 64 t
-// passes), `cnt` (uniform) the number of passing values.
-template <uint32_t B>
-__device__ __forceinline__ uint64_t block_marks(int64_t clo, int64_t chi, const uint32_t* st, uint32_t valid,
-                                                uint32_t lane, uint32_t& cnt) {
-  cnt = 0;
-  if (clo >= chi) return 0;
-  const Extract ex(st, lane, B);
-  const uint32_t lo32 = (uint32_t)clo, wm1 = (uint32_t)(chi - clo - 1);
-  uint64_t mine = 0;
-  if (valid == kBlockValues) {
+// Pass marks of one lane's 32 codes (held in w, stream bits [32 B l', ...) of
+// its block, values 32 l' .. 32 l' + 31) for the code window [lo32, lo32 +
+// wm1]: bit t of the result for value 32 l' + t; with VALID, values at or
+// past `valid` (the block's valid count) fail.
+template <uint32_t B, bool VALID>
+__device__ __forceinline__ uint32_t lane_marks(const uint32_t (&w)[B], uint32_t lo32, uint32_t wm1, uint32_t v0,
+                                               uint32_t valid) {
+  uint32_t bits = 0;
 #pragma unroll
-    for (uint32_t t = 0; t < 16u; ++t) {
-      const uint64_t m = ballot((ex(t) - lo32) <= wm1);
-      mine = lane == t ? m : mine;
-      cnt += (uint32_t)__builtin_popcountll(m);
+  for (uint32_t t = 0; t < 32u; ++t) {
+    const uint32_t bit = t * B, wi = bit >> 5, sh = bit & 31u;
+    uint32_t c;
+    if (B == 32) c = w[t];
+    else if (sh + B <= 32) c = (w[wi] >> sh) & ((1u << (B & 31u)) - 1u);
+    else c = __builtin_amdgcn_alignbit(w[wi + 1 < B ? wi + 1 : wi], w[wi], sh) & ((1u << (B & 31u)) - 1u);
+    bool hit = (c - lo32) <= wm1;
+    if (VALID) hit = hit && (v0 + t < valid);
+    bits |= (hit ? 1u : 0u) << t;
+  }
+  return bits;
+}
+
+// The lane's B words, in 16-byte (B a multiple of 4) or 8-byte (B even)
+// pieces; the slice starts at a multiple of 4 B bytes of a 16-byte aligned
+// payload.  A load instruction touches one line per lane.  In one or two
+// pieces the lines are used up at once and the loads are nontemporal (the
+// payload stream then leaves the marks in the last-level cache for the write
+// pass); in more pieces they are plain, so that the lane's later pieces hit
+// the lines in the L1 instead of fetching them again.
+typedef uint32_t SelU32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t SelU32x2 __attribute__((ext_vector_type(2)));
+template <typename T, bool NT>
+__device__ __forceinline__ T load_piece(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <uint32_t B>
+__device__ __forceinline__ void load_lane_words(const uint32_t* __restrict__ src, uint32_t (&w)[B]) {
+  constexpr uint32_t kPieces = B % 4u == 0u ? B / 4u : B % 2u == 0u ? B / 2u : B;
+  constexpr bool kNT = kPieces <= 2u;
+  if constexpr (B % 4u == 0u) {
+#pragma unroll
+    for (uint32_t i = 0; i < B / 4u; ++i) {
+      const SelU32x4 v = load_piece<SelU32x4, kNT>(reinterpret_cast<const SelU32x4*>(src) + i);
+      w[4u * i] = v.x;
+      w[4u * i + 1u] = v.y;
+      w[4u * i + 2u] = v.z;
+      w[4u * i + 3u] = v.w;
+    }
+  } else if constexpr (B % 2u == 0u) {
+#pragma unroll
+    for (uint32_t i = 0; i < B / 2u; ++i) {
+      const SelU32x2 v = load_piece<SelU32x2, kNT>(reinterpret_cast<const SelU32x2*>(src) + i);
+      w[2u * i] = v.x;
+      w[2u * i + 1u] = v.y;
     }
   } else {
 #pragma unroll
-    for (uint32_t t = 0; t < 16u; ++t) {
-      const uint64_t m = ballot(((ex(t) - lo32) <= wm1) && (lane + 64u * t < valid));
-      mine = lane == t ? m : mine;
-      cnt += (uint32_t)__builtin_popcountll(m);
-    }
+    for (uint32_t i = 0; i < B; ++i) w[i] = load_piece<uint32_t, kNT>(src + i);
   }
-  return mine;
 }
 
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+// 32-bit codes, one per word: lane l' of the half-wavefront reads words
+// 32 i + l' (coalesced, nontemporal), and the half's ballot of pass i is mark word i,
+// which lane i keeps.  Every lane of the half takes the same branch, so
+// the ballot's other half (the other block, or inactive) is dropped.
+template <bool VALID>
+__device__ __forceinline__ uint32_t wide_marks(const uint32_t* __restrict__ blk, uint32_t l, uint32_t half,
+                                               uint32_t lo32, uint32_t wm1, uint32_t valid) {
+  uint32_t c[32];
+#pragma unroll
+  for (uint32_t i = 0; i < 32u; ++i) c[i] = __builtin_nontemporal_load(blk + 32u * i + l);
+  uint32_t bits = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < 32u; ++i) {
+    bool hit = (c[i] - lo32) <= wm1;
+    if (VALID) hit = hit && (32u * i + l < valid);
+    const uint64_t bal = __ballot(hit);
+    const uint32_t mine = half ? (uint32_t)(bal >> 32) : (uint32_t)bal;
+    bits = l == i ? mine : bits;
+  }
+  return bits;
+}
 
-// Group geometry of the mark pass for width B.
-template <uint32_t B>
-struct MarkGroup {
-  static constexpr uint32_t kBlocks = B >= 32u ? 1u : 32u / B;      // G
-  static constexpr uint32_t kWords = 32u * B;                       // words per block
-  static constexpr uint32_t kPiecesPerBlock = 8u * B;               // 16-byte pieces per block
-  static constexpr uint32_t kPieces = kBlocks * kPiecesPerBlock;    // at most 256
-};
-
-// Zone maps and reference of one group's blocks: lane j < G holds block
-// k0 + j's (loads issued by `issue`, consumed later by `classify` and the
-// decode).
-struct GroupInfo {
-  uint32_t zmn, zmx, ref;
-  __device__ __forceinline__ void issue(const SelParams& p, uint64_t k0, uint32_t G, uint32_t lane) {
-    const uint64_t k = k0 + lane;
-    const bool in = lane < G && k < p.nb;
-    zmn = in && p.use_zm ? p.zmin[k] : 0u;
-    zmx = in && p.use_zm ? p.zmax[k] : 0u;
-    ref = in && p.refs ? p.refs[k] : 0u;
+// 16-bit codes: mark word 8 i + j' (values 256 i + 32 j' .. + 31, 64 bytes)
+// is read in pass i by lanes 4 j' .. 4 j' + 3 of the half-wavefront, 16
+// bytes each (coalesced, nontemporal); each lane marks its 8 codes, and two
+// shuffles within the quad join the four bytes.  Lane l' then takes word l'
+// from the quad that built it.
+template <bool VALID>
+__device__ __forceinline__ uint32_t quad_marks(const uint32_t* __restrict__ blk, uint32_t l, uint32_t lo32,
+                                               uint32_t wm1, uint32_t valid) {
+  SelU32x4 v[4];
+#pragma unroll
+  for (uint32_t i = 0; i < 4u; ++i) v[i] = __builtin_nontemporal_load(reinterpret_cast<const SelU32x4*>(blk) + 32u * i + l);
+  uint32_t r[4];
+#pragma unroll
+  for (uint32_t i = 0; i < 4u; ++i) {
+    uint32_t bits8 = 0;
+#pragma unroll
+    for (uint32_t c = 0; c < 8u; ++c) {
+      const uint32_t code = (v[i][c >> 1] >> (16u * (c & 1u))) & 0xFFFFu;
+      bool hit = (code - lo32) <= wm1;
+      if (VALID) hit = hit && (256u * i + 8u * l + c < valid);
+      bits8 |= (hit ? 1u : 0u) << c;
+    }
+    uint32_t x = bits8 << (8u * (l & 3u));
+    x |= __shfl_xor(x, 1, 32);
+    x |= __shfl_xor(x, 2, 32);
+    r[i] = x;
   }
-  // 0: skip, 1: decode, 2: all-match (lanes past the group or the column: 0)
-  __device__ __forceinline__ uint32_t classify(const SelParams& p, const ZRange& zr, uint64_t k0, uint32_t G,
-                                               uint32_t lane) const {
-    if (!(lane < G && k0 + lane < p.nb) || zr.lo >= zr.hi) return 0u;
-    if (!p.use_zm) return 1u;
-    if ((int64_t)zmx < zr.lo || (int64_t)zmn >= zr.hi) return 0u;
-    if (p.use_am && (int64_t)zmn >= zr.lo && (int64_t)zmx < zr.hi) return 2u;
-    return 1u;
+  uint32_t out = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < 4u; ++i) {
+    const uint32_t t = __shfl(r[i], (int)(4u * (l & 7u)), 32);
+    out = (l >> 3) == i ? t : out;
   }
-};
-
-// A group's words in registers: lane takes 16-byte pieces lane + 64 q, only
-// those of blocks whose bit is set in `need` (pieces of other blocks are
-// neither loaded nor staged).  A native vector type, so that the copies stay
-// register moves (HIP's uint4 is a struct copied by memcpy).
-template <uint32_t B>
-struct GroupRegs {
-  using Geo = MarkGroup<B>;
-  u32x4 r0, r1, r2, r3;
-  __device__ __forceinline__ static bool has(uint32_t need, uint32_t q) {
-    return q < Geo::kPieces && ((need >> (q / Geo::kPiecesPerBlock)) & 1u);
-  }
-  __device__ __forceinline__ void load(const SelParams& p, uint64_t k0, uint32_t need, uint32_t lane) {
-    // adjacent lanes read adjacent 16 bytes: whole lines, streamed (non-temporal)
-    const u32x4* src = reinterpret_cast<const u32x4*>(p.payload + k0 * Geo::kWords);
-    if (has(need, lane)) r0 = __builtin_nontemporal_load(src + lane);
-    if (Geo::kPieces > 64u && has(need, lane + 64u)) r1 = __builtin_nontemporal_load(src + lane + 64u);
-    if (Geo::kPieces > 128u && has(need, lane + 128u)) r2 = __builtin_nontemporal_load(src + lane + 128u);
-    if (Geo::kPieces > 192u && has(need, lane + 192u)) r3 = __builtin_nontemporal_load(src + lane + 192u);
-  }
-  __device__ __forceinline__ void store(uint32_t* st, uint32_t need, uint32_t lane) const {
-    u32x4* dst = reinterpret_cast<u32x4*>(st);
-    __builtin_amdgcn_wave_barrier();
-    if (has(need, lane)) dst[lane] = r0;
-    if (Geo::kPieces > 64u && has(need, lane + 64u)) dst[lane + 64u] = r1;
-    if (Geo::kPieces > 128u && has(need, lane + 128u)) dst[lane + 128u] = r2;
-    if (Geo::kPieces > 192u && has(need, lane + 192u)) dst[lane + 192u] = r3;
-    st[Geo::kBlocks * Geo::kWords] = 0u;  // the funnel's spill word; every lane writes the same value
-    __builtin_amdgcn_wave_barrier();
-  }
-};
+  return out;
+}
 
 }  // namespace
 
+// Mark pass: a wavefront takes two blocks at a time, half a wavefront each;
+// lane l' of a half holds the 32 consecutive codes of values 32 l' .. 32 l' +
+// 31 (the block's words l' B .. l' B + B - 1, read straight into registers)
+// and writes their marks as one 32-bit word, word l' of the block's 1024-bit
+// mark string, which the write pass reads as 16 words of 64 bits (bit l of
+// word t: value 64 t + l).  The block's count is the half-wavefront's sum.
+// Zone maps decide per block: skipped (count 0, no marks), decoded, or, with
+// the all-match shortcut, taken whole (count = its valid values, no marks).
 template <uint32_t B>
 __global__ __launch_bounds__(256) void select_mark_kernel(const SelParams p) {
-  using Geo = MarkGroup<B>;
-  constexpr uint32_t G = Geo::kBlocks;
-  __shared__ __align__(16) uint32_t lds[kSelWaves][kRtStageWords];
-  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t lane = threadIdx.x & 63u, l = lane & 31u, half = lane >> 5;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  uint32_t* st = lds[wave];
   const ZRange zr = load_range(p);
-  const uint64_t ng = (p.nb + G - 1) / G;
-  const uint64_t tw = (uint64_t)gridDim.x * kSelWaves;
   const int64_t top = int64_t(1) << B;
-  uint64_t g = (uint64_t)blockIdx.x * kSelWaves + wave;
-  if (g >= ng) return;
-  GroupRegs<B> regs;
-  GroupInfo cur, nxt;
-  cur.issue(p, g * G, G, lane);
-  uint32_t cls = cur.classify(p, zr, g * G, G, lane);
-  uint32_t need = (uint32_t)ballot(cls == 1u);
-  if (need) regs.load(p, g * G, need, lane);
-  nxt.issue(p, (g + tw) * G, G, lane);
-  // Vector loads retire in order: a group's words are issued before the zone
-  // maps of the group after it, and whatever a group's decode needs was loaded
-  // an iteration earlier, so the waits below are for loads long in flight.
-  for (; g < ng; g += tw) {
-    regs.store(st, need, lane);
-    const uint64_t k0 = g * G;
-    const uint32_t cls_c = cls, need_c = need, ref_c = cur.ref;
-    const uint64_t gn = g + tw;
-    cls = nxt.classify(p, zr, gn * G, G, lane);
-    need = (uint32_t)ballot(cls == 1u);
-    if (need) regs.load(p, gn * G, need, lane);  // in flight while this group decodes
-    cur = nxt;
-    nxt.issue(p, (gn + tw) * G, G, lane);
-    uint32_t cnt_v = 0;
-#pragma unroll 1
-    for (uint32_t j = 0; j < G; ++j) {
-      const uint64_t k = k0 + j;
-      if (k >= p.nb) break;
-      const uint32_t c = __builtin_amdgcn_readlane(cls_c, j);
-      const uint32_t valid = k == p.nb - 1 ? (uint32_t)(p.n - k * kBlockValues) : kBlockValues;
-      uint32_t cnt = c == 2u ? valid : 0u;
-      if ((need_c >> j) & 1u) {
-        int64_t clo = zr.lo, chi = zr.hi;
-        if (p.enc != ENC_DICT) {
-          const int64_t ref = (int64_t)__builtin_amdgcn_readlane(ref_c, j);
-          clo = clo - ref > 0 ? clo - ref : 0;
-          chi = chi - ref < top ? chi - ref : top;
-        }
-        const uint64_t mine = block_marks<B>(clo, chi, st + j * Geo::kWords, valid, lane, cnt);
-        if (lane < 16u) p.marks[k * 16u + lane] = mine;
+  const uint64_t npairs = (p.nb + 1u) / 2u;
+  const uint64_t tw = (uint64_t)gridDim.x * kSelWaves;
+  uint32_t* marks32 = reinterpret_cast<uint32_t*>(p.marks);
+  for (uint64_t q = (uint64_t)blockIdx.x * kSelWaves + wave; q < npairs; q += tw) {
+    const uint64_t k = 2u * q + half;
+    const bool in = k < p.nb;
+    const int cls = in ? block_class(p, zr, k) : 0;
+    const uint32_t valid = k == p.nb - 1u ? (uint32_t)(p.n - k * kBlockValues) : kBlockValues;
+    uint32_t cnt = 0;
+    if (cls == 1) {
+      int64_t clo = zr.lo, chi = zr.hi;
+      if (p.enc != ENC_DICT && p.refs) {
+        const int64_t ref = (int64_t)p.refs[k];
+        clo = clo - ref > 0 ? clo - ref : 0;
+        chi = chi - ref < top ? chi - ref : top;
       }
-      cnt_v = lane == j ? cnt : cnt_v;
+      if (clo < chi) {
+        const uint32_t lo32 = (uint32_t)clo, wm1 = (uint32_t)(chi - clo - 1);
+        uint32_t bits;
+        if constexpr (B == 32u) {
+          bits = valid == kBlockValues ? wide_marks<false>(p.payload + k * 1024u, l, half, lo32, wm1, valid)
+                                       : wide_marks<true>(p.payload + k * 1024u, l, half, lo32, wm1, valid);
+        } else if constexpr (B == 16u) {
+          bits = valid == kBlockValues ? quad_marks<false>(p.payload + k * 512u, l, lo32, wm1, valid)
+                                       : quad_marks<true>(p.payload + k * 512u, l, lo32, wm1, valid);
+        } else {
+          const uint32_t* src = p.payload + k * (32u * B) + l * B;
+          uint32_t w[B];
+          load_lane_words<B>(src, w);
+          bits = valid == kBlockValues ? lane_marks<B, false>(w, lo32, wm1, 32u * l, valid)
+                                       : lane_marks<B, true>(w, lo32, wm1, 32u * l, valid);
+        }
+        marks32[k * 32u + l] = bits;
+        cnt = (uint32_t)__builtin_popcount(bits);
+      }
     }
-    if (lane < G && k0 + lane < p.nb) p.counts[k0 + lane] = cnt_v;
+    // the half-wavefront's sum (lanes of the other half hold the other block)
+#pragma unroll
+    for (int o = 16; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, 32);
+    if (cls == 2) cnt = valid;
+    if (in && l == 0u) p.counts[k] = cnt;
   }
 }
 
@@ -471,6 +497,22 @@ using MarkTableT = decltype(make_mark_table(std::make_index_sequence<32>{}));
 
 hipError_t launch_select_mark(const SelParams& p, uint32_t grid, hipStream_t st) {
   if (p.b < 1 || p.b > 32) return hipErrorInvalidValue;
+  // no more work-groups than fit at once (the registers limit them): a
+  // grid-strided loop with a late second wave of work-groups runs that wave
+  // on a part of the chip
+  static int fit[32] = {};
+  const void* fn = reinterpret_cast<const void*>(MarkTableT::fns[p.b - 1]);
+  if (fit[p.b - 1] == 0) {
+    int dev = 0, cus = 0, occ = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, 64 * kSelWaves, 0) == hipSuccess && occ > 0 &&
+        cus > 0)
+      fit[p.b - 1] = cus * occ;
+    else
+      fit[p.b - 1] = -1;
+  }
+  if (fit[p.b - 1] > 0 && grid > (uint32_t)fit[p.b - 1]) grid = (uint32_t)fit[p.b - 1];
   hipLaunchKernelGGL(MarkTableT::fns[p.b - 1], dim3(grid), dim3(64 * kSelWaves), 0, st, p);
   return hipGetLastError();
 }
