@@ -141,38 +141,41 @@ __device__ __forceinline__ uint32_t wide_marks(const uint32_t* __restrict__ blk,
   return bits;
 }
 
-// 16-bit codes: mark word 8 i + j' (values 256 i + 32 j' .. + 31, 64 bytes)
-// is read in pass i by lanes 4 j' .. 4 j' + 3 of the half-wavefront, 16
-// bytes each (coalesced, nontemporal); each lane marks its 8 codes, and two
-// shuffles within the quad join the four bytes.  Lane l' then takes word l'
-// from the quad that built it.
-template <bool VALID>
-__device__ __forceinline__ uint32_t quad_marks(const uint32_t* __restrict__ blk, uint32_t l, uint32_t lo32,
-                                               uint32_t wm1, uint32_t valid) {
-  SelU32x4 v[4];
+// B = 8 or 16: the 4 B bytes of a mark word are read by a group of
+// P = B / 4 lanes, 16 bytes each; in pass i (of P) lane l' reads piece
+// 32 i + l' of the block (coalesced, nontemporal), the 32 / P codes of
+// values (32 i + l') 32 / P + c, which are bits (l' mod P) 32 / P + c of
+// mark word (32 i + l') / P.  Shuffles within the group join the pieces,
+// and lane l' then takes word l' from the group that built it.
+template <uint32_t B, bool VALID>
+__device__ __forceinline__ uint32_t group_marks(const uint32_t* __restrict__ blk, uint32_t l, uint32_t lo32,
+                                                uint32_t wm1, uint32_t valid) {
+  static_assert(B == 8u || B == 16u, "group marks take 8- or 16-bit codes");
+  constexpr uint32_t P = B / 4u, kCodes = 32u / P, kPerWord = 32u / B, kMask = (1u << B) - 1u;
+  SelU32x4 v[P];
 #pragma unroll
-  for (uint32_t i = 0; i < 4u; ++i) v[i] = __builtin_nontemporal_load(reinterpret_cast<const SelU32x4*>(blk) + 32u * i + l);
-  uint32_t r[4];
+  for (uint32_t i = 0; i < P; ++i) v[i] = __builtin_nontemporal_load(reinterpret_cast<const SelU32x4*>(blk) + 32u * i + l);
+  uint32_t r[P];
 #pragma unroll
-  for (uint32_t i = 0; i < 4u; ++i) {
-    uint32_t bits8 = 0;
+  for (uint32_t i = 0; i < P; ++i) {
+    uint32_t bits = 0;
 #pragma unroll
-    for (uint32_t c = 0; c < 8u; ++c) {
-      const uint32_t code = (v[i][c >> 1] >> (16u * (c & 1u))) & 0xFFFFu;
+    for (uint32_t c = 0; c < kCodes; ++c) {
+      const uint32_t code = (v[i][c / kPerWord] >> (B * (c % kPerWord))) & kMask;
       bool hit = (code - lo32) <= wm1;
-      if (VALID) hit = hit && (256u * i + 8u * l + c < valid);
-      bits8 |= (hit ? 1u : 0u) << c;
+      if (VALID) hit = hit && ((32u * i + l) * kCodes + c < valid);
+      bits |= (hit ? 1u : 0u) << c;
     }
-    uint32_t x = bits8 << (8u * (l & 3u));
-    x |= __shfl_xor(x, 1, 32);
-    x |= __shfl_xor(x, 2, 32);
+    uint32_t x = bits << (kCodes * (l % P));
+#pragma unroll
+    for (uint32_t o = 1; o < P; o <<= 1) x |= __shfl_xor(x, (int)o, 32);
     r[i] = x;
   }
   uint32_t out = 0;
 #pragma unroll
-  for (uint32_t i = 0; i < 4u; ++i) {
-    const uint32_t t = __shfl(r[i], (int)(4u * (l & 7u)), 32);
-    out = (l >> 3) == i ? t : out;
+  for (uint32_t i = 0; i < P; ++i) {
+    const uint32_t t = __shfl(r[i], (int)(P * (l % kCodes)), 32);
+    out = l / kCodes == i ? t : out;
   }
   return out;
 }
@@ -215,9 +218,9 @@ __global__ __launch_bounds__(256) void select_mark_kernel(const SelParams p) {
         if constexpr (B == 32u) {
           bits = valid == kBlockValues ? wide_marks<false>(p.payload + k * 1024u, l, half, lo32, wm1, valid)
                                        : wide_marks<true>(p.payload + k * 1024u, l, half, lo32, wm1, valid);
-        } else if constexpr (B == 16u) {
-          bits = valid == kBlockValues ? quad_marks<false>(p.payload + k * 512u, l, lo32, wm1, valid)
-                                       : quad_marks<true>(p.payload + k * 512u, l, lo32, wm1, valid);
+        } else if constexpr (B == 8u || B == 16u) {
+          bits = valid == kBlockValues ? group_marks<B, false>(p.payload + k * (32u * B), l, lo32, wm1, valid)
+                                       : group_marks<B, true>(p.payload + k * (32u * B), l, lo32, wm1, valid);
         } else {
           const uint32_t* src = p.payload + k * (32u * B) + l * B;
           uint32_t w[B];
