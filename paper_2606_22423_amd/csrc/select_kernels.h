@@ -15,7 +15,7 @@ struct SelParams {
   const uint32_t* zmin;    // zone maps (values / codes), or null
   const uint32_t* zmax;
   const int64_t* zrange;   // device: the predicate in the zone-map / code domain (written by setup)
-  uint64_t* marks;         // select: 16 pass ballots per block (bit l of word t: value l + 64 t)
+  uint64_t* marks;         // select: 1024-bit mark string per block, 16 words (bit l of word t: value l + 64 t)
   uint32_t* counts;        // per block (select) or per chunk of positions (refine)
   uint32_t* offsets;       // exclusive prefix of counts
   uint64_t n, nb;

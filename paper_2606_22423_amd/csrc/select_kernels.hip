@@ -3,26 +3,26 @@
 // list (refine by another column's predicate, gather values).
 //
 // Select runs in three steps so that the output order is the row order:
-//  1. mark (one kernel per width b): every wavefront takes groups of
-//     G = max(1, 32 / b) consecutive blocks (at most 4 KB of words), groups
-//     g = w, w + W, ... (W wavefronts); it tests the zone maps, stages the
-//     blocks that need decoding in LDS, decodes them (values j = lane + 64 t)
-//     and stores each block's 16 pass ballots (one bit per value, 128 bytes)
-//     and match count.  The next group's words are in flight in registers
-//     while the current group decodes from LDS, and the zone maps and block
-//     references arrive one group further ahead, so no load waits in the
-//     steady state;
+//  1. mark (one kernel per width b): every wavefront takes two blocks at a
+//     time, half a wavefront each; after the zone-map test, lane l' of a
+//     half marks the 32 values 32 l' .. 32 l' + 31 of its block from codes
+//     in registers and stores them as one 32-bit word (the block's 1024-bit
+//     mark string, 128 bytes, one bit per value), and the half's popcount
+//     sum is the block's match count.  Codes of 8 and 16 bits are read
+//     coalesced by groups of b / 4 lanes per mark word, 32-bit codes by the
+//     whole half with one ballot per word, other widths as each lane's own
+//     slice of b words;
 //  2. an exclusive scan of the counts gives each block its output offset
 //     (tiles of 1024 counts per work-group, one work-group over the tile
 //     totals, then the tile offsets added back);
-//  3. write: groups of 16 consecutive blocks per wavefront; the ballots of the
-//     group's blocks with matches arrive in one round of loads, each nonzero
-//     ballot gets its output offset (the block's offset plus a prefix sum of
-//     the popcounts of the block's earlier steps) and its matches leave with
-//     mbcnt, so every position lands at its rank in row order.  The payload
-//     is not read again.
+//  3. write: groups of 16 consecutive blocks per wavefront; the marks of the
+//     group's blocks with matches arrive in one round of loads, read as 16
+//     64-bit words per block; four consecutive blocks fill one contiguous
+//     output range, expanded in the wavefront's LDS buffer and copied out
+//     with coalesced stores, so every position lands at its rank in row
+//     order.  The payload is not read again.
 //     A block entirely inside the predicate (all-match, with zone maps) has
-//     no ballots: its position range is written without being read.
+//     no marks: its position range is written without being read.
 // Work loops use a wave-uniform block index (readfirstlane), so their
 // control flow is the same in every lane.
 #include "device_common.h"
